@@ -1,0 +1,166 @@
+/*
+ * liblrqo — low-rank K-ary quadratic maximisation on one MI355X (gfx950).
+ *
+ * Problem (Sec. 1, eq. max_quad with the K-th roots of unity of eq. AK_def,
+ * in the factor form of Sec. 2.2, eq. quad_max-norm):
+ *
+ *        maximise  ||V^H z||^2 = z^H (V V^H) z   over  z in A_K^n,
+ *        A_K = { exp(2 pi i k / K) : k = 0 .. K-1 }.
+ *
+ * An assignment is returned as uint8 labels k_i (z_i = exp(2 pi i k_i / K)),
+ * so K <= 255.  The objective is always the FP64 value ||V^H z||^2 of the
+ * returned labels.
+ *
+ * Memory: every array argument named "device" must be device memory of the
+ * current HIP device; host arguments are ordinary host memory.  The caller
+ * owns all of them; the library never frees or keeps caller memory.  The
+ * library's own scratch (per device, grown on demand) is released by
+ * lrqo_shutdown().
+ *
+ * Ordering: work is enqueued on the stream set by lrqo_set_stream (the null
+ * stream by default) and every solve call synchronises that stream before it
+ * returns, because results are delivered to host memory.
+ *
+ * Errors: every call returns an lrqo_status; no exception crosses the ABI.
+ * Argument errors are detected before any device work is issued.  A short
+ * description of the last failure of the calling thread is available from
+ * lrqo_last_error().  On error the contents of outputs are unspecified.
+ */
+#ifndef LRQO_H
+#define LRQO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lrqo_status {
+    LRQO_OK = 0,
+    LRQO_EINVAL = -1,     /* argument out of range, null pointer, bad layout */
+    LRQO_ENOMEM = -2,     /* device scratch could not be allocated */
+    LRQO_EDEVICE = -3,    /* a HIP runtime call failed (message says which) */
+    LRQO_ETOOBIG = -4,    /* exact enumeration larger than the cap */
+    LRQO_ENOTFINITE = -5  /* V holds a NaN or an infinity */
+} lrqo_status;
+
+#define LRQO_MAX_R 8
+#define LRQO_MAX_K 255
+#define LRQO_MAX_TOPK 64
+
+/* Version as major*10000 + minor*100 + patch. */
+int32_t lrqo_version(void);
+
+/* Text of the calling thread's last error ("" if none). */
+const char* lrqo_last_error(void);
+
+/* Stream used by later calls of the calling thread (a hipStream_t; NULL is
+ * the null stream).  Returns LRQO_OK. */
+lrqo_status lrqo_set_stream(void* hip_stream);
+
+/* Release the library's device scratch on every device it touched. */
+lrqo_status lrqo_shutdown(void);
+
+/* --------------------------------------------------------------------------
+ * Sampled maximisation (Sec. 4.2, eq. def_f; Thm. rr_tail).
+ *
+ * Draws directions c_s, s = first_index .. first_index + S - 1, uniformly on
+ * the complex unit sphere of C^r as c = g / ||g||, g a standard Gaussian in
+ * R^{2r} (proof of Lemma innerIsBeta), rounds each row by the decision rule
+ * (Sec. 3, eq. decision_rule: z_i = the K-th root nearest in phase to
+ * (V c)_i) and keeps the best f(c) = ||V^H z(c)||^2.
+ *
+ * Direction stream (the paper fixes none): Philox4x32-10 with key
+ * (seed & 0xffffffff, seed >> 32) and counter (s & 0xffffffff, s >> 32,
+ * instance, b) for blocks b = 0..ceil(2r/4)-1; word t of block b is uniform
+ * u[4b+t] = ((x >> 9) + 1/2) * 2^-23; g[2j] = sqrt(-2 ln u[2j]) cos(2 pi u[2j+1]),
+ * g[2j+1] = sqrt(-2 ln u[2j]) sin(2 pi u[2j+1]); c_j = (g[2j] + i g[2j+1])/||g||.
+ * The device evaluates this stream in FP32.
+ *
+ * Scoring: every candidate is scored in FP32; the best `rescore_topk` FP32
+ * scores (ties to the lower index) are re-evaluated in FP64 from the same
+ * FP32 direction widened to FP64; the FP64 arg-max (ties to the lower index)
+ * is the result.  Labels and objective are therefore exactly those of the
+ * FP64 decision rule at the returned direction.
+ *
+ * V (device): n x r, row-major.  complex layout: interleaved FP32 (re, im),
+ * element (i, j) at V[2*(i*r + j)]; real layout (options->real_v = 1):
+ * FP32, element (i, j) at V[i*r + j].
+ * z (device): n uint8 labels of the winner.
+ * Ranges: 1 <= n <= 2^31 - 1, 1 <= r <= 8, 2 <= K <= 255,
+ * 1 <= S <= 2^32 - 1; otherwise LRQO_EINVAL.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lrqo_sampled_options {
+    int32_t real_v;          /* 0: complex64 V; 1: real FP32 V */
+    int32_t precision;       /* 0: FP32 scorer; 1: BF16 MFMA for V c with
+                                FP32 recompute of rows inside the BF16 error
+                                margin (results as for 0) */
+    int32_t rescore_topk;    /* 1..64; 0 means 64 */
+    uint32_t instance;       /* counter word 2 of the direction stream */
+    uint64_t first_index;    /* index of the first direction (range splitting) */
+    float* f_out;            /* optional device [S]: FP32 score of every direction */
+} lrqo_sampled_options;
+
+typedef struct lrqo_sampled_result {
+    int64_t best_index;      /* absolute stream index s of the winner */
+    double obj;              /* FP64 ||V^H z||^2 of the returned labels */
+    double fp32_obj;         /* the FP32 scorer's value for the same direction */
+    double best_c[2 * LRQO_MAX_R]; /* winner's direction, FP64 copy of the FP32 values, (re, im) pairs */
+    int64_t flagged_rows;    /* precision 1: row-candidates recomputed in FP32 */
+    float device_ms;         /* device time of the call, from stream events */
+    float score_ms;          /* device time of the fused scoring kernels alone */
+    int32_t rescored;        /* candidates that went through the FP64 rescore */
+    int32_t slices;          /* row slices of the scoring launch */
+} lrqo_sampled_result;
+
+/* Complex V, FP32 scorer, 64-way FP64 rescore, instance 0, first index 0. */
+lrqo_status lrqo_solve_sampled(const float* V, int64_t n, int32_t r, int32_t K, int64_t S,
+                               uint64_t seed, uint8_t* z, double* obj);
+
+/* Full form.  opt may be NULL (defaults above); res (host) may be NULL. */
+lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t K, int64_t S,
+                                  uint64_t seed, const lrqo_sampled_options* opt, uint8_t* z,
+                                  lrqo_sampled_result* res);
+
+/* --------------------------------------------------------------------------
+ * Exact maximisation by arrangement-vertex enumeration (Sec. 3, Alg. 2,
+ * Thm. rankr).
+ *
+ * Builds the augmented real rows a_{i,m} = [Im(rho_m V_i), Re(rho_m V_i)],
+ * rho_m = exp(-i pi (2m+1)/K), m < B_K (eq. tildeV, Def. BK), enumerates every
+ * set of 2d-1 rows with at most two per coordinate (d = r, r-1, ..., 1, the
+ * recursion of Alg. 2 on the leading d columns), solves the FP64 null vector
+ * of each full-rank set (rank test sigma ratio > 1e-10 in the pivots of a
+ * fully pivoted elimination), takes both signs, labels untouched rows by the
+ * decision rule and tries, for coordinates in the set, both labels beside the
+ * boundary (one row in the set) or all K labels (two rows: V_i c = 0,
+ * Cor. two_implies_all).  Candidates are scored in FP32; the best 64 are
+ * rescored in FP64 and the FP64 maximum is returned.
+ *
+ * V (device): n x r complex128, interleaved (re, im), row-major.
+ * z (device): n uint8 labels.  obj (host): FP64 objective.
+ * Ranges: 1 <= r <= 4, r <= n, 2 <= K <= 255; the number of index sets
+ * C(n B_K, 2r-1) must not exceed max_sets (default 2^34) or LRQO_ETOOBIG.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lrqo_exact_result {
+    double obj;              /* FP64 objective of the returned labels */
+    int64_t index_sets;      /* valid index sets enumerated (all levels) */
+    int64_t rank_deficient;  /* sets rejected by the rank test */
+    int64_t candidates;      /* scored label vectors */
+    float device_ms;
+} lrqo_exact_result;
+
+lrqo_status lrqo_solve_exact(const double* V, int64_t n, int32_t r, int32_t K, uint8_t* z,
+                             double* obj);
+
+/* max_sets <= 0 means the default cap; res (host) may be NULL. */
+lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K,
+                                int64_t max_sets, uint8_t* z, lrqo_exact_result* res);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRQO_H */

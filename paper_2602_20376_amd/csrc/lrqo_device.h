@@ -1,0 +1,128 @@
+// Device-side building blocks shared by the liblrqo kernels: the direction
+// stream, the FP64 decision rule and small reductions.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lrqo {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11): per round
+// (hi0,lo0) = M0*x0, (hi1,lo1) = M1*x2, x <- (hi1^x1^k0, lo1, hi0^x3^k1, lo0),
+// then the key is bumped by the Weyl constants.
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Uniform on (0,1) with 23 random bits, exactly representable in FP32.
+__device__ __forceinline__ float uniform_from_bits(uint32_t x) {
+    return (static_cast<float>(x >> 9) + 0.5f) * 0x1p-23f;
+}
+
+// Direction c_s of the stream (seed, instance) in C^R, FP32, as
+// c[2j] = Re c_j, c[2j+1] = Im c_j.  Box-Muller on uniform pairs, then
+// normalisation to the unit sphere.
+template <int R>
+__device__ __forceinline__ void direction_f32(uint64_t seed, uint64_t s, uint32_t instance,
+                                              float (&c)[2 * R]) {
+    constexpr int NB = (2 * R + 3) / 4;
+    float u[4 * NB];
+    const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const U4 o = philox4x32_10(U4{static_cast<uint32_t>(s), static_cast<uint32_t>(s >> 32),
+                                      instance, static_cast<uint32_t>(b)},
+                                   k0, k1);
+        u[4 * b + 0] = uniform_from_bits(o.x);
+        u[4 * b + 1] = uniform_from_bits(o.y);
+        u[4 * b + 2] = uniform_from_bits(o.z);
+        u[4 * b + 3] = uniform_from_bits(o.w);
+    }
+    float norm2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const float rad = sqrtf(-2.0f * logf(u[2 * j]));
+        float sn, cs;
+        sincospif(2.0f * u[2 * j + 1], &sn, &cs);
+        c[2 * j] = rad * cs;
+        c[2 * j + 1] = rad * sn;
+        norm2 += c[2 * j] * c[2 * j] + c[2 * j + 1] * c[2 * j + 1];
+    }
+    const float inv = 1.0f / sqrtf(norm2);
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) c[j] *= inv;
+}
+
+// ---------------------------------------------------------------- labels
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// Decision rule in FP64: the K-th root nearest in phase,
+// k = floor(K arg(w)/(2 pi) + 1/2) mod K, with w = 0 -> 0.
+// Non-finite input maps to 0 so that table lookups stay in range (the
+// library reports such input as an error).
+__device__ __forceinline__ int label_f64(double wr, double wi, int K) {
+    if (wr == 0.0 && wi == 0.0) return 0;
+    const double x = static_cast<double>(K) * atan2(wi, wr) / kTwoPi + 0.5;
+    if (!(x > -2.0 * K && x < 2.0 * K)) return 0;
+    int k = static_cast<int>(floor(x)) % K;
+    return k < 0 ? k + K : k;
+}
+
+// Same rule in FP32 for any K.
+__device__ __forceinline__ int label_f32_generic(float wr, float wi, int K) {
+    const float x = static_cast<float>(K) * (atan2f(wi, wr) * 0.15915494309189535f) + 0.5f;
+    if (!(x > -(float)K && x < (float)K)) return 0;
+    int k = static_cast<int>(floorf(x));
+    k = k >= K ? k - K : k;
+    k = k < 0 ? k + K : k;
+    return (wr == 0.0f && wi == 0.0f) ? 0 : k;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Packed arg-max key: objective bits above, complemented index below, so the
+// unsigned maximum is the largest objective and, among equal objectives, the
+// lowest index.  f >= 0, so its IEEE bits order like the values.
+__device__ __forceinline__ unsigned long long pack_key(float f, uint32_t idx) {
+    return (static_cast<unsigned long long>(__float_as_uint(f)) << 32) |
+           static_cast<unsigned long long>(0xFFFFFFFFu - idx);
+}
+__device__ __forceinline__ uint32_t key_index(unsigned long long key) {
+    return 0xFFFFFFFFu - static_cast<uint32_t>(key & 0xFFFFFFFFull);
+}
+__device__ __forceinline__ float key_value(unsigned long long key) {
+    return __uint_as_float(static_cast<uint32_t>(key >> 32));
+}
+
+}  // namespace lrqo

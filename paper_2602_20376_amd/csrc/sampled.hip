@@ -1,0 +1,528 @@
+// Sampled maximisation (Sec. 4.2): fused FP32 scorer over uniform sphere
+// directions, top-T selection, FP64 rescore of the T best, label write-out.
+//
+// Kernels, in launch order:
+//   k_check_finite  flags a NaN/Inf in V
+//   k_score         fused candidate generation + scoring (A1, A3-A6): each
+//                   lane owns CPL directions in registers; the block streams
+//                   row tiles of V through LDS (every lane of a wave reads the
+//                   same row: an LDS broadcast); per row-candidate it forms
+//                   w = V_i c, rounds arg(w) to the nearest K-th root and
+//                   accumulates s += conj(V_i) z_i.  With several row slices
+//                   (gridDim.y > 1) it writes partial sums instead.
+//   k_finalize      sums the slice partials in a fixed order -> f = ||s||^2
+//   k_topk          bitonic sort of packed (f, index) keys per 2048-chunk,
+//                   keeps the best T; repeated until T keys are left
+//   k_rescore       FP64 re-evaluation of each kept direction, row-sliced
+//   k_pick          FP64 arg-max of the rescored candidates (ties -> lowest index)
+//   k_labels        FP64 decision rule of the winner -> uint8 labels
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "lrqo_device.h"
+#include "lrqo_runtime.h"
+#include "sampled_internal.h"
+
+namespace lrqo {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kTile = 256;        // rows per LDS tile
+constexpr int kTopChunk = 2048;   // keys sorted per block in k_topk
+
+// ------------------------------------------------------------ nearest root
+// KS selects a closed form for small K (2, 3, 4); KS = 0 is any K via atan2
+// and an LDS table of roots.
+template <int KS>
+__device__ __forceinline__ void nearest_root(float wr, float wi, int K, const float2* roots,
+                                             float& zr, float& zi) {
+    if constexpr (KS == 2) {
+        const bool k0 = wr >= 0.0f;
+        zr = k0 ? 1.0f : -1.0f;
+        zi = 0.0f;
+    } else if constexpr (KS == 3) {
+        // label 0 iff |arg w| < pi/3  <=>  |wi| < sqrt(3) wr; otherwise the
+        // sign of wi picks omega (upper half) or omega^2 (lower half)
+        const bool k0 = fabsf(wi) <= wr * 1.7320508075688772f;
+        zr = k0 ? 1.0f : -0.5f;
+        zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
+    } else if constexpr (KS == 4) {
+        const bool horiz = fabsf(wr) >= fabsf(wi);
+        zr = horiz ? copysignf(1.0f, wr) : 0.0f;
+        zi = horiz ? 0.0f : copysignf(1.0f, wi);
+    } else {
+        const int k = label_f32_generic(wr, wi, K);
+        const float2 t = roots[k];
+        zr = t.x;
+        zi = t.y;
+    }
+}
+
+template <int R, bool REAL>
+struct Row {
+    static constexpr int F = REAL ? R : 2 * R;  // floats per row of V
+};
+
+// ------------------------------------------------------------ checks
+__global__ void k_check_finite(const float* __restrict__ V, int64_t count, DevResult* res) {
+    bool bad = false;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(V[e]);
+    if (bad) res->nonfinite = 1;
+}
+
+// ------------------------------------------------------------ fused scorer
+template <int R, int CPL, bool REAL, int KS>
+__global__ __launch_bounds__(kBlock) void k_score(ScoreParams p) {
+    constexpr int RF = Row<R, REAL>::F;
+    __shared__ __align__(16) float tile[kTile * RF];
+    __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
+    const int tid = threadIdx.x;
+    if constexpr (KS == 0) {
+        for (int k = tid; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
+    }
+
+    float c[CPL][2 * R], acc[CPL][2 * R];
+    const uint32_t base = blockIdx.x * (uint32_t)(kBlock * CPL) + tid;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        const uint32_t idx = base + q * kBlock;
+        if (idx < p.S) {
+            direction_f32<R>(p.seed, p.first + idx, p.instance, c[q]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) c[q][j] = 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) acc[q][j] = 0.0f;
+    }
+
+    const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
+    const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
+    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
+        const int cnt = (int)min((int64_t)kTile, r1 - t0);
+        __syncthreads();
+        const float* __restrict__ src = p.V + t0 * RF;
+        for (int e = tid; e < cnt * RF; e += kBlock) tile[e] = src[e];
+        __syncthreads();
+        for (int i = 0; i < cnt; ++i) {
+            float v[RF];
+#pragma unroll
+            for (int e = 0; e < RF; ++e) v[e] = tile[i * RF + e];
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                float wr = 0.0f, wi = 0.0f;
+                if constexpr (REAL) {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        wr = fmaf(v[j], c[q][2 * j], wr);
+                        wi = fmaf(v[j], c[q][2 * j + 1], wi);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const float vr = v[2 * j], vi = v[2 * j + 1];
+                        wr = fmaf(vr, c[q][2 * j], fmaf(-vi, c[q][2 * j + 1], wr));
+                        wi = fmaf(vr, c[q][2 * j + 1], fmaf(vi, c[q][2 * j], wi));
+                    }
+                }
+                float zr, zi;
+                nearest_root<KS>(wr, wi, p.K, roots_s, zr, zi);
+                if constexpr (REAL) {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        acc[q][2 * j] = fmaf(v[j], zr, acc[q][2 * j]);
+                        acc[q][2 * j + 1] = fmaf(v[j], zi, acc[q][2 * j + 1]);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const float vr = v[2 * j], vi = v[2 * j + 1];
+                        // conj(V_ij) z_i
+                        acc[q][2 * j] = fmaf(vr, zr, fmaf(vi, zi, acc[q][2 * j]));
+                        acc[q][2 * j + 1] = fmaf(vr, zi, fmaf(-vi, zr, acc[q][2 * j + 1]));
+                    }
+                }
+            }
+        }
+    }
+
+    if (gridDim.y == 1) {
+        unsigned long long best = 0;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const uint32_t idx = base + q * kBlock;
+            if (idx < p.S) {
+                float f = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 2 * R; ++j) f = fmaf(acc[q][j], acc[q][j], f);
+                p.f_out[idx] = f;
+                const unsigned long long key = pack_key(f, idx);
+                best = key > best ? key : best;
+            }
+        }
+        best = wave_max_u64(best);
+        if ((tid & (kWave - 1)) == 0 && best) atomicMax(p.best_key, best);
+    } else {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const uint32_t idx = base + q * kBlock;
+            if (idx < p.S) {
+#pragma unroll
+                for (int j = 0; j < 2 * R; ++j)
+                    p.partial[((size_t)blockIdx.y * (2 * R) + j) * p.S + idx] = acc[q][j];
+            }
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ partial, int P,
+                                                     uint32_t S, float* __restrict__ f_out,
+                                                     unsigned long long* best_key) {
+    const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
+    unsigned long long best = 0;
+    if (idx < S) {
+        float f = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) {
+            float a = 0.0f;
+            for (int p = 0; p < P; ++p) a += partial[((size_t)p * (2 * R) + j) * S + idx];
+            f = fmaf(a, a, f);
+        }
+        f_out[idx] = f;
+        best = pack_key(f, idx);
+    }
+    best = wave_max_u64(best);
+    if ((threadIdx.x & (kWave - 1)) == 0 && best) atomicMax(best_key, best);
+}
+
+// ------------------------------------------------------------ top-T
+// Each block sorts one chunk of packed keys (descending) in LDS and keeps
+// its first T.  Keys come from f (index = position) or from a previous pass.
+// Padding keys are 0, below every real key (a real key has index < 2^32-1,
+// so its low word is nonzero).
+__global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
+                                                 const unsigned long long* __restrict__ keys_in,
+                                                 uint32_t count, int T,
+                                                 unsigned long long* __restrict__ keys_out) {
+    __shared__ unsigned long long sk[kTopChunk];
+    const uint32_t base = blockIdx.x * (uint32_t)kTopChunk;
+    for (int e = threadIdx.x; e < kTopChunk; e += kBlock) {
+        const uint32_t g = base + e;
+        unsigned long long key = 0;
+        if (g < count) key = f ? pack_key(f[g], g) : keys_in[g];
+        sk[e] = key;
+    }
+    __syncthreads();
+    for (int k = 2; k <= kTopChunk; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int e = threadIdx.x; e < kTopChunk; e += kBlock) {
+                const int x = e ^ j;
+                if (x > e) {
+                    const unsigned long long a = sk[e], b = sk[x];
+                    const bool desc = (e & k) == 0;
+                    if (desc ? (a < b) : (a > b)) {
+                        sk[e] = b;
+                        sk[x] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < T; e += kBlock) keys_out[(size_t)blockIdx.x * T + e] = sk[e];
+}
+
+// ------------------------------------------------------------ FP64 rescore
+template <int R, bool REAL>
+__global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
+    __shared__ double2 roots_s[LRQO_MAX_K];
+    __shared__ double red[kBlock / kWave][2 * R];
+    for (int k = threadIdx.x; k < p.K; k += kBlock) roots_s[k] = p.roots64[k];
+    __syncthreads();
+    const int t = blockIdx.x;
+    const uint32_t idx = key_index(p.keys[t]);
+    float cf[2 * R];
+    direction_f32<R>(p.seed, p.first + idx, p.instance, cf);
+    double c[2 * R], acc[2 * R];
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) {
+        c[j] = (double)cf[j];
+        acc[j] = 0.0;
+    }
+    const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
+    const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
+    constexpr int RF = Row<R, REAL>::F;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+        const float* row = p.V + i * RF;
+        double wr = 0.0, wi = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const double vr = REAL ? (double)row[j] : (double)row[2 * j];
+            const double vi = REAL ? 0.0 : (double)row[2 * j + 1];
+            wr += vr * c[2 * j] - vi * c[2 * j + 1];
+            wi += vr * c[2 * j + 1] + vi * c[2 * j];
+        }
+        const double2 z = roots_s[label_f64(wr, wi, p.K)];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const double vr = REAL ? (double)row[j] : (double)row[2 * j];
+            const double vi = REAL ? 0.0 : (double)row[2 * j + 1];
+            acc[2 * j] += vr * z.x + vi * z.y;
+            acc[2 * j + 1] += vr * z.y - vi * z.x;
+        }
+    }
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) {
+        const double s = wave_sum_f64(acc[j]);
+        if (lane == 0) red[wave][j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * R) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) s += red[w][threadIdx.x];
+        p.partial[((size_t)t * gridDim.y + blockIdx.y) * (2 * R) + threadIdx.x] = s;
+    }
+}
+
+template <int R>
+__global__ void k_pick(const double* __restrict__ partial, int T, int P,
+                       const unsigned long long* __restrict__ keys, uint64_t seed,
+                       uint32_t instance, uint64_t first, DevResult* res) {
+    if (threadIdx.x != 0) return;
+    int bt = -1;
+    double bf = -1.0;
+    uint32_t bidx = 0xFFFFFFFFu;
+    for (int t = 0; t < T; ++t) {
+        double f = 0.0;
+        for (int j = 0; j < 2 * R; ++j) {
+            double a = 0.0;
+            for (int q = 0; q < P; ++q) a += partial[((size_t)t * P + q) * (2 * R) + j];
+            f += a * a;
+        }
+        const uint32_t idx = key_index(keys[t]);
+        if (f > bf || (f == bf && idx < bidx)) {
+            bf = f;
+            bt = t;
+            bidx = idx;
+        }
+    }
+    if (bt < 0) {  // only with non-finite scores; the host reports the error
+        bt = 0;
+        bidx = key_index(keys[0]);
+    }
+    float cf[2 * R];
+    direction_f32<R>(seed, first + bidx, instance, cf);
+    res->best_index = (int64_t)(first + bidx);
+    res->obj = bf;
+    res->fp32_obj = (double)key_value(keys[bt]);
+    for (int j = 0; j < 2 * LRQO_MAX_R; ++j) res->c[j] = j < 2 * R ? (double)cf[j] : 0.0;
+}
+
+template <int R, bool REAL>
+__global__ __launch_bounds__(kBlock) void k_labels(const float* __restrict__ V, int64_t n, int K,
+                                                   const DevResult* __restrict__ res,
+                                                   uint8_t* __restrict__ z) {
+    constexpr int RF = Row<R, REAL>::F;
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float* row = V + i * RF;
+    double wr = 0.0, wi = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const double vr = REAL ? (double)row[j] : (double)row[2 * j];
+        const double vi = REAL ? 0.0 : (double)row[2 * j + 1];
+        wr += vr * res->c[2 * j] - vi * res->c[2 * j + 1];
+        wi += vr * res->c[2 * j + 1] + vi * res->c[2 * j];
+    }
+    z[i] = (uint8_t)label_f64(wr, wi, K);
+}
+
+// ------------------------------------------------------------ host driver
+int cands_per_lane(int R) { return R <= 2 ? 4 : (R <= 4 ? 2 : 1); }
+
+template <int R, bool REAL, int KS>
+void launch_score(const ScoreParams& p, dim3 grid, hipStream_t st) {
+    constexpr int CPL = R <= 2 ? 4 : (R <= 4 ? 2 : 1);
+    hipLaunchKernelGGL((k_score<R, CPL, REAL, KS>), grid, dim3(kBlock), 0, st, p);
+}
+
+template <int R, bool REAL>
+void launch_score_k(const ScoreParams& p, dim3 grid, hipStream_t st) {
+    switch (p.K) {
+        case 2: launch_score<R, REAL, 2>(p, grid, st); break;
+        case 3: launch_score<R, REAL, 3>(p, grid, st); break;
+        case 4: launch_score<R, REAL, 4>(p, grid, st); break;
+        default: launch_score<R, REAL, 0>(p, grid, st); break;
+    }
+}
+
+template <int R, bool REAL>
+lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
+    const uint32_t S = (uint32_t)job.S;
+    const int CPL = cands_per_lane(R);
+    const int64_t cand_blocks = ((int64_t)S + kBlock * CPL - 1) / (kBlock * CPL);
+
+    // ---- fused scorer
+    ScoreParams p{};
+    p.V = job.V;
+    p.n = job.n;
+    p.K = job.K;
+    p.seed = job.seed;
+    p.instance = job.instance;
+    p.first = job.first;
+    p.S = S;
+    p.f_out = sc.f32;
+    p.partial = sc.partial;
+    p.best_key = sc.best_key;
+    p.roots32 = sc.roots32;
+    p.rows_per_slice = sc.rows_per_slice;
+    LRQO_HIP(hipEventRecord(job.ev_score0, st));
+    launch_score_k<R, REAL>(p, dim3((unsigned)cand_blocks, (unsigned)sc.slices), st);
+    LRQO_HIP(hipGetLastError());
+    if (sc.slices > 1) {
+        hipLaunchKernelGGL((k_finalize<R>), dim3((S + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                           sc.partial, sc.slices, S, sc.f32, sc.best_key);
+        LRQO_HIP(hipGetLastError());
+    }
+    LRQO_HIP(hipEventRecord(job.ev_score1, st));
+
+    // ---- top-T
+    const int T = sc.topk;
+    const unsigned long long* keys = nullptr;
+    uint32_t count = S;
+    int ping = 0;
+    bool from_f = true;
+    while (from_f || count > (uint32_t)T) {
+        const uint32_t blocks = (count + kTopChunk - 1) / kTopChunk;
+        unsigned long long* out = ping ? sc.keys_b : sc.keys_a;
+        hipLaunchKernelGGL(k_topk, dim3(blocks), dim3(kBlock), 0, st, from_f ? sc.f32 : nullptr,
+                           keys, count, T, out);
+        LRQO_HIP(hipGetLastError());
+        keys = out;
+        count = blocks * (uint32_t)T;
+        ping ^= 1;
+        from_f = false;
+        if (blocks == 1) break;
+    }
+
+    // ---- FP64 rescore of the T kept keys
+    RescoreParams rp{};
+    rp.V = job.V;
+    rp.n = job.n;
+    rp.K = job.K;
+    rp.seed = job.seed;
+    rp.instance = job.instance;
+    rp.first = job.first;
+    rp.keys = keys;
+    rp.roots64 = sc.roots64;
+    rp.partial = sc.rescore;
+    rp.rows_per_slice = sc.rescore_rows;
+    hipLaunchKernelGGL((k_rescore<R, REAL>), dim3(T, sc.rescore_slices), dim3(kBlock), 0, st, rp);
+    LRQO_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_pick<R>), dim3(1), dim3(64), 0, st, sc.rescore, T, sc.rescore_slices, keys,
+                       job.seed, job.instance, job.first, sc.result);
+    LRQO_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_labels<R, REAL>), dim3((unsigned)((job.n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, job.V, job.n, job.K, sc.result, job.z);
+    LRQO_HIP(hipGetLastError());
+    return LRQO_OK;
+}
+
+template <bool REAL>
+lrqo_status dispatch_r(const SampledJob& job, Scratch& sc, hipStream_t st) {
+    switch (job.r) {
+        case 1: return run_sampled<1, REAL>(job, sc, st);
+        case 2: return run_sampled<2, REAL>(job, sc, st);
+        case 3: return run_sampled<3, REAL>(job, sc, st);
+        case 4: return run_sampled<4, REAL>(job, sc, st);
+        case 5: return run_sampled<5, REAL>(job, sc, st);
+        case 6: return run_sampled<6, REAL>(job, sc, st);
+        case 7: return run_sampled<7, REAL>(job, sc, st);
+        case 8: return run_sampled<8, REAL>(job, sc, st);
+        default: return fail(LRQO_EINVAL, "r out of range");
+    }
+}
+
+}  // namespace
+
+// Plans the launch shapes and the scratch layout of one sampled solve.
+void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
+    const int R = job.r;
+    const int CPL = cands_per_lane(R);
+    const int64_t cand_blocks = (job.S + kBlock * CPL - 1) / (kBlock * CPL);
+    // enough blocks to fill 256 CUs several times over, slices of >= 1024 rows
+    int64_t slices = std::max<int64_t>(1, (4096 + cand_blocks - 1) / cand_blocks);
+    slices = std::min<int64_t>(slices, std::max<int64_t>(1, job.n / 1024));
+    int64_t rows = (job.n + slices - 1) / slices;
+    rows = ((rows + 63) / 64) * 64;
+    slices = (job.n + rows - 1) / rows;
+    plan.slices = (int)slices;
+    plan.rows_per_slice = rows;
+    plan.topk = (int)std::min<int64_t>(job.topk, job.S);
+    int64_t rrows = std::max<int64_t>(4096, (job.n + 127) / 128);
+    plan.rescore_rows = rrows;
+    plan.rescore_slices = (int)((job.n + rrows - 1) / rrows);
+    CarveSize cs;
+    cs.add<DevResult>(1);
+    cs.add<unsigned long long>(1);
+    cs.add<float2>(LRQO_MAX_K);
+    cs.add<double2>(LRQO_MAX_K);
+    cs.add<float>(job.f_out ? 0 : job.S);
+    cs.add<float>(slices > 1 ? (size_t)slices * 2 * R * job.S : 0);
+    const size_t chunks = (job.S + kTopChunk - 1) / kTopChunk;
+    cs.add<unsigned long long>(chunks * plan.topk);
+    cs.add<unsigned long long>(chunks * plan.topk);
+    cs.add<double>((size_t)plan.topk * plan.rescore_slices * 2 * R);
+    plan.bytes = cs.bytes;
+}
+
+lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena,
+                           void* host_roots /* pinned, >= 4*LRQO_MAX_K doubles */,
+                           hipStream_t st) {
+    Carve cv(arena);
+    Scratch sc{};
+    sc.result = cv.take<DevResult>(1);
+    sc.best_key = cv.take<unsigned long long>(1);
+    sc.roots32 = cv.take<float2>(LRQO_MAX_K);
+    sc.roots64 = cv.take<double2>(LRQO_MAX_K);
+    sc.f32 = job.f_out ? job.f_out : cv.take<float>(job.S);
+    sc.slices = plan.slices;
+    sc.rows_per_slice = plan.rows_per_slice;
+    sc.partial = plan.slices > 1 ? cv.take<float>((size_t)plan.slices * 2 * job.r * job.S) : nullptr;
+    const size_t chunks = (job.S + kTopChunk - 1) / kTopChunk;
+    sc.topk = plan.topk;
+    sc.keys_a = cv.take<unsigned long long>(chunks * plan.topk);
+    sc.keys_b = cv.take<unsigned long long>(chunks * plan.topk);
+    sc.rescore_slices = plan.rescore_slices;
+    sc.rescore_rows = plan.rescore_rows;
+    sc.rescore = cv.take<double>((size_t)plan.topk * plan.rescore_slices * 2 * job.r);
+
+    // roots of unity, FP64 from the host libm and their FP32 roundings
+    double* h64 = static_cast<double*>(host_roots);
+    float* h32 = reinterpret_cast<float*>(h64 + 2 * LRQO_MAX_K);
+    for (int k = 0; k < job.K; ++k) {
+        const double a = 6.283185307179586476925286766559 * (double)k / (double)job.K;
+        h64[2 * k] = std::cos(a);
+        h64[2 * k + 1] = std::sin(a);
+        h32[2 * k] = (float)h64[2 * k];
+        h32[2 * k + 1] = (float)h64[2 * k + 1];
+    }
+    LRQO_HIP(hipMemcpyAsync(sc.roots64, h64, sizeof(double) * 2 * job.K, hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemcpyAsync(sc.roots32, h32, sizeof(float) * 2 * job.K, hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemsetAsync(sc.result, 0, sizeof(DevResult), st));
+    LRQO_HIP(hipMemsetAsync(sc.best_key, 0, sizeof(unsigned long long), st));
+
+    const int64_t vcount = job.n * job.r * (job.real ? 1 : 2);
+    hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(256), 0, st, job.V, vcount, sc.result);
+    LRQO_HIP(hipGetLastError());
+    return job.real ? dispatch_r<true>(job, sc, st) : dispatch_r<false>(job, sc, st);
+}
+
+}  // namespace lrqo

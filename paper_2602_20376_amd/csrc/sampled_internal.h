@@ -1,0 +1,98 @@
+// Internal interfaces of the sampled solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lrqo.h"
+
+namespace lrqo {
+
+// Result block written by the device and copied to pinned host memory.
+struct DevResult {
+    int64_t best_index;
+    double obj;
+    double fp32_obj;
+    double c[2 * LRQO_MAX_R];
+    int32_t nonfinite;
+    int32_t pad;
+    int64_t flagged_rows;
+};
+
+struct ScoreParams {
+    const float* V;
+    int64_t n;
+    int K;
+    uint64_t seed;
+    uint32_t instance;
+    uint64_t first;
+    uint32_t S;
+    int64_t rows_per_slice;
+    float* f_out;
+    float* partial;
+    unsigned long long* best_key;
+    const float2* roots32;
+};
+
+struct RescoreParams {
+    const float* V;
+    int64_t n;
+    int K;
+    uint64_t seed;
+    uint32_t instance;
+    uint64_t first;
+    const unsigned long long* keys;
+    const double2* roots64;
+    double* partial;
+    int64_t rows_per_slice;
+};
+
+struct SampledJob {
+    const float* V;
+    int64_t n;
+    int r;
+    int K;
+    int64_t S;
+    uint64_t seed;
+    uint32_t instance;
+    uint64_t first;
+    bool real;
+    int precision;
+    int topk;
+    float* f_out;
+    uint8_t* z;
+    hipEvent_t ev_score0;   // recorded before / after the scoring kernels
+    hipEvent_t ev_score1;
+};
+
+struct ScratchPlan {
+    int slices = 1;
+    int64_t rows_per_slice = 0;
+    int topk = 64;
+    int rescore_slices = 1;
+    int64_t rescore_rows = 0;
+    size_t bytes = 0;
+};
+
+struct Scratch {
+    DevResult* result;
+    unsigned long long* best_key;
+    float2* roots32;
+    double2* roots64;
+    float* f32;
+    float* partial;
+    int slices;
+    int64_t rows_per_slice;
+    int topk;
+    unsigned long long* keys_a;
+    unsigned long long* keys_b;
+    double* rescore;
+    int rescore_slices;
+    int64_t rescore_rows;
+};
+
+void plan_sampled(const SampledJob& job, ScratchPlan& plan);
+lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena,
+                           void* host_roots, hipStream_t st);
+
+}  // namespace lrqo

@@ -1,0 +1,176 @@
+"""Python binding of liblrqo (ctypes).  Argument marshalling only: every step
+of the solve runs in the library's HIP kernels.  PyTorch supplies device
+memory and the current stream.
+
+The library must be built (``python -m paper_2602_20376_amd.build``); if it is
+missing, every call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrqo.so")
+
+MAX_R = 8
+MAX_K = 255
+MAX_TOPK = 64
+
+STATUS = {0: "LRQO_OK", -1: "LRQO_EINVAL", -2: "LRQO_ENOMEM", -3: "LRQO_EDEVICE",
+          -4: "LRQO_ETOOBIG", -5: "LRQO_ENOTFINITE"}
+
+# every entry point declared in include/lrqo.h
+EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown",
+           "lrqo_solve_sampled", "lrqo_solve_sampled_ex", "lrqo_solve_exact",
+           "lrqo_solve_exact_ex")
+
+
+class LrqoError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class SampledOptions(ctypes.Structure):
+    _fields_ = [("real_v", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("rescore_topk", ctypes.c_int32), ("instance", ctypes.c_uint32),
+                ("first_index", ctypes.c_uint64), ("f_out", ctypes.c_void_p)]
+
+
+class SampledResult(ctypes.Structure):
+    _fields_ = [("best_index", ctypes.c_int64), ("obj", ctypes.c_double),
+                ("fp32_obj", ctypes.c_double), ("best_c", ctypes.c_double * (2 * MAX_R)),
+                ("flagged_rows", ctypes.c_int64), ("device_ms", ctypes.c_float),
+                ("score_ms", ctypes.c_float), ("rescored", ctypes.c_int32),
+                ("slices", ctypes.c_int32)]
+
+
+class ExactResult(ctypes.Structure):
+    _fields_ = [("obj", ctypes.c_double), ("index_sets", ctypes.c_int64),
+                ("rank_deficient", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("device_ms", ctypes.c_float)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblrqo.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"liblrqo.so not found at {path}: build it with "
+                           "`python -m paper_2602_20376_amd.build`")
+    lib = ctypes.CDLL(path)
+    i32, i64, u32, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    vp = ctypes.c_void_p
+    lib.lrqo_version.restype = i32
+    lib.lrqo_last_error.restype = ctypes.c_char_p
+    lib.lrqo_set_stream.argtypes = [vp]
+    lib.lrqo_set_stream.restype = i32
+    lib.lrqo_shutdown.restype = i32
+    lib.lrqo_solve_sampled.argtypes = [vp, i64, i32, i32, i64, u64, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.lrqo_solve_sampled.restype = i32
+    lib.lrqo_solve_sampled_ex.argtypes = [vp, i64, i32, i32, i64, u64,
+                                          ctypes.POINTER(SampledOptions), vp,
+                                          ctypes.POINTER(SampledResult)]
+    lib.lrqo_solve_sampled_ex.restype = i32
+    lib.lrqo_solve_exact.argtypes = [vp, i64, i32, i32, vp, ctypes.POINTER(ctypes.c_double)]
+    lib.lrqo_solve_exact.restype = i32
+    lib.lrqo_solve_exact_ex.argtypes = [vp, i64, i32, i32, i64, vp, ctypes.POINTER(ExactResult)]
+    lib.lrqo_solve_exact_ex.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load().lrqo_last_error().decode(errors="replace")
+        raise LrqoError(status, msg)
+
+
+def last_error() -> str:
+    return load().lrqo_last_error().decode(errors="replace")
+
+
+def _bind_stream(torch):
+    load().lrqo_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+@dataclass
+class SampledOutput:
+    z: object            # torch uint8 (n,) on the device
+    obj: float
+    best_index: int
+    best_c: list         # complex FP64 copy of the winner's FP32 direction
+    fp32_obj: float
+    device_ms: float
+    score_ms: float
+    rescored: int
+    flagged_rows: int
+    slices: int
+
+
+def _factor_view(V, real):
+    """Return (tensor holding the FP32 layout, n, r, real flag)."""
+    import torch
+
+    if not V.is_cuda:
+        raise ValueError("V must be a device tensor")
+    if V.dtype == torch.complex64:
+        if V.dim() != 2:
+            raise ValueError("complex V must be (n, r)")
+        return torch.view_as_real(V.contiguous()).contiguous(), V.shape[0], V.shape[1], False
+    if V.dtype == torch.float32:
+        if real or V.dim() == 2:
+            if V.dim() != 2:
+                raise ValueError("real V must be (n, r)")
+            return V.contiguous(), V.shape[0], V.shape[1], True
+        if V.dim() == 3 and V.shape[2] == 2:
+            return V.contiguous(), V.shape[0], V.shape[1], False
+    raise ValueError("V must be complex64 (n, r), float32 (n, r) real, or float32 (n, r, 2)")
+
+
+def solve_sampled(V, K: int, S: int, seed: int, *, real: bool | None = None, precision: int = 0,
+                  topk: int = 64, instance: int = 0, first_index: int = 0, f_out=None,
+                  z=None) -> SampledOutput:
+    """Best of S sampled directions (see lrqo_solve_sampled_ex)."""
+    import torch
+
+    lib = load()
+    Vf, n, r, is_real = _factor_view(V, real)
+    if z is None:
+        z = torch.empty(n, dtype=torch.uint8, device=V.device)
+    opt = SampledOptions(1 if is_real else 0, int(precision), int(topk), int(instance),
+                         int(first_index), ctypes.c_void_p(f_out.data_ptr() if f_out is not None else 0))
+    res = SampledResult()
+    with torch.cuda.device(V.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_solve_sampled_ex(ctypes.c_void_p(Vf.data_ptr()), n, r, int(K), int(S),
+                                         int(seed) & (2**64 - 1), ctypes.byref(opt),
+                                         ctypes.c_void_p(z.data_ptr()), ctypes.byref(res)))
+    c = [complex(res.best_c[2 * j], res.best_c[2 * j + 1]) for j in range(r)]
+    return SampledOutput(z, res.obj, res.best_index, c, res.fp32_obj, res.device_ms,
+                         res.score_ms, res.rescored, res.flagged_rows, res.slices)
+
+
+def solve_exact(V, K: int, *, max_sets: int = 0, z=None):
+    """Exact solve (see lrqo_solve_exact_ex).  V: complex128 (n, r) device."""
+    import torch
+
+    lib = load()
+    if not V.is_cuda or V.dtype != torch.complex128 or V.dim() != 2:
+        raise ValueError("V must be a complex128 (n, r) device tensor")
+    Vc = torch.view_as_real(V.contiguous()).contiguous()
+    n, r = V.shape
+    if z is None:
+        z = torch.empty(n, dtype=torch.uint8, device=V.device)
+    res = ExactResult()
+    with torch.cuda.device(V.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_solve_exact_ex(ctypes.c_void_p(Vc.data_ptr()), n, r, int(K), int(max_sets),
+                                       ctypes.c_void_p(z.data_ptr()), ctypes.byref(res)))
+    return z, res

@@ -1,0 +1,109 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects
+bad arguments on the host before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2602_20376_amd import lrqo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lrqo.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:lrqo_status|int32_t|const char\*)\s+(lrqo_\w+)\s*\(",
+                                 text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lrqo.LIB_PATH):
+        pytest.fail("liblrqo.so is not built (python -m paper_2602_20376_amd.build)")
+    return lrqo.load()
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(lrqo.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", lrqo.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lrqo_\w+)", out))
+    for name in _declared():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_version_and_error_text(lib):
+    assert lib.lrqo_version() >= 100
+    assert isinstance(lib.lrqo_last_error(), bytes)
+
+
+def _sampled(lib, V=1, n=10, r=2, K=3, S=16, z=1, opt=None):
+    res = lrqo.SampledResult()
+    return lib.lrqo_solve_sampled_ex(ctypes.c_void_p(V), n, r, K, S, 1,
+                                     ctypes.byref(opt) if opt is not None else None,
+                                     ctypes.c_void_p(z), ctypes.byref(res))
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(n=0), "n must"),
+    (dict(n=2**31), "n must"), (dict(r=0), "r must"), (dict(r=9), "r must"),
+    (dict(K=1), "K must"), (dict(K=256), "K must"), (dict(S=0), "S must"),
+    (dict(S=2**32), "S must"),
+])
+def test_sampled_rejects_bad_arguments(lib, kw, msg):
+    assert _sampled(lib, **kw) == -1
+    assert msg in lrqo.last_error()
+
+
+def test_sampled_rejects_bad_options(lib):
+    o = lrqo.SampledOptions(2, 0, 0, 0, 0, None)
+    assert _sampled(lib, opt=o) == -1 and "real_v" in lrqo.last_error()
+    o = lrqo.SampledOptions(0, 5, 0, 0, 0, None)
+    assert _sampled(lib, opt=o) == -1 and "precision" in lrqo.last_error()
+    o = lrqo.SampledOptions(0, 0, 65, 0, 0, None)
+    assert _sampled(lib, opt=o) == -1 and "rescore_topk" in lrqo.last_error()
+    o = lrqo.SampledOptions(0, 0, 0, 0, 2**64 - 8, None)
+    assert _sampled(lib, opt=o) == -1 and "overflows" in lrqo.last_error()
+
+
+def test_simple_entry_rejects_null_obj(lib):
+    assert lib.lrqo_solve_sampled(ctypes.c_void_p(1), 4, 2, 3, 4, 1, ctypes.c_void_p(1), None) == -1
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=5), "r must"),
+    (dict(n=1, r=2), "n must"), (dict(K=1), "K must"), (dict(K=300), "K must"),
+])
+def test_exact_rejects_bad_arguments(lib, kw, msg):
+    args = dict(V=1, n=12, r=2, K=3, z=1)
+    args.update(kw)
+    res = lrqo.ExactResult()
+    st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(args["V"]), args["n"], args["r"], args["K"], 0,
+                                 ctypes.c_void_p(args["z"]), ctypes.byref(res))
+    assert st == -1
+    assert msg in lrqo.last_error()
+
+
+def test_exact_size_cap(lib):
+    """C(n B_K, 2r-1) above the cap is refused before any device work."""
+    res = lrqo.ExactResult()
+    st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(1), 10**6, 4, 3, 0, ctypes.c_void_p(1),
+                                 ctypes.byref(res))
+    assert st == -4 and "index sets" in lrqo.last_error()
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    saved = lrqo._lib
+    try:
+        lrqo._lib = None
+        with pytest.raises(RuntimeError, match="not found"):
+            lrqo.load(str(tmp_path / "missing.so"))
+    finally:
+        lrqo._lib = saved

@@ -1,0 +1,220 @@
+"""GPU parity of the sampled solver against the FP64 oracle, through the C-ABI.
+
+Bar (per row / per result):
+  * labels: bit-exact with the oracle's FP64 decision rule at the returned
+    direction, except rows whose FP64 phase lies within 1e-5 rad of a
+    decision boundary;
+  * objective: the FP64 rescore equals the oracle's f at the returned
+    direction to 1e-12 relative (same arithmetic, different summation order),
+    and is within 1e-5 relative of the oracle's best of the same S directions;
+  * per-candidate FP32 scores: within the FP32 summation bound of the oracle's
+    value wherever no row sits within the FP32 rounding of a boundary.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_20376_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lrqo_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_20376_amd import lrqo
+
+    lrqo.load()
+    return lrqo
+
+
+def _to_dev(V, real):
+    if real:
+        return torch.from_numpy(inputs.as_real_f32(V)).cuda()
+    return torch.from_numpy(V.astype(np.complex64)).cuda()
+
+
+def _fp32_exact(V):
+    """The FP64 values of the FP32-stored factor (what the GPU reads)."""
+    return V.astype(np.complex64).astype(np.complex128)
+
+
+def check_result(V, K, S, seed, out, real=False, f32=None, full_oracle=True, sample=None,
+                 instance=0, first=0):
+    V = _fp32_exact(V)
+    n, r = V.shape
+    c = np.array(out.best_c, dtype=np.complex128)
+    assert abs(np.linalg.norm(c) - 1.0) < 1e-6
+    # the returned direction is the stream's FP32 direction
+    c64 = oracle.direction(seed, out.best_index, r, instance)
+    assert np.max(np.abs(c - c64)) < 1e-5
+    z_or, dist = oracle.labels(V, K, c)
+    z_gpu = out.z.cpu().numpy()
+    far = dist > 1e-5
+    assert np.array_equal(z_gpu[far], z_or[far]), int(np.sum(z_gpu[far] != z_or[far]))
+    f_or, _ = oracle.f_of_c(V, K, c)
+    assert abs(out.obj - f_or) <= 1e-12 * f_or
+    assert abs(oracle.objective(V, K, z_gpu) - out.obj) <= 1e-12 * out.obj
+    if full_oracle:
+        ref = oracle.sampled(V, K, S, seed, instance=instance, s0=first, want_margin=f32 is not None)
+        assert out.obj >= ref["best_f"] * (1 - 1e-5), (out.obj, ref["best_f"])
+        assert out.obj <= ref["best_f"] * (1 + 1e-5), (out.obj, ref["best_f"])
+        if f32 is not None:
+            _check_f32(V, f32, ref["f"], ref["margin"])
+        return ref
+    if sample is not None:
+        fs = []
+        for s in sample:
+            cs = oracle.direction(seed, first + int(s), r, instance)
+            fs.append(oracle.f_of_c(V, K, cs))
+        f_ref = np.array([a for a, _ in fs])
+        m_ref = np.array([b for _, b in fs])
+        assert out.obj >= f_ref.max() * (1 - 1e-5)
+        if f32 is not None:
+            # at n ~ 1e5 about half the candidates hold some row within the
+            # FP32 rounding of a boundary; the rest must meet the bound
+            _check_f32(V, f32[sample], f_ref, m_ref, min_clean=0.2)
+    return None
+
+
+def _check_f32(V, f32, f64, margin, min_clean=0.5):
+    """FP32 scores against FP64 where no row is within the FP32 rounding of a
+    boundary.  Bound: each partial sum of n terms carries at most n u of the
+    sum of absolute terms (u = 2^-24, FMA accumulation), squared norm doubles
+    the relative error."""
+    n = V.shape[0]
+    u = 2.0 ** -24
+    scale = np.sum(np.sum(np.abs(V), axis=0) ** 2)
+    tol = 4.0 * (n + 16) * u * scale + 1e-6 * np.abs(f64)
+    ok = margin > 64 * u
+    assert np.mean(ok) >= min_clean
+    err = np.abs(f32.astype(np.float64) - f64)
+    assert np.all(err[ok] <= tol[ok]), float(np.max(err[ok] / tol[ok]))
+
+
+CASES = [
+    # n, r, K, S, real
+    (12, 2, 3, 4096, False),
+    (1, 1, 3, 100, False),
+    (7, 1, 2, 333, True),
+    (200, 3, 5, 5000, False),
+    (257, 4, 3, 4097, True),
+    (1000, 8, 16, 2000, False),
+    (300, 2, 255, 1500, False),
+    (64, 4, 4, 1024, False),
+    (513, 3, 8, 3000, True),
+    (100, 5, 3, 777, False),
+    (2049, 2, 2, 1, False),
+]
+
+
+@pytest.mark.parametrize("n,r,K,S,real", CASES)
+def test_sampled_parity_small(lrqo_mod, n, r, K, S, real):
+    seed = 7000 + 31 * n + r + K
+    V = inputs.random_V(n, r, seed, real=real)
+    f32 = torch.empty(S, dtype=torch.float32, device="cuda")
+    out = lrqo_mod.solve_sampled(_to_dev(V, real), K, S, seed, real=real, f_out=f32)
+    check_result(V, K, S, seed, out, real=real, f32=f32.cpu().numpy())
+
+
+def test_exact_small_config_sampled(lrqo_mod):
+    """The 12 x 2 complex workload: best-of-4096 reaches the brute-force OPT."""
+    from oracle import brute
+
+    inst = inputs.exact_small()
+    V = _fp32_exact(inst.V)
+    out = lrqo_mod.solve_sampled(_to_dev(V, False), 3, 4096, inst.seed)
+    check_result(V, 3, 4096, inst.seed, out)
+    opt, zb, _ = brute.brute_force(V, 3)
+    assert abs(out.obj - opt) <= 1e-12 * opt
+    assert np.array_equal(oracle.canonical(out.z.cpu().numpy(), 3), oracle.canonical(zb, 3))
+
+
+def test_range_split_and_instance(lrqo_mod):
+    """Disjoint index ranges merged by (obj, -index) equal the whole range;
+    the instance word changes the stream."""
+    V = inputs.random_V(300, 3, 99)
+    Vd = _to_dev(V, False)
+    whole = lrqo_mod.solve_sampled(Vd, 3, 4000, 5)
+    parts = [lrqo_mod.solve_sampled(Vd, 3, 1000, 5, first_index=1000 * p) for p in range(4)]
+    best = max(parts, key=lambda o: (o.obj, -o.best_index))
+    assert best.best_index == whole.best_index and best.obj == whole.obj
+    check_result(V, 3, 1000, 5, parts[2], first=2000)
+    other = lrqo_mod.solve_sampled(Vd, 3, 4000, 5, instance=3)
+    check_result(V, 3, 4000, 5, other, instance=3)
+
+
+def test_deterministic_repeat(lrqo_mod):
+    V = inputs.random_V(5000, 4, 123)
+    Vd = _to_dev(V, False)
+    f1 = torch.empty(20000, device="cuda")
+    f2 = torch.empty(20000, device="cuda")
+    a = lrqo_mod.solve_sampled(Vd, 3, 20000, 1, f_out=f1)
+    b = lrqo_mod.solve_sampled(Vd, 3, 20000, 1, f_out=f2)
+    assert a.best_index == b.best_index and a.obj == b.obj
+    assert torch.equal(f1, f2) and torch.equal(a.z, b.z)
+
+
+def test_topk_one_and_rescore_consistency(lrqo_mod):
+    V = inputs.random_V(400, 2, 44)
+    Vd = _to_dev(V, False)
+    one = lrqo_mod.solve_sampled(Vd, 3, 3000, 2, topk=1)
+    full = lrqo_mod.solve_sampled(Vd, 3, 3000, 2)
+    assert one.rescored == 1 and full.rescored == 64
+    assert full.obj >= one.obj * (1 - 1e-12)
+    check_result(V, 3, 3000, 2, one)
+
+
+def test_degenerate_rows(lrqo_mod):
+    """Zero rows, duplicated rows and rows on exact boundaries (general
+    position violated) still give oracle-consistent results."""
+    V = inputs.random_V(120, 2, 5)
+    V[10] = 0
+    V[20:30] = V[30]
+    V[40] = np.array([1.0, 0.0])       # real rows: phases 0 and pi for real c
+    out = lrqo_mod.solve_sampled(_to_dev(V, False), 4, 2000, 8)
+    check_result(V, 4, 2000, 8, out)
+
+
+def test_nonfinite_is_rejected(lrqo_mod):
+    V = inputs.random_V(50, 2, 6).astype(np.complex64)
+    V[7, 1] = np.nan
+    with pytest.raises(lrqo_mod.LrqoError, match="ENOTFINITE"):
+        lrqo_mod.solve_sampled(torch.from_numpy(V).cuda(), 3, 100, 1)
+
+
+def test_host_pointer_is_rejected(lrqo_mod):
+    import ctypes
+
+    V = np.zeros((4, 2, 2), dtype=np.float32)
+    z = torch.empty(4, dtype=torch.uint8, device="cuda")
+    res = lrqo_mod.SampledResult()
+    st = lrqo_mod.load().lrqo_solve_sampled_ex(V.ctypes.data_as(ctypes.c_void_p), 4, 2, 3, 8, 1,
+                                               None, ctypes.c_void_p(z.data_ptr()),
+                                               ctypes.byref(res))
+    assert st == -1 and "device memory" in lrqo_mod.last_error()
+
+
+# ---------------------------------------------------------------- full sizes
+
+def test_maxcut_er_full_size(lrqo_mod):
+    """Workload: ER n = 100,000, r = 4, K = 3, S = 65,536, real V, in the
+    launch configuration the benchmark times.  The oracle scores the GPU's
+    winner, 300 sampled directions and the labels one by one, and the full
+    best-of-S on the first 2048 directions."""
+    inst = inputs.maxcut_er()
+    Vd = _to_dev(inst.V, True)
+    f32 = torch.empty(inst.S, dtype=torch.float32, device="cuda")
+    out = lrqo_mod.solve_sampled(Vd, inst.K, inst.S, inst.seed, real=True, f_out=f32)
+    f32h = f32.cpu().numpy()
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([rng.choice(inst.S, 300, replace=False),
+                                       np.argsort(f32h)[-16:]]))
+    check_result(inst.V, inst.K, inst.S, inst.seed, out, real=True, f32=f32h,
+                 full_oracle=False, sample=sample)
+    assert out.best_index == int(np.argmax(f32h)) or out.obj >= f32h.max() * (1 - 1e-5)
+    part = lrqo_mod.solve_sampled(Vd, inst.K, 2048, inst.seed, real=True)
+    check_result(inst.V, inst.K, 2048, inst.seed, part, real=True)
