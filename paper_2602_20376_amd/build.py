@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrqo.so")
-SOURCES = ["lrqo_runtime.hip", "sampled.hip", "api_sampled.hip", "exact.hip"]
+SOURCES = ["lrqo_runtime.hip", "select.hip", "sampled.hip", "api_sampled.hip", "exact.hip"]
 ARCH = "gfx950"
 
 
@@ -32,6 +32,9 @@ def hipcc() -> str:
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # MFMA accumulators in ordinary VGPRs: in-place accumulation, no
+          # accumulator-register copies inside the scoring loops
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
           "-I", os.path.join(ROOT, "include")]
 

@@ -1,19 +1,856 @@
-// Exact maximisation (Sec. 3, Alg. 2): placeholder until the vertex
-// enumeration kernels land.
+// Exact maximisation by arrangement-vertex enumeration (Sec. 3, Alg. 2).
+//
+// Geometry.  Row (i, m), m < B_K, of the augmented real matrix (eq. tildeV)
+// is a_{i,m} = [Im(rho_m V_i), Re(rho_m V_i)], rho_m = exp(-i pi (2m+1)/K),
+// so that a_{i,m} . [Re c; Im c] = Im(rho_m V_i c): it vanishes when V_i c is
+// on the line of decision boundary m (Lemma antipodal).  Rows are numbered
+// group-major, j = i B_K + m.  A vertex is the null direction of 2d-1 rows
+// with at most two rows per coordinate (Lemma rank_deficiency); level d uses
+// the leading d columns (d = r: the main loop of Alg. 2; d < r: its
+// recursion), and every candidate is scored with the full factor.
+//
+// Kernels:
+//   k_to_f32        FP32 copy of V for the scorer
+//   k_exact_score   one thread per index set (grid-stride): colex unranking,
+//                   FP64 null vector by twice-orthogonalised Gram-Schmidt,
+//                   both signs scored in FP32 over all rows (row tiles in
+//                   LDS), coordinates in the set tried with every label the
+//                   vertex leaves open; best FP32 score per set -> fbuf
+//   topk_select     best 64 sets (select.hip)
+//   k_exact_rescore FP64 re-evaluation of each kept set (both signs, all
+//                   label combinations), rows split over the block
+//   k_exact_pick    FP64 arg-max (ties -> lowest set index)
+//   k_exact_labels  labels of the winner
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "lrqo_device.h"
 #include "lrqo_runtime.h"
+#include "select.h"
+
+namespace lrqo {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kTile = 256;
+constexpr int kMaxR = 4;
+constexpr int kMaxM = 2 * kMaxR - 1;
+constexpr int kTopT = 64;
+constexpr double kRankTol = 1e-10;
+constexpr int64_t kMaxCombos = 1 << 20;
+
+struct ExactParams {
+    const double* V64;   // n x r complex128, interleaved
+    const float* V32;    // n x r complex64, interleaved
+    int64_t n;
+    int r;
+    int K;
+    int B;
+    int64_t N;                          // n * B rows of the augmented matrix
+    const unsigned long long* binom;    // C(x, k) at [k * (N + 1) + x], k = 0 .. 7
+    const double2* rho;                 // [B]
+    const double2* roots64;             // [K]
+    const float2* roots32;              // [K]
+    uint64_t count;                     // index sets at this level
+    uint64_t offset;                    // global index of this level's first set
+    float* fbuf;
+    unsigned long long* stats;          // valid sets, rank deficient, candidates
+};
+
+struct LevelTable {
+    uint64_t offset[kMaxR + 1];
+    uint64_t count[kMaxR + 1];
+};
+
+struct RescoreEntry {
+    double f;
+    int32_t sign;     // 0: +v, 1: -v
+    int32_t pad;
+    int64_t combo;
+};
+
+struct ExactDevResult {
+    double obj;
+    int64_t gidx;
+    int32_t level;
+    int32_t sign;
+    int64_t combo;
+    int32_t nonfinite;
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------- vertex
+// Colex unranking: rank = sum_t C(c_t, t+1) with c_0 < c_1 < ... < c_{M-1}.
+template <int M>
+__device__ __forceinline__ void unrank(uint64_t rank, const unsigned long long* binom, int64_t N,
+                                       int64_t (&c)[M]) {
+    int64_t hi = N - 1;
+#pragma unroll
+    for (int t = M - 1; t >= 0; --t) {
+        const unsigned long long* col = binom + (size_t)(t + 1) * (N + 1);
+        int64_t lo = t, h = hi;
+        while (lo < h) {
+            const int64_t mid = (lo + h + 1) >> 1;
+            if (col[mid] <= rank) lo = mid;
+            else h = mid - 1;
+        }
+        c[t] = lo;
+        rank -= col[lo];
+        hi = lo - 1;
+    }
+}
+
+// The vertex of one index set: groups g[t], boundary ids mm[t], unit null
+// vector v in R^{2D}.  Returns false for a set with three rows of one group
+// (invalid) or below the rank tolerance (rank_deficient set accordingly).
+template <int D>
+__device__ bool vertex(const ExactParams& p, uint64_t rank, int64_t (&g)[2 * D - 1],
+                       int (&mm)[2 * D - 1], double (&v)[2 * D], bool& valid) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    int64_t c[M];
+    unrank<M>(rank, p.binom, p.N, c);
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        g[t] = c[t] / p.B;
+        mm[t] = (int)(c[t] - g[t] * p.B);
+    }
+    valid = true;
+#pragma unroll
+    for (int t = 0; t + 2 < M; ++t) valid &= g[t] != g[t + 2];
+    if (!valid) return false;
+
+    double a[M][C2];
+    double amax = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const double2 rh = p.rho[mm[t]];
+        double nrm = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double vr = p.V64[(g[t] * p.r + j) * 2], vi = p.V64[(g[t] * p.r + j) * 2 + 1];
+            const double pr = rh.x * vr - rh.y * vi;   // rho V_ij
+            const double pi = rh.x * vi + rh.y * vr;
+            a[t][j] = pi;
+            a[t][D + j] = pr;
+            nrm += pr * pr + pi * pi;
+        }
+        amax = fmax(amax, sqrt(nrm));
+    }
+    // orthonormalise the rows (Gram-Schmidt, two passes)
+    double rmin = INFINITY;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int u = 0; u < t; ++u) {
+                double d = 0.0;
+#pragma unroll
+                for (int k = 0; k < C2; ++k) d += a[u][k] * a[t][k];
+#pragma unroll
+                for (int k = 0; k < C2; ++k) a[t][k] -= d * a[u][k];
+            }
+        }
+        double nrm = 0.0;
+#pragma unroll
+        for (int k = 0; k < C2; ++k) nrm += a[t][k] * a[t][k];
+        nrm = sqrt(nrm);
+        rmin = fmin(rmin, nrm);
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+#pragma unroll
+        for (int k = 0; k < C2; ++k) a[t][k] *= inv;
+    }
+    // complement direction: the unit vector e_k with the largest residual
+    // after removing the row space, projected and normalised
+    int kb = 0;
+    double wb = -1.0;
+#pragma unroll
+    for (int k = 0; k < C2; ++k) {
+        double w = 1.0;
+#pragma unroll
+        for (int t = 0; t < M; ++t) w -= a[t][k] * a[t][k];
+        if (w > wb) {
+            wb = w;
+            kb = k;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < C2; ++j) v[j] = 0.0;
+#pragma unroll
+    for (int k = 0; k < C2; ++k) {
+        if (k == kb) {
+#pragma unroll
+            for (int j = 0; j < C2; ++j) {
+                double x = (j == k) ? 1.0 : 0.0;
+#pragma unroll
+                for (int t = 0; t < M; ++t) x -= a[t][k] * a[t][j];
+                v[j] = x;
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < C2; ++k) d += a[t][k] * v[k];
+#pragma unroll
+        for (int k = 0; k < C2; ++k) v[k] -= d * a[t][k];
+    }
+    double nv = 0.0;
+#pragma unroll
+    for (int k = 0; k < C2; ++k) nv += v[k] * v[k];
+    const double inv = 1.0 / sqrt(nv);
+#pragma unroll
+    for (int k = 0; k < C2; ++k) v[k] *= inv;
+    return amax > 0.0 && rmin > kRankTol * amax;
+}
+
+// Options left open at a vertex for the coordinates of the set (both rows
+// of a double group share one entry; the second gets count 1): first label
+// o[t] and count cnt[t] of consecutive labels mod K.
+template <int D>
+__device__ void open_labels(const ExactParams& p, const int64_t (&g)[2 * D - 1],
+                            const int (&mm)[2 * D - 1], const double (&c)[2 * D],
+                            int (&o)[2 * D - 1], int (&cnt)[2 * D - 1]) {
+    constexpr int M = 2 * D - 1;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const bool first = (t == 0) || (g[t] != g[t - 1]);
+        const bool dbl = first && (t + 1 < M) && (g[t + 1] == g[t]);
+        o[t] = 0;
+        cnt[t] = 1;
+        if (!first) continue;
+        if (dbl) {
+            cnt[t] = p.K;   // V_i c = 0: every label borders the vertex
+            continue;
+        }
+        double wr = 0.0, wi = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double vr = p.V64[(g[t] * p.r + j) * 2], vi = p.V64[(g[t] * p.r + j) * 2 + 1];
+            wr += vr * c[j] - vi * c[D + j];
+            wi += vr * c[D + j] + vi * c[j];
+        }
+        const double2 rh = p.rho[mm[t]];
+        const double re = rh.x * wr - rh.y * wi;   // Re(rho_m w_i)
+        if (re > 0.0) {
+            o[t] = mm[t];                          // on ray pi(2m+1)/K: labels m, m+1
+            cnt[t] = 2;
+        } else if (p.K & 1) {
+            o[t] = label_f64(wr, wi, p.K);         // opposite ray is a root direction
+        } else {
+            o[t] = (mm[t] + p.K / 2) % p.K;        // opposite ray is boundary m + K/2
+            cnt[t] = 2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- FP32 scoring
+template <int R>
+__global__ void k_to_f32(const double* __restrict__ V64, float* __restrict__ V32, int64_t count,
+                         int* nonfinite) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double x = V64[e];
+        if (!isfinite(x)) *nonfinite = 1;
+        V32[e] = (float)x;
+    }
+}
+
+template <int R, int D, int KS>
+__global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    __shared__ __align__(16) float tile[kTile * 2 * R];
+    __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
+    const int tid = threadIdx.x;
+    if constexpr (KS == 0) {
+        for (int k = tid; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
+        const uint64_t rank = base + tid;
+        const bool active = rank < p.count;
+        int64_t g[M];
+        int mm[M];
+        double v[C2];
+        bool valid = false, ok = false;
+        if (active) ok = vertex<D>(p, rank, g, mm, v, valid);
+        if (!ok) {
+#pragma unroll
+            for (int t = 0; t < M; ++t) g[t] = -1;
+        }
+        // FP32 directions for both signs
+        float c[2][2 * D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            c[0][2 * j] = ok ? (float)v[j] : 0.0f;
+            c[0][2 * j + 1] = ok ? (float)v[D + j] : 0.0f;
+            c[1][2 * j] = -c[0][2 * j];
+            c[1][2 * j + 1] = -c[0][2 * j + 1];
+        }
+        float acc[2][2 * R];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) acc[s][j] = 0.0f;
+
+        for (int64_t t0 = 0; t0 < p.n; t0 += kTile) {
+            const int cnt = (int)min((int64_t)kTile, p.n - t0);
+            __syncthreads();
+            const float* __restrict__ src = p.V32 + t0 * 2 * R;
+            for (int e = tid; e < cnt * 2 * R; e += kBlock) tile[e] = src[e];
+            __syncthreads();
+            for (int i = 0; i < cnt; ++i) {
+                const int64_t row = t0 + i;
+                float vv[2 * R];
+#pragma unroll
+                for (int e = 0; e < 2 * R; ++e) vv[e] = tile[i * 2 * R + e];
+                bool touched = false;
+#pragma unroll
+                for (int t = 0; t < M; ++t) touched |= (row == g[t]);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    float wr = 0.0f, wi = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        const float vr = vv[2 * j], vi = vv[2 * j + 1];
+                        wr = fmaf(vr, c[s][2 * j], fmaf(-vi, c[s][2 * j + 1], wr));
+                        wi = fmaf(vr, c[s][2 * j + 1], fmaf(vi, c[s][2 * j], wi));
+                    }
+                    float zr, zi;
+                    nearest_root<KS>(wr, wi, p.K, roots_s, zr, zi);
+                    zr = touched ? 0.0f : zr;
+                    zi = touched ? 0.0f : zi;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const float vr = vv[2 * j], vi = vv[2 * j + 1];
+                        acc[s][2 * j] = fmaf(vr, zr, fmaf(vi, zi, acc[s][2 * j]));
+                        acc[s][2 * j + 1] = fmaf(vr, zi, fmaf(-vi, zr, acc[s][2 * j + 1]));
+                    }
+                }
+            }
+        }
+
+        float best = 0.0f;
+        unsigned long long ncand = 0;
+        if (ok) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                double cs[C2];
+#pragma unroll
+                for (int k = 0; k < C2; ++k) cs[k] = s ? -v[k] : v[k];
+                int o[M], cn[M];
+                open_labels<D>(p, g, mm, cs, o, cn);
+                int64_t total = 1;
+#pragma unroll
+                for (int t = 0; t < M; ++t) total *= cn[t];
+                ncand += (unsigned long long)total;
+                for (int64_t combo = 0; combo < total; ++combo) {
+                    float sr[2 * R];
+#pragma unroll
+                    for (int j = 0; j < 2 * R; ++j) sr[j] = acc[s][j];
+                    int64_t rest = combo;
+#pragma unroll
+                    for (int t = 0; t < M; ++t) {
+                        if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
+                        const int q = (int)(rest % cn[t]);
+                        rest /= cn[t];
+                        int k = o[t] + q;
+                        k = k >= p.K ? k - p.K : k;
+                        const float2 z = p.roots32[k];
+#pragma unroll
+                        for (int j = 0; j < R; ++j) {
+                            const float vr = p.V32[(g[t] * R + j) * 2], vi = p.V32[(g[t] * R + j) * 2 + 1];
+                            sr[2 * j] = fmaf(vr, z.x, fmaf(vi, z.y, sr[2 * j]));
+                            sr[2 * j + 1] = fmaf(vr, z.y, fmaf(-vi, z.x, sr[2 * j + 1]));
+                        }
+                    }
+                    float f = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < 2 * R; ++j) f = fmaf(sr[j], sr[j], f);
+                    best = fmaxf(best, f);
+                }
+            }
+        }
+        if (active) p.fbuf[p.offset + rank] = best;
+        // statistics
+        unsigned long long a0 = (active && valid) ? 1ull : 0ull;
+        unsigned long long a1 = (active && valid && !ok) ? 1ull : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            a0 += __shfl_xor(a0, off, kWave);
+            a1 += __shfl_xor(a1, off, kWave);
+            ncand += __shfl_xor(ncand, off, kWave);
+        }
+        if ((tid & (kWave - 1)) == 0) {
+            if (a0) atomicAdd(&p.stats[0], a0);
+            if (a1) atomicAdd(&p.stats[1], a1);
+            if (ncand) atomicAdd(&p.stats[2], ncand);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- FP64 rescore
+__device__ __forceinline__ int level_of(const LevelTable& lt, int r, uint64_t gidx,
+                                        uint64_t& rank) {
+    for (int d = r; d >= 1; --d) {
+        if (gidx >= lt.offset[d] && gidx < lt.offset[d] + lt.count[d]) {
+            rank = gidx - lt.offset[d];
+            return d;
+        }
+    }
+    rank = 0;
+    return 0;
+}
+
+template <int R, int D>
+__device__ void rescore_one(ExactParams p, uint64_t rank, RescoreEntry* out) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    __shared__ double red[kBlock / kWave][2 * R];
+    __shared__ double base[2 * R];
+    __shared__ double bf[kBlock];
+    __shared__ long long bc[kBlock];
+    int64_t g[M];
+    int mm[M];
+    double v[C2];
+    bool valid;
+    const bool ok = vertex<D>(p, rank, g, mm, v, valid);
+    RescoreEntry best{-1.0, 0, 0, 0};
+    if (!ok) {
+        if (threadIdx.x == 0) *out = best;
+        return;
+    }
+    for (int s = 0; s < 2; ++s) {
+        double cs[C2];
+#pragma unroll
+        for (int k = 0; k < C2; ++k) cs[k] = s ? -v[k] : v[k];
+        double acc[2 * R];
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) acc[j] = 0.0;
+        for (int64_t i = threadIdx.x; i < p.n; i += kBlock) {
+            bool touched = false;
+#pragma unroll
+            for (int t = 0; t < M; ++t) touched |= (i == g[t]);
+            if (touched) continue;
+            double wr = 0.0, wi = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const double vr = p.V64[(i * p.r + j) * 2], vi = p.V64[(i * p.r + j) * 2 + 1];
+                wr += vr * cs[j] - vi * cs[D + j];
+                wi += vr * cs[D + j] + vi * cs[j];
+            }
+            const double2 z = p.roots64[label_f64(wr, wi, p.K)];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const double vr = p.V64[(i * R + j) * 2], vi = p.V64[(i * R + j) * 2 + 1];
+                acc[2 * j] += vr * z.x + vi * z.y;
+                acc[2 * j + 1] += vr * z.y - vi * z.x;
+            }
+        }
+        const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) {
+            const double x = wave_sum_f64(acc[j]);
+            if (lane == 0) red[wave][j] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * R) {
+            double x = 0.0;
+            for (int w = 0; w < kBlock / kWave; ++w) x += red[w][threadIdx.x];
+            base[threadIdx.x] = x;
+        }
+        __syncthreads();
+        int o[M], cn[M];
+        open_labels<D>(p, g, mm, cs, o, cn);
+        int64_t total = 1;
+#pragma unroll
+        for (int t = 0; t < M; ++t) total *= cn[t];
+        double myf = -1.0;
+        long long myc = -1;
+        for (int64_t combo = threadIdx.x; combo < total; combo += kBlock) {
+            double sr[2 * R];
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) sr[j] = base[j];
+            int64_t rest = combo;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
+                const int q = (int)(rest % cn[t]);
+                rest /= cn[t];
+                int k = o[t] + q;
+                k = k >= p.K ? k - p.K : k;
+                const double2 z = p.roots64[k];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const double vr = p.V64[(g[t] * R + j) * 2], vi = p.V64[(g[t] * R + j) * 2 + 1];
+                    sr[2 * j] += vr * z.x + vi * z.y;
+                    sr[2 * j + 1] += vr * z.y - vi * z.x;
+                }
+            }
+            double f = 0.0;
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) f += sr[j] * sr[j];
+            if (f > myf) {
+                myf = f;
+                myc = combo;
+            }
+        }
+        bf[threadIdx.x] = myf;
+        bc[threadIdx.x] = myc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int t = 0; t < kBlock; ++t) {
+                if (bc[t] < 0) continue;
+                if (bf[t] > best.f || (bf[t] == best.f && s == best.sign && bc[t] < best.combo)) {
+                    best.f = bf[t];
+                    best.sign = s;
+                    best.combo = bc[t];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = best;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_exact_rescore(ExactParams p, LevelTable lt,
+                                                          const unsigned long long* keys,
+                                                          RescoreEntry* out) {
+    const int t = blockIdx.x;
+    uint64_t rank;
+    const int d = level_of(lt, R, key_index(keys[t]), rank);
+    switch (d) {
+        case 1: rescore_one<R, 1>(p, rank, out + t); break;
+        case 2: if constexpr (R >= 2) rescore_one<R, 2>(p, rank, out + t); break;
+        case 3: if constexpr (R >= 3) rescore_one<R, 3>(p, rank, out + t); break;
+        case 4: if constexpr (R >= 4) rescore_one<R, 4>(p, rank, out + t); break;
+        default:
+            if (threadIdx.x == 0) out[t] = RescoreEntry{-1.0, 0, 0, 0};
+    }
+}
+
+__global__ void k_exact_pick(const RescoreEntry* __restrict__ e, const unsigned long long* keys,
+                             int T, LevelTable lt, int r, ExactDevResult* res) {
+    if (threadIdx.x != 0) return;
+    int bt = -1;
+    uint32_t bidx = 0xFFFFFFFFu;
+    for (int t = 0; t < T; ++t) {
+        if (e[t].f < 0.0) continue;
+        const uint32_t idx = key_index(keys[t]);
+        if (bt < 0 || e[t].f > e[bt].f || (e[t].f == e[bt].f && idx < bidx)) {
+            bt = t;
+            bidx = idx;
+        }
+    }
+    if (bt < 0) {
+        res->obj = -1.0;
+        res->level = 0;
+        return;
+    }
+    uint64_t rank;
+    res->obj = e[bt].f;
+    res->gidx = bidx;
+    res->level = level_of(lt, r, bidx, rank);
+    res->sign = e[bt].sign;
+    res->combo = e[bt].combo;
+}
+
+template <int R, int D>
+__device__ void labels_one(const ExactParams& p, uint64_t rank, const ExactDevResult& res,
+                           int64_t i, uint8_t* z) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    int64_t g[M];
+    int mm[M];
+    double v[C2];
+    bool valid;
+    vertex<D>(p, rank, g, mm, v, valid);
+    double cs[C2];
+#pragma unroll
+    for (int k = 0; k < C2; ++k) cs[k] = res.sign ? -v[k] : v[k];
+    int o[M], cn[M];
+    open_labels<D>(p, g, mm, cs, o, cn);
+    int64_t rest = res.combo;
+    int lab = -1;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
+        const int q = (int)(rest % cn[t]);
+        rest /= cn[t];
+        int k = o[t] + q;
+        k = k >= p.K ? k - p.K : k;
+        if (g[t] == i) lab = k;
+    }
+    if (lab < 0) {
+        double wr = 0.0, wi = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const double vr = p.V64[(i * p.r + j) * 2], vi = p.V64[(i * p.r + j) * 2 + 1];
+            wr += vr * cs[j] - vi * cs[D + j];
+            wi += vr * cs[D + j] + vi * cs[j];
+        }
+        lab = label_f64(wr, wi, p.K);
+    }
+    z[i] = (uint8_t)lab;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_exact_labels(ExactParams p, LevelTable lt,
+                                                         const ExactDevResult* __restrict__ res,
+                                                         uint8_t* __restrict__ z) {
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= p.n || res->level == 0) return;
+    uint64_t rank;
+    const int d = level_of(lt, R, (uint64_t)res->gidx, rank);
+    switch (d) {
+        case 1: labels_one<R, 1>(p, rank, *res, i, z); break;
+        case 2: if constexpr (R >= 2) labels_one<R, 2>(p, rank, *res, i, z); break;
+        case 3: if constexpr (R >= 3) labels_one<R, 3>(p, rank, *res, i, z); break;
+        case 4: if constexpr (R >= 4) labels_one<R, 4>(p, rank, *res, i, z); break;
+        default: break;
+    }
+}
+
+// ---------------------------------------------------------------- host
+unsigned __int128 binom128(int64_t x, int k) {
+    if (k < 0 || x < k) return 0;
+    unsigned __int128 c = 1;
+    for (int t = 1; t <= k; ++t) {
+        c = c * (unsigned __int128)(x - k + t) / (unsigned __int128)t;
+        if (c > ((unsigned __int128)1 << 100)) return (unsigned __int128)1 << 100;
+    }
+    return c;
+}
+
+int boundary_count(int K) { return (K % 2 == 0) ? K / 2 : K; }
+
+template <int R, int D>
+void launch_level(const ExactParams& p, hipStream_t st) {
+    const uint64_t blocks = std::min<uint64_t>((p.count + kBlock - 1) / kBlock, 8192);
+    switch (p.K) {
+        case 2: hipLaunchKernelGGL((k_exact_score<R, D, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+        case 3: hipLaunchKernelGGL((k_exact_score<R, D, 3>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+        case 4: hipLaunchKernelGGL((k_exact_score<R, D, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+        default: hipLaunchKernelGGL((k_exact_score<R, D, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+    }
+}
+
+template <int R>
+lrqo_status run_exact(ExactParams p, const LevelTable& lt, const unsigned long long** keys_out,
+                      unsigned long long* ka, unsigned long long* kb, RescoreEntry* entries,
+                      ExactDevResult* dres, uint8_t* z, uint32_t total, int T, hipStream_t st) {
+    for (int d = R; d >= 1; --d) {
+        if (lt.count[d] == 0) continue;
+        ExactParams q = p;
+        q.count = lt.count[d];
+        q.offset = lt.offset[d];
+        switch (d) {
+            case 1: launch_level<R, 1>(q, st); break;
+            case 2: if constexpr (R >= 2) launch_level<R, 2>(q, st); break;
+            case 3: if constexpr (R >= 3) launch_level<R, 3>(q, st); break;
+            case 4: if constexpr (R >= 4) launch_level<R, 4>(q, st); break;
+        }
+        LRQO_HIP(hipGetLastError());
+    }
+    const unsigned long long* keys = nullptr;
+    LRQO_TRY(topk_select(p.fbuf, total, T, ka, kb, st, &keys));
+    hipLaunchKernelGGL((k_exact_rescore<R>), dim3(T), dim3(kBlock), 0, st, p, lt, keys, entries);
+    LRQO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_exact_pick, dim3(1), dim3(64), 0, st, entries, keys, T, lt, R, dres);
+    LRQO_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_exact_labels<R>), dim3((unsigned)((p.n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, p, lt, dres, z);
+    LRQO_HIP(hipGetLastError());
+    *keys_out = keys;
+    return LRQO_OK;
+}
+
+}  // namespace
+}  // namespace lrqo
 
 extern "C" {
 
 lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K,
                                 int64_t max_sets, uint8_t* z, lrqo_exact_result* res) {
-    (void)V; (void)n; (void)r; (void)K; (void)max_sets; (void)z; (void)res;
-    return lrqo::fail(LRQO_EINVAL, "exact solver not built yet");
+    using namespace lrqo;
+    clear_error();
+    if (!V) return fail(LRQO_EINVAL, "V is null");
+    if (!z) return fail(LRQO_EINVAL, "z is null");
+    if (r < 1 || r > kMaxR) return fail(LRQO_EINVAL, "r must be in [1, 4] for the exact solver");
+    if (n < r || n > (1 << 24)) return fail(LRQO_EINVAL, "n must be in [r, 2^24]");
+    if (K < 2 || K > LRQO_MAX_K) return fail(LRQO_EINVAL, "K must be in [2, 255]");
+    const int B = boundary_count(K);
+    const int64_t N = n * B;
+    if (N > (1 << 22)) return fail(LRQO_ETOOBIG, "n B_K above 2^22 rows: too many index sets");
+    // label combinations of one vertex: at most 2^(2r-1-2p) K^p, p double groups
+    for (int pdbl = 0; 2 * pdbl <= 2 * r - 1; ++pdbl) {
+        long double combos = std::ldexp(1.0L, 2 * r - 1 - 2 * pdbl) * std::pow((long double)K, pdbl);
+        if (combos > (long double)kMaxCombos)
+            return fail(LRQO_ETOOBIG, "label combinations per vertex exceed 2^20 (K too large for r)");
+    }
+    const uint64_t cap = max_sets > 0 ? (uint64_t)max_sets : ((1ull << 31) - 1);
+    LevelTable lt{};
+    unsigned __int128 total128 = 0;
+    for (int d = r; d >= 1; --d) {
+        const unsigned __int128 c = binom128(N, 2 * d - 1);
+        lt.offset[d] = (uint64_t)std::min<unsigned __int128>(total128, ~0ull);
+        lt.count[d] = (uint64_t)std::min<unsigned __int128>(c, ~0ull);
+        total128 += c;
+    }
+    if (total128 > (unsigned __int128)cap || total128 > 0xFFFFFFF0ull)
+        return fail(LRQO_ETOOBIG, "number of index sets C(n B_K, 2d-1) summed over levels exceeds the cap");
+    const uint32_t total = (uint32_t)total128;
+
+    DeviceCtx* ctx = device_ctx();
+    if (!ctx) return LRQO_EDEVICE;
+    if (!is_device_pointer(V)) return fail(LRQO_EINVAL, "V is not device memory");
+    if (!is_device_pointer(z)) return fail(LRQO_EINVAL, "z is not device memory");
+
+    const int T = (int)std::min<uint32_t>(kTopT, total);
+    const int Mmax = 2 * r - 1;
+    const size_t binom_entries = (size_t)(Mmax + 1) * (size_t)(N + 1);
+    CarveSize cs;
+    cs.add<ExactDevResult>(1);
+    cs.add<unsigned long long>(4);
+    cs.add<float>((size_t)n * r * 2);
+    cs.add<unsigned long long>(binom_entries);
+    cs.add<double2>(LRQO_MAX_K);
+    cs.add<double2>(LRQO_MAX_K);
+    cs.add<float2>(LRQO_MAX_K);
+    cs.add<float>(total);
+    cs.add<unsigned long long>(topk_buffer_keys(total, T));
+    cs.add<unsigned long long>(topk_buffer_keys(total, T));
+    cs.add<RescoreEntry>(T);
+    const size_t host_bytes = 4096 + binom_entries * sizeof(unsigned long long) +
+                              LRQO_MAX_K * (2 * sizeof(double2) + sizeof(float2));
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    LRQO_TRY(reserve_arena(ctx, cs.bytes));
+    LRQO_TRY(reserve_host(ctx, host_bytes));
+    hipStream_t st = current_stream();
+    Carve cv(ctx->arena);
+    ExactDevResult* dres = cv.take<ExactDevResult>(1);
+    unsigned long long* stats = cv.take<unsigned long long>(4);
+    float* V32 = cv.take<float>((size_t)n * r * 2);
+    unsigned long long* binom = cv.take<unsigned long long>(binom_entries);
+    double2* rho = cv.take<double2>(LRQO_MAX_K);
+    double2* roots64 = cv.take<double2>(LRQO_MAX_K);
+    float2* roots32 = cv.take<float2>(LRQO_MAX_K);
+    float* fbuf = cv.take<float>(total);
+    unsigned long long* ka = cv.take<unsigned long long>(topk_buffer_keys(total, T));
+    unsigned long long* kb = cv.take<unsigned long long>(topk_buffer_keys(total, T));
+    RescoreEntry* entries = cv.take<RescoreEntry>(T);
+
+    // host tables (pinned staging): result block, binomials, rho, roots
+    char* hb = static_cast<char*>(ctx->host);
+    ExactDevResult* hres = reinterpret_cast<ExactDevResult*>(hb);
+    unsigned long long* hstats = reinterpret_cast<unsigned long long*>(hb + 256);
+    unsigned long long* hbin = reinterpret_cast<unsigned long long*>(hb + 4096);
+    double2* hrho = reinterpret_cast<double2*>(hbin + binom_entries);
+    double2* hr64 = hrho + LRQO_MAX_K;
+    float2* hr32 = reinterpret_cast<float2*>(hr64 + LRQO_MAX_K);
+    // C(x, k) by Pascal's rule, saturating at 2^64-1 (only values below the
+    // set count, <= 2^32, are ever compared exactly)
+    for (int k = 0; k <= Mmax; ++k)
+        for (int64_t x = 0; x <= N; ++x) {
+            unsigned long long c;
+            if (k == 0) c = 1;
+            else if (x == 0) c = 0;
+            else {
+                const unsigned long long a = hbin[(size_t)k * (N + 1) + x - 1];
+                const unsigned long long b = hbin[(size_t)(k - 1) * (N + 1) + x - 1];
+                c = (a > ~0ull - b) ? ~0ull : a + b;
+            }
+            hbin[(size_t)k * (N + 1) + x] = c;
+        }
+    const double pi = 3.14159265358979323846264338327950288;
+    for (int m = 0; m < B; ++m) {
+        const double a = -pi * (2.0 * m + 1.0) / (double)K;
+        hrho[m] = make_double2(std::cos(a), std::sin(a));
+    }
+    for (int k = 0; k < K; ++k) {
+        const double a = 2.0 * pi * (double)k / (double)K;
+        hr64[k] = make_double2(std::cos(a), std::sin(a));
+        hr32[k] = make_float2((float)hr64[k].x, (float)hr64[k].y);
+    }
+
+    LRQO_HIP(hipEventRecord(ctx->ev_start, st));
+    LRQO_HIP(hipMemcpyAsync(binom, hbin, binom_entries * sizeof(unsigned long long),
+                            hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemcpyAsync(rho, hrho, sizeof(double2) * B, hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemcpyAsync(roots64, hr64, sizeof(double2) * K, hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemcpyAsync(roots32, hr32, sizeof(float2) * K, hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemsetAsync(dres, 0, sizeof(ExactDevResult), st));
+    LRQO_HIP(hipMemsetAsync(stats, 0, 4 * sizeof(unsigned long long), st));
+
+    ExactParams p{};
+    p.V64 = V;
+    p.V32 = V32;
+    p.n = n;
+    p.r = r;
+    p.K = K;
+    p.B = B;
+    p.N = N;
+    p.binom = binom;
+    p.rho = rho;
+    p.roots64 = roots64;
+    p.roots32 = roots32;
+    p.fbuf = fbuf;
+    p.stats = stats;
+
+    const int64_t vcount = n * r * 2;
+    int* nonfinite = &dres->nonfinite;
+    const unsigned long long* keys = nullptr;
+    lrqo_status s = LRQO_OK;
+    switch (r) {
+        case 1:
+            hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            s = run_exact<1>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            s = run_exact<2>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            s = run_exact<3>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            s = run_exact<4>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            break;
+    }
+    if (s != LRQO_OK) return s;
+    LRQO_HIP(hipMemcpyAsync(hres, dres, sizeof(ExactDevResult), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipMemcpyAsync(hstats, stats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
+    LRQO_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    LRQO_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    if (hres->nonfinite) return fail(LRQO_ENOTFINITE, "V holds a NaN or an infinity");
+    if (hres->level == 0) return fail(LRQO_EDEVICE, "no full-rank vertex found (degenerate V)");
+    if (res) {
+        std::memset(res, 0, sizeof *res);
+        res->obj = hres->obj;
+        res->index_sets = (int64_t)hstats[0];
+        res->rank_deficient = (int64_t)hstats[1];
+        res->candidates = (int64_t)hstats[2];
+        res->device_ms = ms;
+    }
+    return LRQO_OK;
 }
 
 lrqo_status lrqo_solve_exact(const double* V, int64_t n, int32_t r, int32_t K, uint8_t* z,
                              double* obj) {
-    (void)obj;
-    return lrqo_solve_exact_ex(V, n, r, K, 0, z, nullptr);
+    if (!obj) return lrqo::fail(LRQO_EINVAL, "obj is null");
+    lrqo_exact_result res;
+    const lrqo_status st = lrqo_solve_exact_ex(V, n, r, K, 0, z, &res);
+    if (st == LRQO_OK) *obj = res.obj;
+    return st;
 }
 
 }  // extern "C"

@@ -125,4 +125,32 @@ __device__ __forceinline__ float key_value(unsigned long long key) {
     return __uint_as_float(static_cast<uint32_t>(key >> 32));
 }
 
+// ------------------------------------------------------------ nearest root
+// KS selects a closed form for small K (2, 3, 4); KS = 0 is any K via atan2
+// and an LDS table of roots.
+template <int KS>
+__device__ __forceinline__ void nearest_root(float wr, float wi, int K, const float2* roots,
+                                             float& zr, float& zi) {
+    if constexpr (KS == 2) {
+        const bool k0 = wr >= 0.0f;
+        zr = k0 ? 1.0f : -1.0f;
+        zi = 0.0f;
+    } else if constexpr (KS == 3) {
+        // label 0 iff |arg w| < pi/3  <=>  |wi| < sqrt(3) wr; otherwise the
+        // sign of wi picks omega (upper half) or omega^2 (lower half)
+        const bool k0 = fabsf(wi) <= wr * 1.7320508075688772f;
+        zr = k0 ? 1.0f : -0.5f;
+        zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
+    } else if constexpr (KS == 4) {
+        const bool horiz = fabsf(wr) >= fabsf(wi);
+        zr = horiz ? copysignf(1.0f, wr) : 0.0f;
+        zi = horiz ? 0.0f : copysignf(1.0f, wi);
+    } else {
+        const int k = label_f32_generic(wr, wi, K);
+        const float2 t = roots[k];
+        zr = t.x;
+        zi = t.y;
+    }
+}
+
 }  // namespace lrqo

@@ -11,8 +11,7 @@
 //                   accumulates s += conj(V_i) z_i.  With several row slices
 //                   (gridDim.y > 1) it writes partial sums instead.
 //   k_finalize      sums the slice partials in a fixed order -> f = ||s||^2
-//   k_topk          bitonic sort of packed (f, index) keys per 2048-chunk,
-//                   keeps the best T; repeated until T keys are left
+//   topk_select     best T packed (f, index) keys (select.hip)
 //   k_rescore       FP64 re-evaluation of each kept direction, row-sliced
 //   k_pick          FP64 arg-max of the rescored candidates (ties -> lowest index)
 //   k_labels        FP64 decision rule of the winner -> uint8 labels
@@ -24,6 +23,14 @@
 #include "lrqo_device.h"
 #include "lrqo_runtime.h"
 #include "sampled_internal.h"
+#include "select.h"
+
+#ifndef LRQO_SCORE_MFMA
+#define LRQO_SCORE_MFMA 0
+#endif
+#ifndef LRQO_SCORE_CPL
+#define LRQO_SCORE_CPL 4
+#endif
 
 namespace lrqo {
 
@@ -31,35 +38,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTile = 256;        // rows per LDS tile
-constexpr int kTopChunk = 2048;   // keys sorted per block in k_topk
-
-// ------------------------------------------------------------ nearest root
-// KS selects a closed form for small K (2, 3, 4); KS = 0 is any K via atan2
-// and an LDS table of roots.
-template <int KS>
-__device__ __forceinline__ void nearest_root(float wr, float wi, int K, const float2* roots,
-                                             float& zr, float& zi) {
-    if constexpr (KS == 2) {
-        const bool k0 = wr >= 0.0f;
-        zr = k0 ? 1.0f : -1.0f;
-        zi = 0.0f;
-    } else if constexpr (KS == 3) {
-        // label 0 iff |arg w| < pi/3  <=>  |wi| < sqrt(3) wr; otherwise the
-        // sign of wi picks omega (upper half) or omega^2 (lower half)
-        const bool k0 = fabsf(wi) <= wr * 1.7320508075688772f;
-        zr = k0 ? 1.0f : -0.5f;
-        zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
-    } else if constexpr (KS == 4) {
-        const bool horiz = fabsf(wr) >= fabsf(wi);
-        zr = horiz ? copysignf(1.0f, wr) : 0.0f;
-        zi = horiz ? 0.0f : copysignf(1.0f, wi);
-    } else {
-        const int k = label_f32_generic(wr, wi, K);
-        const float2 t = roots[k];
-        zr = t.x;
-        zi = t.y;
-    }
-}
 
 template <int R, bool REAL>
 struct Row {
@@ -180,6 +158,262 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreParams p) {
     }
 }
 
+// ------------------------------------------------------------ fused scorer, r <= 4
+// Per row (an LDS broadcast) each lane forms w = V_i c and the nearest root
+// z on the vector ALU for its CPL candidates and accumulates s += conj(V_i) z.
+// The accumulation has two implementations with the same register layout:
+// vector-ALU FMAs (default; fastest measured on real factors), or
+// v_mfma_f32_4x4x1f32 (16 independent 4x4x1 blocks per wave; block b holds
+// lanes 4b..4b+3, lane 4b+m supplies A_b[m], lane 4b+n supplies B_b[n], and
+// register m of lane 4b+n accumulates D_b[m][n] = sum_i A_b[m] B_b[n]; with
+// B = the lane's own z and A = component m of the row, register m of every
+// lane is a component of that lane's own s: no cross-lane reduction).
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f d) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, d, 0, 0, 0);
+}
+
+// K = 3 with the real part of w pre-scaled by sqrt(3): label 0 iff
+// |Im w| <= sqrt(3) Re w; otherwise the sign of Im w picks omega or omega^2.
+__device__ __forceinline__ void nearest_root_k3s(float wr3, float wi, float& zr, float& zi) {
+    const bool k0 = fabsf(wi) <= wr3;
+    zr = k0 ? 1.0f : -0.5f;
+    zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
+}
+
+// Block = 4 waves holding the same 64*CPL candidates; wave w takes rows
+// w, w+4, w+8, ... of every LDS tile and the four partial sums are added
+// through LDS at the end (fixed order).
+template <int R, int CPL, bool REAL, int KS>
+__device__ __forceinline__ void score_row(const float* __restrict__ row, float a1, float a2,
+                                         const float (&c)[CPL][2 * R], const float (&c3)[CPL][2 * R],
+                                         int K, const float2* roots, v4f (&dr)[CPL], v4f (&di)[CPL]) {
+#if LRQO_SCORE_MFMA
+    constexpr int RF = Row<R, REAL>::F;
+    constexpr bool PACK = !REAL && R <= 2;
+    float v[RF];
+#pragma unroll
+    for (int e = 0; e < RF; ++e) v[e] = row[e];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        float wr = 0.0f, wi = 0.0f;
+        if constexpr (REAL) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                wr = fmaf(v[j], c3[q][2 * j], wr);
+                wi = fmaf(v[j], c[q][2 * j + 1], wi);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float vr = v[2 * j], vi = v[2 * j + 1];
+                wr = fmaf(vr, c3[q][2 * j], fmaf(-vi, c3[q][2 * j + 1], wr));
+                wi = fmaf(vr, c[q][2 * j + 1], fmaf(vi, c[q][2 * j], wi));
+            }
+        }
+        float zr, zi;
+        if constexpr (KS == 3) nearest_root_k3s(wr, wi, zr, zi);
+        else nearest_root<KS>(wr, wi, K, roots, zr, zi);
+        if constexpr (REAL || PACK) {
+            dr[q] = mfma4(a1, zr, dr[q]);
+            di[q] = mfma4(a1, zi, di[q]);
+        } else {
+            dr[q] = mfma4(a1, zr, dr[q]);
+            dr[q] = mfma4(a2, zi, dr[q]);
+            di[q] = mfma4(a1, zi, di[q]);
+            di[q] = mfma4(a2, -zr, di[q]);
+        }
+    }
+#else
+    // vector-ALU accumulation in the same register layout as the MFMA form:
+    // dr[q][m] / di[q][m] hold the components the MFMA form would hold
+    constexpr int RF = Row<R, REAL>::F;
+    constexpr bool PACK = !REAL && R <= 2;
+    (void)a1; (void)a2;
+    float v[RF];
+#pragma unroll
+    for (int e = 0; e < RF; ++e) v[e] = row[e];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        float wr = 0.0f, wi = 0.0f;
+        if constexpr (REAL) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                wr = fmaf(v[j], c3[q][2 * j], wr);
+                wi = fmaf(v[j], c[q][2 * j + 1], wi);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float vr = v[2 * j], vi = v[2 * j + 1];
+                wr = fmaf(vr, c3[q][2 * j], fmaf(-vi, c3[q][2 * j + 1], wr));
+                wi = fmaf(vr, c[q][2 * j + 1], fmaf(vi, c[q][2 * j], wi));
+            }
+        }
+        float zr, zi;
+        if constexpr (KS == 3) nearest_root_k3s(wr, wi, zr, zi);
+        else nearest_root<KS>(wr, wi, K, roots, zr, zi);
+        if constexpr (REAL) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                dr[q][j] = fmaf(v[j], zr, dr[q][j]);
+                di[q][j] = fmaf(v[j], zi, di[q][j]);
+            }
+        } else if constexpr (PACK) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float vr = v[2 * j], vi = v[2 * j + 1];
+                dr[q][j] = fmaf(vr, zr, dr[q][j]);
+                dr[q][2 + j] = fmaf(vi, zr, dr[q][2 + j]);
+                di[q][j] = fmaf(vr, zi, di[q][j]);
+                di[q][2 + j] = fmaf(vi, zi, di[q][2 + j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float vr = v[2 * j], vi = v[2 * j + 1];
+                dr[q][j] = fmaf(vr, zr, fmaf(vi, zi, dr[q][j]));
+                di[q][j] = fmaf(vr, zi, fmaf(-vi, zr, di[q][j]));
+            }
+        }
+    }
+#endif
+}
+
+template <int R, int CPL, bool REAL, int KS>
+__global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
+    static_assert(R <= 4, "MFMA accumulation covers r <= 4");
+    constexpr int RF = Row<R, REAL>::F;
+    // complex r <= 2 packs [Re V_0, Re V_1, Im V_0, Im V_1] into one A operand
+    constexpr bool PACK = !REAL && R <= 2;
+    constexpr int NW = kBlock / kWave;
+    __shared__ __align__(16) float tile[kTile * RF];
+    __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
+    __shared__ float red[NW - 1][CPL * 2 * R][kWave];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int m = lane & 3;
+    if constexpr (KS == 0) {
+        for (int k = tid; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
+    }
+    // LDS offsets of this lane's A-operand elements within a row
+    int off1 = -1, off2 = -1;
+    if constexpr (REAL) {
+        off1 = m < R ? m : -1;
+    } else if constexpr (PACK) {
+        const int j = m & 1;                       // column
+        off1 = j < R ? 2 * j + (m >> 1) : -1;      // m = 0,1: Re V_j ; m = 2,3: Im V_j
+    } else {
+        off1 = m < R ? 2 * m : -1;                 // Re V_m
+        off2 = m < R ? 2 * m + 1 : -1;             // Im V_m
+    }
+
+    float c[CPL][2 * R], c3[CPL][2 * R];
+    v4f dr[CPL], di[CPL];
+    const uint32_t base = blockIdx.x * (uint32_t)(kWave * CPL) + lane;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        const uint32_t idx = base + q * kWave;
+        if (idx < p.S) {
+            direction_f32<R>(p.seed, p.first + idx, p.instance, c[q]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) c[q][j] = 0.0f;
+        }
+        // K = 3: the real part of w is formed with sqrt(3) c
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) c3[q][j] = (KS == 3) ? 1.7320508075688772f * c[q][j] : c[q][j];
+        dr[q] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        di[q] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+
+    const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
+    const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
+    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
+        const int cnt = (int)min((int64_t)kTile, r1 - t0);
+        __syncthreads();
+        const float* __restrict__ src = p.V + t0 * RF;
+        for (int e = tid; e < cnt * RF; e += kBlock) tile[e] = src[e];
+        __syncthreads();
+        if (cnt == kTile) {
+#pragma unroll 4
+            for (int ii = 0; ii < kTile / NW; ++ii) {
+                const int i = wave + NW * ii;
+                const float a1 = off1 >= 0 ? tile[i * RF + off1] : 0.0f;
+                const float a2 = (!REAL && !PACK && off2 >= 0) ? tile[i * RF + off2] : 0.0f;
+                score_row<R, CPL, REAL, KS>(tile + i * RF, a1, a2, c, c3, p.K, roots_s, dr, di);
+            }
+        } else {
+            for (int i = wave; i < cnt; i += NW) {
+                const float a1 = off1 >= 0 ? tile[i * RF + off1] : 0.0f;
+                const float a2 = (!REAL && !PACK && off2 >= 0) ? tile[i * RF + off2] : 0.0f;
+                score_row<R, CPL, REAL, KS>(tile + i * RF, a1, a2, c, c3, p.K, roots_s, dr, di);
+            }
+        }
+    }
+
+    // per-lane sums s_j (re, im) of this lane's candidates, then across waves
+    float acc[CPL][2 * R];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if constexpr (PACK) {
+                // dr[m] = sum A_m zr, di[m] = sum A_m zi with A = [Re V_0, Re V_1, Im V_0, Im V_1]
+                acc[q][2 * j] = dr[q][j] + di[q][2 + j];       // Re: Re V zr + Im V zi
+                acc[q][2 * j + 1] = di[q][j] - dr[q][2 + j];   // Im: Re V zi - Im V zr
+            } else {
+                acc[q][2 * j] = dr[q][j];
+                acc[q][2 * j + 1] = di[q][j];
+            }
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) red[wave - 1][q * 2 * R + j][lane] = acc[q][j];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < NW - 1; ++w)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) acc[q][j] += red[w][q * 2 * R + j][lane];
+
+    if (gridDim.y == 1) {
+        unsigned long long best = 0;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const uint32_t idx = base + q * kWave;
+            if (idx < p.S) {
+                float f = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 2 * R; ++j) f = fmaf(acc[q][j], acc[q][j], f);
+                p.f_out[idx] = f;
+                const unsigned long long key = pack_key(f, idx);
+                best = key > best ? key : best;
+            }
+        }
+        best = wave_max_u64(best);
+        if (lane == 0 && best) atomicMax(p.best_key, best);
+    } else {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const uint32_t idx = base + q * kWave;
+            if (idx < p.S) {
+#pragma unroll
+                for (int j = 0; j < 2 * R; ++j)
+                    p.partial[((size_t)blockIdx.y * (2 * R) + j) * p.S + idx] = acc[q][j];
+            }
+        }
+    }
+}
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ partial, int P,
                                                      uint32_t S, float* __restrict__ f_out,
@@ -199,43 +433,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ p
     }
     best = wave_max_u64(best);
     if ((threadIdx.x & (kWave - 1)) == 0 && best) atomicMax(best_key, best);
-}
-
-// ------------------------------------------------------------ top-T
-// Each block sorts one chunk of packed keys (descending) in LDS and keeps
-// its first T.  Keys come from f (index = position) or from a previous pass.
-// Padding keys are 0, below every real key (a real key has index < 2^32-1,
-// so its low word is nonzero).
-__global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
-                                                 const unsigned long long* __restrict__ keys_in,
-                                                 uint32_t count, int T,
-                                                 unsigned long long* __restrict__ keys_out) {
-    __shared__ unsigned long long sk[kTopChunk];
-    const uint32_t base = blockIdx.x * (uint32_t)kTopChunk;
-    for (int e = threadIdx.x; e < kTopChunk; e += kBlock) {
-        const uint32_t g = base + e;
-        unsigned long long key = 0;
-        if (g < count) key = f ? pack_key(f[g], g) : keys_in[g];
-        sk[e] = key;
-    }
-    __syncthreads();
-    for (int k = 2; k <= kTopChunk; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int e = threadIdx.x; e < kTopChunk; e += kBlock) {
-                const int x = e ^ j;
-                if (x > e) {
-                    const unsigned long long a = sk[e], b = sk[x];
-                    const bool desc = (e & k) == 0;
-                    if (desc ? (a < b) : (a > b)) {
-                        sk[e] = b;
-                        sk[x] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int e = threadIdx.x; e < T; e += kBlock) keys_out[(size_t)blockIdx.x * T + e] = sk[e];
 }
 
 // ------------------------------------------------------------ FP64 rescore
@@ -291,25 +488,34 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
     }
 }
 
+// One thread per kept candidate sums its slice partials (fixed order);
+// thread 0 then takes the FP64 arg-max, ties to the lowest index.
 template <int R>
-__global__ void k_pick(const double* __restrict__ partial, int T, int P,
-                       const unsigned long long* __restrict__ keys, uint64_t seed,
-                       uint32_t instance, uint64_t first, DevResult* res) {
-    if (threadIdx.x != 0) return;
-    int bt = -1;
-    double bf = -1.0;
-    uint32_t bidx = 0xFFFFFFFFu;
-    for (int t = 0; t < T; ++t) {
+__global__ __launch_bounds__(64) void k_pick(const double* __restrict__ partial, int T, int P,
+                                             const unsigned long long* __restrict__ keys,
+                                             uint64_t seed, uint32_t instance, uint64_t first,
+                                             DevResult* res) {
+    __shared__ double fs[64];
+    const int t = threadIdx.x;
+    if (t < T) {
         double f = 0.0;
         for (int j = 0; j < 2 * R; ++j) {
             double a = 0.0;
             for (int q = 0; q < P; ++q) a += partial[((size_t)t * P + q) * (2 * R) + j];
             f += a * a;
         }
-        const uint32_t idx = key_index(keys[t]);
-        if (f > bf || (f == bf && idx < bidx)) {
-            bf = f;
-            bt = t;
+        fs[t] = f;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    int bt = -1;
+    double bf = -1.0;
+    uint32_t bidx = 0xFFFFFFFFu;
+    for (int u = 0; u < T; ++u) {
+        const uint32_t idx = key_index(keys[u]);
+        if (fs[u] > bf || (fs[u] == bf && idx < bidx)) {
+            bf = fs[u];
+            bt = u;
             bidx = idx;
         }
     }
@@ -345,12 +551,19 @@ __global__ __launch_bounds__(kBlock) void k_labels(const float* __restrict__ V, 
 }
 
 // ------------------------------------------------------------ host driver
-int cands_per_lane(int R) { return R <= 2 ? 4 : (R <= 4 ? 2 : 1); }
+// Candidates per lane, and per block (the MFMA scorer's 4 waves share one
+// set of 64*CPL candidates; the vector-ALU scorer's 256 lanes hold distinct ones).
+int cands_per_lane(int R) { return R <= 4 ? LRQO_SCORE_CPL : 1; }
+int cands_per_block(int R) { return R <= 4 ? kWave * cands_per_lane(R) : kBlock * cands_per_lane(R); }
 
 template <int R, bool REAL, int KS>
 void launch_score(const ScoreParams& p, dim3 grid, hipStream_t st) {
-    constexpr int CPL = R <= 2 ? 4 : (R <= 4 ? 2 : 1);
-    hipLaunchKernelGGL((k_score<R, CPL, REAL, KS>), grid, dim3(kBlock), 0, st, p);
+    constexpr int CPL = R <= 4 ? LRQO_SCORE_CPL : 1;
+    if constexpr (R <= 4) {
+        hipLaunchKernelGGL((k_score_rows<R, CPL, REAL, KS>), grid, dim3(kBlock), 0, st, p);
+    } else {
+        hipLaunchKernelGGL((k_score<R, CPL, REAL, KS>), grid, dim3(kBlock), 0, st, p);
+    }
 }
 
 template <int R, bool REAL>
@@ -366,8 +579,7 @@ void launch_score_k(const ScoreParams& p, dim3 grid, hipStream_t st) {
 template <int R, bool REAL>
 lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     const uint32_t S = (uint32_t)job.S;
-    const int CPL = cands_per_lane(R);
-    const int64_t cand_blocks = ((int64_t)S + kBlock * CPL - 1) / (kBlock * CPL);
+    const int64_t cand_blocks = ((int64_t)S + cands_per_block(R) - 1) / cands_per_block(R);
 
     // ---- fused scorer
     ScoreParams p{};
@@ -396,21 +608,7 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     // ---- top-T
     const int T = sc.topk;
     const unsigned long long* keys = nullptr;
-    uint32_t count = S;
-    int ping = 0;
-    bool from_f = true;
-    while (from_f || count > (uint32_t)T) {
-        const uint32_t blocks = (count + kTopChunk - 1) / kTopChunk;
-        unsigned long long* out = ping ? sc.keys_b : sc.keys_a;
-        hipLaunchKernelGGL(k_topk, dim3(blocks), dim3(kBlock), 0, st, from_f ? sc.f32 : nullptr,
-                           keys, count, T, out);
-        LRQO_HIP(hipGetLastError());
-        keys = out;
-        count = blocks * (uint32_t)T;
-        ping ^= 1;
-        from_f = false;
-        if (blocks == 1) break;
-    }
+    LRQO_TRY(topk_select(sc.f32, S, T, sc.keys_a, sc.keys_b, st, &keys));
 
     // ---- FP64 rescore of the T kept keys
     RescoreParams rp{};
@@ -455,10 +653,9 @@ lrqo_status dispatch_r(const SampledJob& job, Scratch& sc, hipStream_t st) {
 // Plans the launch shapes and the scratch layout of one sampled solve.
 void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     const int R = job.r;
-    const int CPL = cands_per_lane(R);
-    const int64_t cand_blocks = (job.S + kBlock * CPL - 1) / (kBlock * CPL);
+    const int64_t cand_blocks = (job.S + cands_per_block(R) - 1) / cands_per_block(R);
     // enough blocks to fill 256 CUs several times over, slices of >= 1024 rows
-    int64_t slices = std::max<int64_t>(1, (4096 + cand_blocks - 1) / cand_blocks);
+    int64_t slices = std::max<int64_t>(1, (2048 + cand_blocks - 1) / cand_blocks);
     slices = std::min<int64_t>(slices, std::max<int64_t>(1, job.n / 1024));
     int64_t rows = (job.n + slices - 1) / slices;
     rows = ((rows + 63) / 64) * 64;
@@ -476,9 +673,8 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     cs.add<double2>(LRQO_MAX_K);
     cs.add<float>(job.f_out ? 0 : job.S);
     cs.add<float>(slices > 1 ? (size_t)slices * 2 * R * job.S : 0);
-    const size_t chunks = (job.S + kTopChunk - 1) / kTopChunk;
-    cs.add<unsigned long long>(chunks * plan.topk);
-    cs.add<unsigned long long>(chunks * plan.topk);
+    cs.add<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
+    cs.add<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
     cs.add<double>((size_t)plan.topk * plan.rescore_slices * 2 * R);
     plan.bytes = cs.bytes;
 }
@@ -496,10 +692,9 @@ lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void*
     sc.slices = plan.slices;
     sc.rows_per_slice = plan.rows_per_slice;
     sc.partial = plan.slices > 1 ? cv.take<float>((size_t)plan.slices * 2 * job.r * job.S) : nullptr;
-    const size_t chunks = (job.S + kTopChunk - 1) / kTopChunk;
     sc.topk = plan.topk;
-    sc.keys_a = cv.take<unsigned long long>(chunks * plan.topk);
-    sc.keys_b = cv.take<unsigned long long>(chunks * plan.topk);
+    sc.keys_a = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
+    sc.keys_b = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
     sc.rescore_slices = plan.rescore_slices;
     sc.rescore_rows = plan.rescore_rows;
     sc.rescore = cv.take<double>((size_t)plan.topk * plan.rescore_slices * 2 * job.r);

@@ -1,0 +1,22 @@
+// Top-T selection of packed (objective, index) keys.  Internal header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lrqo.h"
+
+namespace lrqo {
+
+// Keys needed in each of the two ping-pong buffers of topk_select.
+size_t topk_buffer_keys(uint32_t count, int T);
+
+// Best T keys of f[0..count) (key = FP32 bits of f above, complemented index
+// below: larger f first, lower index first among equal f), sorted
+// descending, at *out (one of buf_a / buf_b).  Requires 1 <= T <= 64 and
+// T <= count; f must be finite and >= 0.
+lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long long* buf_a,
+                        unsigned long long* buf_b, hipStream_t st,
+                        const unsigned long long** out);
+
+}  // namespace lrqo

@@ -12,7 +12,7 @@ import os
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblrqo.so")
+LIB_PATH = os.environ.get("LRQO_LIBRARY") or os.path.join(HERE, "liblrqo.so")
 
 MAX_R = 8
 MAX_K = 255

@@ -80,6 +80,7 @@ def test_simple_entry_rejects_null_obj(lib):
 @pytest.mark.parametrize("kw,msg", [
     (dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=5), "r must"),
     (dict(n=1, r=2), "n must"), (dict(K=1), "K must"), (dict(K=300), "K must"),
+    (dict(n=2**25, r=1), "n must"),
 ])
 def test_exact_rejects_bad_arguments(lib, kw, msg):
     args = dict(V=1, n=12, r=2, K=3, z=1)
