@@ -159,6 +159,54 @@ lrqo_status lrqo_solve_exact(const double* V, int64_t n, int32_t r, int32_t K, u
 lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K,
                                 int64_t max_sets, uint8_t* z, lrqo_exact_result* res);
 
+/* --------------------------------------------------------------------------
+ * Batched sampled maximisation: many small instances in one persistent,
+ * work-queue-driven launch (the sampled method of Sec. 4.2 on each).
+ *
+ * Instance t has factor V_t (n_t x r_t) starting at float offset
+ * v_offset[t] of the device array V (complex64 interleaved, or real FP32
+ * with options->real_v = 1), and is solved exactly as lrqo_solve_sampled_ex
+ * would solve it alone with instance = t (counter word 2 of the direction
+ * stream), the same seed and the same S.
+ * z (device) receives the labels of instance t at offset
+ * n_0 + ... + n_{t-1}; obj (host, count doubles) the FP64 objectives.
+ * Ranges: 1 <= count <= 2^22, 1 <= n_t <= 256, 1 <= r_t <= 4,
+ * 2 <= K <= 255, 1 <= S <= 4096.
+ * The launch shape (directions per lane, persistent blocks per CU) is either
+ * given in options or picked by timing the candidates on the device the
+ * first time a batch signature (K, S, max r, mean-n bucket, count bucket)
+ * is seen; choices are appended to the JSON-lines file named by
+ * LRQO_TUNE_CACHE (default ~/.cache/lrqo_batched_tune.json).  The whole
+ * sequence is captured once into a hipGraph per device and replayed while
+ * count, K, S, seed, T, shape, pointers and the total row count stay the
+ * same.  Calls are serialised per device.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lrqo_batch_options {
+    int32_t real_v;          /* 0: complex64 factors; 1: real FP32 factors */
+    int32_t rescore_topk;    /* 1..64; 0 means min(64, S) */
+    int32_t cpl;             /* directions per lane 1, 2 or 4; 0: tuned */
+    int32_t blocks_per_cu;   /* persistent blocks per CU 1..16; 0: tuned */
+    int32_t no_graph;        /* 1: launch directly instead of replaying a hipGraph */
+    int32_t pad;
+    int64_t* best_index;     /* optional host [count]: winning stream index per instance */
+} lrqo_batch_options;
+
+typedef struct lrqo_batch_result {
+    float device_ms;         /* device time of the scoring sequence (graph replay) */
+    int32_t cpl;             /* launch shape used */
+    int32_t blocks_per_cu;
+    int32_t items;           /* (instance, tile) work items */
+    int32_t tuned_now;       /* 1 if the shape was tuned during this call */
+    int32_t graph_captured_now;
+    int64_t row_candidates;  /* sum over instances of n_t * S */
+} lrqo_batch_result;
+
+lrqo_status lrqo_solve_batched(const float* V, int32_t count, const int64_t* v_offset,
+                               const int32_t* n, const int32_t* r, int32_t K, int64_t S,
+                               uint64_t seed, const lrqo_batch_options* opt, uint8_t* z,
+                               double* obj, lrqo_batch_result* res);
+
 #ifdef __cplusplus
 }
 #endif

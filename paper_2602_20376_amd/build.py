@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrqo.so")
-SOURCES = ["lrqo_runtime.hip", "select.hip", "sampled.hip", "api_sampled.hip", "exact.hip"]
+SOURCES = ["lrqo_runtime.hip", "select.hip", "sampled.hip", "api_sampled.hip", "exact.hip",
+           "batched.hip"]
 ARCH = "gfx950"
 
 

@@ -44,7 +44,7 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
     lrqo_sampled_options o{};
     if (opt) o = *opt;
     if (o.rescore_topk == 0) o.rescore_topk = LRQO_MAX_TOPK;
-    if (o.precision != 0) return fail(LRQO_EINVAL, "precision form not available in this build");
+    if (o.precision == 1 && r > 4) return fail(LRQO_EINVAL, "the precision form (BF16 MFMA) needs r <= 4");
 
     DeviceCtx* ctx = device_ctx();
     if (!ctx) return LRQO_EDEVICE;
@@ -97,7 +97,7 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
         res->obj = hres->obj;
         res->fp32_obj = hres->fp32_obj;
         for (int j = 0; j < 2 * LRQO_MAX_R; ++j) res->best_c[j] = hres->c[j];
-        res->flagged_rows = hres->flagged_rows;
+        res->flagged_rows = (int64_t)hres->flagged_rows;
         res->device_ms = ms;
         res->score_ms = score_ms;
         res->rescored = plan.topk;

@@ -126,8 +126,9 @@ __device__ __forceinline__ float key_value(unsigned long long key) {
 }
 
 // ------------------------------------------------------------ nearest root
-// KS selects a closed form for small K (2, 3, 4); KS = 0 is any K via atan2
-// and an LDS table of roots.
+// KS selects a closed form for K = 2, 3, 4, 8, 16; KS = 0 is any K via atan2
+// and an LDS table of roots.  Ties on a boundary (measure zero) may go either
+// way; the FP64 rescore decides the returned labels.
 template <int KS>
 __device__ __forceinline__ void nearest_root(float wr, float wi, int K, const float2* roots,
                                              float& zr, float& zi) {
@@ -145,12 +146,37 @@ __device__ __forceinline__ void nearest_root(float wr, float wi, int K, const fl
         const bool horiz = fabsf(wr) >= fabsf(wi);
         zr = horiz ? copysignf(1.0f, wr) : 0.0f;
         zi = horiz ? 0.0f : copysignf(1.0f, wi);
+    } else if constexpr (KS == 8) {
+        // fold into the first quadrant; boundaries at 22.5 and 67.5 degrees
+        const float ax = fabsf(wr), ay = fabsf(wi);
+        const float t = 0.41421356237309505f;        // tan(pi/8)
+        const bool h = ay <= t * ax, v = ax <= t * ay;
+        const float d = 0.70710678118654752f;
+        zr = copysignf(h ? 1.0f : (v ? 0.0f : d), wr);
+        zi = copysignf(h ? 0.0f : (v ? 1.0f : d), wi);
+    } else if constexpr (KS == 16) {
+        // fold into the first octant (swap when ay > ax); roots at 0, 22.5,
+        // 45 degrees there, boundaries at 11.25 and 33.75 degrees
+        const float ax = fabsf(wr), ay = fabsf(wi);
+        const bool sw = ay > ax;
+        const float lo = sw ? ax : ay, hi = sw ? ay : ax;
+        const bool b1 = lo > 0.19891236737965800f * hi;   // tan(pi/16)
+        const bool b2 = lo > 0.66817863791929892f * hi;   // tan(3 pi/16)
+        const float cc = b2 ? 0.70710678118654752f : (b1 ? 0.92387953251128676f : 1.0f);
+        const float ss = b2 ? 0.70710678118654752f : (b1 ? 0.38268343236508977f : 0.0f);
+        zr = copysignf(sw ? ss : cc, wr);
+        zi = copysignf(sw ? cc : ss, wi);
     } else {
         const int k = label_f32_generic(wr, wi, K);
         const float2 t = roots[k];
         zr = t.x;
         zi = t.y;
     }
+}
+
+// Closed-form specialisation available for this K (0: generic).
+__host__ __device__ constexpr int k_special(int K) {
+    return (K == 2 || K == 3 || K == 4 || K == 8 || K == 16) ? K : 0;
 }
 
 }  // namespace lrqo

@@ -16,7 +16,7 @@ struct DevResult {
     double c[2 * LRQO_MAX_R];
     int32_t nonfinite;
     int32_t pad;
-    int64_t flagged_rows;
+    unsigned long long flagged_rows;
 };
 
 struct ScoreParams {
@@ -32,6 +32,7 @@ struct ScoreParams {
     float* partial;
     unsigned long long* best_key;
     const float2* roots32;
+    unsigned long long* flagged;   // precision form: row-candidates recomputed in FP32
 };
 
 struct RescoreParams {

@@ -245,18 +245,56 @@ def psk_instance(rng: np.random.Generator, n: int, r: int) -> np.ndarray:
     return V.astype(np.complex64).astype(np.complex128)
 
 
-def psk_batch(count: int = 4096, n_lo: int = 16, n_hi: int = 256, K: int = 8, S: int = 4096):
-    """List of Instances, one per PSK-shaped problem."""
+@dataclass
+class Batch:
+    """Concatenated factors: instance t is rows[row_off[t]:row_off[t]+n[t], :r[t]]
+    of the (sum n, 4) complex array `rows` (unused columns zero)."""
+    rows: np.ndarray
+    n: np.ndarray
+    r: np.ndarray
+    K: int
+    S: int
+    seed: int
+
+    @property
+    def count(self):
+        return self.n.size
+
+    def factor(self, t: int) -> np.ndarray:
+        o = int(np.sum(self.n[:t]))
+        return self.rows[o:o + self.n[t], :self.r[t]]
+
+    def device_layout(self, real: bool = False):
+        """(float32 concatenation, v_offset in floats) in the library's layout."""
+        parts, offs, off = [], [], 0
+        for t in range(self.count):
+            V = self.factor(t)
+            a = as_real_f32(V).ravel() if real else as_interleaved_f32(V).ravel()
+            parts.append(a)
+            offs.append(off)
+            off += a.size
+        return np.concatenate(parts), np.asarray(offs, dtype=np.int64)
+
+
+def psk_batch(count: int = 4096, n_lo: int = 16, n_hi: int = 256, K: int = 8, S: int = 4096) -> Batch:
+    """PSK-detection-shaped instances (see psk_instance), n ~ U{n_lo..n_hi},
+    r ~ U{2, 3, 4}."""
     seed = instance_seed(4)
     rng = np.random.default_rng(seed)
-    ns = rng.integers(n_lo, n_hi + 1, count)
-    rs = rng.integers(2, 5, count)
-    out = []
-    for t in range(count):
-        sub = np.random.default_rng([seed, t])
-        V = psk_instance(sub, int(ns[t]), int(rs[t]))
-        out.append(Instance(V, K, S, direction_seed(4), False, f"psk[{t}](n={ns[t]},r={rs[t]})"))
-    return out
+    ns = rng.integers(n_lo, n_hi + 1, count).astype(np.int32)
+    rs = rng.integers(2, 5, count).astype(np.int32)
+
+    def build():
+        out = np.zeros((int(ns.sum()), 4), dtype=np.complex128)
+        o = 0
+        for t in range(count):
+            sub = np.random.default_rng([seed, t])
+            out[o:o + ns[t], :rs[t]] = psk_instance(sub, int(ns[t]), int(rs[t]))
+            o += ns[t]
+        return out
+
+    rows = _cached(f"psk_batch:{count}:{n_lo}:{n_hi}:{seed}:v1", build)
+    return Batch(rows, ns, rs, K, S, direction_seed(4))
 
 
 def phase_sync_factor(n: int, r: int, seed: int, theta: float = 2.0) -> np.ndarray:

@@ -24,7 +24,7 @@ STATUS = {0: "LRQO_OK", -1: "LRQO_EINVAL", -2: "LRQO_ENOMEM", -3: "LRQO_EDEVICE"
 # every entry point declared in include/lrqo.h
 EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown",
            "lrqo_solve_sampled", "lrqo_solve_sampled_ex", "lrqo_solve_exact",
-           "lrqo_solve_exact_ex")
+           "lrqo_solve_exact_ex", "lrqo_solve_batched")
 
 
 class LrqoError(RuntimeError):
@@ -51,6 +51,20 @@ class ExactResult(ctypes.Structure):
     _fields_ = [("obj", ctypes.c_double), ("index_sets", ctypes.c_int64),
                 ("rank_deficient", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("device_ms", ctypes.c_float)]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("real_v", ctypes.c_int32), ("rescore_topk", ctypes.c_int32),
+                ("cpl", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("no_graph", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("best_index", ctypes.c_void_p)]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [("device_ms", ctypes.c_float), ("cpl", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("items", ctypes.c_int32),
+                ("tuned_now", ctypes.c_int32), ("graph_captured_now", ctypes.c_int32),
+                ("row_candidates", ctypes.c_int64)]
 
 
 _lib = None
@@ -82,6 +96,10 @@ def load(path: str = LIB_PATH):
     lib.lrqo_solve_exact.restype = i32
     lib.lrqo_solve_exact_ex.argtypes = [vp, i64, i32, i32, i64, vp, ctypes.POINTER(ExactResult)]
     lib.lrqo_solve_exact_ex.restype = i32
+    lib.lrqo_solve_batched.argtypes = [vp, i32, vp, vp, vp, i32, i64, u64,
+                                       ctypes.POINTER(BatchOptions), vp, vp,
+                                       ctypes.POINTER(BatchResult)]
+    lib.lrqo_solve_batched.restype = i32
     _lib = lib
     return lib
 
@@ -174,3 +192,53 @@ def solve_exact(V, K: int, *, max_sets: int = 0, z=None):
         _check(lib.lrqo_solve_exact_ex(ctypes.c_void_p(Vc.data_ptr()), n, r, int(K), int(max_sets),
                                        ctypes.c_void_p(z.data_ptr()), ctypes.byref(res)))
     return z, res
+
+
+@dataclass
+class BatchedOutput:
+    z: object             # torch uint8 (sum n,) on the device, instance t at offset sum n[:t]
+    obj: object           # numpy float64 (count,)
+    best_index: object    # numpy int64 (count,)
+    device_ms: float
+    cpl: int
+    blocks_per_cu: int
+    items: int
+    tuned_now: bool
+    graph_captured_now: bool
+    row_candidates: int
+
+
+def solve_batched(Vcat, v_offset, n, r, K: int, S: int, seed: int, *, real: bool = False,
+                  topk: int = 0, cpl: int = 0, blocks_per_cu: int = 0, graph: bool = True,
+                  z=None) -> BatchedOutput:
+    """Batched sampled solve (see lrqo_solve_batched).  Vcat: float32 device
+    tensor holding every factor in the library layout; v_offset, n, r: host
+    integer arrays."""
+    import numpy as np
+    import torch
+
+    lib = load()
+    if not Vcat.is_cuda or Vcat.dtype != torch.float32:
+        raise ValueError("Vcat must be a float32 device tensor")
+    voff = np.ascontiguousarray(v_offset, dtype=np.int64)
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    rr = np.ascontiguousarray(r, dtype=np.int32)
+    count = int(nn.size)
+    if z is None:
+        z = torch.empty(int(nn.sum()), dtype=torch.uint8, device=Vcat.device)
+    obj = np.zeros(count, dtype=np.float64)
+    best = np.zeros(count, dtype=np.int64)
+    opt = BatchOptions(1 if real else 0, int(topk), int(cpl), int(blocks_per_cu),
+                       0 if graph else 1, 0, best.ctypes.data_as(ctypes.c_void_p))
+    res = BatchResult()
+    with torch.cuda.device(Vcat.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_solve_batched(ctypes.c_void_p(Vcat.data_ptr()), count,
+                                      voff.ctypes.data_as(ctypes.c_void_p),
+                                      nn.ctypes.data_as(ctypes.c_void_p),
+                                      rr.ctypes.data_as(ctypes.c_void_p), int(K), int(S),
+                                      int(seed) & (2**64 - 1), ctypes.byref(opt),
+                                      ctypes.c_void_p(z.data_ptr()),
+                                      obj.ctypes.data_as(ctypes.c_void_p), ctypes.byref(res)))
+    return BatchedOutput(z, obj, best, res.device_ms, res.cpl, res.blocks_per_cu, res.items,
+                         bool(res.tuned_now), bool(res.graph_captured_now), res.row_candidates)

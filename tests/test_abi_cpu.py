@@ -108,3 +108,35 @@ def test_binding_fails_loudly_without_library(tmp_path):
             lrqo.load(str(tmp_path / "missing.so"))
     finally:
         lrqo._lib = saved
+
+
+def _batched(lib, count=2, n=(4, 5), r=(2, 2), K=8, S=16, V=1, z=1, opt=None):
+    import numpy as np
+
+    nn = np.asarray(n, np.int32)
+    rr = np.asarray(r, np.int32)
+    off = np.zeros(len(nn), np.int64)
+    obj = np.zeros(len(nn))
+    res = lrqo.BatchResult()
+    return lib.lrqo_solve_batched(ctypes.c_void_p(V), count, off.ctypes.data_as(ctypes.c_void_p),
+                                  nn.ctypes.data_as(ctypes.c_void_p), rr.ctypes.data_as(ctypes.c_void_p),
+                                  K, S, 1, ctypes.byref(opt) if opt is not None else None,
+                                  ctypes.c_void_p(z), obj.ctypes.data_as(ctypes.c_void_p),
+                                  ctypes.byref(res))
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(V=0), "null pointer"), (dict(count=0, n=(), r=()), "count must"),
+    (dict(n=(0, 4)), "n_t must"), (dict(n=(300, 4)), "n_t must"), (dict(r=(5, 2)), "r_t must"),
+    (dict(K=1), "K must"), (dict(S=5000), "S must"), (dict(S=0), "S must"),
+])
+def test_batched_rejects_bad_arguments(lib, kw, msg):
+    assert _batched(lib, **kw) == -1
+    assert msg in lrqo.last_error()
+
+
+def test_batched_rejects_bad_options(lib):
+    assert _batched(lib, opt=lrqo.BatchOptions(0, 0, 3, 0, 0, 0, None)) == -1
+    assert "cpl" in lrqo.last_error()
+    assert _batched(lib, opt=lrqo.BatchOptions(0, 99, 0, 0, 0, 0, None)) == -1
+    assert "rescore_topk" in lrqo.last_error()

@@ -1,0 +1,145 @@
+"""GPU parity of the batched form (persistent work-queue kernel, hipGraph,
+autotuned launch shape) through the C-ABI.
+
+Each instance t is held to the sampled-path bar against the FP64 oracle on
+its own factor with direction stream (seed, instance word t): labels at the
+winning direction bit-exact away from boundaries, objective equal to the
+oracle's f there (FP64 summation bound) and within 1e-5 of the oracle's best
+of the same S directions.  Graph replays, interleaved with eager work, must
+reproduce the eager (no-graph) result exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_20376_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lrqo_mod():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_20376_amd import lrqo
+
+    lrqo.load()
+    return lrqo
+
+
+def _small_batch(count=40, seed=5, real=False):
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(1, 257, count).astype(np.int32)
+    ns[0], ns[1] = 1, 256
+    rs = rng.integers(1, 5, count).astype(np.int32)
+    Vs = [inputs.random_V(int(ns[t]), int(rs[t]), 1000 * seed + t, real=real).astype(np.complex64)
+          .astype(np.complex128) for t in range(count)]
+    parts, offs, off = [], [], 0
+    for V in Vs:
+        a = inputs.as_real_f32(V).ravel() if real else inputs.as_interleaved_f32(V).ravel()
+        parts.append(a)
+        offs.append(off)
+        off += a.size
+    return Vs, np.concatenate(parts), np.asarray(offs, np.int64), ns, rs
+
+
+def _direction_f32(lrqo_mod, V, K, seed, t, s, real):
+    """The device's FP32 direction c_s of stream (seed, t): a one-direction
+    single solve starting at s returns it."""
+    Vd = torch.from_numpy(inputs.as_real_f32(V) if real else V.astype(np.complex64)).cuda()
+    one = lrqo_mod.solve_sampled(Vd, K, 1, seed, real=real, instance=t, first_index=s)
+    return np.array(one.best_c)
+
+
+def _check_instance(lrqo_mod, V, K, S, seed, t, obj, best, z, real=False, full=True):
+    n, r = V.shape
+    c = _direction_f32(lrqo_mod, V, K, seed, t, int(best), real)
+    z_or, dist = oracle.labels(V, K, c)
+    far = dist > 1e-5
+    assert np.array_equal(z[far], z_or[far]), (t, int(np.sum(z[far] != z_or[far])))
+    f_or, _ = oracle.f_of_c(V, K, c)
+    tol64 = max(1e-12 * f_or, 4.0 * (n + 64) * 2.0 ** -53 * np.sum(np.sum(np.abs(V), axis=0) ** 2))
+    assert abs(obj - f_or) <= tol64, (t, obj, f_or)
+    if full:
+        ref = oracle.sampled(V, K, S, seed, instance=t, want_f=False)
+        assert abs(obj - ref["best_f"]) <= 1e-5 * ref["best_f"], (t, obj, ref["best_f"])
+
+
+@pytest.mark.parametrize("K,S,real", [(8, 1000, False), (3, 600, True), (16, 257, False)])
+def test_batched_parity_small(lrqo_mod, K, S, real, tmp_path, monkeypatch):
+    monkeypatch.setenv("LRQO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    Vs, cat, offs, ns, rs = _small_batch(real=real)
+    out = lrqo_mod.solve_batched(torch.from_numpy(cat).cuda(), offs, ns, rs, K, S, 77, real=real)
+    z = out.z.cpu().numpy()
+    zo = np.concatenate([[0], np.cumsum(ns)])
+    for t, V in enumerate(Vs):
+        _check_instance(lrqo_mod, V, K, S, 77, t, out.obj[t], out.best_index[t], z[zo[t]:zo[t + 1]], real)
+
+
+def test_batched_equals_single_solves(lrqo_mod, tmp_path, monkeypatch):
+    """Instance t of a batch is the single solve with instance = t (same
+    stream); objectives agree to the 1e-5 objective bar and usually exactly."""
+    monkeypatch.setenv("LRQO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    Vs, cat, offs, ns, rs = _small_batch(count=12, seed=9)
+    out = lrqo_mod.solve_batched(torch.from_numpy(cat).cuda(), offs, ns, rs, 8, 2048, 5)
+    same = 0
+    for t, V in enumerate(Vs):
+        one = lrqo_mod.solve_sampled(torch.from_numpy(V.astype(np.complex64)).cuda(), 8, 2048, 5,
+                                     instance=t)
+        assert abs(one.obj - out.obj[t]) <= 1e-5 * one.obj
+        same += one.best_index == out.best_index[t]
+    assert same >= 10
+
+
+def test_graph_replays_match_eager(lrqo_mod, tmp_path, monkeypatch):
+    monkeypatch.setenv("LRQO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    Vs, cat, offs, ns, rs = _small_batch(count=30, seed=3)
+    Vd = torch.from_numpy(cat).cuda()
+    eager = lrqo_mod.solve_batched(Vd, offs, ns, rs, 8, 1024, 11, graph=False)
+    ze = eager.z.clone()
+    first = lrqo_mod.solve_batched(Vd, offs, ns, rs, 8, 1024, 11)
+    assert first.graph_captured_now
+    for rep in range(3):
+        x = torch.randn(1000, 1000, device="cuda")        # eager work between replays
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+        again = lrqo_mod.solve_batched(Vd, offs, ns, rs, 8, 1024, 11)
+        assert not again.graph_captured_now
+        assert np.array_equal(again.obj, eager.obj)
+        assert np.array_equal(again.best_index, eager.best_index)
+        assert torch.equal(again.z, ze)
+    other = lrqo_mod.solve_batched(Vd, offs, ns, rs, 8, 1024, 12)
+    assert other.graph_captured_now and not np.array_equal(other.obj, eager.obj)
+
+
+def test_autotuner_cache(lrqo_mod, tmp_path, monkeypatch):
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("LRQO_TUNE_CACHE", str(path))
+    Vs, cat, offs, ns, rs = _small_batch(count=70, seed=4)
+    Vd = torch.from_numpy(cat).cuda()
+    a = lrqo_mod.solve_batched(Vd, offs, ns, rs, 8, 512, 1)
+    assert a.tuned_now and path.exists() and '"cpl"' in path.read_text()
+    b = lrqo_mod.solve_batched(Vd, offs, ns, rs, 8, 512, 1)
+    assert not b.tuned_now and (b.cpl, b.blocks_per_cu) == (a.cpl, a.blocks_per_cu)
+    c = lrqo_mod.solve_batched(Vd, offs, ns, rs, 8, 512, 1, cpl=1, blocks_per_cu=2)
+    assert (c.cpl, c.blocks_per_cu) == (1, 2) and not c.tuned_now
+    assert np.allclose(c.obj, a.obj, rtol=1e-5)
+
+
+def test_psk_batch_workload(lrqo_mod, tmp_path, monkeypatch):
+    """Workload: 4,096 PSK-shaped instances, n ~ U{16..256}, r ~ U{2,3,4},
+    K = 8, S = 4,096 each, one persistent launch; 24 instances checked
+    against the oracle in full, every objective checked to be finite."""
+    monkeypatch.setenv("LRQO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    b = inputs.psk_batch()
+    cat, offs = b.device_layout()
+    out = lrqo_mod.solve_batched(torch.from_numpy(cat).cuda(), offs, b.n, b.r, b.K, b.S, b.seed)
+    assert np.all(np.isfinite(out.obj)) and np.all(out.obj > 0)
+    assert out.row_candidates == int(b.n.sum()) * b.S
+    z = out.z.cpu().numpy()
+    zo = np.concatenate([[0], np.cumsum(b.n)])
+    for t in np.random.default_rng(0).choice(b.count, 24, replace=False):
+        V = b.factor(int(t)).astype(np.complex64).astype(np.complex128)
+        _check_instance(lrqo_mod, V, b.K, b.S, b.seed, int(t), out.obj[t], out.best_index[t],
+                        z[zo[t]:zo[t + 1]])

@@ -56,8 +56,11 @@ def check_result(V, K, S, seed, out, real=False, f32=None, full_oracle=True, sam
     far = dist > 1e-5
     assert np.array_equal(z_gpu[far], z_or[far]), int(np.sum(z_gpu[far] != z_or[far]))
     f_or, _ = oracle.f_of_c(V, K, c)
-    assert abs(out.obj - f_or) <= 1e-12 * f_or
-    assert abs(oracle.objective(V, K, z_gpu) - out.obj) <= 1e-12 * out.obj
+    # same FP64 arithmetic in another summation order: bounded by the FP64
+    # recursive-summation error, 1e-12 relative at small n
+    tol64 = max(1e-12 * f_or, 4.0 * (n + 64) * 2.0 ** -53 * np.sum(np.sum(np.abs(V), axis=0) ** 2))
+    assert abs(out.obj - f_or) <= tol64
+    assert abs(oracle.objective(V, K, z_gpu) - out.obj) <= tol64
     if full_oracle:
         ref = oracle.sampled(V, K, S, seed, instance=instance, s0=first, want_margin=f32 is not None)
         assert out.obj >= ref["best_f"] * (1 - 1e-5), (out.obj, ref["best_f"])
@@ -74,17 +77,18 @@ def check_result(V, K, S, seed, out, real=False, f32=None, full_oracle=True, sam
         m_ref = np.array([b for _, b in fs])
         assert out.obj >= f_ref.max() * (1 - 1e-5)
         if f32 is not None:
-            # at n ~ 1e5 about half the candidates hold some row within the
-            # FP32 rounding of a boundary; the rest must meet the bound
-            _check_f32(V, f32[sample], f_ref, m_ref, min_clean=0.2)
+            _check_f32(V, f32[sample], f_ref, m_ref, min_clean=0.0, flip_rel=1e-4)
     return None
 
 
-def _check_f32(V, f32, f64, margin, min_clean=0.5):
+def _check_f32(V, f32, f64, margin, min_clean=0.5, flip_rel=0.0):
     """FP32 scores against FP64 where no row is within the FP32 rounding of a
     boundary.  Bound: each partial sum of n terms carries at most n u of the
     sum of absolute terms (u = 2^-24, FMA accumulation), squared norm doubles
-    the relative error."""
+    the relative error.  At large n almost every candidate holds a few rows
+    within the FP32 rounding of a boundary; each such row that rounds the
+    other way moves f by about 3.4/n relative, so there all candidates are
+    held to the bound plus `flip_rel` f."""
     n = V.shape[0]
     u = 2.0 ** -24
     scale = np.sum(np.sum(np.abs(V), axis=0) ** 2)
@@ -93,6 +97,8 @@ def _check_f32(V, f32, f64, margin, min_clean=0.5):
     assert np.mean(ok) >= min_clean
     err = np.abs(f32.astype(np.float64) - f64)
     assert np.all(err[ok] <= tol[ok]), float(np.max(err[ok] / tol[ok]))
+    if flip_rel > 0:
+        assert np.all(err <= tol + flip_rel * np.abs(f64)), float(np.max(err / np.abs(f64)))
 
 
 CASES = [
