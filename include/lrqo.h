@@ -100,6 +100,9 @@ typedef struct lrqo_sampled_options {
     uint32_t instance;       /* counter word 2 of the direction stream */
     uint64_t first_index;    /* index of the first direction (range splitting) */
     float* f_out;            /* optional device [S]: FP32 score of every direction */
+    const float* directions; /* optional device [S][2r]: unit directions to score in
+                                place of the stream ((re, im) pairs, FP32); then
+                                first_index must be 0 and best_index indexes this list */
 } lrqo_sampled_options;
 
 typedef struct lrqo_sampled_result {
@@ -206,6 +209,55 @@ lrqo_status lrqo_solve_batched(const float* V, int32_t count, const int64_t* v_o
                                const int32_t* n, const int32_t* r, int32_t K, int64_t S,
                                uint64_t seed, const lrqo_batch_options* opt, uint8_t* z,
                                double* obj, lrqo_batch_result* res);
+
+/* --------------------------------------------------------------------------
+ * Learned direction proposal (rank 3).  A permutation-invariant network over
+ * the rows of V (in a canonical gauge: V -> V G, G unitary from the fourth
+ * moment sum_i |v_i|^2 v_i^H v_i and the K-th and first column moments)
+ * gives a 32-component von Mises-Fisher mixture on the unit sphere of C^3;
+ * lrqo_proposal_sample draws directions from it (every
+ * round(1/uniform_fraction)-th one is the uniform stream's direction instead)
+ * for lrqo_solve_sampled_ex(options.directions).  Parameters: 21,248 floats,
+ * packed [W1 64x6, b1 64, W2 64x64, b2 64, W3 256x64, b3 256] row-major.
+ * Training: lrqo_proposal_train_step computes the mean over a batch of
+ * -log((1/K) sum_t p(omega^t c*_can)) for target directions c*, its gradient
+ * (hand-written backward) and, with update = 1, one Adam step
+ * (beta = 0.9, 0.999, eps = 1e-8).  V here is complex64 (n x 3) only.
+ * A handle belongs to the device current at creation; calls on one handle
+ * must not overlap.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lrqo_proposal lrqo_proposal;
+
+int32_t lrqo_proposal_param_count(void);
+
+/* init (host): parameter count doubles.  *out receives the handle. */
+lrqo_status lrqo_proposal_create(const double* init, int32_t K, lrqo_proposal** out);
+lrqo_status lrqo_proposal_destroy(lrqo_proposal* p);
+
+/* Parameters and Adam state to / from host memory (checkpoint / resume);
+ * m, v and step may be NULL. */
+lrqo_status lrqo_proposal_get_state(lrqo_proposal* p, float* theta, float* m, float* v, int64_t* step);
+lrqo_status lrqo_proposal_set_state(lrqo_proposal* p, const float* theta, const float* m, const float* v,
+                                    int64_t step);
+
+/* V (device): instances concatenated, instance t at float offset
+ * v_offset[t] (host), n[t] rows (host); targets (host): count x 6 floats,
+ * the best direction of each instance as (re, im) pairs.  mean_loss (host)
+ * and grad_out (host, parameter count floats) may be NULL. */
+lrqo_status lrqo_proposal_train_step(lrqo_proposal* p, const float* V, int32_t count,
+                                     const int64_t* v_offset, const int64_t* n,
+                                     const float* targets, float lr, int32_t update,
+                                     double* mean_loss, float* grad_out);
+
+/* S directions (device dirs, S x 6 floats) for the factor V (device, n x 3
+ * complex64); uniform directions come from stream (seed, instance). */
+lrqo_status lrqo_proposal_sample(lrqo_proposal* p, const float* V, int64_t n, int64_t S, uint64_t seed,
+                                 uint32_t instance, float uniform_fraction, float* dirs);
+
+/* Canonical gauge of V (device, n x 3 complex64): frame_out (host, 19
+ * doubles) = G (3x3 complex row-major, (re, im)) then the scale s. */
+lrqo_status lrqo_proposal_frame(lrqo_proposal* p, const float* V, int64_t n, double* frame_out);
 
 #ifdef __cplusplus
 }

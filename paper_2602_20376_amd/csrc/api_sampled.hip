@@ -27,6 +27,8 @@ lrqo_status check_sampled_args(const float* V, int64_t n, int32_t r, int32_t K, 
             return fail(LRQO_EINVAL, "rescore_topk must be in [0, 64]");
         if (opt->first_index > UINT64_MAX - (uint64_t)S)
             return fail(LRQO_EINVAL, "first_index + S overflows");
+        if (opt->directions && opt->first_index != 0)
+            return fail(LRQO_EINVAL, "first_index must be 0 with a direction list");
     }
     return LRQO_OK;
 }
@@ -51,6 +53,8 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
     if (!is_device_pointer(V)) return fail(LRQO_EINVAL, "V is not device memory");
     if (!is_device_pointer(z)) return fail(LRQO_EINVAL, "z is not device memory");
     if (o.f_out && !is_device_pointer(o.f_out)) return fail(LRQO_EINVAL, "f_out is not device memory");
+    if (o.directions && !is_device_pointer(o.directions))
+        return fail(LRQO_EINVAL, "directions is not device memory");
 
     SampledJob job{};
     job.V = V;
@@ -65,6 +69,7 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
     job.precision = o.precision;
     job.topk = o.rescore_topk;
     job.f_out = o.f_out;
+    job.dirs = o.directions;
     job.z = z;
     job.ev_score0 = ctx->ev_score0;
     job.ev_score1 = ctx->ev_score1;

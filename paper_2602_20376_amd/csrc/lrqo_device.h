@@ -70,6 +70,18 @@ __device__ __forceinline__ void direction_f32(uint64_t seed, uint64_t s, uint32_
     for (int j = 0; j < 2 * R; ++j) c[j] *= inv;
 }
 
+// Direction s: from the stream, or row s of a caller-supplied list.
+template <int R>
+__device__ __forceinline__ void direction_any(const float* dirs, uint64_t seed, uint64_t s,
+                                              uint32_t instance, float (&c)[2 * R]) {
+    if (dirs) {
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) c[j] = dirs[s * (2 * R) + j];
+    } else {
+        direction_f32<R>(seed, s, instance, c);
+    }
+}
+
 // ---------------------------------------------------------------- labels
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreParams p) {
     for (int q = 0; q < CPL; ++q) {
         const uint32_t idx = base + q * kBlock;
         if (idx < p.S) {
-            direction_f32<R>(p.seed, p.first + idx, p.instance, c[q]);
+            direction_any<R>(p.dirs, p.seed, p.first + idx, p.instance, c[q]);
         } else {
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) c[q][j] = 0.0f;
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
     for (int q = 0; q < CPL; ++q) {
         const uint32_t idx = base + q * kWave;
         if (idx < p.S) {
-            direction_f32<R>(p.seed, p.first + idx, p.instance, c[q]);
+            direction_any<R>(p.dirs, p.seed, p.first + idx, p.instance, c[q]);
         } else {
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) c[q][j] = 0.0f;
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16(ScoreParams p) {
     for (int q = 0; q < CPL; ++q) {
         const uint32_t idx = base + q * kWave;
         if (idx < p.S) {
-            direction_f32<R>(p.seed, p.first + idx, p.instance, c[q]);
+            direction_any<R>(p.dirs, p.seed, p.first + idx, p.instance, c[q]);
         } else {
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) c[q][j] = 0.0f;
@@ -756,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
     const int t = blockIdx.x;
     const uint32_t idx = key_index(p.keys[t]);
     float cf[2 * R];
-    direction_f32<R>(p.seed, p.first + idx, p.instance, cf);
+    direction_any<R>(p.dirs, p.seed, p.first + idx, p.instance, cf);
     double c[2 * R], acc[2 * R];
 #pragma unroll
     for (int j = 0; j < 2 * R; ++j) {
@@ -805,7 +805,7 @@ template <int R>
 __global__ __launch_bounds__(64) void k_pick(const double* __restrict__ partial, int T, int P,
                                              const unsigned long long* __restrict__ keys,
                                              uint64_t seed, uint32_t instance, uint64_t first,
-                                             DevResult* res) {
+                                             const float* dirs, DevResult* res) {
     __shared__ double fs[64];
     const int t = threadIdx.x;
     if (t < T) {
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(64) void k_pick(const double* __restrict__ partial,
         bidx = key_index(keys[0]);
     }
     float cf[2 * R];
-    direction_f32<R>(seed, first + bidx, instance, cf);
+    direction_any<R>(dirs, seed, first + bidx, instance, cf);
     res->best_index = (int64_t)(first + bidx);
     res->obj = bf;
     res->fp32_obj = (double)key_value(keys[bt]);
@@ -927,6 +927,7 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     p.rows_per_slice = sc.rows_per_slice;
     LRQO_HIP(hipEventRecord(job.ev_score0, st));
     p.flagged = &sc.result->flagged_rows;
+    p.dirs = job.dirs;
     launch_score_k<R, REAL>(p, dim3((unsigned)cand_blocks, (unsigned)sc.slices), st, job.precision);
     LRQO_HIP(hipGetLastError());
     if (sc.slices > 1) {
@@ -953,10 +954,11 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     rp.roots64 = sc.roots64;
     rp.partial = sc.rescore;
     rp.rows_per_slice = sc.rescore_rows;
+    rp.dirs = job.dirs;
     hipLaunchKernelGGL((k_rescore<R, REAL>), dim3(T, sc.rescore_slices), dim3(kBlock), 0, st, rp);
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_pick<R>), dim3(1), dim3(64), 0, st, sc.rescore, T, sc.rescore_slices, keys,
-                       job.seed, job.instance, job.first, sc.result);
+                       job.seed, job.instance, job.first, job.dirs, sc.result);
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_labels<R, REAL>), dim3((unsigned)((job.n + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, job.V, job.n, job.K, sc.result, job.z);

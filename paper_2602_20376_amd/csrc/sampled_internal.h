@@ -33,6 +33,7 @@ struct ScoreParams {
     unsigned long long* best_key;
     const float2* roots32;
     unsigned long long* flagged;   // precision form: row-candidates recomputed in FP32
+    const float* dirs;             // optional [S][2r] directions in place of the stream
 };
 
 struct RescoreParams {
@@ -46,6 +47,7 @@ struct RescoreParams {
     const double2* roots64;
     double* partial;
     int64_t rows_per_slice;
+    const float* dirs;
 };
 
 struct SampledJob {
@@ -61,6 +63,7 @@ struct SampledJob {
     int precision;
     int topk;
     float* f_out;
+    const float* dirs;
     uint8_t* z;
     hipEvent_t ev_score0;   // recorded before / after the scoring kernels
     hipEvent_t ev_score1;

@@ -339,3 +339,39 @@ def as_real_f32(V: np.ndarray) -> np.ndarray:
     """(n, r) real-valued factor -> (n, r) float32 row-major."""
     assert np.all(V.imag == 0)
     return np.ascontiguousarray(V.real.astype(np.float32))
+
+
+# ----------------------------------------------------------------------------
+# learned proposal: initial weights and training instances
+# ----------------------------------------------------------------------------
+
+PROPOSAL_DIMS = {"d_in": 6, "hidden": 64, "ncomp": 32}
+
+
+def proposal_init(seed: int) -> np.ndarray:
+    """Initial parameters of the direction-proposal network, packed as
+    [W1 (64x6), b1 (64), W2 (64x64), b2 (64), W3 (256x64), b3 (256)],
+    row-major, float64.  He-normal hidden layers, a small head; the head
+    bias gives every mixture component a random mean direction, equal
+    weight and concentration 20."""
+    d, h, c = PROPOSAL_DIMS["d_in"], PROPOSAL_DIMS["hidden"], PROPOSAL_DIMS["ncomp"]
+    out_dim = c * (d + 2)
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((h, d)) * np.sqrt(2.0 / d)
+    b1 = np.zeros(h)
+    W2 = rng.standard_normal((h, h)) * np.sqrt(2.0 / h)
+    b2 = np.zeros(h)
+    W3 = rng.standard_normal((out_dim, h)) * (0.1 / np.sqrt(h))
+    b3 = np.zeros((c, d + 2))
+    b3[:, :d] = rng.standard_normal((c, d))
+    b3[:, d] = 0.0
+    b3[:, d + 1] = np.log(20.0)
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, W3.ravel(), b3.ravel()])
+
+
+def phase_sync_training_set(count: int, seed: int = 7000, n_lo: int = 1 << 10, n_hi: int = 1 << 14):
+    """(list of V, list of n) phase-synchronisation factors, n ~ log-uniform in
+    [n_lo, n_hi]: the training distribution of the proposal network."""
+    rng = np.random.default_rng(seed)
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).astype(np.int64)
+    return [phase_sync_factor(int(ns[t]), 3, seed * 100003 + t) for t in range(count)], ns

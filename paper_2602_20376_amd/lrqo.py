@@ -24,7 +24,10 @@ STATUS = {0: "LRQO_OK", -1: "LRQO_EINVAL", -2: "LRQO_ENOMEM", -3: "LRQO_EDEVICE"
 # every entry point declared in include/lrqo.h
 EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown",
            "lrqo_solve_sampled", "lrqo_solve_sampled_ex", "lrqo_solve_exact",
-           "lrqo_solve_exact_ex", "lrqo_solve_batched")
+           "lrqo_solve_exact_ex", "lrqo_solve_batched", "lrqo_proposal_param_count",
+           "lrqo_proposal_create", "lrqo_proposal_destroy", "lrqo_proposal_get_state",
+           "lrqo_proposal_set_state", "lrqo_proposal_train_step", "lrqo_proposal_sample",
+           "lrqo_proposal_frame")
 
 
 class LrqoError(RuntimeError):
@@ -36,7 +39,8 @@ class LrqoError(RuntimeError):
 class SampledOptions(ctypes.Structure):
     _fields_ = [("real_v", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rescore_topk", ctypes.c_int32), ("instance", ctypes.c_uint32),
-                ("first_index", ctypes.c_uint64), ("f_out", ctypes.c_void_p)]
+                ("first_index", ctypes.c_uint64), ("f_out", ctypes.c_void_p),
+                ("directions", ctypes.c_void_p)]
 
 
 class SampledResult(ctypes.Structure):
@@ -100,6 +104,22 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(BatchOptions), vp, vp,
                                        ctypes.POINTER(BatchResult)]
     lib.lrqo_solve_batched.restype = i32
+    lib.lrqo_proposal_param_count.restype = i32
+    lib.lrqo_proposal_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.lrqo_proposal_create.restype = i32
+    lib.lrqo_proposal_destroy.argtypes = [vp]
+    lib.lrqo_proposal_destroy.restype = i32
+    lib.lrqo_proposal_get_state.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.lrqo_proposal_get_state.restype = i32
+    lib.lrqo_proposal_set_state.argtypes = [vp, vp, vp, vp, i64]
+    lib.lrqo_proposal_set_state.restype = i32
+    lib.lrqo_proposal_train_step.argtypes = [vp, vp, i32, vp, vp, vp, ctypes.c_float, i32,
+                                             ctypes.POINTER(ctypes.c_double), vp]
+    lib.lrqo_proposal_train_step.restype = i32
+    lib.lrqo_proposal_sample.argtypes = [vp, vp, i64, i64, u64, u32, ctypes.c_float, vp]
+    lib.lrqo_proposal_sample.restype = i32
+    lib.lrqo_proposal_frame.argtypes = [vp, vp, i64, vp]
+    lib.lrqo_proposal_frame.restype = i32
     _lib = lib
     return lib
 
@@ -154,7 +174,7 @@ def _factor_view(V, real):
 
 def solve_sampled(V, K: int, S: int, seed: int, *, real: bool | None = None, precision: int = 0,
                   topk: int = 64, instance: int = 0, first_index: int = 0, f_out=None,
-                  z=None) -> SampledOutput:
+                  z=None, directions=None) -> SampledOutput:
     """Best of S sampled directions (see lrqo_solve_sampled_ex)."""
     import torch
 
@@ -163,7 +183,8 @@ def solve_sampled(V, K: int, S: int, seed: int, *, real: bool | None = None, pre
     if z is None:
         z = torch.empty(n, dtype=torch.uint8, device=V.device)
     opt = SampledOptions(1 if is_real else 0, int(precision), int(topk), int(instance),
-                         int(first_index), ctypes.c_void_p(f_out.data_ptr() if f_out is not None else 0))
+                         int(first_index), ctypes.c_void_p(f_out.data_ptr() if f_out is not None else 0),
+                         ctypes.c_void_p(directions.data_ptr() if directions is not None else 0))
     res = SampledResult()
     with torch.cuda.device(V.device):
         _bind_stream(torch)
@@ -242,3 +263,103 @@ def solve_batched(Vcat, v_offset, n, r, K: int, S: int, seed: int, *, real: bool
                                       obj.ctypes.data_as(ctypes.c_void_p), ctypes.byref(res)))
     return BatchedOutput(z, obj, best, res.device_ms, res.cpl, res.blocks_per_cu, res.items,
                          bool(res.tuned_now), bool(res.graph_captured_now), res.row_candidates)
+
+
+class Proposal:
+    """Handle of the learned direction proposal (see lrqo_proposal_* in lrqo.h)."""
+
+    def __init__(self, init_params, K: int):
+        import numpy as np
+
+        lib = load()
+        self.nparam = int(lib.lrqo_proposal_param_count())
+        init = np.ascontiguousarray(init_params, dtype=np.float64)
+        if init.size != self.nparam:
+            raise ValueError(f"expected {self.nparam} parameters")
+        h = ctypes.c_void_p()
+        _check(lib.lrqo_proposal_create(init.ctypes.data_as(ctypes.c_void_p), int(K), ctypes.byref(h)))
+        self._h = h
+        self.K = int(K)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lrqo_proposal_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_state(self):
+        import numpy as np
+
+        th = np.zeros(self.nparam, np.float32)
+        m = np.zeros(self.nparam, np.float32)
+        v = np.zeros(self.nparam, np.float32)
+        step = ctypes.c_int64()
+        _check(load().lrqo_proposal_get_state(self._h, th.ctypes.data_as(ctypes.c_void_p),
+                                              m.ctypes.data_as(ctypes.c_void_p),
+                                              v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(step)))
+        return {"theta": th, "m": m, "v": v, "step": int(step.value)}
+
+    def set_state(self, state):
+        import numpy as np
+
+        th = np.ascontiguousarray(state["theta"], np.float32)
+        m = np.ascontiguousarray(state["m"], np.float32)
+        v = np.ascontiguousarray(state["v"], np.float32)
+        _check(load().lrqo_proposal_set_state(self._h, th.ctypes.data_as(ctypes.c_void_p),
+                                              m.ctypes.data_as(ctypes.c_void_p),
+                                              v.ctypes.data_as(ctypes.c_void_p), int(state["step"])))
+
+    def train_step(self, Vcat, v_offset, n, targets, lr: float, update: bool = True,
+                   want_grad: bool = False):
+        """Vcat: float32 device tensor of concatenated (n_t x 3) complex64
+        factors; v_offset, n: host int64 arrays; targets: host (count, 6)."""
+        import numpy as np
+        import torch
+
+        voff = np.ascontiguousarray(v_offset, np.int64)
+        nn = np.ascontiguousarray(n, np.int64)
+        tg = np.ascontiguousarray(targets, np.float32)
+        loss = ctypes.c_double()
+        g = np.zeros(self.nparam, np.float32) if want_grad else None
+        with torch.cuda.device(Vcat.device):
+            _bind_stream(torch)
+            _check(load().lrqo_proposal_train_step(
+                self._h, ctypes.c_void_p(Vcat.data_ptr()), int(nn.size),
+                voff.ctypes.data_as(ctypes.c_void_p), nn.ctypes.data_as(ctypes.c_void_p),
+                tg.ctypes.data_as(ctypes.c_void_p), float(lr), 1 if update else 0,
+                ctypes.byref(loss), g.ctypes.data_as(ctypes.c_void_p) if g is not None else None))
+        return float(loss.value), g
+
+    def sample(self, V, S: int, seed: int, instance: int = 0, uniform_fraction: float = 0.0,
+               out=None):
+        """(S, 6) float32 device tensor of proposed directions for V
+        (complex64 (n, 3) device tensor)."""
+        import torch
+
+        Vf = torch.view_as_real(V.contiguous()).contiguous()
+        if out is None:
+            out = torch.empty((int(S), 6), dtype=torch.float32, device=V.device)
+        with torch.cuda.device(V.device):
+            _bind_stream(torch)
+            _check(load().lrqo_proposal_sample(self._h, ctypes.c_void_p(Vf.data_ptr()), int(V.shape[0]),
+                                               int(S), int(seed) & (2**64 - 1), int(instance),
+                                               float(uniform_fraction), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def frame(self, V):
+        import numpy as np
+        import torch
+
+        Vf = torch.view_as_real(V.contiguous()).contiguous()
+        out = np.zeros(19, np.float64)
+        with torch.cuda.device(V.device):
+            _bind_stream(torch)
+            _check(load().lrqo_proposal_frame(self._h, ctypes.c_void_p(Vf.data_ptr()), int(V.shape[0]),
+                                              out.ctypes.data_as(ctypes.c_void_p)))
+        G = (out[0:18:2] + 1j * out[1:18:2]).reshape(3, 3)
+        return G, float(out[18])
