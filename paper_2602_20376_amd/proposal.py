@@ -80,3 +80,31 @@ def load_into(prop: "lrqo.Proposal", path: str) -> dict:
     with np.load(path, allow_pickle=False) as z:
         prop.set_state({"theta": z["theta"], "m": z["m"], "v": z["v"], "step": int(z["step"])})
         return json.loads(bytes(z["meta"]).decode() or "{}")
+
+
+def knee(f_in_order, ref: float, frac: float = 0.999):
+    """Samples needed for the running best of a direction stream to reach
+    frac * ref (None if it never does)."""
+    best = np.maximum.accumulate(np.asarray(f_in_order, dtype=np.float64))
+    hit = np.nonzero(best >= frac * ref)[0]
+    return int(hit[0]) + 1 if hit.size else None
+
+
+def train_default(K: int = 16, count: int = 10_000, label_S: int = 16_384, epochs: int = 30,
+                  batch: int = 128, lr: float = 2e-3, seed: int = 1, log=None):
+    """The proposal trained on `count` phase-synchronisation instances at
+    n ~ log-uniform [2^10, 2^14], labelled by the plain sampler's best of
+    label_S directions.  Returns (proposal, loss history, seconds by phase)."""
+    import time
+
+    t = time.perf_counter()
+    Vs, _ = inputs.phase_sync_training_set(count, seed=7000)
+    t_gen = time.perf_counter() - t
+    t = time.perf_counter()
+    best_c, _ = label_targets(Vs, K, label_S, 31)
+    t_label = time.perf_counter() - t
+    prop = lrqo.Proposal(inputs.proposal_init(seed), K)
+    t = time.perf_counter()
+    hist = train(prop, Vs, best_c, epochs=epochs, batch=batch, lr=lr, log=log)
+    t_train = time.perf_counter() - t
+    return prop, hist, {"generate_s": t_gen, "label_s": t_label, "train_s": t_train}
