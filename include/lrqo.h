@@ -112,7 +112,7 @@ typedef struct lrqo_sampled_result {
     double best_c[2 * LRQO_MAX_R]; /* winner's direction, FP64 copy of the FP32 values, (re, im) pairs */
     int64_t flagged_rows;    /* precision 1: row-candidates recomputed in FP32 */
     float device_ms;         /* device time of the call, from stream events */
-    float score_ms;          /* device time of the fused scoring kernels alone */
+    float score_ms;          /* device time of the fused scoring kernel alone */
     int32_t rescored;        /* candidates that went through the FP64 rescore */
     int32_t slices;          /* row slices of the scoring launch */
 } lrqo_sampled_result;

@@ -799,26 +799,30 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
     }
 }
 
-// One thread per kept candidate sums its slice partials (fixed order);
-// thread 0 then takes the FP64 arg-max, ties to the lowest index.
+// Thread (t, j) sums component j of kept candidate t over the slices
+// (fixed order); thread t forms f_t; thread 0 takes the FP64 arg-max, ties
+// to the lowest index.
 template <int R>
-__global__ __launch_bounds__(64) void k_pick(const double* __restrict__ partial, int T, int P,
-                                             const unsigned long long* __restrict__ keys,
-                                             uint64_t seed, uint32_t instance, uint64_t first,
-                                             const float* dirs, DevResult* res) {
+__global__ __launch_bounds__(64 * 2 * R) void k_pick(const double* __restrict__ partial, int T, int P,
+                                                     const unsigned long long* __restrict__ keys,
+                                                     uint64_t seed, uint32_t instance, uint64_t first,
+                                                     const float* dirs, DevResult* res) {
+    __shared__ double comp[64][2 * R];
     __shared__ double fs[64];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x / (2 * R), j = threadIdx.x % (2 * R);
     if (t < T) {
-        double f = 0.0;
-        for (int j = 0; j < 2 * R; ++j) {
-            double a = 0.0;
-            for (int q = 0; q < P; ++q) a += partial[((size_t)t * P + q) * (2 * R) + j];
-            f += a * a;
-        }
-        fs[t] = f;
+        double a = 0.0;
+        for (int q = 0; q < P; ++q) a += partial[((size_t)t * P + q) * (2 * R) + j];
+        comp[t][j] = a;
     }
     __syncthreads();
-    if (t != 0) return;
+    if (threadIdx.x < T) {
+        double f = 0.0;
+        for (int jj = 0; jj < 2 * R; ++jj) f += comp[threadIdx.x][jj] * comp[threadIdx.x][jj];
+        fs[threadIdx.x] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     int bt = -1;
     double bf = -1.0;
     uint32_t bidx = 0xFFFFFFFFu;
@@ -839,7 +843,7 @@ __global__ __launch_bounds__(64) void k_pick(const double* __restrict__ partial,
     res->best_index = (int64_t)(first + bidx);
     res->obj = bf;
     res->fp32_obj = (double)key_value(keys[bt]);
-    for (int j = 0; j < 2 * LRQO_MAX_R; ++j) res->c[j] = j < 2 * R ? (double)cf[j] : 0.0;
+    for (int jj = 0; jj < 2 * LRQO_MAX_R; ++jj) res->c[jj] = jj < 2 * R ? (double)cf[jj] : 0.0;
 }
 
 template <int R, bool REAL>
@@ -930,12 +934,12 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     p.dirs = job.dirs;
     launch_score_k<R, REAL>(p, dim3((unsigned)cand_blocks, (unsigned)sc.slices), st, job.precision);
     LRQO_HIP(hipGetLastError());
+    LRQO_HIP(hipEventRecord(job.ev_score1, st));
     if (sc.slices > 1) {
         hipLaunchKernelGGL((k_finalize<R>), dim3((S + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
                            sc.partial, sc.slices, S, sc.f32, sc.best_key);
         LRQO_HIP(hipGetLastError());
     }
-    LRQO_HIP(hipEventRecord(job.ev_score1, st));
 
     // ---- top-T
     const int T = sc.topk;
@@ -957,7 +961,7 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     rp.dirs = job.dirs;
     hipLaunchKernelGGL((k_rescore<R, REAL>), dim3(T, sc.rescore_slices), dim3(kBlock), 0, st, rp);
     LRQO_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_pick<R>), dim3(1), dim3(64), 0, st, sc.rescore, T, sc.rescore_slices, keys,
+    hipLaunchKernelGGL((k_pick<R>), dim3(1), dim3(64 * 2 * R), 0, st, sc.rescore, T, sc.rescore_slices, keys,
                        job.seed, job.instance, job.first, job.dirs, sc.result);
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_labels<R, REAL>), dim3((unsigned)((job.n + kBlock - 1) / kBlock)),

@@ -1,6 +1,11 @@
-// Top-T selection: each block sorts one chunk of 2048 packed keys in LDS
-// (bitonic, descending) and keeps its first T; passes repeat over the
-// survivors until one block remains.
+// Top-T selection of packed keys with one 64-key list per wavefront: lane l
+// holds the l-th largest key seen so far.  Each wave streams 64-key tiles,
+// sorts a tile across its lanes (bitonic network over lane shuffles) and
+// merges it into the running list (half-cleaner against the reversed tile,
+// then a bitonic merge); tiles with no key above the running 64th are
+// skipped.  The four lists of a block are merged the same way, the block
+// writes its best T, and passes repeat over the survivors until one block
+// remains.
 #include "lrqo_device.h"
 #include "lrqo_runtime.h"
 #include "select.h"
@@ -9,8 +14,40 @@ namespace lrqo {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kChunk = 2048;
+constexpr int kWaves = 4;
+constexpr int kBlock = 64 * kWaves;
+constexpr int kChunk = 2048;  // keys per block, kChunk / kWaves per wave
+
+__device__ __forceinline__ unsigned long long kmax(unsigned long long a, unsigned long long b) {
+    return a > b ? a : b;
+}
+__device__ __forceinline__ unsigned long long kmin(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+// One key per lane, returned sorted descending by lane.
+__device__ __forceinline__ unsigned long long wave_sort_desc(unsigned long long x, int lane) {
+    for (int k = 2; k <= 64; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned long long y = __shfl_xor(x, j, 64);
+            // in a descending run the lower lane of a pair keeps the larger key
+            const bool keep_max = ((lane & j) == 0) == ((lane & k) == 0);
+            x = keep_max ? kmax(x, y) : kmin(x, y);
+        }
+    }
+    return x;
+}
+
+// Best 64 of two descending lists (one key per lane), descending.
+__device__ __forceinline__ unsigned long long wave_top_union(unsigned long long a,
+                                                             unsigned long long b, int lane) {
+    unsigned long long x = kmax(a, __shfl(b, 63 - lane, 64));  // bitonic, holds the best 64
+    for (int j = 32; j > 0; j >>= 1) {
+        const unsigned long long y = __shfl_xor(x, j, 64);
+        x = (lane & j) == 0 ? kmax(x, y) : kmin(x, y);
+    }
+    return x;
+}
 
 // Keys come from f (index = position) or from a previous pass.  Padding keys
 // are 0, below every real key (a real key's index is < 2^32-1, so its low
@@ -19,32 +56,23 @@ __global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
                                                  const unsigned long long* __restrict__ keys_in,
                                                  uint32_t count, int T,
                                                  unsigned long long* __restrict__ keys_out) {
-    __shared__ unsigned long long sk[kChunk];
-    const uint32_t base = blockIdx.x * (uint32_t)kChunk;
-    for (int e = threadIdx.x; e < kChunk; e += kBlock) {
-        const uint32_t g = base + e;
+    __shared__ unsigned long long top[kWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t base = blockIdx.x * (uint32_t)kChunk + (uint32_t)w * (kChunk / kWaves);
+    unsigned long long run = 0;
+    for (int t = 0; t < kChunk / kWaves; t += 64) {
+        const uint32_t g = base + (uint32_t)(t + lane);
         unsigned long long key = 0;
         if (g < count) key = f ? pack_key(f[g], g) : keys_in[g];
-        sk[e] = key;
+        const unsigned long long floor64 = __shfl(run, 63, 64);
+        if (__ballot(key > floor64) == 0) continue;  // uniform across the wave
+        run = wave_top_union(run, wave_sort_desc(key, lane), lane);
     }
+    top[w][lane] = run;
     __syncthreads();
-    for (int k = 2; k <= kChunk; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int e = threadIdx.x; e < kChunk; e += kBlock) {
-                const int x = e ^ j;
-                if (x > e) {
-                    const unsigned long long a = sk[e], b = sk[x];
-                    const bool desc = (e & k) == 0;
-                    if (desc ? (a < b) : (a > b)) {
-                        sk[e] = b;
-                        sk[x] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int e = threadIdx.x; e < T; e += kBlock) keys_out[(size_t)blockIdx.x * T + e] = sk[e];
+    if (w != 0) return;
+    for (int v = 1; v < kWaves; ++v) run = wave_top_union(run, top[v][lane], lane);
+    if (lane < T) keys_out[(size_t)blockIdx.x * T + lane] = run;
 }
 
 }  // namespace
