@@ -39,6 +39,8 @@ def parse():
                     help="skip the precision / batched / learned-proposal measurements")
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
+    ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal"),
+                    help="measure only this form and print its record (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized float32 device tensor once before timing "
                          "(a known-size kernel for scaling memory counters)")
@@ -190,6 +192,12 @@ def main():
     import torch
 
     from paper_2602_20376_amd import inputs, lrqo
+
+    if args.form:
+        fn = {"precision_bf16": form_precision, "batched": form_batched,
+              "learned_proposal": lambda: form_learned(args.train_count)}[args.form]
+        print(json.dumps({"form": args.form, **fn()}), flush=True)
+        return
 
     inst = inputs.maxcut_er()
     n, r, K, S = inst.n, inst.r, inst.K, inst.S

@@ -24,7 +24,8 @@ Steps, in the paper's order and notation:
 7. A coordinate with two rows in I has V_i c = 0 (Cor. two_implies_all): all
    K labels are tried.  This enumerates a superset of the (B_K-1)^p adjacent
    cells of Lemma adjacent_cells and replaces the fixed-angle construction of
-   Alg. 3, whose embedding matrix is not dimensionally consistent as printed.
+   the ambiguity-resolution subroutine (Alg. resolve, appendix to Sec. 3),
+   whose embedding matrix is not dimensionally consistent as printed.
 8. Every combination is scored in FP64 with the full factor; the maximum is
    kept, ties going to the first candidate in enumeration order.
 9. For r > 1 the same enumeration runs on the leading columns V_{:,1:d},

@@ -11,11 +11,11 @@
 //                    from a queue sorted by decreasing cost with an atomic
 //                    cursor, stages V_t in LDS, scores its tile of
 //                    directions (FP32, CPL per lane) and writes FP32 scores
-//   k_batch_topk     per instance: best T packed (score, index) keys
-//   k_batch_rescore  per instance: FP64 rescore of the T kept directions,
-//                    arg-max (ties to the lower index), FP64 labels of the
-//                    winner into the library's label buffer, copied to the
-//                    caller's array after the replay
+//   k_batch_select   per instance: best T packed (score, index) keys, FP64
+//                    rescore of the T kept directions, arg-max (ties to the
+//                    lower index), FP64 labels of the winner into the
+//                    library's label buffer, copied to the caller's array
+//                    after the replay
 // Launch shape (directions per lane, persistent blocks per CU) comes from a
 // small autotuner that times the candidates on the device once per batch
 // signature and keeps the choice in a JSON cache file.
@@ -41,7 +41,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxRows = 256;       // rows of one instance staged in LDS
-constexpr int kMaxS = 4096;         // directions per instance (one LDS sort)
+constexpr int kMaxS = 4096;         // directions per instance
 constexpr int kTopT = 64;
 
 struct BatchDevParams {
@@ -60,7 +60,6 @@ struct BatchDevParams {
     int32_t tile;                   // directions per item
     unsigned int* cursor;
     float* f;                       // [count][S]
-    unsigned long long* keys;       // [count][T]
     double* obj;                    // [count]
     int64_t* best;                  // [count]
     uint8_t* z;
@@ -166,54 +165,62 @@ __global__ __launch_bounds__(kBlock) void k_batch_score(BatchDevParams p) {
     }
 }
 
-// Per instance: best T keys of its S scores (bitonic sort of up to 4096
-// keys in LDS, descending).
-__global__ __launch_bounds__(kBlock) void k_batch_topk(BatchDevParams p) {
-    __shared__ unsigned long long sk[kMaxS];
-    const int t = blockIdx.x;
-    int N = 1;
-    while (N < p.S) N <<= 1;
-    for (int e = threadIdx.x; e < N; e += kBlock)
-        sk[e] = e < p.S ? pack_key(p.f[(size_t)t * p.S + e], (uint32_t)e) : 0ull;
-    __syncthreads();
-    for (int k = 2; k <= N; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int e = threadIdx.x; e < N; e += kBlock) {
-                const int x = e ^ j;
-                if (x > e) {
-                    const unsigned long long a = sk[e], b = sk[x];
-                    const bool desc = (e & k) == 0;
-                    if (desc ? (a < b) : (a > b)) {
-                        sk[e] = b;
-                        sk[x] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int e = threadIdx.x; e < p.T; e += kBlock) p.keys[(size_t)t * p.T + e] = sk[e];
-}
+// Per instance (one block of four waves):
+//   select   best T of its S FP32 scores as packed keys: each wave keeps a
+//            64-key list over a quarter of the scores, wave 0 merges the four
+//   rescore  FP64 objective of each kept direction; wave w takes rows
+//            w, w+4, ..., and the four partial sums are added in wave order
+//   pick     FP64 arg-max over the kept directions, ties to the lower index
+//   labels   FP64 decision rule of the winner for every row
+struct SelectShared {
+    unsigned long long top[kBlock / 64][64];
+    double part[kBlock / 64][kTopT][8];
+    double2 roots[LRQO_MAX_K];
+    double cbest[8];
+};
 
-// Per instance: FP64 rescore of the kept directions (one thread each), the
-// arg-max, and the winner's labels.
-template <int R>
-__device__ void rescore_instance(const BatchDevParams& p, int t, double* fs, uint32_t* idxs) {
-    const int n = p.n[t];
+template <int R, int KS>
+__device__ void select_rescore(const BatchDevParams& p, int t, SelectShared& sh) {
+    constexpr int NW = kBlock / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int S = p.S, T = p.T, n = p.n[t];
+    const float* f = p.f + (size_t)t * S;
     const float* V = p.V + p.voff[t];
-    const int q = threadIdx.x;
-    if (q < p.T) {
-        const uint32_t s = key_index(p.keys[(size_t)t * p.T + q]);
+
+    // ---- select
+    const int per = (S + NW * 64 - 1) / (NW * 64) * 64;
+    const int lo = w * per, hi = min(S, lo + per);
+    unsigned long long run = 0;
+    for (int b = lo; b < hi; b += 64) {
+        const int s = b + lane;
+        const unsigned long long key = s < hi ? pack_key(f[s], (uint32_t)s) : 0ull;
+        const unsigned long long floor64 = __shfl(run, 63, 64);
+        if (__ballot(key > floor64) == 0) continue;  // uniform across the wave
+        run = wave_top_union(run, wave_sort_desc(key, lane), lane);
+    }
+    sh.top[w][lane] = run;
+    __syncthreads();
+    if (w == 0) {
+        for (int v = 1; v < NW; ++v) run = wave_top_union(run, sh.top[v][lane], lane);
+        sh.top[0][lane] = run;
+    }
+    __syncthreads();
+
+    // ---- rescore
+    const bool live = lane < T;
+    uint32_t idx = 0xFFFFFFFFu;
+    if (live) {
+        idx = key_index(sh.top[0][lane]);
         float cf[2 * R];
-        direction_f32<R>(p.seed, s, (uint32_t)t, cf);
+        direction_f32<R>(p.seed, idx, (uint32_t)t, cf);
         double c[2 * R], acc[2 * R];
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) {
             c[j] = (double)cf[j];
             acc[j] = 0.0;
         }
-        for (int i = 0; i < n; ++i) {
-            double wr = 0.0, wi = 0.0, vr[R], vi[R];
+        for (int i = w; i < n; i += NW) {
+            double vr[R], vi[R], wr = 0.0, wi = 0.0;
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 vr[j] = p.real ? (double)V[i * R + j] : (double)V[(i * R + j) * 2];
@@ -221,55 +228,88 @@ __device__ void rescore_instance(const BatchDevParams& p, int t, double* fs, uin
                 wr += vr[j] * c[2 * j] - vi[j] * c[2 * j + 1];
                 wi += vr[j] * c[2 * j + 1] + vi[j] * c[2 * j];
             }
-            const double2 z = p.roots64[label_f64(wr, wi, p.K)];
+            double zr, zi;
+            nearest_root64<KS>(wr, wi, p.K, sh.roots, zr, zi);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                acc[2 * j] += vr[j] * z.x + vi[j] * z.y;
-                acc[2 * j + 1] += vr[j] * z.y - vi[j] * z.x;
+                acc[2 * j] += vr[j] * zr + vi[j] * zi;
+                acc[2 * j + 1] += vr[j] * zi - vi[j] * zr;
             }
         }
-        double f = 0.0;
 #pragma unroll
-        for (int j = 0; j < 2 * R; ++j) f += acc[j] * acc[j];
-        fs[q] = f;
-        idxs[q] = s;
+        for (int j = 0; j < 2 * R; ++j) sh.part[w][lane][j] = acc[j];
     }
     __syncthreads();
-    __shared__ double cbest[2 * LRQO_MAX_R];
-    if (threadIdx.x == 0) {
-        int bt = 0;
-        for (int u = 1; u < p.T; ++u)
-            if (fs[u] > fs[bt] || (fs[u] == fs[bt] && idxs[u] < idxs[bt])) bt = u;
-        p.obj[t] = fs[bt];
-        p.best[t] = idxs[bt];
-        float cf[2 * R];
-        direction_f32<R>(p.seed, idxs[bt], (uint32_t)t, cf);
-        for (int j = 0; j < 2 * R; ++j) cbest[j] = (double)cf[j];
+
+    // ---- pick (wave 0)
+    if (w == 0) {
+        double fq = -1.0;
+        if (live) {
+            fq = 0.0;
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) {
+                double a = 0.0;
+                for (int v = 0; v < NW; ++v) a += sh.part[v][lane][j];
+                fq += a * a;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double fo = __shfl_xor(fq, off, 64);
+            const uint32_t io = __shfl_xor(idx, off, 64);
+            if (fo > fq || (fo == fq && io < idx)) {
+                fq = fo;
+                idx = io;
+            }
+        }
+        if (lane == 0) {
+            p.obj[t] = fq;
+            p.best[t] = idx;
+            float cf[2 * R];
+            direction_f32<R>(p.seed, idx, (uint32_t)t, cf);
+            for (int j = 0; j < 2 * R; ++j) sh.cbest[j] = (double)cf[j];
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+
+    // ---- labels of the winner
+    for (int i = threadIdx.x; i < n; i += kBlock) {
         double wr = 0.0, wi = 0.0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const double vr = p.real ? (double)V[i * R + j] : (double)V[(i * R + j) * 2];
             const double vi = p.real ? 0.0 : (double)V[(i * R + j) * 2 + 1];
-            wr += vr * cbest[2 * j] - vi * cbest[2 * j + 1];
-            wi += vr * cbest[2 * j + 1] + vi * cbest[2 * j];
+            wr += vr * sh.cbest[2 * j] - vi * sh.cbest[2 * j + 1];
+            wi += vr * sh.cbest[2 * j + 1] + vi * sh.cbest[2 * j];
         }
         p.z[p.zoff[t] + i] = (uint8_t)label_f64(wr, wi, p.K);
     }
 }
 
-__global__ __launch_bounds__(64) void k_batch_rescore(BatchDevParams p) {
-    __shared__ double fs[kTopT];
-    __shared__ uint32_t idxs[kTopT];
+template <int KS>
+__global__ __launch_bounds__(kBlock) void k_batch_select(BatchDevParams p) {
+    __shared__ SelectShared sh;
     const int t = blockIdx.x;
+    for (int k = threadIdx.x; k < p.K; k += kBlock) sh.roots[k] = p.roots64[k];
+    __syncthreads();
     switch (p.r[t]) {
-        case 1: rescore_instance<1>(p, t, fs, idxs); break;
-        case 2: rescore_instance<2>(p, t, fs, idxs); break;
-        case 3: rescore_instance<3>(p, t, fs, idxs); break;
-        case 4: rescore_instance<4>(p, t, fs, idxs); break;
+        case 1: select_rescore<1, KS>(p, t, sh); break;
+        case 2: select_rescore<2, KS>(p, t, sh); break;
+        case 3: select_rescore<3, KS>(p, t, sh); break;
+        case 4: select_rescore<4, KS>(p, t, sh); break;
         default: break;
+    }
+}
+
+void launch_select(const BatchDevParams& p, hipStream_t st) {
+    const dim3 g(p.count), b(kBlock);
+    switch (k_special(p.K)) {
+        case 2: hipLaunchKernelGGL((k_batch_select<2>), g, b, 0, st, p); break;
+        case 3: hipLaunchKernelGGL((k_batch_select<3>), g, b, 0, st, p); break;
+        case 4: hipLaunchKernelGGL((k_batch_select<4>), g, b, 0, st, p); break;
+        case 8: hipLaunchKernelGGL((k_batch_select<8>), g, b, 0, st, p); break;
+        case 16: hipLaunchKernelGGL((k_batch_select<16>), g, b, 0, st, p); break;
+        default: hipLaunchKernelGGL((k_batch_select<0>), g, b, 0, st, p); break;
     }
 }
 
@@ -455,7 +495,6 @@ lrqo_status lrqo_solve_batched(const float* V, int32_t count, const int64_t* v_o
     cs.add<int32_t>(max_items);        // items
     cs.add<unsigned int>(64);          // cursor, flags
     cs.add<float>((size_t)count * S);  // scores
-    cs.add<unsigned long long>((size_t)count * T);
     cs.add<double>(count);             // obj
     cs.add<int64_t>(count);            // best index
     cs.add<float2>(LRQO_MAX_K);
@@ -476,7 +515,6 @@ lrqo_status lrqo_solve_batched(const float* V, int32_t count, const int64_t* v_o
     int32_t* d_items = cv.take<int32_t>(max_items);
     unsigned int* d_cursor = cv.take<unsigned int>(64);
     float* d_f = cv.take<float>((size_t)count * S);
-    unsigned long long* d_keys = cv.take<unsigned long long>((size_t)count * T);
     double* d_obj = cv.take<double>(count);
     int64_t* d_best = cv.take<int64_t>(count);
     float2* d_r32 = cv.take<float2>(LRQO_MAX_K);
@@ -522,7 +560,6 @@ lrqo_status lrqo_solve_batched(const float* V, int32_t count, const int64_t* v_o
     p.real = o.real_v;
     p.cursor = d_cursor;
     p.f = d_f;
-    p.keys = d_keys;
     p.obj = d_obj;
     p.best = d_best;
     p.z = d_z;
@@ -626,8 +663,7 @@ lrqo_status lrqo_solve_batched(const float* V, int32_t count, const int64_t* v_o
         LRQO_HIP(hipMemcpyAsync(d_items, h_items, sizeof(int32_t) * p.nitems, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_bfill, dim3(1), dim3(64), 0, s, d_cursor);
         launch_score(p, ls.cpl, blocks, s);
-        hipLaunchKernelGGL(k_batch_topk, dim3(count), dim3(kBlock), 0, s, p);
-        hipLaunchKernelGGL(k_batch_rescore, dim3(count), dim3(64), 0, s, p);
+        launch_select(p, s);
         LRQO_HIP(hipMemcpyAsync(h_obj, d_obj, sizeof(double) * count, hipMemcpyDeviceToHost, s));
         LRQO_HIP(hipMemcpyAsync(h_best, d_best, sizeof(int64_t) * count, hipMemcpyDeviceToHost, s));
         return LRQO_OK;

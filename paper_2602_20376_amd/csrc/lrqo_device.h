@@ -123,6 +123,42 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
+// ---------------------------------------------------------------- wave top-64
+// A wave holds a list of 64 packed keys, one per lane, lane l the l-th
+// largest.  wave_sort_desc sorts one key per lane (bitonic network over lane
+// shuffles); wave_top_union keeps the best 64 of two such lists (a
+// half-cleaner against the reversed second list, then a bitonic merge).
+__device__ __forceinline__ unsigned long long key_max(unsigned long long a, unsigned long long b) {
+    return a > b ? a : b;
+}
+__device__ __forceinline__ unsigned long long key_min(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+// One key per lane, returned sorted descending by lane.
+__device__ __forceinline__ unsigned long long wave_sort_desc(unsigned long long x, int lane) {
+    for (int k = 2; k <= 64; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned long long y = __shfl_xor(x, j, 64);
+            // in a descending run the lower lane of a pair keeps the larger key
+            const bool keep_max = ((lane & j) == 0) == ((lane & k) == 0);
+            x = keep_max ? key_max(x, y) : key_min(x, y);
+        }
+    }
+    return x;
+}
+
+// Best 64 of two descending lists (one key per lane), descending.
+__device__ __forceinline__ unsigned long long wave_top_union(unsigned long long a,
+                                                             unsigned long long b, int lane) {
+    unsigned long long x = key_max(a, __shfl(b, 63 - lane, 64));  // bitonic, holds the best 64
+    for (int j = 32; j > 0; j >>= 1) {
+        const unsigned long long y = __shfl_xor(x, j, 64);
+        x = (lane & j) == 0 ? key_max(x, y) : key_min(x, y);
+    }
+    return x;
+}
+
 // Packed arg-max key: objective bits above, complemented index below, so the
 // unsigned maximum is the largest objective and, among equal objectives, the
 // lowest index.  f >= 0, so its IEEE bits order like the values.
@@ -181,6 +217,47 @@ __device__ __forceinline__ void nearest_root(float wr, float wi, int K, const fl
     } else {
         const int k = label_f32_generic(wr, wi, K);
         const float2 t = roots[k];
+        zr = t.x;
+        zi = t.y;
+    }
+}
+
+// The same closed forms in FP64 for the rescore (any K through label_f64
+// and an FP64 root table).  Away from decision boundaries they agree with
+// label_f64; on a boundary (measure zero) either neighbour may be taken.
+template <int KS>
+__device__ __forceinline__ void nearest_root64(double wr, double wi, int K, const double2* roots,
+                                               double& zr, double& zi) {
+    if constexpr (KS == 2) {
+        zr = wr >= 0.0 ? 1.0 : -1.0;
+        zi = 0.0;
+    } else if constexpr (KS == 3) {
+        const bool k0 = fabs(wi) <= wr * 1.7320508075688772;
+        zr = k0 ? 1.0 : -0.5;
+        zi = k0 ? 0.0 : copysign(0.86602540378443865, wi);
+    } else if constexpr (KS == 4) {
+        const bool horiz = fabs(wr) >= fabs(wi);
+        zr = horiz ? copysign(1.0, wr) : 0.0;
+        zi = horiz ? 0.0 : copysign(1.0, wi);
+    } else if constexpr (KS == 8) {
+        const double ax = fabs(wr), ay = fabs(wi);
+        const double t = 0.41421356237309505;         // tan(pi/8)
+        const bool h = ay <= t * ax, v = ax <= t * ay;
+        const double d = 0.70710678118654752;
+        zr = copysign(h ? 1.0 : (v ? 0.0 : d), wr);
+        zi = copysign(h ? 0.0 : (v ? 1.0 : d), wi);
+    } else if constexpr (KS == 16) {
+        const double ax = fabs(wr), ay = fabs(wi);
+        const bool sw = ay > ax;
+        const double lo = sw ? ax : ay, hi = sw ? ay : ax;
+        const bool b1 = lo > 0.19891236737965800 * hi;  // tan(pi/16)
+        const bool b2 = lo > 0.66817863791929892 * hi;  // tan(3 pi/16)
+        const double cc = b2 ? 0.70710678118654752 : (b1 ? 0.92387953251128676 : 1.0);
+        const double ss = b2 ? 0.70710678118654752 : (b1 ? 0.38268343236508977 : 0.0);
+        zr = copysign(sw ? ss : cc, wr);
+        zi = copysign(sw ? cc : ss, wi);
+    } else {
+        const double2 t = roots[label_f64(wr, wi, K)];
         zr = t.x;
         zi = t.y;
     }

@@ -747,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ p
 }
 
 // ------------------------------------------------------------ FP64 rescore
-template <int R, bool REAL>
+template <int R, bool REAL, int KS>
 __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
     __shared__ double2 roots_s[LRQO_MAX_K];
     __shared__ double red[kBlock / kWave][2 * R];
@@ -776,13 +776,14 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
             wr += vr * c[2 * j] - vi * c[2 * j + 1];
             wi += vr * c[2 * j + 1] + vi * c[2 * j];
         }
-        const double2 z = roots_s[label_f64(wr, wi, p.K)];
+        double zr, zi;
+        nearest_root64<KS>(wr, wi, p.K, roots_s, zr, zi);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const double vr = REAL ? (double)row[j] : (double)row[2 * j];
             const double vi = REAL ? 0.0 : (double)row[2 * j + 1];
-            acc[2 * j] += vr * z.x + vi * z.y;
-            acc[2 * j + 1] += vr * z.y - vi * z.x;
+            acc[2 * j] += vr * zr + vi * zi;
+            acc[2 * j + 1] += vr * zi - vi * zr;
         }
     }
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -959,7 +960,15 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     rp.partial = sc.rescore;
     rp.rows_per_slice = sc.rescore_rows;
     rp.dirs = job.dirs;
-    hipLaunchKernelGGL((k_rescore<R, REAL>), dim3(T, sc.rescore_slices), dim3(kBlock), 0, st, rp);
+    const dim3 rgrid(T, sc.rescore_slices);
+    switch (k_special(job.K)) {
+        case 2: hipLaunchKernelGGL((k_rescore<R, REAL, 2>), rgrid, dim3(kBlock), 0, st, rp); break;
+        case 3: hipLaunchKernelGGL((k_rescore<R, REAL, 3>), rgrid, dim3(kBlock), 0, st, rp); break;
+        case 4: hipLaunchKernelGGL((k_rescore<R, REAL, 4>), rgrid, dim3(kBlock), 0, st, rp); break;
+        case 8: hipLaunchKernelGGL((k_rescore<R, REAL, 8>), rgrid, dim3(kBlock), 0, st, rp); break;
+        case 16: hipLaunchKernelGGL((k_rescore<R, REAL, 16>), rgrid, dim3(kBlock), 0, st, rp); break;
+        default: hipLaunchKernelGGL((k_rescore<R, REAL, 0>), rgrid, dim3(kBlock), 0, st, rp); break;
+    }
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_pick<R>), dim3(1), dim3(64 * 2 * R), 0, st, sc.rescore, T, sc.rescore_slices, keys,
                        job.seed, job.instance, job.first, job.dirs, sc.result);

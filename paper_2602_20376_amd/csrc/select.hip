@@ -18,37 +18,6 @@ constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 constexpr int kChunk = 2048;  // keys per block, kChunk / kWaves per wave
 
-__device__ __forceinline__ unsigned long long kmax(unsigned long long a, unsigned long long b) {
-    return a > b ? a : b;
-}
-__device__ __forceinline__ unsigned long long kmin(unsigned long long a, unsigned long long b) {
-    return a < b ? a : b;
-}
-
-// One key per lane, returned sorted descending by lane.
-__device__ __forceinline__ unsigned long long wave_sort_desc(unsigned long long x, int lane) {
-    for (int k = 2; k <= 64; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const unsigned long long y = __shfl_xor(x, j, 64);
-            // in a descending run the lower lane of a pair keeps the larger key
-            const bool keep_max = ((lane & j) == 0) == ((lane & k) == 0);
-            x = keep_max ? kmax(x, y) : kmin(x, y);
-        }
-    }
-    return x;
-}
-
-// Best 64 of two descending lists (one key per lane), descending.
-__device__ __forceinline__ unsigned long long wave_top_union(unsigned long long a,
-                                                             unsigned long long b, int lane) {
-    unsigned long long x = kmax(a, __shfl(b, 63 - lane, 64));  // bitonic, holds the best 64
-    for (int j = 32; j > 0; j >>= 1) {
-        const unsigned long long y = __shfl_xor(x, j, 64);
-        x = (lane & j) == 0 ? kmax(x, y) : kmin(x, y);
-    }
-    return x;
-}
-
 // Keys come from f (index = position) or from a previous pass.  Padding keys
 // are 0, below every real key (a real key's index is < 2^32-1, so its low
 // word is nonzero).
