@@ -91,7 +91,7 @@ def knee(f_in_order, ref: float, frac: float = 0.999):
 
 
 def train_default(K: int = 16, count: int = 10_000, label_S: int = 16_384, epochs: int = 30,
-                  batch: int = 128, lr: float = 2e-3, seed: int = 1, log=None):
+                  batch: int = 64, lr: float = 3e-3, seed: int = 1, log=None):
     """The proposal trained on `count` phase-synchronisation instances at
     n ~ log-uniform [2^10, 2^14], labelled by the plain sampler's best of
     label_S directions.  Returns (proposal, loss history, seconds by phase)."""

@@ -224,3 +224,21 @@ def test_maxcut_er_full_size(lrqo_mod):
     assert out.best_index == int(np.argmax(f32h)) or out.obj >= f32h.max() * (1 - 1e-5)
     part = lrqo_mod.solve_sampled(Vd, inst.K, 2048, inst.seed, real=True)
     check_result(inst.V, inst.K, 2048, inst.seed, part, real=True)
+
+
+def test_phase_sync_full_size(lrqo_mod):
+    """Workload: phase synchronisation n = 262,144, complex r = 3, K = 16,
+    S = 2^20 uniform directions.  The oracle scores the GPU's winner, 200
+    sampled directions plus the 16 best FP32 scores and the labels one by one,
+    and the full best-of-S on the first 2048 directions."""
+    inst = inputs.phase_sync()
+    Vd = _to_dev(inst.V, False)
+    f32 = torch.empty(inst.S, dtype=torch.float32, device="cuda")
+    out = lrqo_mod.solve_sampled(Vd, inst.K, inst.S, inst.seed, f_out=f32)
+    f32h = f32.cpu().numpy()
+    rng = np.random.default_rng(1)
+    sample = np.unique(np.concatenate([rng.choice(inst.S, 200, replace=False),
+                                       np.argsort(f32h)[-16:]]))
+    check_result(inst.V, inst.K, inst.S, inst.seed, out, f32=f32h, full_oracle=False, sample=sample)
+    part = lrqo_mod.solve_sampled(Vd, inst.K, 2048, inst.seed)
+    check_result(inst.V, inst.K, 2048, inst.seed, part)
