@@ -25,9 +25,6 @@
 #include "sampled_internal.h"
 #include "select.h"
 
-#ifndef LRQO_SCORE_MFMA
-#define LRQO_SCORE_MFMA 0
-#endif
 #ifndef LRQO_BF16_SPLIT
 #define LRQO_BF16_SPLIT 2
 #endif
@@ -162,20 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreParams p) {
 }
 
 // ------------------------------------------------------------ fused scorer, r <= 4
-// Per row (an LDS broadcast) each lane forms w = V_i c and the nearest root
-// z on the vector ALU for its CPL candidates and accumulates s += conj(V_i) z.
-// The accumulation has two implementations with the same register layout:
-// vector-ALU FMAs (default; fastest measured on real factors), or
-// v_mfma_f32_4x4x1f32 (16 independent 4x4x1 blocks per wave; block b holds
-// lanes 4b..4b+3, lane 4b+m supplies A_b[m], lane 4b+n supplies B_b[n], and
-// register m of lane 4b+n accumulates D_b[m][n] = sum_i A_b[m] B_b[n]; with
-// B = the lane's own z and A = component m of the row, register m of every
-// lane is a component of that lane's own s: no cross-lane reduction).
+// Per row every lane forms w = V_i c and the nearest root z on the vector
+// ALU for its CPL candidates and accumulates s += conj(V_i) z.  The four
+// waves of a block hold the same 64*CPL candidates and split the rows of the
+// block's slice; their partial sums are added through LDS at the end (fixed
+// order).  Rows reach the waves as LDS broadcasts of a staged row tile.
 typedef float v4f __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ v4f mfma4(float a, float b, v4f d) {
-    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, d, 0, 0, 0);
-}
 
 // K = 3 with the real part of w pre-scaled by sqrt(3): label 0 iff
 // |Im w| <= sqrt(3) Re w; otherwise the sign of Im w picks omega or omega^2.
@@ -185,58 +174,14 @@ __device__ __forceinline__ void nearest_root_k3s(float wr3, float wi, float& zr,
     zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
 }
 
-// Block = 4 waves holding the same 64*CPL candidates; wave w takes rows
-// w, w+4, w+8, ... of every LDS tile and the four partial sums are added
-// through LDS at the end (fixed order).
+// One row (values v, in registers or SGPRs) against the lane's candidates;
+// dr[q][j] / di[q][j] accumulate the real / imaginary part of s_j (for
+// complex r <= 2 the packed form keeps Re V and Im V products apart).
 template <int R, int CPL, bool REAL, int KS>
-__device__ __forceinline__ void score_row(const float* __restrict__ row, float a1, float a2,
-                                         const float (&c)[CPL][2 * R], const float (&c3)[CPL][2 * R],
-                                         int K, const float2* roots, v4f (&dr)[CPL], v4f (&di)[CPL]) {
-#if LRQO_SCORE_MFMA
-    constexpr int RF = Row<R, REAL>::F;
+__device__ __forceinline__ void score_vals(const float (&v)[Row<R, REAL>::F],
+                                          const float (&c)[CPL][2 * R], const float (&c3)[CPL][2 * R],
+                                          int K, const float2* roots, v4f (&dr)[CPL], v4f (&di)[CPL]) {
     constexpr bool PACK = !REAL && R <= 2;
-    float v[RF];
-#pragma unroll
-    for (int e = 0; e < RF; ++e) v[e] = row[e];
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-        float wr = 0.0f, wi = 0.0f;
-        if constexpr (REAL) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                wr = fmaf(v[j], c3[q][2 * j], wr);
-                wi = fmaf(v[j], c[q][2 * j + 1], wi);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const float vr = v[2 * j], vi = v[2 * j + 1];
-                wr = fmaf(vr, c3[q][2 * j], fmaf(-vi, c3[q][2 * j + 1], wr));
-                wi = fmaf(vr, c[q][2 * j + 1], fmaf(vi, c[q][2 * j], wi));
-            }
-        }
-        float zr, zi;
-        if constexpr (KS == 3) nearest_root_k3s(wr, wi, zr, zi);
-        else nearest_root<KS>(wr, wi, K, roots, zr, zi);
-        if constexpr (REAL || PACK) {
-            dr[q] = mfma4(a1, zr, dr[q]);
-            di[q] = mfma4(a1, zi, di[q]);
-        } else {
-            dr[q] = mfma4(a1, zr, dr[q]);
-            dr[q] = mfma4(a2, zi, dr[q]);
-            di[q] = mfma4(a1, zi, di[q]);
-            di[q] = mfma4(a2, -zr, di[q]);
-        }
-    }
-#else
-    // vector-ALU accumulation in the same register layout as the MFMA form:
-    // dr[q][m] / di[q][m] hold the components the MFMA form would hold
-    constexpr int RF = Row<R, REAL>::F;
-    constexpr bool PACK = !REAL && R <= 2;
-    (void)a1; (void)a2;
-    float v[RF];
-#pragma unroll
-    for (int e = 0; e < RF; ++e) v[e] = row[e];
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
         float wr = 0.0f, wi = 0.0f;
@@ -281,14 +226,23 @@ __device__ __forceinline__ void score_row(const float* __restrict__ row, float a
             }
         }
     }
-#endif
+}
+
+template <int R, int CPL, bool REAL, int KS>
+__device__ __forceinline__ void score_row(const float* __restrict__ row, const float (&c)[CPL][2 * R],
+                                         const float (&c3)[CPL][2 * R], int K, const float2* roots,
+                                         v4f (&dr)[CPL], v4f (&di)[CPL]) {
+    constexpr int RF = Row<R, REAL>::F;
+    float v[RF];
+#pragma unroll
+    for (int e = 0; e < RF; ++e) v[e] = row[e];
+    score_vals<R, CPL, REAL, KS>(v, c, c3, K, roots, dr, di);
 }
 
 template <int R, int CPL, bool REAL, int KS>
 __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
-    static_assert(R <= 4, "MFMA accumulation covers r <= 4");
+    static_assert(R <= 4, "the packed accumulators hold r <= 4");
     constexpr int RF = Row<R, REAL>::F;
-    // complex r <= 2 packs [Re V_0, Re V_1, Im V_0, Im V_1] into one A operand
     constexpr bool PACK = !REAL && R <= 2;
     constexpr int NW = kBlock / kWave;
     __shared__ __align__(16) float tile[kTile * RF];
@@ -297,20 +251,9 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int m = lane & 3;
     if constexpr (KS == 0) {
         for (int k = tid; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
-    }
-    // LDS offsets of this lane's A-operand elements within a row
-    int off1 = -1, off2 = -1;
-    if constexpr (REAL) {
-        off1 = m < R ? m : -1;
-    } else if constexpr (PACK) {
-        const int j = m & 1;                       // column
-        off1 = j < R ? 2 * j + (m >> 1) : -1;      // m = 0,1: Re V_j ; m = 2,3: Im V_j
-    } else {
-        off1 = m < R ? 2 * m : -1;                 // Re V_m
-        off2 = m < R ? 2 * m + 1 : -1;             // Im V_m
+        __syncthreads();
     }
 
     float c[CPL][2 * R], c3[CPL][2 * R];
@@ -342,18 +285,11 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
         __syncthreads();
         if (cnt == kTile) {
 #pragma unroll 4
-            for (int ii = 0; ii < kTile / NW; ++ii) {
-                const int i = wave + NW * ii;
-                const float a1 = off1 >= 0 ? tile[i * RF + off1] : 0.0f;
-                const float a2 = (!REAL && !PACK && off2 >= 0) ? tile[i * RF + off2] : 0.0f;
-                score_row<R, CPL, REAL, KS>(tile + i * RF, a1, a2, c, c3, p.K, roots_s, dr, di);
-            }
+            for (int ii = 0; ii < kTile / NW; ++ii)
+                score_row<R, CPL, REAL, KS>(tile + (wave + NW * ii) * RF, c, c3, p.K, roots_s, dr, di);
         } else {
-            for (int i = wave; i < cnt; i += NW) {
-                const float a1 = off1 >= 0 ? tile[i * RF + off1] : 0.0f;
-                const float a2 = (!REAL && !PACK && off2 >= 0) ? tile[i * RF + off2] : 0.0f;
-                score_row<R, CPL, REAL, KS>(tile + i * RF, a1, a2, c, c3, p.K, roots_s, dr, di);
-            }
+            for (int i = wave; i < cnt; i += NW)
+                score_row<R, CPL, REAL, KS>(tile + i * RF, c, c3, p.K, roots_s, dr, di);
         }
     }
 
@@ -364,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             if constexpr (PACK) {
-                // dr[m] = sum A_m zr, di[m] = sum A_m zi with A = [Re V_0, Re V_1, Im V_0, Im V_1]
+                // dr = [Re V zr, Im V zr], di = [Re V zi, Im V zi] per column
                 acc[q][2 * j] = dr[q][j] + di[q][2 + j];       // Re: Re V zr + Im V zi
                 acc[q][2 * j + 1] = di[q][j] - dr[q][2 + j];   // Im: Re V zi - Im V zr
             } else {
