@@ -259,6 +259,67 @@ lrqo_status lrqo_proposal_sample(lrqo_proposal* p, const float* V, int64_t n, in
  * doubles) = G (3x3 complex row-major, (re, im)) then the scale s. */
 lrqo_status lrqo_proposal_frame(lrqo_proposal* p, const float* V, int64_t n, double* frame_out);
 
+/* --------------------------------------------------------------------------
+ * Objective on the graph and greedy local refinement (the step after the
+ * low-rank solve: labels scored on the original sparse matrix and improved by
+ * single-vertex moves; appendix "Rank-1 at Scale", eq. incremental and the
+ * hybrid warm start).
+ *
+ * Graph on n vertices as a symmetric adjacency in CSR, all arrays device
+ * memory: row_ptr[n+1] (int64: row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz), col[nnz] (int32: 0 <= col < n, no self loop) and
+ * w[nnz] (FP64 edge weights, finite) or NULL for unit weights.  Every edge
+ * {i, j} must appear as (i, j) and (j, i) with equal weights (not checked).
+ * The matrix is the Laplacian Q = L = D - A, as for Max-K-Cut (Sec. 5), so
+ *     z^H L z = sum over edges {i, j} of w_ij |z_i - z_j|^2,
+ * and the cut weight is the sum of w_ij over edges whose ends carry
+ * different labels (for K = 3, z^H L z = 3 cut).  The CSR layout, the
+ * range of every index and every label of z (< K) are checked on the device
+ * before use; a violation returns LRQO_EINVAL.  n <= 2^31 - 1.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lrqo_graph {
+    const int64_t* row_ptr;  /* device [n + 1] */
+    const int32_t* col;      /* device [nnz] (may be NULL when nnz = 0) */
+    const double* w;         /* device [nnz] or NULL (unit weights) */
+    int64_t n;
+    int64_t nnz;
+} lrqo_graph;
+
+/* z^H L z and the cut weight of labels z (device uint8 [n], labels < K,
+ * 2 <= K <= 255), as FP64 host values; sums are taken in a fixed order. */
+lrqo_status lrqo_graph_objective(const lrqo_graph* g, int32_t K, const uint8_t* z, double* quad,
+                                 double* cut);
+
+/* Greedy local search on z^H L z from the labels in z (device uint8 [n],
+ * updated in place), 2 <= K <= 16.  One round: every vertex finds its best
+ * other label b (gain 2 sum_k c_k (cos(2 pi (a-k)/K) - cos(2 pi (b-k)/K)),
+ * c_k the weight of its neighbours with label k; ties to the lowest b), is a
+ * candidate when the gain exceeds 1e-12 of its weighted degree, and moves
+ * when its (gain, -index) beats that of every neighbouring candidate.  Moving
+ * vertices are pairwise non-adjacent, so each round raises z^H L z by the sum
+ * of their gains; rounds repeat until none moves (a single-vertex local
+ * optimum) or max_rounds have moved. */
+typedef struct lrqo_refine_options {
+    int32_t max_rounds;      /* rounds that move at least one vertex; 0: 1,000,000 */
+    int32_t check_every;     /* rounds launched between host checks, 1..64; 0: 8 */
+} lrqo_refine_options;
+
+typedef struct lrqo_refine_result {
+    double quad_before;      /* z^H L z of the input labels */
+    double quad_after;       /* z^H L z of the returned labels */
+    double cut_before;
+    double cut_after;
+    int64_t moves;           /* vertex moves over all rounds */
+    int32_t rounds;          /* rounds that moved at least one vertex */
+    int32_t converged;       /* 1: no vertex has a positive gain */
+    float device_ms;         /* device time of the rounds */
+    float pad;
+} lrqo_refine_result;
+
+lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z,
+                               const lrqo_refine_options* opt, lrqo_refine_result* res);
+
 #ifdef __cplusplus
 }
 #endif

@@ -138,6 +138,35 @@ def laplacian(n: int, i: np.ndarray, j: np.ndarray):
     return (sp.diags(deg) - A).tocsr()
 
 
+def csr_adjacency(n: int, i: np.ndarray, j: np.ndarray, w: np.ndarray | None = None):
+    """Symmetric adjacency of the undirected edges (i, j) (each once, i != j)
+    in the CSR layout of the library's graph calls: row_ptr (int64, n + 1),
+    col (int32), w (float64 or None); the entries of a row sorted by column."""
+    i = np.asarray(i, dtype=np.int64)
+    j = np.asarray(j, dtype=np.int64)
+    src = np.concatenate([i, j])
+    dst = np.concatenate([j, i])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
+    ww = None
+    if w is not None:
+        w = np.asarray(w, dtype=np.float64)
+        ww = np.concatenate([w, w])[order]
+    return row_ptr, dst.astype(np.int32), ww
+
+
+def random_edges(n: int, m: int, seed: int):
+    """m distinct undirected edges without self loops, uniform."""
+    rng = np.random.default_rng(seed)
+
+    def draw(k):
+        return rng.integers(0, n, k), rng.integers(0, n, k)
+
+    return _unique_pairs(rng, n, m, draw)
+
+
 def top_factor_sparse(L, r: int, seed: int) -> np.ndarray:
     """V = U diag(sqrt(lambda)) from the r largest eigenpairs of a PSD sparse
     matrix (FP64 Lanczos via ARPACK), columns in descending eigenvalue order."""
@@ -218,6 +247,12 @@ def maxcut_er(n: int = 100_000, mean_degree: float = 10.0, r: int = 4, K: int = 
     V32 = _cached(f"maxcut_er:{n}:{mean_degree}:{r}:{seed}:v1", build)
     return Instance(V32.astype(np.float64).astype(np.complex128), K, S, direction_seed(2), True,
                     f"maxcut_er(n={n},deg={mean_degree:g},r={r},K={K},S={S})")
+
+
+def maxcut_er_graph(n: int = 100_000, mean_degree: float = 10.0):
+    """The graph whose Laplacian gives the maxcut_er factor: its undirected
+    edges (i, j), same seed."""
+    return er_edges(n, mean_degree, instance_seed(2))
 
 
 def maxcut_ppm(n: int = 1_000_000, r: int = 3, K: int = 3, S: int = 1 << 20,

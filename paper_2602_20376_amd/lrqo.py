@@ -27,7 +27,7 @@ EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown"
            "lrqo_solve_exact_ex", "lrqo_solve_batched", "lrqo_proposal_param_count",
            "lrqo_proposal_create", "lrqo_proposal_destroy", "lrqo_proposal_get_state",
            "lrqo_proposal_set_state", "lrqo_proposal_train_step", "lrqo_proposal_sample",
-           "lrqo_proposal_frame")
+           "lrqo_proposal_frame", "lrqo_graph_objective", "lrqo_refine_greedy")
 
 
 class LrqoError(RuntimeError):
@@ -69,6 +69,23 @@ class BatchResult(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("items", ctypes.c_int32),
                 ("tuned_now", ctypes.c_int32), ("graph_captured_now", ctypes.c_int32),
                 ("row_candidates", ctypes.c_int64)]
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("nnz", ctypes.c_int64)]
+
+
+class RefineOptions(ctypes.Structure):
+    _fields_ = [("max_rounds", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class RefineResult(ctypes.Structure):
+    _fields_ = [("quad_before", ctypes.c_double), ("quad_after", ctypes.c_double),
+                ("cut_before", ctypes.c_double), ("cut_after", ctypes.c_double),
+                ("moves", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("device_ms", ctypes.c_float),
+                ("pad", ctypes.c_float)]
 
 
 _lib = None
@@ -119,6 +136,12 @@ def load(path: str = LIB_PATH):
     lib.lrqo_proposal_sample.argtypes = [vp, vp, i64, i64, u64, u32, ctypes.c_float, vp]
     lib.lrqo_proposal_sample.restype = i32
     lib.lrqo_proposal_frame.argtypes = [vp, vp, i64, vp]
+    lib.lrqo_graph_objective.restype = ctypes.c_int
+    lib.lrqo_graph_objective.argtypes = [ctypes.POINTER(Graph), i32, vp, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+    lib.lrqo_refine_greedy.restype = ctypes.c_int
+    lib.lrqo_refine_greedy.argtypes = [ctypes.POINTER(Graph), i32, vp, ctypes.POINTER(RefineOptions),
+                                       ctypes.POINTER(RefineResult)]
     lib.lrqo_proposal_frame.restype = i32
     _lib = lib
     return lib
@@ -363,3 +386,55 @@ class Proposal:
                                               out.ctypes.data_as(ctypes.c_void_p)))
         G = (out[0:18:2] + 1j * out[1:18:2]).reshape(3, 3)
         return G, float(out[18])
+
+
+def _graph(row_ptr, col, w):
+    """lrqo_graph of device tensors row_ptr (int64 [n+1]), col (int32
+    [nnz]) and w (float64 [nnz] or None)."""
+    import torch
+
+    if not (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.dim() == 1):
+        raise ValueError("row_ptr must be an int64 device vector")
+    if not (col.is_cuda and col.dtype == torch.int32 and col.dim() == 1):
+        raise ValueError("col must be an int32 device vector")
+    if w is not None and not (w.is_cuda and w.dtype == torch.float64 and w.shape == col.shape):
+        raise ValueError("w must be a float64 device vector shaped like col")
+    return Graph(ctypes.c_void_p(row_ptr.data_ptr()),
+                 ctypes.c_void_p(col.data_ptr() if col.numel() else 0),
+                 ctypes.c_void_p(w.data_ptr() if w is not None and w.numel() else 0),
+                 int(row_ptr.numel()) - 1, int(col.numel()))
+
+
+def graph_objective(row_ptr, col, w, K: int, z):
+    """(z^H L z, cut weight) of device labels z on the graph (see
+    lrqo_graph_objective)."""
+    import torch
+
+    lib = load()
+    g = _graph(row_ptr, col, w)
+    if not (z.is_cuda and z.dtype == torch.uint8 and z.numel() == g.n):
+        raise ValueError("z must be a uint8 device vector of n labels")
+    q, c = ctypes.c_double(), ctypes.c_double()
+    with torch.cuda.device(z.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_graph_objective(ctypes.byref(g), int(K), ctypes.c_void_p(z.data_ptr()),
+                                        ctypes.byref(q), ctypes.byref(c)))
+    return q.value, c.value
+
+
+def refine_greedy(row_ptr, col, w, K: int, z, *, max_rounds: int = 0, check_every: int = 0):
+    """Greedy local search on z^H L z, labels z updated in place (see
+    lrqo_refine_greedy).  Returns the RefineResult."""
+    import torch
+
+    lib = load()
+    g = _graph(row_ptr, col, w)
+    if not (z.is_cuda and z.dtype == torch.uint8 and z.numel() == g.n and z.is_contiguous()):
+        raise ValueError("z must be a contiguous uint8 device vector of n labels")
+    opt = RefineOptions(int(max_rounds), int(check_every))
+    res = RefineResult()
+    with torch.cuda.device(z.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_refine_greedy(ctypes.byref(g), int(K), ctypes.c_void_p(z.data_ptr()),
+                                      ctypes.byref(opt), ctypes.byref(res)))
+    return res
