@@ -39,7 +39,7 @@ def parse():
                     help="skip the precision / batched / learned-proposal measurements")
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
-    ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal"),
+    ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal", "refine"),
                     help="measure only this form and print its record (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized float32 device tensor once before timing "
@@ -144,6 +144,46 @@ def form_batched():
             "mean_obj": float(np.mean(out.obj))}
 
 
+def form_refine():
+    """The step after the path on maxcut_er: the sampled solve's labels
+    scored as a cut on the graph itself, then refined by the greedy local
+    search to a single-vertex local optimum (unit weights, K = 3)."""
+    import numpy as np
+    import torch
+
+    from paper_2602_20376_amd import inputs, lrqo
+
+    inst = inputs.maxcut_er()
+    i, j = inputs.maxcut_er_graph()
+    rp, col, _ = inputs.csr_adjacency(inst.n, i, j)
+    rpd, cold = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    V = torch.from_numpy(inputs.as_real_f32(inst.V)).cuda()
+    z0 = lrqo.solve_sampled(V, inst.K, inst.S, inst.seed, real=True).z
+    runs = []
+    for _ in range(3):
+        z = z0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = lrqo.refine_greedy(rpd, cold, None, inst.K, z)
+        torch.cuda.synchronize()
+        runs.append(((time.perf_counter() - t) * 1000.0, res))
+    wall, res = min(runs, key=lambda x: x[1].device_ms)
+    n, nnz = inst.n, int(col.size)
+    # algorithmic bytes of one round (gain + move kernels, unit weights):
+    # row_ptr twice, col twice, neighbour labels and gains gathered, own
+    # label / gain / target / next label
+    bytes_round = 16 * n + 4 * nnz + nnz + n + 8 * n + n + 8 * n + 4 * nnz + 8 * nnz + 3 * n
+    return {"workload": "maxcut_er graph", "n": n, "nnz": nnz, "K": inst.K,
+            "cut_sampled": res.cut_before, "cut_refined": res.cut_after,
+            "edges": nnz // 2, "cut_fraction_refined": res.cut_after / (nnz // 2),
+            "rounds": res.rounds, "moves": res.moves, "converged": bool(res.converged),
+            "device_ms": res.device_ms, "wall_ms": wall,
+            "launched_rounds": res.launched,
+            "us_per_round": 1000.0 * res.device_ms / max(1, res.launched),
+            "algorithmic_bytes_per_round": bytes_round,
+            "achieved_GBps": bytes_round * res.launched / (res.device_ms / 1000.0) / 1e9}
+
+
 def form_learned(train_count):
     """Learned proposal against uniform sampling on phase synchronisation
     (n = 262,144, r = 3, K = 16): samples needed to reach 99.9% of the best
@@ -194,7 +234,7 @@ def main():
     from paper_2602_20376_amd import inputs, lrqo
 
     if args.form:
-        fn = {"precision_bf16": form_precision, "batched": form_batched,
+        fn = {"precision_bf16": form_precision, "batched": form_batched, "refine": form_refine,
               "learned_proposal": lambda: form_learned(args.train_count)}[args.form]
         print(json.dumps({"form": args.form, **fn()}), flush=True)
         return
@@ -250,6 +290,7 @@ def main():
     if not args.no_forms:
         forms = {}
         for name, fn in (("precision_bf16", form_precision), ("batched", form_batched),
+                         ("refine", form_refine),
                          ("learned_proposal", lambda: form_learned(args.train_count))):
             print(f"bench: measuring {name}", file=sys.stderr, flush=True)
             try:

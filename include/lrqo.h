@@ -313,8 +313,8 @@ typedef struct lrqo_refine_result {
     int64_t moves;           /* vertex moves over all rounds */
     int32_t rounds;          /* rounds that moved at least one vertex */
     int32_t converged;       /* 1: no vertex has a positive gain */
-    float device_ms;         /* device time of the rounds */
-    float pad;
+    float device_ms;         /* device time of the launched rounds */
+    int32_t launched;        /* rounds launched (the last check interval may run past convergence) */
 } lrqo_refine_result;
 
 lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z,

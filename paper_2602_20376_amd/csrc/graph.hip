@@ -351,7 +351,7 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
     const double* cosd = s.table + LRQO_MAX_K;
     uint8_t* zbuf[2] = {z, s.zb};
     int cur = 0;
-    int64_t rounds = 0, moves = 0;
+    int64_t rounds = 0, moves = 0, launched = 0;
     bool converged = false;
     float total_ms = 0.0f;
     while (!converged && rounds < max_rounds) {
@@ -367,6 +367,7 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
         }
         LRQO_HIP(hipGetLastError());
         LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
+        launched += todo;
         LRQO_HIP(hipMemcpyAsync(h.moves, s.moves, sizeof(unsigned long long) * todo, hipMemcpyDeviceToHost, st));
         LRQO_HIP(hipStreamSynchronize(st));
         float ms = 0.0f;
@@ -388,6 +389,7 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
     r.rounds = (int32_t)rounds;
     r.converged = converged ? 1 : 0;
     r.device_ms = total_ms;
+    r.launched = (int32_t)launched;
     if (res) *res = r;
     return LRQO_OK;
 }

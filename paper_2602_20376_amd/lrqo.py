@@ -85,7 +85,7 @@ class RefineResult(ctypes.Structure):
                 ("cut_before", ctypes.c_double), ("cut_after", ctypes.c_double),
                 ("moves", ctypes.c_int64), ("rounds", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("device_ms", ctypes.c_float),
-                ("pad", ctypes.c_float)]
+                ("launched", ctypes.c_int32)]
 
 
 _lib = None
