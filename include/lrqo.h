@@ -260,6 +260,32 @@ lrqo_status lrqo_proposal_sample(lrqo_proposal* p, const float* V, int64_t n, in
 lrqo_status lrqo_proposal_frame(lrqo_proposal* p, const float* V, int64_t n, double* frame_out);
 
 /* --------------------------------------------------------------------------
+ * Exact rank-1 maximisation by the phase sweep (Sec. 2.5, Alg. 1,
+ * Thm. rank1): maximise |z^H q|^2 over z in A_K^n for one vector q (the
+ * rank-1 case of the problem; with q_i = v1_i + i v2_i built from two real
+ * eigenvectors this is the two-eigenvector rounding of the appendix
+ * "Rank-1 at Scale").
+ *
+ * q: device complex128 [n], interleaved (re, im); z: device uint8 [n] out.
+ * Boundary points phi_i = (2 pi/K)(1/2 + floor(x_i) - x_i), x_i =
+ * K arg(q_i)/(2 pi), are evaluated in FP64 with the operations in that order
+ * and sorted stably (equal points keep coordinate order); the n+1 cells are
+ * scored by FP64 prefix sums in a fixed order and the best cell wins (ties
+ * to the earlier cell).  1 <= n <= 2^31 - 1, 2 <= K <= 255.  A non-finite
+ * entry of q returns LRQO_ENOTFINITE.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lrqo_rank1_result {
+    double obj;              /* |z^H q|^2 of the returned labels (FP64, fixed-order sum) */
+    double sweep_obj;        /* the chosen cell's value from the sweep's prefix sums */
+    int64_t best_cell;       /* 0: assignment at phi = -pi/K; l: after the l-th boundary point */
+    float device_ms;
+    int32_t sort_passes;     /* 8-bit radix passes run (digits that differ between keys) */
+} lrqo_rank1_result;
+
+lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, lrqo_rank1_result* res);
+
+/* --------------------------------------------------------------------------
  * Objective on the graph and greedy local refinement (the step after the
  * low-rank solve: labels scored on the original sparse matrix and improved by
  * single-vertex moves; appendix "Rank-1 at Scale", eq. incremental and the

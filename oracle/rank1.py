@@ -31,3 +31,27 @@ def rank1_sweep(q: np.ndarray, K: int):
         if f > best:
             best, best_k = f, k.copy()
     return float(best), best_k.astype(np.uint8)
+
+
+def rank1_cells(q: np.ndarray, K: int):
+    """Objective of every cell of the sweep, in sweep order: f[0] is the
+    assignment at phi = -pi/K, f[l] the one after the l-th boundary point.
+    Returns (f, order, k0) with `order` the stable argsort of the boundary
+    points and k0 the starting labels."""
+    q = np.asarray(q, dtype=np.complex128).ravel()
+    theta = np.angle(q)
+    x = K * theta / (2.0 * np.pi)
+    phi = (2.0 * np.pi / K) * (0.5 + np.floor(x) - x)
+    order = np.argsort(phi, kind="stable")
+    k0 = np.mod(np.floor(x).astype(np.int64), K)
+    roots = np.exp(2j * np.pi * np.arange(K) / K)
+    k = k0.copy()
+    s = np.sum(np.conj(q) * roots[k])
+    f = np.empty(q.size + 1)
+    f[0] = abs(s) ** 2
+    for l, i in enumerate(order, start=1):
+        new = (k[i] + 1) % K
+        s += np.conj(q[i]) * (roots[new] - roots[k[i]])
+        k[i] = new
+        f[l] = abs(s) ** 2
+    return f, order, k0

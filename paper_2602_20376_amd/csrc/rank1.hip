@@ -1,0 +1,408 @@
+// Exact rank-1 maximisation by the phase sweep (Sec. 2.5, Alg. 1,
+// Thm. rank1): max |z^H q|^2 over z in A_K^n.
+//
+// Every coordinate changes its label once as the auxiliary angle phi sweeps
+// (-pi/K, pi/K]: at phi_i = (2 pi/K)(1/2 + floor(x_i) - x_i), x_i =
+// K arg(q_i)/(2 pi).  Starting from k_i = floor(x_i) mod K (the assignment
+// at phi = -pi/K), the n+1 cells of the sweep are the prefixes of the
+// boundary points in sorted order, and s = sum_i conj(q_i) omega^k_i moves
+// by d_i = conj(q_i)(omega^(k_i+1) - omega^k_i) at each of them, so the
+// objective of cell l is |s_0 + d_(1) + ... + d_(l)|^2.
+//
+// Kernels:
+//   k_r1_prep     per coordinate: phi (same FP64 expression as Alg. 1),
+//                 sortable key, k_0, d, block partials of s_0, finiteness,
+//                 OR / AND of the keys (digits that never change skip a pass)
+//   radix sort    stable by key (sort.hip): ties keep coordinate order
+//   k_r1_tiles    per tile of 2048 sorted positions: sum of d
+//   k_r1_tilepre  s_0 plus the tile sums before each tile (fixed order)
+//   k_r1_cells    per tile: running s through its positions, |s|^2 per cell,
+//                 best cell of the tile (ties to the earlier cell)
+//   k_r1_pick     best cell over the tiles and cell 0
+//   k_r1_labels   labels of the best cell: k_0 advanced by one for the
+//                 coordinates whose boundary comes at or before it
+//   k_r1_obj      FP64 |z^H q|^2 of the returned labels (block partials)
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lrqo_device.h"
+#include "lrqo_runtime.h"
+#include "sort.h"
+
+namespace lrqo {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 8;                  // sorted positions per thread in the cell scan
+constexpr int kTile = kBlock * kItems;     // 2048
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+__device__ __forceinline__ unsigned long long order_key(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// conj(q) * w
+__device__ __forceinline__ double2 cconj_mul(double2 q, double2 w) {
+    return make_double2(q.x * w.x + q.y * w.y, q.x * w.y - q.y * w.x);
+}
+
+// Fixed-order block sum of a complex value per thread.
+__device__ __forceinline__ double2 block_sum_c(double2 v) {
+    __shared__ double sx[kBlock], sy[kBlock];
+    sx[threadIdx.x] = v.x;
+    sy[threadIdx.x] = v.y;
+    __syncthreads();
+    for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sx[threadIdx.x] += sx[threadIdx.x + h];
+            sy[threadIdx.x] += sy[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    const double2 r = make_double2(sx[0], sy[0]);
+    __syncthreads();
+    return r;
+}
+
+struct R1Dev {
+    const double2* q;
+    int64_t n;
+    int K;
+    const double2* roots;            // [K]
+    unsigned long long* keys;
+    uint32_t* vals;
+    uint8_t* k0;
+    double2* d;
+    double2* part;                   // block partials
+    unsigned long long* key_or_and;  // [2]
+    int* flag;
+};
+
+__global__ __launch_bounds__(kBlock) void k_r1_prep(R1Dev p) {
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    double2 c0 = make_double2(0.0, 0.0);
+    unsigned long long key = 0;
+    bool live = i < p.n;
+    if (live) {
+        const double2 q = p.q[i];
+        if (!isfinite(q.x) || !isfinite(q.y)) atomicOr(p.flag, 1);
+        // the expressions of Alg. 1, rounded step by step as written
+        const double theta = atan2(q.y, q.x);
+        const double x = __ddiv_rn(__dmul_rn((double)p.K, theta), 2.0 * kPi);
+        const double fl = floor(x);
+        const double phi = __dmul_rn(__ddiv_rn(2.0 * kPi, (double)p.K), __dsub_rn(__dadd_rn(0.5, fl), x));
+        int k = (int)fmod(fl, (double)p.K);
+        k += k < 0 ? p.K : 0;
+        key = order_key(phi);
+        p.keys[i] = key;
+        p.vals[i] = (uint32_t)i;
+        p.k0[i] = (uint8_t)k;
+        const int k1 = k + 1 == p.K ? 0 : k + 1;
+        const double2 a = p.roots[k], b = p.roots[k1];
+        p.d[i] = cconj_mul(q, make_double2(b.x - a.x, b.y - a.y));
+        c0 = cconj_mul(q, a);
+    }
+    const unsigned long long wor = [&] {
+        unsigned long long v = live ? key : 0ull;
+        for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, kWave);
+        return v;
+    }();
+    const unsigned long long wand = [&] {
+        unsigned long long v = live ? key : ~0ull;
+        for (int off = 32; off > 0; off >>= 1) v &= __shfl_xor(v, off, kWave);
+        return v;
+    }();
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicOr(&p.key_or_and[0], wor);
+        atomicAnd(&p.key_or_and[1], wand);
+    }
+    const double2 s = block_sum_c(c0);
+    if (threadIdx.x == 0) p.part[blockIdx.x] = s;
+}
+
+// Fixed-order sum of `count` complex partials into out[0] (one block).
+__global__ __launch_bounds__(kBlock) void k_r1_sum(const double2* __restrict__ part, int64_t count,
+                                                   double2* __restrict__ out) {
+    double2 a = make_double2(0.0, 0.0);
+    for (int64_t t = threadIdx.x; t < count; t += kBlock) a = cadd(a, part[t]);
+    const double2 s = block_sum_c(a);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// Thread t of tile b owns sorted positions b*kTile + t*kItems .. + kItems-1.
+__global__ __launch_bounds__(kBlock) void k_r1_tiles(const double2* __restrict__ d, const uint32_t* __restrict__ order,
+                                                     int64_t n, double2* __restrict__ tile_sum) {
+    const int64_t p0 = blockIdx.x * (int64_t)kTile + (int64_t)threadIdx.x * kItems;
+    double2 a = make_double2(0.0, 0.0);
+    for (int e = 0; e < kItems; ++e)
+        if (p0 + e < n) a = cadd(a, d[order[p0 + e]]);
+    const double2 s = block_sum_c(a);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
+}
+
+// tile_pre[b] = s_0 + sum of tile_sum[0..b-1] (one block, sequential by
+// segments: each thread a contiguous run of tiles, thread 0 chains them).
+__global__ __launch_bounds__(kBlock) void k_r1_tilepre(const double2* __restrict__ tile_sum, int64_t tiles,
+                                                       const double2* __restrict__ s0,
+                                                       double2* __restrict__ tile_pre) {
+    __shared__ double2 seg[kBlock];
+    const int64_t per = (tiles + kBlock - 1) / kBlock;
+    const int64_t lo = threadIdx.x * per, hi = min(tiles, lo + per);
+    double2 a = make_double2(0.0, 0.0);
+    for (int64_t t = lo; t < hi; ++t) a = cadd(a, tile_sum[t]);
+    seg[threadIdx.x] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 run = s0[0];
+        for (int t = 0; t < kBlock; ++t) {
+            const double2 v = seg[t];
+            seg[t] = run;
+            run = cadd(run, v);
+        }
+    }
+    __syncthreads();
+    double2 run = seg[threadIdx.x];
+    for (int64_t t = lo; t < hi; ++t) {
+        tile_pre[t] = run;
+        run = cadd(run, tile_sum[t]);
+    }
+}
+
+struct Best {
+    double f;
+    int64_t cell;
+};
+
+__device__ __forceinline__ bool better(double f, int64_t c, double g, int64_t e) {
+    return f > g || (f == g && c < e);
+}
+
+__global__ __launch_bounds__(kBlock) void k_r1_cells(const double2* __restrict__ d, const uint32_t* __restrict__ order,
+                                                     int64_t n, const double2* __restrict__ tile_pre,
+                                                     Best* __restrict__ tile_best) {
+    __shared__ double2 tp[kBlock];
+    __shared__ double bf[kBlock];
+    __shared__ int64_t bc[kBlock];
+    const int64_t p0 = blockIdx.x * (int64_t)kTile + (int64_t)threadIdx.x * kItems;
+    double2 dv[kItems];
+    double2 a = make_double2(0.0, 0.0);
+    for (int e = 0; e < kItems; ++e) {
+        dv[e] = p0 + e < n ? d[order[p0 + e]] : make_double2(0.0, 0.0);
+        a = cadd(a, dv[e]);
+    }
+    // exclusive prefix of the thread sums in thread order (fixed order)
+    tp[threadIdx.x] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 run = tile_pre[blockIdx.x];
+        for (int t = 0; t < kBlock; ++t) {
+            const double2 v = tp[t];
+            tp[t] = run;
+            run = cadd(run, v);
+        }
+    }
+    __syncthreads();
+    double2 s = tp[threadIdx.x];
+    double best = -1.0;
+    int64_t cell = INT64_MAX;
+    for (int e = 0; e < kItems; ++e) {
+        if (p0 + e >= n) break;
+        s = cadd(s, dv[e]);
+        const double f = s.x * s.x + s.y * s.y;
+        if (f > best) {          // strict: ties keep the earlier cell
+            best = f;
+            cell = p0 + e + 1;   // cell l follows the l-th boundary point
+        }
+    }
+    bf[threadIdx.x] = best;
+    bc[threadIdx.x] = cell;
+    __syncthreads();
+    for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h && better(bf[threadIdx.x + h], bc[threadIdx.x + h], bf[threadIdx.x], bc[threadIdx.x])) {
+            bf[threadIdx.x] = bf[threadIdx.x + h];
+            bc[threadIdx.x] = bc[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_best[blockIdx.x] = Best{bf[0], bc[0]};
+}
+
+__global__ __launch_bounds__(kBlock) void k_r1_pick(const Best* __restrict__ tile_best, int64_t tiles,
+                                                    const double2* __restrict__ s0, Best* __restrict__ out) {
+    __shared__ double bf[kBlock];
+    __shared__ int64_t bc[kBlock];
+    double best = -1.0;
+    int64_t cell = INT64_MAX;
+    if (threadIdx.x == 0) {
+        best = s0[0].x * s0[0].x + s0[0].y * s0[0].y;
+        cell = 0;
+    }
+    for (int64_t t = threadIdx.x; t < tiles; t += kBlock)
+        if (better(tile_best[t].f, tile_best[t].cell, best, cell)) {
+            best = tile_best[t].f;
+            cell = tile_best[t].cell;
+        }
+    bf[threadIdx.x] = best;
+    bc[threadIdx.x] = cell;
+    __syncthreads();
+    for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h && better(bf[threadIdx.x + h], bc[threadIdx.x + h], bf[threadIdx.x], bc[threadIdx.x])) {
+            bf[threadIdx.x] = bf[threadIdx.x + h];
+            bc[threadIdx.x] = bc[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = Best{bf[0], bc[0]};
+}
+
+__global__ __launch_bounds__(kBlock) void k_r1_labels(const uint32_t* __restrict__ order, const uint8_t* __restrict__ k0,
+                                                      int64_t n, int K, const Best* __restrict__ best,
+                                                      uint8_t* __restrict__ z) {
+    const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t i = order[p];
+    int k = k0[i] + (p + 1 <= best->cell ? 1 : 0);
+    z[i] = (uint8_t)(k == K ? 0 : k);
+}
+
+__global__ __launch_bounds__(kBlock) void k_r1_obj(const double2* __restrict__ q, const uint8_t* __restrict__ z,
+                                                   int64_t n, const double2* __restrict__ roots,
+                                                   double2* __restrict__ part) {
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const double2 v = i < n ? cconj_mul(q[i], roots[z[i]]) : make_double2(0.0, 0.0);
+    const double2 s = block_sum_c(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+}  // namespace
+}  // namespace lrqo
+
+extern "C" {
+
+lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, lrqo_rank1_result* res) {
+    using namespace lrqo;
+    clear_error();
+    if (!q || !z) return fail(LRQO_EINVAL, "null pointer argument");
+    if (n < 1 || n > 0x7fffffffLL) return fail(LRQO_EINVAL, "n must be in [1, 2^31 - 1]");
+    if (K < 2 || K > LRQO_MAX_K) return fail(LRQO_EINVAL, "K must be in [2, 255]");
+    if (!is_device_pointer(q)) return fail(LRQO_EINVAL, "q is not device memory");
+    if (!is_device_pointer(z)) return fail(LRQO_EINVAL, "z is not device memory");
+    DeviceCtx* ctx = device_ctx();
+    if (!ctx) return LRQO_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const hipStream_t st = current_stream();
+
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    const int64_t nparts = std::max(blocks, tiles);
+    CarveSize cs;
+    cs.add<unsigned long long>(n);
+    cs.add<uint32_t>(n);
+    cs.add<unsigned long long>(n);
+    cs.add<uint32_t>(n);
+    cs.add<uint32_t>(radix_hist_entries(n));
+    cs.add<uint8_t>(n);
+    cs.add<double2>(n);
+    cs.add<double2>(nparts);
+    cs.add<double2>(tiles);
+    cs.add<double2>(tiles);
+    cs.add<Best>(tiles);
+    cs.add<Best>(1);
+    cs.add<double2>(4);
+    cs.add<double2>(LRQO_MAX_K);
+    cs.add<unsigned long long>(2);
+    cs.add<int>(4);
+    CarveSize hs;
+    hs.add<double2>(LRQO_MAX_K);
+    hs.add<unsigned long long>(2);
+    hs.add<int>(4);
+    hs.add<double2>(1);
+    hs.add<Best>(1);
+    LRQO_TRY(reserve_arena(ctx, cs.bytes));
+    LRQO_TRY(reserve_host(ctx, hs.bytes));
+    Carve cv(ctx->arena);
+    unsigned long long* keys = cv.take<unsigned long long>(n);
+    uint32_t* vals = cv.take<uint32_t>(n);
+    unsigned long long* keys_t = cv.take<unsigned long long>(n);
+    uint32_t* vals_t = cv.take<uint32_t>(n);
+    uint32_t* hist = cv.take<uint32_t>(radix_hist_entries(n));
+    uint8_t* k0 = cv.take<uint8_t>(n);
+    double2* d = cv.take<double2>(n);
+    double2* part = cv.take<double2>(nparts);
+    double2* tile_sum = cv.take<double2>(tiles);
+    double2* tile_pre = cv.take<double2>(tiles);
+    Best* tile_best = cv.take<Best>(tiles);
+    Best* best = cv.take<Best>(1);
+    double2* s0 = cv.take<double2>(4);
+    double2* roots = cv.take<double2>(LRQO_MAX_K);
+    unsigned long long* orand = cv.take<unsigned long long>(2);
+    int* flag = cv.take<int>(4);
+    Carve hv(ctx->host);
+    double2* h_roots = hv.take<double2>(LRQO_MAX_K);
+    unsigned long long* h_orand = hv.take<unsigned long long>(2);
+    int* h_flag = hv.take<int>(4);
+    double2* h_s = hv.take<double2>(1);
+    Best* h_best = hv.take<Best>(1);
+
+    // roots omega^k = exp(2 pi i k / K), argument (2 pi k)/K
+    for (int k = 0; k < K; ++k) {
+        const double a = (2.0 * kPi * (double)k) / (double)K;
+        h_roots[k] = make_double2(std::cos(a), std::sin(a));
+    }
+    h_orand[0] = 0ull;
+    h_orand[1] = ~0ull;
+    h_flag[0] = 0;
+    LRQO_HIP(hipEventRecord(ctx->ev_start, st));
+    LRQO_HIP(hipMemcpyAsync(roots, h_roots, sizeof(double2) * K, hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemcpyAsync(orand, h_orand, sizeof(unsigned long long) * 2, hipMemcpyHostToDevice, st));
+    LRQO_HIP(hipMemcpyAsync(flag, h_flag, sizeof(int), hipMemcpyHostToDevice, st));
+    R1Dev p{reinterpret_cast<const double2*>(q), n, K, roots, keys, vals, k0, d, part, orand, flag};
+    hipLaunchKernelGGL(k_r1_prep, dim3((unsigned)blocks), dim3(kBlock), 0, st, p);
+    hipLaunchKernelGGL(k_r1_sum, dim3(1), dim3(kBlock), 0, st, part, blocks, s0);
+    LRQO_HIP(hipGetLastError());
+    LRQO_HIP(hipMemcpyAsync(h_orand, orand, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipMemcpyAsync(h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipStreamSynchronize(st));
+    if (h_flag[0]) return fail(LRQO_ENOTFINITE, "q holds a NaN or an infinity");
+
+    unsigned mask = 0;
+    const unsigned long long varying = h_orand[0] ^ h_orand[1];
+    for (int dgt = 0; dgt < 8; ++dgt)
+        if ((varying >> (8 * dgt)) & 0xFFull) mask |= 1u << dgt;
+    bool in_tmp = false;
+    LRQO_TRY(radix_sort_pairs(keys, vals, keys_t, vals_t, hist, n, mask, st, &in_tmp));
+    const uint32_t* order = in_tmp ? vals_t : vals;
+
+    hipLaunchKernelGGL(k_r1_tiles, dim3((unsigned)tiles), dim3(kBlock), 0, st, d, order, n, tile_sum);
+    hipLaunchKernelGGL(k_r1_tilepre, dim3(1), dim3(kBlock), 0, st, tile_sum, tiles, s0, tile_pre);
+    hipLaunchKernelGGL(k_r1_cells, dim3((unsigned)tiles), dim3(kBlock), 0, st, d, order, n, tile_pre, tile_best);
+    hipLaunchKernelGGL(k_r1_pick, dim3(1), dim3(kBlock), 0, st, tile_best, tiles, s0, best);
+    hipLaunchKernelGGL(k_r1_labels, dim3((unsigned)blocks), dim3(kBlock), 0, st, order, k0, n, K, best, z);
+    hipLaunchKernelGGL(k_r1_obj, dim3((unsigned)blocks), dim3(kBlock), 0, st, p.q, z, n, roots, part);
+    hipLaunchKernelGGL(k_r1_sum, dim3(1), dim3(kBlock), 0, st, part, blocks, s0 + 1);
+    LRQO_HIP(hipGetLastError());
+    LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
+    LRQO_HIP(hipMemcpyAsync(h_s, s0 + 1, sizeof(double2), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipMemcpyAsync(h_best, best, sizeof(Best), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    LRQO_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    if (res) {
+        std::memset(res, 0, sizeof *res);
+        res->obj = h_s[0].x * h_s[0].x + h_s[0].y * h_s[0].y;
+        res->sweep_obj = h_best[0].f;
+        res->best_cell = h_best[0].cell;
+        res->device_ms = ms;
+        res->sort_passes = __builtin_popcount(mask);
+    }
+    return LRQO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits.
+//
+// Per pass (one 8-bit digit):
+//   k_digit_hist     per tile of 2048 pairs: digit counts -> hist[digit][tile]
+//   k_scan_u32       exclusive prefix of hist in digit-major, tile-minor
+//                    order: the first output slot of (digit, tile)
+//   k_digit_scatter  per tile: four waves take consecutive quarters; each
+//                    wave counts its digits, the waves' counts are offset
+//                    in wave order, then every wave walks its quarter in
+//                    64-pair steps: lanes holding the same digit are found
+//                    with eight ballots, a lane's slot is the digit's running
+//                    offset plus the number of such lanes below it, and the
+//                    lowest of them advances the offset.  Slots therefore
+//                    follow input order within a digit: the pass is stable.
+#include <algorithm>
+
+#include "lrqo_device.h"
+#include "lrqo_runtime.h"
+#include "sort.h"
+
+namespace lrqo {
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kBlock = kWaves * kWave;   // 256
+constexpr int kSteps = 8;                // 64-pair steps per wave
+constexpr int kTile = kWaves * kSteps * kWave;  // 2048 pairs per block
+constexpr int kBins = 256;
+constexpr int kScanBlock = 1024;
+static_assert(kBlock == kBins, "one thread per digit bin");
+
+__device__ __forceinline__ int digit_of(unsigned long long key, int shift) {
+    return (int)((key >> shift) & 0xFFull);
+}
+
+__global__ __launch_bounds__(kBlock) void k_digit_hist(const unsigned long long* __restrict__ keys,
+                                                       int64_t n, int shift, uint32_t* __restrict__ hist,
+                                                       int64_t tiles) {
+    __shared__ uint32_t h[kBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = blockIdx.x * (int64_t)kTile;
+    for (int e = threadIdx.x; e < kTile; e += kBlock) {
+        const int64_t idx = base + e;
+        if (idx < n) atomicAdd(&h[digit_of(keys[idx], shift)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive prefix sum of count entries in place, one block: each thread
+// sums a contiguous segment, thread 0 scans the segment totals, each thread
+// writes its segment.
+__global__ __launch_bounds__(kScanBlock) void k_scan_u32(uint32_t* __restrict__ a, int64_t count) {
+    __shared__ uint32_t seg[kScanBlock];
+    const int64_t per = (count + kScanBlock - 1) / kScanBlock;
+    const int64_t lo = threadIdx.x * per, hi = min(count, lo + per);
+    uint32_t s = 0;
+    for (int64_t e = lo; e < hi; ++e) s += a[e];
+    seg[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int t = 0; t < kScanBlock; ++t) {
+            const uint32_t v = seg[t];
+            seg[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    uint32_t run = seg[threadIdx.x];
+    for (int64_t e = lo; e < hi; ++e) {
+        const uint32_t v = a[e];
+        a[e] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long long* __restrict__ keys_in,
+                                                          const uint32_t* __restrict__ vals_in,
+                                                          unsigned long long* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out, int64_t n,
+                                                          int shift, const uint32_t* __restrict__ offs,
+                                                          int64_t tiles) {
+    __shared__ uint32_t cnt[kWaves][kBins];
+    __shared__ uint32_t base[kWaves][kBins];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    for (int v = 0; v < kWaves; ++v) cnt[v][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t chunk = blockIdx.x * (int64_t)kTile + (int64_t)w * (kSteps * kWave);
+    for (int t = 0; t < kSteps; ++t) {
+        const int64_t idx = chunk + t * kWave + lane;
+        if (idx < n) atomicAdd(&cnt[w][digit_of(keys_in[idx], shift)], 1u);
+    }
+    __syncthreads();
+    {
+        uint32_t run = offs[(int64_t)threadIdx.x * tiles + blockIdx.x];
+        for (int v = 0; v < kWaves; ++v) {
+            base[v][threadIdx.x] = run;
+            run += cnt[v][threadIdx.x];
+        }
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int t = 0; t < kSteps; ++t) {
+        const int64_t idx = chunk + t * kWave + lane;
+        const bool valid = idx < n;
+        const unsigned long long key = valid ? keys_in[idx] : 0ull;
+        const uint32_t val = valid ? vals_in[idx] : 0u;
+        const int d = digit_of(key, shift);
+        unsigned long long match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const unsigned long long m = __ballot(bit);
+            match &= bit ? m : ~m;
+        }
+        const uint32_t lower = (uint32_t)__popcll(match & below);
+        const uint32_t slot = base[w][d] + lower;   // every lane reads before the update below
+        if (valid) {
+            keys_out[slot] = key;
+            vals_out[slot] = val;
+        }
+        if (valid && lower == 0) base[w][d] += (uint32_t)__popcll(match);
+        __builtin_amdgcn_wave_barrier();  // the next step's reads stay after this update
+    }
+}
+
+}  // namespace
+
+size_t radix_hist_entries(int64_t n) {
+    return (size_t)kBins * (size_t)((n + kTile - 1) / kTile);
+}
+
+lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp,
+                             uint32_t* vals_tmp, uint32_t* hist, int64_t n, unsigned digit_mask,
+                             hipStream_t st, bool* in_tmp) {
+    const int64_t tiles = (n + kTile - 1) / kTile;
+    unsigned long long* kin = keys;
+    uint32_t* vin = vals;
+    unsigned long long* kout = keys_tmp;
+    uint32_t* vout = vals_tmp;
+    bool tmp = false;
+    for (int d = 0; d < 8; ++d) {
+        if (!((digit_mask >> d) & 1u)) continue;
+        const int shift = 8 * d;
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, st, hist, (int64_t)kBins * tiles);
+        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
+                           shift, hist, tiles);
+        LRQO_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        tmp = !tmp;
+    }
+    *in_tmp = tmp;
+    return LRQO_OK;
+}
+
+}  // namespace lrqo

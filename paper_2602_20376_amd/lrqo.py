@@ -27,7 +27,8 @@ EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown"
            "lrqo_solve_exact_ex", "lrqo_solve_batched", "lrqo_proposal_param_count",
            "lrqo_proposal_create", "lrqo_proposal_destroy", "lrqo_proposal_get_state",
            "lrqo_proposal_set_state", "lrqo_proposal_train_step", "lrqo_proposal_sample",
-           "lrqo_proposal_frame", "lrqo_graph_objective", "lrqo_refine_greedy")
+           "lrqo_proposal_frame", "lrqo_solve_rank1", "lrqo_graph_objective",
+           "lrqo_refine_greedy")
 
 
 class LrqoError(RuntimeError):
@@ -69,6 +70,12 @@ class BatchResult(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("items", ctypes.c_int32),
                 ("tuned_now", ctypes.c_int32), ("graph_captured_now", ctypes.c_int32),
                 ("row_candidates", ctypes.c_int64)]
+
+
+class Rank1Result(ctypes.Structure):
+    _fields_ = [("obj", ctypes.c_double), ("sweep_obj", ctypes.c_double),
+                ("best_cell", ctypes.c_int64), ("device_ms", ctypes.c_float),
+                ("sort_passes", ctypes.c_int32)]
 
 
 class Graph(ctypes.Structure):
@@ -136,6 +143,8 @@ def load(path: str = LIB_PATH):
     lib.lrqo_proposal_sample.argtypes = [vp, vp, i64, i64, u64, u32, ctypes.c_float, vp]
     lib.lrqo_proposal_sample.restype = i32
     lib.lrqo_proposal_frame.argtypes = [vp, vp, i64, vp]
+    lib.lrqo_solve_rank1.restype = i32
+    lib.lrqo_solve_rank1.argtypes = [vp, i64, i32, vp, ctypes.POINTER(Rank1Result)]
     lib.lrqo_graph_objective.restype = ctypes.c_int
     lib.lrqo_graph_objective.argtypes = [ctypes.POINTER(Graph), i32, vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
@@ -386,6 +395,26 @@ class Proposal:
                                               out.ctypes.data_as(ctypes.c_void_p)))
         G = (out[0:18:2] + 1j * out[1:18:2]).reshape(3, 3)
         return G, float(out[18])
+
+
+def solve_rank1(q, K: int, *, z=None):
+    """Exact rank-1 sweep (see lrqo_solve_rank1).  q: complex128 (n,) device
+    tensor.  Returns (labels, Rank1Result)."""
+    import torch
+
+    lib = load()
+    if not (q.is_cuda and q.dtype == torch.complex128 and q.dim() == 1):
+        raise ValueError("q must be a complex128 (n,) device tensor")
+    qc = torch.view_as_real(q.contiguous()).contiguous()
+    n = int(q.numel())
+    if z is None:
+        z = torch.empty(n, dtype=torch.uint8, device=q.device)
+    res = Rank1Result()
+    with torch.cuda.device(q.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_solve_rank1(ctypes.c_void_p(qc.data_ptr()), n, int(K), ctypes.c_void_p(z.data_ptr()),
+                                    ctypes.byref(res)))
+    return z, res
 
 
 def _graph(row_ptr, col, w):
