@@ -39,7 +39,8 @@ def parse():
                     help="skip the precision / batched / learned-proposal measurements")
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
-    ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal", "refine"),
+    ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal", "refine",
+                                       "rank1_hybrid"),
                     help="measure only this form and print its record (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized float32 device tensor once before timing "
@@ -184,6 +185,44 @@ def form_refine():
             "achieved_GBps": bytes_round * res.launched / (res.device_ms / 1000.0) / 1e9}
 
 
+def form_rank1_hybrid():
+    """Rank-1 at scale on the 3-block planted partition (n = 10^6, K = 3):
+    the exact phase sweep of q = v1 + i v2 (two leading Laplacian
+    eigenvectors), its cut on the graph, and the greedy refinement from it
+    (the hybrid warm start); the sampled rank-3 solve's cut beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2602_20376_amd import inputs, lrqo
+
+    inst = inputs.maxcut_ppm()
+    V = inst.V.real
+    q = V[:, 0] / np.linalg.norm(V[:, 0]) + 1j * V[:, 1] / np.linalg.norm(V[:, 1])
+    qd = torch.from_numpy(q).cuda()
+    lrqo.solve_rank1(qd, inst.K)
+    runs = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        z, res = lrqo.solve_rank1(qd, inst.K)
+        torch.cuda.synchronize()
+        runs.append(((time.perf_counter() - t) * 1000.0, res.device_ms))
+    i, j = inputs.maxcut_ppm_graph()
+    rp, col, _ = inputs.csr_adjacency(inst.n, i, j)
+    rpd, cold = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    ref = lrqo.refine_greedy(rpd, cold, None, inst.K, z)
+    Vd = torch.from_numpy(inputs.as_real_f32(inst.V)).cuda()
+    zs = lrqo.solve_sampled(Vd, inst.K, inst.S, inst.seed, real=True).z
+    _, cut_sampled = lrqo.graph_objective(rpd, cold, None, inst.K, zs)
+    return {"workload": "maxcut_ppm", "n": inst.n, "K": inst.K, "edges": int(len(i)),
+            "rank1_ms": min(r[0] for r in runs), "rank1_device_ms": min(r[1] for r in runs),
+            "rank1_cells_per_s": (inst.n + 1) / (min(r[1] for r in runs) / 1000.0),
+            "rank1_obj": res.obj, "rank1_sort_passes": res.sort_passes,
+            "cut_rank1": ref.cut_before, "cut_rank1_refined": ref.cut_after,
+            "refine_rounds": ref.rounds, "refine_device_ms": ref.device_ms,
+            "cut_sampled_rank3": cut_sampled}
+
+
 def form_learned(train_count):
     """Learned proposal against uniform sampling on phase synchronisation
     (n = 262,144, r = 3, K = 16): samples needed to reach 99.9% of the best
@@ -235,6 +274,7 @@ def main():
 
     if args.form:
         fn = {"precision_bf16": form_precision, "batched": form_batched, "refine": form_refine,
+              "rank1_hybrid": form_rank1_hybrid,
               "learned_proposal": lambda: form_learned(args.train_count)}[args.form]
         print(json.dumps({"form": args.form, **fn()}), flush=True)
         return
@@ -290,7 +330,7 @@ def main():
     if not args.no_forms:
         forms = {}
         for name, fn in (("precision_bf16", form_precision), ("batched", form_batched),
-                         ("refine", form_refine),
+                         ("refine", form_refine), ("rank1_hybrid", form_rank1_hybrid),
                          ("learned_proposal", lambda: form_learned(args.train_count))):
             print(f"bench: measuring {name}", file=sys.stderr, flush=True)
             try:

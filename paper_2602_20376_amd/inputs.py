@@ -269,6 +269,12 @@ def maxcut_ppm(n: int = 1_000_000, r: int = 3, K: int = 3, S: int = 1 << 20,
                     f"maxcut_ppm(n={n},r={r},K={K},S={S})")
 
 
+def maxcut_ppm_graph(n: int = 1_000_000, c_in: float = 8.0, c_out: float = 2.0):
+    """The graph whose Laplacian gives the maxcut_ppm factor: its undirected
+    edges (i, j), same seed."""
+    return planted_partition_edges(n, c_in / n, c_out / n, instance_seed(3))
+
+
 def psk_instance(rng: np.random.Generator, n: int, r: int) -> np.ndarray:
     """One PSK-detection-shaped factor (complex, FP32-representable)."""
     H = complex_gaussian(rng, (r, n))
