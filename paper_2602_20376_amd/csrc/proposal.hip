@@ -559,19 +559,37 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bwd(const float* __restrict__ V,
 
 // grad[p] = (1/B) * (sum over row items of the MLP partials + sum over
 // instances of the head partials), fixed order.
-__global__ void k_grad_reduce(const float* __restrict__ mlp_partial, int nitems,
-                              const float* __restrict__ head_partial, int count,
-                              float* __restrict__ grad) {
+// Gradient = (sum of the row-tile partials of the MLP parameters, sum of
+// the per-instance head partials) / count, in two fixed-order levels:
+// chunk c of the partials -> gpart[c][p], then the chunks in order.
+constexpr int kGradChunks = 64;
+
+__global__ void k_grad_partial(const float* __restrict__ mlp_partial, int nitems,
+                               const float* __restrict__ head_partial, int count,
+                               float* __restrict__ gpart) {
     constexpr int NG = H * DIN + H + H * H + H;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
     if (p >= NP) return;
     float a = 0.0f;
     if (p < NG) {
-        for (int it = 0; it < nitems; ++it) a += mlp_partial[(size_t)it * NG + p];
+        const int per = (nitems + kGradChunks - 1) / kGradChunks;
+        const int lo = c * per, hi = min(nitems, lo + per);
+        for (int it = lo; it < hi; ++it) a += mlp_partial[(size_t)it * NG + p];
     } else {
         const int q = p - NG;
-        for (int t = 0; t < count; ++t) a += head_partial[(size_t)t * (OUT * H + OUT) + q];
+        const int per = (count + kGradChunks - 1) / kGradChunks;
+        const int lo = c * per, hi = min(count, lo + per);
+        for (int t = lo; t < hi; ++t) a += head_partial[(size_t)t * (OUT * H + OUT) + q];
     }
+    gpart[(size_t)c * NP + p] = a;
+}
+
+__global__ void k_grad_reduce(const float* __restrict__ gpart, int count, float* __restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NP) return;
+    float a = 0.0f;
+    for (int c = 0; c < kGradChunks; ++c) a += gpart[(size_t)c * NP + p];
     grad[p] = a / (float)count;
 }
 
@@ -903,6 +921,7 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     cs.add<float>(count);                    // loss
     cs.add<float>((size_t)count * (OUT * H + OUT));
     cs.add<float>(bp.inst.size() * NG);
+    cs.add<float>((size_t)kGradChunks * NP);
     LRQO_TRY(ensure_scratch(P, cs.bytes));
     Carve cv(P->scratch);
     FwdBufs b{};
@@ -920,6 +939,7 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     float* loss = cv.take<float>(count);
     float* headp = cv.take<float>((size_t)count * (OUT * H + OUT));
     float* mlpp = cv.take<float>(bp.inst.size() * NG);
+    float* gpart = cv.take<float>((size_t)kGradChunks * NP);
     hipStream_t st = current_stream();
     LRQO_TRY(run_embed(P, V, count, v_offset, n, fp, b, st));
     LRQO_HIP(hipMemcpyAsync(tin, targets, sizeof(float) * count * 6, hipMemcpyHostToDevice, st));
@@ -932,8 +952,9 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)bp.inst.size()), dim3(kBlock), 0, st, V, b.voff, b.n, b.frames,
                        P->theta, dm, items, mlpp);
     LRQO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_grad_reduce, dim3((NP + 255) / 256), dim3(256), 0, st, mlpp, (int)bp.inst.size(), headp,
-                       count, P->grad);
+    hipLaunchKernelGGL(k_grad_partial, dim3((NP + 255) / 256, kGradChunks), dim3(256), 0, st, mlpp,
+                       (int)bp.inst.size(), headp, count, gpart);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((NP + 255) / 256), dim3(256), 0, st, gpart, count, P->grad);
     LRQO_HIP(hipGetLastError());
     if (update) {
         P->step += 1;

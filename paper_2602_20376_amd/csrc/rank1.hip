@@ -11,8 +11,9 @@
 //
 // Kernels:
 //   k_r1_prep     per coordinate: phi (same FP64 expression as Alg. 1),
-//                 sortable key, k_0, d, block partials of s_0, finiteness,
-//                 OR / AND of the keys (digits that never change skip a pass)
+//                 sortable key, k_0, d, block partials of s_0 and of the
+//                 OR / AND of the keys (digits that never change skip a
+//                 pass), finiteness
 //   radix sort    stable by key (sort.hip): ties keep coordinate order
 //   k_r1_tiles    per tile of 2048 sorted positions: sum of d
 //   k_r1_tilepre  s_0 plus the tile sums before each tile (fixed order)
@@ -81,7 +82,7 @@ struct R1Dev {
     uint8_t* k0;
     double2* d;
     double2* part;                   // block partials
-    unsigned long long* key_or_and;  // [2]
+    unsigned long long* orand_part;  // [2 * blocks]: OR, AND of the keys per block
     int* flag;
 };
 
@@ -119,12 +120,44 @@ __global__ __launch_bounds__(kBlock) void k_r1_prep(R1Dev p) {
         for (int off = 32; off > 0; off >>= 1) v &= __shfl_xor(v, off, kWave);
         return v;
     }();
+    __shared__ unsigned long long wo[kBlock / kWave], wa[kBlock / kWave];
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        atomicOr(&p.key_or_and[0], wor);
-        atomicAnd(&p.key_or_and[1], wand);
+        wo[threadIdx.x / kWave] = wor;
+        wa[threadIdx.x / kWave] = wand;
     }
-    const double2 s = block_sum_c(c0);
-    if (threadIdx.x == 0) p.part[blockIdx.x] = s;
+    const double2 s = block_sum_c(c0);   // synchronises the block
+    if (threadIdx.x == 0) {
+        p.part[blockIdx.x] = s;
+        unsigned long long o = 0ull, a = ~0ull;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            o |= wo[w];
+            a &= wa[w];
+        }
+        p.orand_part[2 * blockIdx.x] = o;
+        p.orand_part[2 * blockIdx.x + 1] = a;
+    }
+}
+
+// OR and AND over the block partials (one block).
+__global__ __launch_bounds__(kBlock) void k_r1_orand(const unsigned long long* __restrict__ part, int64_t blocks,
+                                                     unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long so[kBlock], sa[kBlock];
+    unsigned long long o = 0ull, a = ~0ull;
+    for (int64_t t = threadIdx.x; t < blocks; t += kBlock) {
+        o |= part[2 * t];
+        a &= part[2 * t + 1];
+    }
+    so[threadIdx.x] = o;
+    sa[threadIdx.x] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int t = 1; t < kBlock; ++t) {
+            o |= so[t];
+            a &= sa[t];
+        }
+        out[0] = o;
+        out[1] = a;
+    }
 }
 
 // Fixed-order sum of `count` complex partials into out[0] (one block).
@@ -318,6 +351,7 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     cs.add<double2>(4);
     cs.add<double2>(LRQO_MAX_K);
     cs.add<unsigned long long>(2);
+    cs.add<unsigned long long>(2 * blocks);
     cs.add<int>(4);
     CarveSize hs;
     hs.add<double2>(LRQO_MAX_K);
@@ -343,6 +377,7 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     double2* s0 = cv.take<double2>(4);
     double2* roots = cv.take<double2>(LRQO_MAX_K);
     unsigned long long* orand = cv.take<unsigned long long>(2);
+    unsigned long long* orand_part = cv.take<unsigned long long>(2 * blocks);
     int* flag = cv.take<int>(4);
     Carve hv(ctx->host);
     double2* h_roots = hv.take<double2>(LRQO_MAX_K);
@@ -356,16 +391,14 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
         const double a = (2.0 * kPi * (double)k) / (double)K;
         h_roots[k] = make_double2(std::cos(a), std::sin(a));
     }
-    h_orand[0] = 0ull;
-    h_orand[1] = ~0ull;
     h_flag[0] = 0;
     LRQO_HIP(hipEventRecord(ctx->ev_start, st));
     LRQO_HIP(hipMemcpyAsync(roots, h_roots, sizeof(double2) * K, hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(orand, h_orand, sizeof(unsigned long long) * 2, hipMemcpyHostToDevice, st));
     LRQO_HIP(hipMemcpyAsync(flag, h_flag, sizeof(int), hipMemcpyHostToDevice, st));
-    R1Dev p{reinterpret_cast<const double2*>(q), n, K, roots, keys, vals, k0, d, part, orand, flag};
+    R1Dev p{reinterpret_cast<const double2*>(q), n, K, roots, keys, vals, k0, d, part, orand_part, flag};
     hipLaunchKernelGGL(k_r1_prep, dim3((unsigned)blocks), dim3(kBlock), 0, st, p);
     hipLaunchKernelGGL(k_r1_sum, dim3(1), dim3(kBlock), 0, st, part, blocks, s0);
+    hipLaunchKernelGGL(k_r1_orand, dim3(1), dim3(kBlock), 0, st, orand_part, blocks, orand);
     LRQO_HIP(hipGetLastError());
     LRQO_HIP(hipMemcpyAsync(h_orand, orand, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, st));
     LRQO_HIP(hipMemcpyAsync(h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

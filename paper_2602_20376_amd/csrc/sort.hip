@@ -1,9 +1,10 @@
 // Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits.
 //
 // Per pass (one 8-bit digit):
-//   k_digit_hist     per tile of 2048 pairs: digit counts -> hist[digit][tile]
-//   k_scan_u32       exclusive prefix of hist in digit-major, tile-minor
-//                    order: the first output slot of (digit, tile)
+//   k_digit_hist     per tile of 2048 pairs: digit counts -> hist[digit][tile],
+//                    and the digit totals
+//   k_scan_rows      one block per digit: the first output slot of (digit,
+//                    tile) = totals of the lower digits + prefix along the row
 //   k_digit_scatter  per tile: four waves take consecutive quarters; each
 //                    wave counts its digits, the waves' counts are offset
 //                    in wave order, then every wave walks its quarter in
@@ -36,7 +37,7 @@ __device__ __forceinline__ int digit_of(unsigned long long key, int shift) {
 
 __global__ __launch_bounds__(kBlock) void k_digit_hist(const unsigned long long* __restrict__ keys,
                                                        int64_t n, int shift, uint32_t* __restrict__ hist,
-                                                       int64_t tiles) {
+                                                       int64_t tiles, uint32_t* __restrict__ totals) {
     __shared__ uint32_t h[kBins];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -47,33 +48,44 @@ __global__ __launch_bounds__(kBlock) void k_digit_hist(const unsigned long long*
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+    if (h[threadIdx.x]) atomicAdd(&totals[threadIdx.x], h[threadIdx.x]);
 }
 
-// Exclusive prefix sum of count entries in place, one block: each thread
-// sums a contiguous segment, thread 0 scans the segment totals, each thread
-// writes its segment.
-__global__ __launch_bounds__(kScanBlock) void k_scan_u32(uint32_t* __restrict__ a, int64_t count) {
-    __shared__ uint32_t seg[kScanBlock];
-    const int64_t per = (count + kScanBlock - 1) / kScanBlock;
-    const int64_t lo = threadIdx.x * per, hi = min(count, lo + per);
-    uint32_t s = 0;
-    for (int64_t e = lo; e < hi; ++e) s += a[e];
-    seg[threadIdx.x] = s;
-    __syncthreads();
+__global__ void k_zero_u32(uint32_t* __restrict__ a, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) a[i] = 0u;
+}
+
+// Block d turns row d of hist (one count per tile) into first output slots:
+// (sum of the totals of the digits below d) + exclusive prefix along the row.
+__global__ __launch_bounds__(kScanBlock) void k_scan_rows(uint32_t* __restrict__ hist, int64_t tiles,
+                                                         const uint32_t* __restrict__ totals) {
+    __shared__ uint32_t buf[kScanBlock];
+    __shared__ uint32_t carry;
+    const int d = blockIdx.x;
     if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int t = 0; t < kScanBlock; ++t) {
-            const uint32_t v = seg[t];
-            seg[t] = run;
-            run += v;
-        }
+        uint32_t b = 0;
+        for (int e = 0; e < d; ++e) b += totals[e];
+        carry = b;
     }
-    __syncthreads();
-    uint32_t run = seg[threadIdx.x];
-    for (int64_t e = lo; e < hi; ++e) {
-        const uint32_t v = a[e];
-        a[e] = run;
-        run += v;
+    uint32_t* row = hist + (int64_t)d * tiles;
+    for (int64_t c0 = 0; c0 < tiles; c0 += kScanBlock) {
+        const int64_t t = c0 + threadIdx.x;
+        const uint32_t v = t < tiles ? row[t] : 0u;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        // inclusive scan in LDS (Hillis-Steele)
+        for (int off = 1; off < kScanBlock; off <<= 1) {
+            const uint32_t add = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+            __syncthreads();
+            buf[threadIdx.x] += add;
+            __syncthreads();
+        }
+        const uint32_t base = carry;
+        if (t < tiles) row[t] = base + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kScanBlock - 1) carry = base + buf[kScanBlock - 1];
+        __syncthreads();
     }
 }
 
@@ -130,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
 }  // namespace
 
 size_t radix_hist_entries(int64_t n) {
-    return (size_t)kBins * (size_t)((n + kTile - 1) / kTile);
+    return (size_t)kBins * (size_t)((n + kTile - 1) / kTile) + kBins;
 }
 
 lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp,
@@ -142,11 +154,14 @@ lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned 
     unsigned long long* kout = keys_tmp;
     uint32_t* vout = vals_tmp;
     bool tmp = false;
+    uint32_t* totals = hist + (size_t)kBins * tiles;
     for (int d = 0; d < 8; ++d) {
         if (!((digit_mask >> d) & 1u)) continue;
         const int shift = 8 * d;
-        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist, tiles);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(kScanBlock), 0, st, hist, (int64_t)kBins * tiles);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBins), 0, st, totals, kBins);
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist, tiles,
+                           totals);
+        hipLaunchKernelGGL(k_scan_rows, dim3(kBins), dim3(kScanBlock), 0, st, hist, tiles, totals);
         hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
                            shift, hist, tiles);
         LRQO_HIP(hipGetLastError());
