@@ -98,11 +98,8 @@ def _near_boundary_rows(V, w, K, c, skip):
 def level_candidates(V: np.ndarray, K: int, d: int, stats: dict):
     """Yield (Z block of candidate labellings) from the vertices of the
     arrangement built on the leading d columns of V, in enumeration order."""
-    V = np.asarray(V, dtype=np.complex128)
-    n = V.shape[0]
-    Vd = V[:, :d]
+    n = np.asarray(V).shape[0]
     B = boundary_count(K)
-    A = tilde_rows(Vd, K)
     size = 2 * d - 1
     sets = []
     for I in itertools.combinations(range(n * B), size):
@@ -111,7 +108,20 @@ def level_candidates(V: np.ndarray, K: int, d: int, stats: dict):
             continue
         sets.append(I)
     stats["index_sets"] = stats.get("index_sets", 0) + len(sets)
-    if not sets:
+    yield from set_candidates(V, K, d, sets, stats)
+
+
+def set_candidates(V: np.ndarray, K: int, d: int, sets, stats: dict):
+    """Yield, for each valid index set I (sorted rows of the augmented matrix
+    of the leading d columns, at most two per coordinate) in the given order,
+    the candidate labellings of its vertex: rank test and null vector by SVD,
+    both signs, the decision rule outside I and the open labels of the
+    coordinates in I."""
+    V = np.asarray(V, dtype=np.complex128)
+    Vd = V[:, :d]
+    B = boundary_count(K)
+    A = tilde_rows(Vd, K)
+    if len(sets) == 0:
         return
     sets = np.asarray(sets, dtype=np.int64)
     _, sv, Vt = np.linalg.svd(A[sets], full_matrices=True)     # (m, size), (m, 2d, 2d)
