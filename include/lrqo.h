@@ -162,6 +162,23 @@ lrqo_status lrqo_solve_exact(const double* V, int64_t n, int32_t r, int32_t K, u
 lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K,
                                 int64_t max_sets, uint8_t* z, lrqo_exact_result* res);
 
+/* Null-vector randomized sampler (the randomized form of Alg. 2 compared
+ * with uniform sphere sampling in Sec. 5, Table samplers): S draws of 2r-1
+ * rows of the augmented matrix of the full factor; a draw whose rows are
+ * distinct, hold at most two rows per coordinate and pass the rank test is
+ * feasible and its vertex is scored exactly as lrqo_solve_exact_ex scores an
+ * enumerated index set; the best FP64 objective wins (ties to the earlier
+ * draw).  Draw s (the paper fixes no generator): with M = 2r-1 and N = n B_K,
+ * row j = (2^32 w[2j+1] + w[2j]) mod N, w[4b+t] = word t of Philox4x32-10
+ * with key (seed & 0xffffffff, seed >> 32) and counter (s & 0xffffffff,
+ * s >> 32, 0x4E554C4C, b); the set is the sorted rows.  Same layouts and
+ * limits as lrqo_solve_exact_ex except n B_K (any) and 1 <= S <= 2^31 - 1.
+ * res->index_sets counts draws with distinct rows and at most two per
+ * coordinate, res->rank_deficient those of them that fail the rank test.
+ * No feasible draw returns LRQO_EINVAL. */
+lrqo_status lrqo_solve_nullvec(const double* V, int64_t n, int32_t r, int32_t K, int64_t S, uint64_t seed,
+                               uint8_t* z, lrqo_exact_result* res);
+
 /* --------------------------------------------------------------------------
  * Batched sampled maximisation: many small instances in one persistent,
  * work-queue-driven launch (the sampled method of Sec. 4.2 on each).

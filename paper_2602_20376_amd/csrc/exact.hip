@@ -59,6 +59,8 @@ struct ExactParams {
     uint64_t offset;                    // global index of this level's first set
     float* fbuf;
     unsigned long long* stats;          // valid sets, rank deficient, candidates
+    int random;                         // 1: index sets drawn at random (null-vector sampler)
+    uint64_t draw_seed;
 };
 
 struct LevelTable {
@@ -104,6 +106,42 @@ __device__ __forceinline__ void unrank(uint64_t rank, const unsigned long long* 
     }
 }
 
+// Null-vector sampler, draw s: M rows of the augmented matrix, row j =
+// (2^32 w[2j+1] + w[2j]) mod N with w the words of Philox4x32-10 (key seed,
+// counter (s lo, s hi, kNullvecStream, block)), sorted; `distinct` is false
+// when a row repeats.
+constexpr uint32_t kNullvecStream = 0x4E554C4Cu;
+
+template <int M>
+__device__ __forceinline__ void draw_rows(uint64_t seed, uint64_t s, int64_t N, int64_t (&c)[M], bool& distinct) {
+    constexpr int NB = (2 * M + 3) / 4;
+    uint32_t w[4 * NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const U4 o = philox4x32_10(U4{(uint32_t)s, (uint32_t)(s >> 32), kNullvecStream, (uint32_t)b},
+                                   (uint32_t)seed, (uint32_t)(seed >> 32));
+        w[4 * b] = o.x;
+        w[4 * b + 1] = o.y;
+        w[4 * b + 2] = o.z;
+        w[4 * b + 3] = o.w;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+        c[j] = (int64_t)((((uint64_t)w[2 * j + 1] << 32) | (uint64_t)w[2 * j]) % (uint64_t)N);
+    for (int t = 1; t < M; ++t) {       // insertion sort, M <= 7
+        const int64_t x = c[t];
+        int u = t - 1;
+        while (u >= 0 && c[u] > x) {
+            c[u + 1] = c[u];
+            --u;
+        }
+        c[u + 1] = x;
+    }
+    distinct = true;
+#pragma unroll
+    for (int t = 0; t + 1 < M; ++t) distinct &= c[t] < c[t + 1];
+}
+
 // The vertex of one index set: groups g[t], boundary ids mm[t], unit null
 // vector v in R^{2D}.  Returns false for a set with three rows of one group
 // (invalid) or below the rank tolerance (rank_deficient set accordingly).
@@ -112,13 +150,15 @@ __device__ bool vertex(const ExactParams& p, uint64_t rank, int64_t (&g)[2 * D -
                        int (&mm)[2 * D - 1], double (&v)[2 * D], bool& valid) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
     int64_t c[M];
-    unrank<M>(rank, p.binom, p.N, c);
+    bool distinct = true;
+    if (p.random) draw_rows<M>(p.draw_seed, rank, p.N, c, distinct);
+    else unrank<M>(rank, p.binom, p.N, c);
 #pragma unroll
     for (int t = 0; t < M; ++t) {
         g[t] = c[t] / p.B;
         mm[t] = (int)(c[t] - g[t] * p.B);
     }
-    valid = true;
+    valid = distinct;
 #pragma unroll
     for (int t = 0; t + 2 < M; ++t) valid &= g[t] != g[t + 2];
     if (!valid) return false;
@@ -669,23 +709,21 @@ lrqo_status run_exact(ExactParams p, const LevelTable& lt, const unsigned long l
     return LRQO_OK;
 }
 
-}  // namespace
-}  // namespace lrqo
-
-extern "C" {
-
-lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K,
-                                int64_t max_sets, uint8_t* z, lrqo_exact_result* res) {
-    using namespace lrqo;
+// Shared by the exact enumeration (random = false: every valid index set of
+// every level, colex order) and the null-vector sampler (random = true:
+// S drawn index sets of level r).
+lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64_t max_sets, bool random,
+                         int64_t S, uint64_t seed, uint8_t* z, lrqo_exact_result* res) {
     clear_error();
     if (!V) return fail(LRQO_EINVAL, "V is null");
     if (!z) return fail(LRQO_EINVAL, "z is null");
-    if (r < 1 || r > kMaxR) return fail(LRQO_EINVAL, "r must be in [1, 4] for the exact solver");
+    if (r < 1 || r > kMaxR) return fail(LRQO_EINVAL, "r must be in [1, 4] for the vertex solvers");
     if (n < r || n > (1 << 24)) return fail(LRQO_EINVAL, "n must be in [r, 2^24]");
     if (K < 2 || K > LRQO_MAX_K) return fail(LRQO_EINVAL, "K must be in [2, 255]");
+    if (random && (S < 1 || S > 0x7FFFFFFFll)) return fail(LRQO_EINVAL, "S must be in [1, 2^31 - 1]");
     const int B = boundary_count(K);
     const int64_t N = n * B;
-    if (N > (1 << 22)) return fail(LRQO_ETOOBIG, "n B_K above 2^22 rows: too many index sets");
+    if (!random && N > (1 << 22)) return fail(LRQO_ETOOBIG, "n B_K above 2^22 rows: too many index sets");
     // label combinations of one vertex: at most 2^(2r-1-2p) K^p, p double groups
     for (int pdbl = 0; 2 * pdbl <= 2 * r - 1; ++pdbl) {
         long double combos = std::ldexp(1.0L, 2 * r - 1 - 2 * pdbl) * std::pow((long double)K, pdbl);
@@ -695,14 +733,20 @@ lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K
     const uint64_t cap = max_sets > 0 ? (uint64_t)max_sets : ((1ull << 31) - 1);
     LevelTable lt{};
     unsigned __int128 total128 = 0;
-    for (int d = r; d >= 1; --d) {
-        const unsigned __int128 c = binom128(N, 2 * d - 1);
-        lt.offset[d] = (uint64_t)std::min<unsigned __int128>(total128, ~0ull);
-        lt.count[d] = (uint64_t)std::min<unsigned __int128>(c, ~0ull);
-        total128 += c;
+    if (random) {
+        lt.offset[r] = 0;
+        lt.count[r] = (uint64_t)S;
+        total128 = (unsigned __int128)S;
+    } else {
+        for (int d = r; d >= 1; --d) {
+            const unsigned __int128 c = binom128(N, 2 * d - 1);
+            lt.offset[d] = (uint64_t)std::min<unsigned __int128>(total128, ~0ull);
+            lt.count[d] = (uint64_t)std::min<unsigned __int128>(c, ~0ull);
+            total128 += c;
+        }
+        if (total128 > (unsigned __int128)cap || total128 > 0xFFFFFFF0ull)
+            return fail(LRQO_ETOOBIG, "number of index sets C(n B_K, 2d-1) summed over levels exceeds the cap");
     }
-    if (total128 > (unsigned __int128)cap || total128 > 0xFFFFFFF0ull)
-        return fail(LRQO_ETOOBIG, "number of index sets C(n B_K, 2d-1) summed over levels exceeds the cap");
     const uint32_t total = (uint32_t)total128;
 
     DeviceCtx* ctx = device_ctx();
@@ -712,7 +756,7 @@ lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K
 
     const int T = (int)std::min<uint32_t>(kTopT, total);
     const int Mmax = 2 * r - 1;
-    const size_t binom_entries = (size_t)(Mmax + 1) * (size_t)(N + 1);
+    const size_t binom_entries = random ? 1 : (size_t)(Mmax + 1) * (size_t)(N + 1);
     CarveSize cs;
     cs.add<ExactDevResult>(1);
     cs.add<unsigned long long>(4);
@@ -755,7 +799,8 @@ lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K
     float2* hr32 = reinterpret_cast<float2*>(hr64 + LRQO_MAX_K);
     // C(x, k) by Pascal's rule, saturating at 2^64-1 (only values below the
     // set count, <= 2^32, are ever compared exactly)
-    for (int k = 0; k <= Mmax; ++k)
+    if (random) hbin[0] = 0;
+    for (int k = 0; k <= (random ? -1 : Mmax); ++k)
         for (int64_t x = 0; x <= N; ++x) {
             unsigned long long c;
             if (k == 0) c = 1;
@@ -801,6 +846,8 @@ lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K
     p.roots32 = roots32;
     p.fbuf = fbuf;
     p.stats = stats;
+    p.random = random ? 1 : 0;
+    p.draw_seed = seed;
 
     const int64_t vcount = n * r * 2;
     int* nonfinite = &dres->nonfinite;
@@ -832,7 +879,9 @@ lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K
     float ms = 0.0f;
     LRQO_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
     if (hres->nonfinite) return fail(LRQO_ENOTFINITE, "V holds a NaN or an infinity");
-    if (hres->level == 0) return fail(LRQO_EDEVICE, "no full-rank vertex found (degenerate V)");
+    if (hres->level == 0)
+        return fail(random ? LRQO_EINVAL : LRQO_EDEVICE,
+                    random ? "no feasible draw among the S draws" : "no full-rank vertex found (degenerate V)");
     if (res) {
         std::memset(res, 0, sizeof *res);
         res->obj = hres->obj;
@@ -842,6 +891,21 @@ lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K
         res->device_ms = ms;
     }
     return LRQO_OK;
+}
+
+}  // namespace
+}  // namespace lrqo
+
+extern "C" {
+
+lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K,
+                                int64_t max_sets, uint8_t* z, lrqo_exact_result* res) {
+    return lrqo::vertex_solve(V, n, r, K, max_sets, false, 0, 0, z, res);
+}
+
+lrqo_status lrqo_solve_nullvec(const double* V, int64_t n, int32_t r, int32_t K, int64_t S, uint64_t seed,
+                               uint8_t* z, lrqo_exact_result* res) {
+    return lrqo::vertex_solve(V, n, r, K, 0, true, S, seed, z, res);
 }
 
 lrqo_status lrqo_solve_exact(const double* V, int64_t n, int32_t r, int32_t K, uint8_t* z,

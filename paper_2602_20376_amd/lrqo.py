@@ -27,7 +27,7 @@ EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown"
            "lrqo_solve_exact_ex", "lrqo_solve_batched", "lrqo_proposal_param_count",
            "lrqo_proposal_create", "lrqo_proposal_destroy", "lrqo_proposal_get_state",
            "lrqo_proposal_set_state", "lrqo_proposal_train_step", "lrqo_proposal_sample",
-           "lrqo_proposal_frame", "lrqo_solve_rank1", "lrqo_graph_objective",
+           "lrqo_proposal_frame", "lrqo_solve_nullvec", "lrqo_solve_rank1", "lrqo_graph_objective",
            "lrqo_refine_greedy")
 
 
@@ -143,6 +143,8 @@ def load(path: str = LIB_PATH):
     lib.lrqo_proposal_sample.argtypes = [vp, vp, i64, i64, u64, u32, ctypes.c_float, vp]
     lib.lrqo_proposal_sample.restype = i32
     lib.lrqo_proposal_frame.argtypes = [vp, vp, i64, vp]
+    lib.lrqo_solve_nullvec.restype = i32
+    lib.lrqo_solve_nullvec.argtypes = [vp, i64, i32, i32, i64, u64, vp, ctypes.POINTER(ExactResult)]
     lib.lrqo_solve_rank1.restype = i32
     lib.lrqo_solve_rank1.argtypes = [vp, i64, i32, vp, ctypes.POINTER(Rank1Result)]
     lib.lrqo_graph_objective.restype = ctypes.c_int
@@ -244,6 +246,27 @@ def solve_exact(V, K: int, *, max_sets: int = 0, z=None):
         _bind_stream(torch)
         _check(lib.lrqo_solve_exact_ex(ctypes.c_void_p(Vc.data_ptr()), n, r, int(K), int(max_sets),
                                        ctypes.c_void_p(z.data_ptr()), ctypes.byref(res)))
+    return z, res
+
+
+def solve_nullvec(V, K: int, S: int, seed: int, *, z=None):
+    """Null-vector randomized sampler (see lrqo_solve_nullvec).  V: complex128
+    (n, r) device tensor.  Returns (labels, ExactResult)."""
+    import torch
+
+    lib = load()
+    if not V.is_cuda or V.dtype != torch.complex128 or V.dim() != 2:
+        raise ValueError("V must be a complex128 (n, r) device tensor")
+    Vc = torch.view_as_real(V.contiguous()).contiguous()
+    n, r = V.shape
+    if z is None:
+        z = torch.empty(n, dtype=torch.uint8, device=V.device)
+    res = ExactResult()
+    with torch.cuda.device(V.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_solve_nullvec(ctypes.c_void_p(Vc.data_ptr()), n, r, int(K), int(S),
+                                      int(seed) & (2**64 - 1), ctypes.c_void_p(z.data_ptr()),
+                                      ctypes.byref(res)))
     return z, res
 
 
