@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
     ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal", "refine",
-                                       "rank1_hybrid"),
+                                       "rank1_hybrid", "samplers"),
                     help="measure only this form and print its record (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized float32 device tensor once before timing "
@@ -223,6 +223,45 @@ def form_rank1_hybrid():
             "cut_sampled_rank3": cut_sampled}
 
 
+def form_samplers():
+    """Uniform sphere against null-vector draws at a matched budget on the
+    maxcut_er factor (K = 3), as in the comparison of the two samplers: rank 2
+    (its two leading columns) and the full rank 4; FP64 objectives, cuts on
+    the graph, feasible share of the null-vector draws."""
+    import numpy as np
+    import torch
+
+    from paper_2602_20376_amd import inputs, lrqo
+
+    inst = inputs.maxcut_er()
+    i, j = inputs.maxcut_er_graph()
+    rp, col, _ = inputs.csr_adjacency(inst.n, i, j)
+    rpd, cold = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+    S = inst.S
+    out = {"workload": "maxcut_er", "n": inst.n, "K": inst.K, "S": S}
+    for r in (2, 4):
+        V = np.ascontiguousarray(inst.V[:, :r])
+        Vr = torch.from_numpy(inputs.as_real_f32(V)).cuda()
+        Vc = torch.from_numpy(V).cuda()
+        t = time.perf_counter()
+        u = lrqo.solve_sampled(Vr, inst.K, S, inst.seed, real=True)
+        torch.cuda.synchronize()
+        tu = (time.perf_counter() - t) * 1000.0
+        t = time.perf_counter()
+        zn, rn = lrqo.solve_nullvec(Vc, inst.K, S, inst.seed)
+        torch.cuda.synchronize()
+        tn = (time.perf_counter() - t) * 1000.0
+        _, cut_u = lrqo.graph_objective(rpd, cold, None, inst.K, u.z)
+        _, cut_n = lrqo.graph_objective(rpd, cold, None, inst.K, zn)
+        out[f"r{r}"] = {"uniform_obj": u.obj, "nullvec_obj": rn.obj,
+                        "uniform_over_nullvec": u.obj / rn.obj,
+                        "cut_uniform": cut_u, "cut_nullvec": cut_n,
+                        "nullvec_feasible": (rn.index_sets - rn.rank_deficient) / S,
+                        "nullvec_valid": rn.index_sets / S,
+                        "uniform_ms": tu, "nullvec_ms": tn}
+    return out
+
+
 def form_learned(train_count):
     """Learned proposal against uniform sampling on phase synchronisation
     (n = 262,144, r = 3, K = 16): samples needed to reach 99.9% of the best
@@ -274,7 +313,7 @@ def main():
 
     if args.form:
         fn = {"precision_bf16": form_precision, "batched": form_batched, "refine": form_refine,
-              "rank1_hybrid": form_rank1_hybrid,
+              "rank1_hybrid": form_rank1_hybrid, "samplers": form_samplers,
               "learned_proposal": lambda: form_learned(args.train_count)}[args.form]
         print(json.dumps({"form": args.form, **fn()}), flush=True)
         return
@@ -331,6 +370,7 @@ def main():
         forms = {}
         for name, fn in (("precision_bf16", form_precision), ("batched", form_batched),
                          ("refine", form_refine), ("rank1_hybrid", form_rank1_hybrid),
+                         ("samplers", form_samplers),
                          ("learned_proposal", lambda: form_learned(args.train_count))):
             print(f"bench: measuring {name}", file=sys.stderr, flush=True)
             try:
