@@ -363,6 +363,52 @@ typedef struct lrqo_refine_result {
 lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z,
                                const lrqo_refine_options* opt, lrqo_refine_result* res);
 
+/* --------------------------------------------------------------------------
+ * Spectral truncation (the step before the solvers): the r largest
+ * eigenpairs of a Hermitian matrix by Lanczos with full reorthogonalisation
+ * (FP64), returned as the factor V = U diag(sqrt(max(lambda, 0))) that the
+ * solvers take (device complex128 n x r, row-major interleaved; for the
+ * Laplacian the imaginary parts are zero to rounding).  Eigenvalues in
+ * descending order; each eigenvector is rotated so that its largest-modulus
+ * entry (lowest index among equals) is real and positive.  Convergence: the
+ * residual bound |beta_m s_{m,k}| of every pair is at most tol times the
+ * largest Ritz value, checked every check_every steps; an invariant Krylov
+ * space ends the iteration early (exact pairs).
+ * ------------------------------------------------------------------------ */
+
+typedef struct lrqo_eigs_options {
+    int32_t max_iter;        /* Lanczos steps, at most min(n, 2000); 0: 300 */
+    int32_t check_every;     /* steps between convergence checks; 0: 10 */
+    double tol;              /* 0: 1e-10 */
+    uint64_t seed;           /* start vector: complex Gaussian entries from Philox4x32-10,
+                                counter (i lo, i hi, 0x5354524C, 0) */
+} lrqo_eigs_options;
+
+typedef struct lrqo_eigs_result {
+    double eigenvalues[LRQO_MAX_R];
+    double residuals[LRQO_MAX_R];
+    int32_t iterations;      /* Lanczos steps taken */
+    int32_t converged;
+    float device_ms;
+    int32_t pad;
+} lrqo_eigs_result;
+
+/* Top-r factor of the Laplacian L = D - A of a graph (layout as for
+ * lrqo_graph_objective, checked on the device), 1 <= r <= 8. */
+lrqo_status lrqo_laplacian_factor(const lrqo_graph* g, int32_t r, const lrqo_eigs_options* opt, double* V,
+                                  lrqo_eigs_result* res);
+
+/* Top-r factor of Q = U U^H + sigma W (phase synchronisation), applied
+ * matrix-free: U device complex128 n x p (row-major interleaved, 0 <= p <= 8)
+ * and W the Hermitian Gaussian matrix defined by w_seed: for i <= j, words
+ * (w0, w1) of Philox4x32-10 with key (w_seed lo, w_seed hi) and counter
+ * (i, j, 0x57484D41, 0) give u = ((w >> 9) + 1/2) 2^-23 and
+ * W_ij = sqrt(-log u0) e^{2 pi i u1} (i < j), W_ii = sqrt(-2 log u0)
+ * cos(2 pi u1), W_ji = conj(W_ij) (evaluated in FP32, accumulated in FP64).
+ * Each product costs n^2 entry evaluations. */
+lrqo_status lrqo_phase_sync_factor(const double* U, int64_t n, int32_t p, double sigma, uint64_t w_seed, int32_t r,
+                                   const lrqo_eigs_options* opt, double* V, lrqo_eigs_result* res);
+
 #ifdef __cplusplus
 }
 #endif

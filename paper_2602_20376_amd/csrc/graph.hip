@@ -22,6 +22,7 @@
 #include <cstring>
 #include <string>
 
+#include "graph_internal.h"
 #include "lrqo_device.h"
 #include "lrqo_runtime.h"
 
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_check_ptr(GraphDev g, int* flag) {
 __global__ __launch_bounds__(kBlock) void k_check_rows(GraphDev g, int K, const uint8_t* z, int* flag) {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= g.n) return;
-    int bad = z[i] >= K ? kBadLabel : 0;
+    int bad = (z && z[i] >= K) ? kBadLabel : 0;
     for (int64_t e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
         const int32_t j = g.col[e];
         if (j < 0 || j >= g.n || j == i) bad |= kBadCol;
@@ -168,40 +169,6 @@ __global__ __launch_bounds__(kBlock) void k_move(GraphDev g, const uint8_t* __re
     if ((threadIdx.x & (kWave - 1)) == 0 && wave_moves) atomicAdd(moves, wave_moves);
 }
 
-lrqo_status check_graph_args(const lrqo_graph* g) {
-    if (!g) return fail(LRQO_EINVAL, "null graph");
-    if (!g->row_ptr) return fail(LRQO_EINVAL, "null row_ptr");
-    if (g->nnz > 0 && !g->col) return fail(LRQO_EINVAL, "null col with nnz > 0");
-    if (g->n < 1 || g->n > 0x7fffffffLL) return fail(LRQO_EINVAL, "n must be in [1, 2^31 - 1]");
-    if (g->nnz < 0) return fail(LRQO_EINVAL, "nnz must be >= 0");
-    if (!is_device_pointer(g->row_ptr)) return fail(LRQO_EINVAL, "row_ptr is not device memory");
-    if (g->nnz > 0 && !is_device_pointer(g->col)) return fail(LRQO_EINVAL, "col is not device memory");
-    if (g->w && !is_device_pointer(g->w)) return fail(LRQO_EINVAL, "w is not device memory");
-    return LRQO_OK;
-}
-
-// Device validation of the CSR and of the labels (two passes: the row pass
-// reads col through row_ptr, so row_ptr is checked first).
-lrqo_status validate(const GraphDev& gd, int K, const uint8_t* z, int* d_flag, int* h_flag,
-                     hipStream_t st) {
-    const unsigned blocks = (unsigned)((gd.n + kBlock - 1) / kBlock);
-    *h_flag = 0;
-    LRQO_HIP(hipMemcpyAsync(d_flag, h_flag, sizeof(int), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_check_ptr, dim3(blocks), dim3(kBlock), 0, st, gd, d_flag);
-    LRQO_HIP(hipGetLastError());
-    LRQO_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    LRQO_HIP(hipStreamSynchronize(st));
-    if (*h_flag) return fail(LRQO_EINVAL, "row_ptr is not a CSR row pointer (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz)");
-    hipLaunchKernelGGL(k_check_rows, dim3(blocks), dim3(kBlock), 0, st, gd, K, z, d_flag);
-    LRQO_HIP(hipGetLastError());
-    LRQO_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
-    LRQO_HIP(hipStreamSynchronize(st));
-    if (*h_flag & kBadCol) return fail(LRQO_EINVAL, "a column index is out of range or a self loop");
-    if (*h_flag & kBadWeight) return fail(LRQO_EINVAL, "a weight is not finite");
-    if (*h_flag & kBadLabel) return fail(LRQO_EINVAL, "a label is not below K");
-    return LRQO_OK;
-}
-
 struct GraphScratch {
     int* flag;
     double* partial;
@@ -294,6 +261,40 @@ lrqo_status objective(const GraphDev& gd, int K, const uint8_t* z, const GraphSc
 }
 
 }  // namespace
+
+lrqo_status check_graph_args(const lrqo_graph* g) {
+    if (!g) return fail(LRQO_EINVAL, "null graph");
+    if (!g->row_ptr) return fail(LRQO_EINVAL, "null row_ptr");
+    if (g->nnz > 0 && !g->col) return fail(LRQO_EINVAL, "null col with nnz > 0");
+    if (g->n < 1 || g->n > 0x7fffffffLL) return fail(LRQO_EINVAL, "n must be in [1, 2^31 - 1]");
+    if (g->nnz < 0) return fail(LRQO_EINVAL, "nnz must be >= 0");
+    if (!is_device_pointer(g->row_ptr)) return fail(LRQO_EINVAL, "row_ptr is not device memory");
+    if (g->nnz > 0 && !is_device_pointer(g->col)) return fail(LRQO_EINVAL, "col is not device memory");
+    if (g->w && !is_device_pointer(g->w)) return fail(LRQO_EINVAL, "w is not device memory");
+    return LRQO_OK;
+}
+
+lrqo_status validate_graph(const lrqo_graph* g, int K, const uint8_t* z, int* d_flag, int* h_flag,
+                           hipStream_t st) {
+    const GraphDev gd{g->row_ptr, g->col, g->w, g->n, g->nnz};
+    const unsigned blocks = (unsigned)((gd.n + kBlock - 1) / kBlock);
+    *h_flag = 0;
+    LRQO_HIP(hipMemcpyAsync(d_flag, h_flag, sizeof(int), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_check_ptr, dim3(blocks), dim3(kBlock), 0, st, gd, d_flag);
+    LRQO_HIP(hipGetLastError());
+    LRQO_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipStreamSynchronize(st));
+    if (*h_flag) return fail(LRQO_EINVAL, "row_ptr is not a CSR row pointer (row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz)");
+    hipLaunchKernelGGL(k_check_rows, dim3(blocks), dim3(kBlock), 0, st, gd, K, z, d_flag);
+    LRQO_HIP(hipGetLastError());
+    LRQO_HIP(hipMemcpyAsync(h_flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipStreamSynchronize(st));
+    if (*h_flag & kBadCol) return fail(LRQO_EINVAL, "a column index is out of range or a self loop");
+    if (*h_flag & kBadWeight) return fail(LRQO_EINVAL, "a weight is not finite");
+    if (*h_flag & kBadLabel) return fail(LRQO_EINVAL, "a label is not below K");
+    return LRQO_OK;
+}
+
 }  // namespace lrqo
 
 extern "C" {
@@ -314,7 +315,7 @@ lrqo_status lrqo_graph_objective(const lrqo_graph* g, int32_t K, const uint8_t* 
     HostScratch h{};
     LRQO_TRY(reserve_graph(ctx, g->n, false, s, h));
     const GraphDev gd{g->row_ptr, g->col, g->w, g->n, g->nnz};
-    LRQO_TRY(validate(gd, K, z, s.flag, h.flag, st));
+    LRQO_TRY(validate_graph(g, K, z, s.flag, h.flag, st));
     LRQO_TRY(upload_tables(K, s, h.table, st));
     return objective(gd, K, z, s, h.out, st, quad, cut);
 }
@@ -341,7 +342,7 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
     HostScratch h{};
     LRQO_TRY(reserve_graph(ctx, g->n, true, s, h));
     const GraphDev gd{g->row_ptr, g->col, g->w, g->n, g->nnz};
-    LRQO_TRY(validate(gd, K, z, s.flag, h.flag, st));
+    LRQO_TRY(validate_graph(g, K, z, s.flag, h.flag, st));
     LRQO_TRY(upload_tables(K, s, h.table, st));
 
     lrqo_refine_result r{};

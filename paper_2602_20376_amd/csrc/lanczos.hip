@@ -1,0 +1,629 @@
+// Spectral truncation (the step before the path): the r largest eigenpairs of
+// a Hermitian operator by Lanczos with full reorthogonalisation in FP64, and
+// the factor V = U diag(sqrt(lambda)) the solvers take.
+//
+// Operators:
+//   Laplacian    L = D - A of a CSR graph (as for Max-K-Cut, Sec. 5):
+//                y_i = sum_j w_ij (x_i - x_j)
+//   phase sync   Q = U U^H + sigma W with W Hermitian Gaussian regenerated
+//                on the fly from a counter-based definition (W_ij from
+//                Philox4x32-10, key seed, counter (min, max, 0x57484D41, 0):
+//                off-diagonal sqrt(-log u0) e^{2 pi i u1}, conjugated below
+//                the diagonal; diagonal sqrt(-2 log u0) cos 2 pi u1), so the
+//                n x n matrix is never stored
+//
+// Per Lanczos step j (basis columns q_0..q_j in HBM, column-major):
+//   w = A q_j; h = Q^H w (alpha_j = Re h_j); w -= Q h; a second pass of the
+//   same (classical Gram-Schmidt, twice); beta_j = ||w||; q_{j+1} = w/beta_j.
+// Every check interval one block finds the r largest eigenvalues of the
+// tridiagonal T_j by Sturm bisection and their vectors by inverse iteration;
+// |beta_j s_{j,k}| bounds the residual of Ritz pair k.  At convergence the
+// Ritz vectors U = Q S are formed, each is rotated so that its
+// largest-modulus entry is real positive, and scaled by sqrt(max(theta, 0)).
+// All sums are fixed-order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "graph_internal.h"
+#include "lrqo_device.h"
+#include "lrqo_runtime.h"
+
+namespace lrqo {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr uint32_t kWStream = 0x57484D41u;
+constexpr int kMaxIter = 2000;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) b
+__device__ __forceinline__ double2 cdot1(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+    __shared__ double sa[kBlock], sb[kBlock];
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sa[threadIdx.x] += sa[threadIdx.x + h];
+            sb[threadIdx.x] += sb[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    a = sa[0];
+    b = sb[0];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- operators
+struct LapOp {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* w;
+    int64_t n;
+};
+
+__global__ __launch_bounds__(kBlock) void k_apply_lap(LapOp g, const double2* __restrict__ x, double2* __restrict__ y) {
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    const double2 xi = x[i];
+    double ar = 0.0, ai = 0.0, deg = 0.0;
+    for (int64_t e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
+        const double w = g.w ? g.w[e] : 1.0;
+        const double2 xj = x[g.col[e]];
+        ar += w * xj.x;
+        ai += w * xj.y;
+        deg += w;
+    }
+    y[i] = make_double2(deg * xi.x - ar, deg * xi.y - ai);
+}
+
+struct PhaseOp {
+    const double2* U;      // n x p row-major
+    int p;
+    double sigma;
+    uint64_t seed;
+    int64_t n;
+};
+
+// c[k] = sum_i conj(U_ik) x_i, one block per k
+__global__ __launch_bounds__(kBlock) void k_utx(PhaseOp o, const double2* __restrict__ x, double2* __restrict__ c) {
+    const int k = blockIdx.x;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = threadIdx.x; i < o.n; i += kBlock) {
+        const double2 t = cdot1(o.U[i * o.p + k], x[i]);
+        ar += t.x;
+        ai += t.y;
+    }
+    block_sum2(ar, ai);
+    if (threadIdx.x == 0) c[k] = make_double2(ar, ai);
+}
+
+__device__ __forceinline__ float2 w_entry32(uint64_t seed, int64_t i, int64_t j) {
+    const uint32_t a = (uint32_t)(i < j ? i : j), b = (uint32_t)(i < j ? j : i);
+    const U4 o = philox4x32_10(U4{a, b, kWStream, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float u0 = uniform_from_bits(o.x), u1 = uniform_from_bits(o.y);
+    float sn, cs;
+    sincospif(2.0f * u1, &sn, &cs);
+    if (a == b) return make_float2(sqrtf(-2.0f * logf(u0)) * cs, 0.0f);
+    const float rad = sqrtf(-logf(u0));
+    return make_float2(rad * cs, i <= j ? rad * sn : -rad * sn);
+}
+
+// y_i = sum_k U_ik c_k + sigma sum_j W_ij x_j; x staged through LDS
+__global__ __launch_bounds__(kBlock) void k_apply_phase(PhaseOp o, const double2* __restrict__ c,
+                                                        const double2* __restrict__ x, double2* __restrict__ y) {
+    __shared__ double2 xs[kBlock];
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const bool live = i < o.n;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t j0 = 0; j0 < o.n; j0 += kBlock) {
+        __syncthreads();
+        xs[threadIdx.x] = j0 + threadIdx.x < o.n ? x[j0 + threadIdx.x] : make_double2(0.0, 0.0);
+        __syncthreads();
+        if (!live) continue;
+        const int cnt = (int)min((int64_t)kBlock, o.n - j0);
+        for (int t = 0; t < cnt; ++t) {
+            const float2 w = w_entry32(o.seed, i, j0 + t);
+            const double wr = (double)w.x, wi = (double)w.y;
+            const double2 xj = xs[t];
+            ar += wr * xj.x - wi * xj.y;
+            ai += wr * xj.y + wi * xj.x;
+        }
+    }
+    if (!live) return;
+    double yr = o.sigma * ar, yi = o.sigma * ai;
+    for (int k = 0; k < o.p; ++k) {
+        const double2 t = cmul(o.U[i * o.p + k], c[k]);
+        yr += t.x;
+        yi += t.y;
+    }
+    y[i] = make_double2(yr, yi);
+}
+
+// ---------------------------------------------------------------- basis algebra
+// h_j = q_j^H w for j < k (one block per column)
+__global__ __launch_bounds__(kBlock) void k_dots(const double2* __restrict__ Q, int64_t n, const double2* __restrict__ w,
+                                                 double2* __restrict__ h) {
+    const int j = blockIdx.x;
+    const double2* q = Q + (int64_t)j * n;
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+        const double2 t = cdot1(q[i], w[i]);
+        ar += t.x;
+        ai += t.y;
+    }
+    block_sum2(ar, ai);
+    if (threadIdx.x == 0) h[j] = make_double2(ar, ai);
+}
+
+// w -= sum_{j<k} q_j h_j
+__global__ __launch_bounds__(kBlock) void k_sub(const double2* __restrict__ Q, int64_t n, int k,
+                                                const double2* __restrict__ h, double2* __restrict__ w) {
+    __shared__ double2 hs[kMaxIter + 1];
+    for (int j = threadIdx.x; j < k; j += kBlock) hs[j] = h[j];
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double2 t = cmul(Q[(int64_t)j * n + i], hs[j]);
+        ar += t.x;
+        ai += t.y;
+    }
+    const double2 wi = w[i];
+    w[i] = make_double2(wi.x - ar, wi.y - ai);
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_part(const double2* __restrict__ w, int64_t n, double* __restrict__ part) {
+    double a = 0.0, b = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double2 t = w[i];
+        a += t.x * t.x + t.y * t.y;
+    }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_final(const double* __restrict__ part, int count, double* __restrict__ out) {
+    double a = 0.0, b = 0.0;
+    for (int t = threadIdx.x; t < count; t += kBlock) a += part[t];
+    block_sum2(a, b);
+    if (threadIdx.x == 0) out[0] = sqrt(a);
+}
+
+// q = w / nrm (nrm read on the device)
+__global__ __launch_bounds__(kBlock) void k_scale(const double2* __restrict__ w, int64_t n, const double* __restrict__ nrm,
+                                                  double2* __restrict__ q) {
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double inv = 1.0 / nrm[0];
+    const double2 t = w[i];
+    q[i] = make_double2(t.x * inv, t.y * inv);
+}
+
+// start vector: standard complex Gaussian entries from the Philox stream
+// (key seed, counter (i lo, i hi, 0x5354524C, 0)), normalised afterwards
+__global__ __launch_bounds__(kBlock) void k_start(int64_t n, uint64_t seed, double2* __restrict__ w) {
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    const U4 o = philox4x32_10(U4{(uint32_t)i, (uint32_t)(i >> 32), 0x5354524Cu, 0u}, (uint32_t)seed,
+                               (uint32_t)(seed >> 32));
+    const double u0 = ((double)(o.x >> 9) + 0.5) * 0x1p-23, u1 = ((double)(o.y >> 9) + 0.5) * 0x1p-23;
+    const double rad = sqrt(-2.0 * log(u0));
+    w[i] = make_double2(rad * cos(2.0 * 3.141592653589793 * u1), rad * sin(2.0 * 3.141592653589793 * u1));
+}
+
+// ---------------------------------------------------------------- tridiagonal
+// Number of eigenvalues of T (diagonal a, off-diagonal b) below x (Sturm).
+__device__ int sturm_below(const double* a, const double* b, int m, double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+        const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
+        d = a[i] - x - (i ? bb / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        cnt += d < 0.0;
+    }
+    return cnt;
+}
+
+// Thread t < r: eigenvalue theta_t (the t-th largest) by bisection and its
+// unit vector by inverse iteration (tridiagonal elimination with partial
+// pivoting); thread 0 then orthonormalises the r vectors in order and
+// forms the residual bounds |b_last s_{m-1,t}|.  S is m x r column-major.
+__global__ void k_tridiag_top(const double* __restrict__ a, const double* __restrict__ b, int m, int r,
+                              double b_last, double* __restrict__ theta, double* __restrict__ S,
+                              double* __restrict__ resid, double* __restrict__ work) {
+    const int t = threadIdx.x;
+    if (t < r) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int i = 0; i < m; ++i) {
+            const double rad = (i ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
+            lo = fmin(lo, a[i] - rad);
+            hi = fmax(hi, a[i] + rad);
+        }
+        const double span = fmax(hi - lo, 1e-300);
+        lo -= 1e-12 * span;
+        hi += 1e-12 * span;
+        const int k = m - 1 - t;      // ascending index
+        for (int it = 0; it < 200 && hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)); ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (sturm_below(a, b, m, mid) > k) hi = mid;
+            else lo = mid;
+        }
+        const double th = 0.5 * (lo + hi);
+        theta[t] = th;
+        // inverse iteration on (T - mu I), mu just off th
+        const double mu = th + 1e-13 * span;
+        double* d0 = work + (size_t)t * 6 * m;   // diagonal after elimination
+        double* d1 = d0 + m;                      // first superdiagonal
+        double* d2 = d1 + m;                      // second superdiagonal (fill-in)
+        double* lm = d2 + m;                      // multipliers
+        double* pv = lm + m;                      // pivot swap flags
+        double* x = pv + m;
+        for (int i = 0; i < m; ++i) x[i] = 1.0 + 0.001 * (double)((i * 7919 + t * 104729) % 97);
+        for (int iter = 0; iter < 4; ++iter) {
+            // factor: rows i, i+1 with partial pivoting
+            double cd = a[0] - mu, cu = m > 1 ? b[0] : 0.0;
+            for (int i = 0; i < m; ++i) {
+                if (i + 1 < m) {
+                    const double nl = b[i], nd = a[i + 1] - mu, nu = i + 2 < m ? b[i + 1] : 0.0;
+                    if (fabs(nl) > fabs(cd)) {   // swap rows i and i+1
+                        d0[i] = nl;
+                        d1[i] = nd;
+                        d2[i] = nu;
+                        const double l = cd / nl;
+                        lm[i] = l;
+                        pv[i] = 1.0;
+                        cd = cu - l * nd;
+                        cu = -l * nu;
+                    } else {
+                        const double piv = cd != 0.0 ? cd : 1e-300;
+                        d0[i] = piv;
+                        d1[i] = cu;
+                        d2[i] = 0.0;
+                        const double l = nl / piv;
+                        lm[i] = l;
+                        pv[i] = 0.0;
+                        cd = nd - l * cu;
+                        cu = nu;
+                    }
+                } else {
+                    d0[i] = cd != 0.0 ? cd : 1e-300;
+                    d1[i] = 0.0;
+                    d2[i] = 0.0;
+                }
+            }
+            // forward: apply swaps and multipliers to x
+            for (int i = 0; i + 1 < m; ++i) {
+                if (pv[i] != 0.0) {
+                    const double tmp = x[i];
+                    x[i] = x[i + 1];
+                    x[i + 1] = tmp;
+                }
+                x[i + 1] -= lm[i] * x[i];
+            }
+            // back substitution
+            for (int i = m - 1; i >= 0; --i) {
+                double s = x[i];
+                if (i + 1 < m) s -= d1[i] * x[i + 1];
+                if (i + 2 < m) s -= d2[i] * x[i + 2];
+                x[i] = s / d0[i];
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
+            nrm = sqrt(nrm);
+            for (int i = 0; i < m; ++i) x[i] /= nrm;
+        }
+        for (int i = 0; i < m; ++i) S[(size_t)t * m + i] = x[i];
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int u = 0; u < r; ++u) {
+            double* su = S + (size_t)u * m;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int v = 0; v < u; ++v) {
+                    const double* sv = S + (size_t)v * m;
+                    double d = 0.0;
+                    for (int i = 0; i < m; ++i) d += sv[i] * su[i];
+                    for (int i = 0; i < m; ++i) su[i] -= d * sv[i];
+                }
+            double nrm = 0.0;
+            for (int i = 0; i < m; ++i) nrm += su[i] * su[i];
+            nrm = sqrt(nrm);
+            for (int i = 0; i < m; ++i) su[i] /= nrm;
+            resid[u] = fabs(b_last * su[m - 1]);
+        }
+    }
+}
+
+// U = Q S (n x r), S m x r column-major
+__global__ __launch_bounds__(kBlock) void k_ritz(const double2* __restrict__ Q, int64_t n, int m, int r,
+                                                 const double* __restrict__ S, double2* __restrict__ Uo) {
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < r; ++k) {
+        double ar = 0.0, ai = 0.0;
+        for (int j = 0; j < m; ++j) {
+            const double s = S[(size_t)k * m + j];
+            const double2 q = Q[(int64_t)j * n + i];
+            ar += q.x * s;
+            ai += q.y * s;
+        }
+        Uo[i * r + k] = make_double2(ar, ai);
+    }
+}
+
+// per block: (max |u_ik|^2, lowest index) for each column k
+__global__ __launch_bounds__(kBlock) void k_colmax(const double2* __restrict__ Uo, int64_t n, int r,
+                                                   double* __restrict__ pmax, int64_t* __restrict__ pidx) {
+    __shared__ double sm[kBlock];
+    __shared__ int64_t si[kBlock];
+    for (int k = 0; k < r; ++k) {
+        double best = -1.0;
+        int64_t bi = INT64_MAX;
+        for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+            const double2 u = Uo[i * r + k];
+            const double v = u.x * u.x + u.y * u.y;
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        sm[threadIdx.x] = best;
+        si[threadIdx.x] = bi;
+        __syncthreads();
+        for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                const double o = sm[threadIdx.x + h];
+                const int64_t oi = si[threadIdx.x + h];
+                if (o > sm[threadIdx.x] || (o == sm[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sm[threadIdx.x] = o;
+                    si[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            pmax[(size_t)blockIdx.x * r + k] = sm[0];
+            pidx[(size_t)blockIdx.x * r + k] = si[0];
+        }
+        __syncthreads();
+    }
+}
+
+// phase of each column from the block partials, then V = U phase sqrt(theta)
+__global__ __launch_bounds__(kBlock) void k_factor(const double2* __restrict__ Uo, int64_t n, int r, int parts,
+                                                   const double* __restrict__ pmax, const int64_t* __restrict__ pidx,
+                                                   const double* __restrict__ theta, double2* __restrict__ V) {
+    __shared__ double2 ph[LRQO_MAX_R];
+    if ((int)threadIdx.x < r) {
+        const int k = threadIdx.x;
+        double best = -1.0;
+        int64_t bi = INT64_MAX;
+        for (int p = 0; p < parts; ++p) {
+            const double v = pmax[(size_t)p * r + k];
+            const int64_t vi = pidx[(size_t)p * r + k];
+            if (v > best || (v == best && vi < bi)) {
+                best = v;
+                bi = vi;
+            }
+        }
+        const double2 u = Uo[bi * r + k];
+        const double mod = sqrt(u.x * u.x + u.y * u.y);
+        const double sc = sqrt(fmax(theta[k], 0.0)) / (mod > 0.0 ? mod : 1.0);
+        ph[k] = make_double2(u.x * sc, -u.y * sc);     // conj(u) / |u| sqrt(theta)
+    }
+    __syncthreads();
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < r; ++k) V[i * r + k] = cmul(Uo[i * r + k], ph[k]);
+}
+
+enum OpKind { kOpLap = 0, kOpPhase = 1 };
+
+lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_t n, int r,
+                           const lrqo_eigs_options* opt, double* Vout, lrqo_eigs_result* res) {
+    lrqo_eigs_options o{};
+    if (opt) o = *opt;
+    if (o.max_iter < 0 || o.max_iter > kMaxIter) return fail(LRQO_EINVAL, "max_iter must be in [0, 2000]");
+    if (o.check_every < 0) return fail(LRQO_EINVAL, "check_every must be >= 0");
+    if (!(o.tol >= 0.0) || o.tol >= 1.0) return fail(LRQO_EINVAL, "tol must be in [0, 1)");
+    const int max_iter = (int)std::min<int64_t>(o.max_iter ? o.max_iter : 300, n);
+    const int every = o.check_every ? o.check_every : 10;
+    const double tol = o.tol > 0.0 ? o.tol : 1e-10;
+    if (max_iter < r) return fail(LRQO_EINVAL, "max_iter (and n) must be at least r");
+    DeviceCtx* ctx = device_ctx();
+    if (!ctx) return LRQO_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const hipStream_t st = current_stream();
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    const int nparts = (int)std::min<int64_t>(blocks, 1024);
+    CarveSize cs;
+    cs.add<double2>((size_t)n * (max_iter + 1));   // basis
+    cs.add<double2>(n);                           // w
+    cs.add<double2>(kMaxIter + 1);                // h
+    cs.add<double2>(LRQO_MAX_R);                  // U^H x
+    cs.add<double>(nparts);                       // norm partials
+    cs.add<double>(4);                            // norm
+    cs.add<double>(kMaxIter + 1);                 // alpha
+    cs.add<double>(kMaxIter + 1);                 // beta
+    cs.add<double>(LRQO_MAX_R);                   // theta
+    cs.add<double>(LRQO_MAX_R);                   // resid
+    cs.add<double>((size_t)(kMaxIter + 1) * LRQO_MAX_R);       // S
+    cs.add<double>((size_t)6 * (kMaxIter + 1) * LRQO_MAX_R);   // tridiagonal work
+    cs.add<double2>((size_t)n * r);               // Ritz vectors
+    cs.add<double>((size_t)nparts * LRQO_MAX_R);
+    cs.add<int64_t>((size_t)nparts * LRQO_MAX_R);
+    CarveSize hs;
+    hs.add<double>(2 * (kMaxIter + 1));
+    hs.add<double>(2 * LRQO_MAX_R);
+    hs.add<double2>(2);
+    LRQO_TRY(reserve_arena(ctx, cs.bytes));
+    LRQO_TRY(reserve_host(ctx, hs.bytes));
+    Carve cv(ctx->arena);
+    double2* Q = cv.take<double2>((size_t)n * (max_iter + 1));
+    double2* w = cv.take<double2>(n);
+    double2* h = cv.take<double2>(kMaxIter + 1);
+    double2* uc = cv.take<double2>(LRQO_MAX_R);
+    double* npart = cv.take<double>(nparts);
+    double* nrm = cv.take<double>(4);
+    double* alpha = cv.take<double>(kMaxIter + 1);
+    double* beta = cv.take<double>(kMaxIter + 1);
+    double* theta = cv.take<double>(LRQO_MAX_R);
+    double* resid = cv.take<double>(LRQO_MAX_R);
+    double* S = cv.take<double>((size_t)(kMaxIter + 1) * LRQO_MAX_R);
+    double* work = cv.take<double>((size_t)6 * (kMaxIter + 1) * LRQO_MAX_R);
+    double2* Uo = cv.take<double2>((size_t)n * r);
+    double* pmax = cv.take<double>((size_t)nparts * LRQO_MAX_R);
+    int64_t* pidx = cv.take<int64_t>((size_t)nparts * LRQO_MAX_R);
+    Carve hv(ctx->host);
+    double* h_ab = hv.take<double>(2 * (kMaxIter + 1));     // alpha then beta
+    double* h_tr = hv.take<double>(2 * LRQO_MAX_R);         // theta then resid
+    double2* h_h = hv.take<double2>(2);
+    double* h_alpha = h_ab;
+    double* h_beta = h_ab + (kMaxIter + 1);
+
+    auto apply = [&](const double2* x, double2* y) -> lrqo_status {
+        if (kind == kOpLap) {
+            hipLaunchKernelGGL(k_apply_lap, dim3((unsigned)blocks), dim3(kBlock), 0, st, lap, x, y);
+        } else {
+            if (ph.p > 0) hipLaunchKernelGGL(k_utx, dim3(ph.p), dim3(kBlock), 0, st, ph, x, uc);
+            hipLaunchKernelGGL(k_apply_phase, dim3((unsigned)blocks), dim3(kBlock), 0, st, ph, uc, x, y);
+        }
+        LRQO_HIP(hipGetLastError());
+        return LRQO_OK;
+    };
+    auto normalize_into = [&](double2* dst) -> lrqo_status {
+        hipLaunchKernelGGL(k_norm_part, dim3(nparts), dim3(kBlock), 0, st, w, n, npart);
+        hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, npart, nparts, nrm);
+        hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(kBlock), 0, st, w, n, nrm, dst);
+        LRQO_HIP(hipGetLastError());
+        return LRQO_OK;
+    };
+
+    LRQO_HIP(hipEventRecord(ctx->ev_start, st));
+    hipLaunchKernelGGL(k_start, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, o.seed, w);
+    LRQO_TRY(normalize_into(Q));
+    int m = 0;              // Lanczos vectors q_0..q_{m-1} complete, T is m x m
+    bool converged = false, breakdown = false;
+    double b_last = 0.0;
+    for (int j = 0; j < max_iter; ++j) {
+        double2* qj = Q + (int64_t)j * n;
+        LRQO_TRY(apply(qj, w));
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(kBlock), 0, st, Q, n, w, h);
+            if (pass == 0) LRQO_HIP(hipMemcpyAsync(h_h, h + j, sizeof(double2), hipMemcpyDeviceToHost, st));
+            hipLaunchKernelGGL(k_sub, dim3((unsigned)blocks), dim3(kBlock), 0, st, Q, n, j + 1, h, w);
+            LRQO_HIP(hipGetLastError());
+            if (pass == 0) {
+                LRQO_HIP(hipStreamSynchronize(st));
+                h_alpha[j] = h_h[0].x;
+            }
+        }
+        hipLaunchKernelGGL(k_norm_part, dim3(nparts), dim3(kBlock), 0, st, w, n, npart);
+        hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, npart, nparts, nrm);
+        LRQO_HIP(hipGetLastError());
+        LRQO_HIP(hipMemcpyAsync(h_beta + j, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+        LRQO_HIP(hipStreamSynchronize(st));
+        m = j + 1;
+        b_last = h_beta[j];
+        double amax = 0.0;
+        for (int i = 0; i <= j; ++i) amax = std::max(amax, std::fabs(h_alpha[i]) + std::fabs(h_beta[i]));
+        breakdown = !(b_last > 1e-13 * amax) || m == n;
+        const bool check = m >= r && (breakdown || m % every == 0 || j + 1 == max_iter);
+        if (check) {
+            LRQO_HIP(hipMemcpyAsync(alpha, h_alpha, sizeof(double) * m, hipMemcpyHostToDevice, st));
+            LRQO_HIP(hipMemcpyAsync(beta, h_beta, sizeof(double) * m, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_tridiag_top, dim3(1), dim3(64), 0, st, alpha, beta, m, r, breakdown ? 0.0 : b_last,
+                               theta, S, resid, work);
+            LRQO_HIP(hipGetLastError());
+            LRQO_HIP(hipMemcpyAsync(h_tr, theta, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+            LRQO_HIP(hipMemcpyAsync(h_tr + LRQO_MAX_R, resid, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+            LRQO_HIP(hipStreamSynchronize(st));
+            const double scale = std::max(std::fabs(h_tr[0]), 1e-300);
+            converged = true;
+            for (int k = 0; k < r; ++k) converged &= h_tr[LRQO_MAX_R + k] <= tol * scale;
+            if (converged || breakdown) break;
+        }
+        if (breakdown) break;
+        LRQO_TRY(normalize_into(Q + (int64_t)(j + 1) * n));
+    }
+    if (m < r) return fail(LRQO_EINVAL, "the Krylov space is smaller than r (graph or operator too small)");
+    hipLaunchKernelGGL(k_ritz, dim3((unsigned)blocks), dim3(kBlock), 0, st, Q, n, m, r, S, Uo);
+    hipLaunchKernelGGL(k_colmax, dim3(nparts), dim3(kBlock), 0, st, Uo, n, r, pmax, pidx);
+    hipLaunchKernelGGL(k_factor, dim3((unsigned)blocks), dim3(kBlock), 0, st, Uo, n, r, nparts, pmax, pidx, theta,
+                       reinterpret_cast<double2*>(Vout));
+    LRQO_HIP(hipGetLastError());
+    LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
+    LRQO_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    LRQO_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    if (res) {
+        std::memset(res, 0, sizeof *res);
+        for (int k = 0; k < r; ++k) {
+            res->eigenvalues[k] = h_tr[k];
+            res->residuals[k] = h_tr[LRQO_MAX_R + k];
+        }
+        res->iterations = m;
+        res->converged = (converged || breakdown) ? 1 : 0;
+        res->device_ms = ms;
+    }
+    return LRQO_OK;
+}
+
+}  // namespace
+}  // namespace lrqo
+
+extern "C" {
+
+lrqo_status lrqo_laplacian_factor(const lrqo_graph* g, int32_t r, const lrqo_eigs_options* opt, double* V,
+                                  lrqo_eigs_result* res) {
+    using namespace lrqo;
+    clear_error();
+    LRQO_TRY(check_graph_args(g));
+    if (!V) return fail(LRQO_EINVAL, "null pointer argument");
+    if (r < 1 || r > LRQO_MAX_R) return fail(LRQO_EINVAL, "r must be in [1, 8]");
+    if (!is_device_pointer(V)) return fail(LRQO_EINVAL, "V is not device memory");
+    {
+        // the CSR layout is checked on the device before any kernel reads
+        // col through row_ptr
+        DeviceCtx* ctx = device_ctx();
+        if (!ctx) return LRQO_EDEVICE;
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        LRQO_TRY(reserve_arena(ctx, 256));
+        LRQO_TRY(reserve_host(ctx, 256));
+        LRQO_TRY(validate_graph(g, 2, nullptr, static_cast<int*>(ctx->arena), static_cast<int*>(ctx->host),
+                                current_stream()));
+    }
+    const LapOp lap{g->row_ptr, g->col, g->w, g->n};
+    const PhaseOp ph{};
+    return lanczos_factor(kOpLap, lap, ph, g->n, r, opt, V, res);
+}
+
+lrqo_status lrqo_phase_sync_factor(const double* U, int64_t n, int32_t p, double sigma, uint64_t w_seed, int32_t r,
+                                   const lrqo_eigs_options* opt, double* V, lrqo_eigs_result* res) {
+    using namespace lrqo;
+    clear_error();
+    if (!U || !V) return fail(LRQO_EINVAL, "null pointer argument");
+    if (n < 1 || n > 0x7fffffffLL) return fail(LRQO_EINVAL, "n must be in [1, 2^31 - 1]");
+    if (p < 0 || p > LRQO_MAX_R) return fail(LRQO_EINVAL, "p must be in [0, 8]");
+    if (r < 1 || r > LRQO_MAX_R) return fail(LRQO_EINVAL, "r must be in [1, 8]");
+    if (!std::isfinite(sigma)) return fail(LRQO_EINVAL, "sigma must be finite");
+    if (!is_device_pointer(U) || !is_device_pointer(V)) return fail(LRQO_EINVAL, "U and V must be device memory");
+    const LapOp lap{};
+    const PhaseOp ph{reinterpret_cast<const double2*>(U), p, sigma, w_seed, n};
+    return lanczos_factor(kOpPhase, lap, ph, n, r, opt, V, res);
+}
+
+}  // extern "C"

@@ -28,7 +28,7 @@ EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown"
            "lrqo_proposal_create", "lrqo_proposal_destroy", "lrqo_proposal_get_state",
            "lrqo_proposal_set_state", "lrqo_proposal_train_step", "lrqo_proposal_sample",
            "lrqo_proposal_frame", "lrqo_solve_nullvec", "lrqo_solve_rank1", "lrqo_graph_objective",
-           "lrqo_refine_greedy")
+           "lrqo_refine_greedy", "lrqo_laplacian_factor", "lrqo_phase_sync_factor")
 
 
 class LrqoError(RuntimeError):
@@ -76,6 +76,17 @@ class Rank1Result(ctypes.Structure):
     _fields_ = [("obj", ctypes.c_double), ("sweep_obj", ctypes.c_double),
                 ("best_cell", ctypes.c_int64), ("device_ms", ctypes.c_float),
                 ("sort_passes", ctypes.c_int32)]
+
+
+class EigsOptions(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class EigsResult(ctypes.Structure):
+    _fields_ = [("eigenvalues", ctypes.c_double * MAX_R), ("residuals", ctypes.c_double * MAX_R),
+                ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("device_ms", ctypes.c_float), ("pad", ctypes.c_int32)]
 
 
 class Graph(ctypes.Structure):
@@ -150,6 +161,12 @@ def load(path: str = LIB_PATH):
     lib.lrqo_graph_objective.restype = ctypes.c_int
     lib.lrqo_graph_objective.argtypes = [ctypes.POINTER(Graph), i32, vp, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
+    lib.lrqo_laplacian_factor.restype = i32
+    lib.lrqo_laplacian_factor.argtypes = [ctypes.POINTER(Graph), i32, ctypes.POINTER(EigsOptions), vp,
+                                          ctypes.POINTER(EigsResult)]
+    lib.lrqo_phase_sync_factor.restype = i32
+    lib.lrqo_phase_sync_factor.argtypes = [vp, i64, i32, ctypes.c_double, u64, i32, ctypes.POINTER(EigsOptions),
+                                           vp, ctypes.POINTER(EigsResult)]
     lib.lrqo_refine_greedy.restype = ctypes.c_int
     lib.lrqo_refine_greedy.argtypes = [ctypes.POINTER(Graph), i32, vp, ctypes.POINTER(RefineOptions),
                                        ctypes.POINTER(RefineResult)]
@@ -490,3 +507,43 @@ def refine_greedy(row_ptr, col, w, K: int, z, *, max_rounds: int = 0, check_ever
         _check(lib.lrqo_refine_greedy(ctypes.byref(g), int(K), ctypes.c_void_p(z.data_ptr()),
                                       ctypes.byref(opt), ctypes.byref(res)))
     return res
+
+
+def laplacian_factor(row_ptr, col, w, r: int, *, max_iter: int = 0, check_every: int = 0, tol: float = 0.0,
+                     seed: int = 0):
+    """Top-r factor of the graph Laplacian (see lrqo_laplacian_factor).
+    Returns (V complex128 (n, r) device tensor, EigsResult)."""
+    import torch
+
+    lib = load()
+    g = _graph(row_ptr, col, w)
+    V = torch.empty((g.n, r), dtype=torch.complex128, device=row_ptr.device)
+    opt = EigsOptions(int(max_iter), int(check_every), float(tol), int(seed) & (2**64 - 1))
+    res = EigsResult()
+    with torch.cuda.device(row_ptr.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_laplacian_factor(ctypes.byref(g), int(r), ctypes.byref(opt), ctypes.c_void_p(V.data_ptr()),
+                                         ctypes.byref(res)))
+    return V, res
+
+
+def phase_sync_factor(U, sigma: float, w_seed: int, r: int, *, max_iter: int = 0, check_every: int = 0,
+                      tol: float = 0.0, seed: int = 0):
+    """Top-r factor of U U^H + sigma W, W from w_seed (see
+    lrqo_phase_sync_factor).  U: complex128 (n, p) device tensor."""
+    import torch
+
+    lib = load()
+    if not (U.is_cuda and U.dtype == torch.complex128 and U.dim() == 2):
+        raise ValueError("U must be a complex128 (n, p) device tensor")
+    Uc = U.contiguous()
+    n, p = U.shape
+    V = torch.empty((n, r), dtype=torch.complex128, device=U.device)
+    opt = EigsOptions(int(max_iter), int(check_every), float(tol), int(seed) & (2**64 - 1))
+    res = EigsResult()
+    with torch.cuda.device(U.device):
+        _bind_stream(torch)
+        _check(lib.lrqo_phase_sync_factor(ctypes.c_void_p(Uc.data_ptr()), int(n), int(p), float(sigma),
+                                          int(w_seed) & (2**64 - 1), int(r), ctypes.byref(opt),
+                                          ctypes.c_void_p(V.data_ptr()), ctypes.byref(res)))
+    return V, res
