@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
     ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal", "refine",
-                                       "rank1_hybrid", "samplers"),
+                                       "rank1_hybrid", "samplers", "spectral"),
                     help="measure only this form and print its record (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized float32 device tensor once before timing "
@@ -262,6 +262,51 @@ def form_samplers():
     return out
 
 
+def form_spectral():
+    """The step before the path on the GPU: the top-r factor of the maxcut_er
+    and planted-partition Laplacians (against ARPACK on the host, the
+    library the inputs are built with) and of the matrix-free phase-sync
+    operator at n = 262,144."""
+    import numpy as np
+    import scipy.sparse.linalg as sla
+    import torch
+
+    from paper_2602_20376_amd import inputs, lrqo
+
+    out = {}
+    for name, (n, edges, r) in {"maxcut_er": (100_000, inputs.maxcut_er_graph(), 4),
+                                "maxcut_ppm": (1_000_000, inputs.maxcut_ppm_graph(), 3)}.items():
+        i, j = edges
+        rp, col, _ = inputs.csr_adjacency(n, i, j)
+        rpd, cold = torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda()
+        lrqo.laplacian_factor(rpd, cold, None, r, tol=1e-10, max_iter=600)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        V, res = lrqo.laplacian_factor(rpd, cold, None, r, tol=1e-10, max_iter=600)
+        torch.cuda.synchronize()
+        gpu_ms = (time.perf_counter() - t) * 1000.0
+        L = inputs.laplacian(n, i, j)
+        t = time.perf_counter()
+        lam, _ = sla.eigsh(L, k=r, which="LA", v0=np.random.default_rng(0).standard_normal(n), tol=1e-10,
+                           ncv=max(4 * r + 1, 24))
+        host_ms = (time.perf_counter() - t) * 1000.0
+        lam = np.sort(lam)[::-1]
+        out[name] = {"n": n, "r": r, "gpu_ms": gpu_ms, "device_ms": res.device_ms, "iterations": res.iterations,
+                     "eigenvalues": list(res.eigenvalues[:r]),
+                     "max_rel_diff_vs_arpack": float(np.max(np.abs(np.array(res.eigenvalues[:r]) - lam) / lam)),
+                     "arpack_host_ms": host_ms}
+    n = 262_144
+    rng = np.random.default_rng(5)
+    U = torch.from_numpy(np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, (n, 3)))).cuda()
+    t = time.perf_counter()
+    V, res = lrqo.phase_sync_factor(U, 0.5 * np.sqrt(n), 77, 3, tol=1e-8, max_iter=120)
+    torch.cuda.synchronize()
+    out["phase_sync"] = {"n": n, "r": 3, "gpu_ms": (time.perf_counter() - t) * 1000.0, "device_ms": res.device_ms,
+                         "iterations": res.iterations, "eigenvalues_over_n": [x / n for x in res.eigenvalues[:3]],
+                         "W_entries_per_s": res.iterations * float(n) * n / (res.device_ms / 1000.0)}
+    return out
+
+
 def form_learned(train_count):
     """Learned proposal against uniform sampling on phase synchronisation
     (n = 262,144, r = 3, K = 16): samples needed to reach 99.9% of the best
@@ -313,7 +358,7 @@ def main():
 
     if args.form:
         fn = {"precision_bf16": form_precision, "batched": form_batched, "refine": form_refine,
-              "rank1_hybrid": form_rank1_hybrid, "samplers": form_samplers,
+              "rank1_hybrid": form_rank1_hybrid, "samplers": form_samplers, "spectral": form_spectral,
               "learned_proposal": lambda: form_learned(args.train_count)}[args.form]
         print(json.dumps({"form": args.form, **fn()}), flush=True)
         return
@@ -370,7 +415,7 @@ def main():
         forms = {}
         for name, fn in (("precision_bf16", form_precision), ("batched", form_batched),
                          ("refine", form_refine), ("rank1_hybrid", form_rank1_hybrid),
-                         ("samplers", form_samplers),
+                         ("samplers", form_samplers), ("spectral", form_spectral),
                          ("learned_proposal", lambda: form_learned(args.train_count))):
             print(f"bench: measuring {name}", file=sys.stderr, flush=True)
             try:
