@@ -28,6 +28,9 @@
 #ifndef LRQO_BF16_SPLIT
 #define LRQO_BF16_SPLIT 2
 #endif
+#ifndef LRQO_SCORE_BLOCKS
+#define LRQO_SCORE_BLOCKS 2048
+#endif
 #ifndef LRQO_SCORE_CPL
 #define LRQO_SCORE_CPL 4
 #endif
@@ -937,7 +940,7 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     const int R = job.r;
     const int64_t cand_blocks = (job.S + cands_per_block(R) - 1) / cands_per_block(R);
     // enough blocks to fill 256 CUs several times over, slices of >= 1024 rows
-    int64_t slices = std::max<int64_t>(1, (2048 + cand_blocks - 1) / cand_blocks);
+    int64_t slices = std::max<int64_t>(1, (LRQO_SCORE_BLOCKS + cand_blocks - 1) / cand_blocks);
     slices = std::min<int64_t>(slices, std::max<int64_t>(1, job.n / 1024));
     int64_t rows = (job.n + slices - 1) / slices;
     rows = ((rows + 63) / 64) * 64;
