@@ -140,3 +140,50 @@ def test_batched_rejects_bad_options(lib):
     assert "cpl" in lrqo.last_error()
     assert _batched(lib, opt=lrqo.BatchOptions(0, 99, 0, 0, 0, 0, None)) == -1
     assert "rescore_topk" in lrqo.last_error()
+
+
+def test_nullvec_rejects_bad_arguments(lib):
+    res = lrqo.ExactResult()
+    call = lambda V=1, n=10, r=2, K=3, S=16, z=1: lib.lrqo_solve_nullvec(
+        ctypes.c_void_p(V), n, r, K, S, 1, ctypes.c_void_p(z), ctypes.byref(res))
+    for kw, msg in [(dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=5), "r must"),
+                    (dict(n=1), "n must"), (dict(K=1), "K must"), (dict(S=0), "S must"),
+                    (dict(S=2**31), "S must")]:
+        assert call(**kw) == -1, kw
+        assert msg in lrqo.last_error(), (kw, lrqo.last_error())
+
+
+def test_rank1_rejects_bad_arguments(lib):
+    res = lrqo.Rank1Result()
+    call = lambda q=1, n=10, K=3, z=1: lib.lrqo_solve_rank1(ctypes.c_void_p(q), n, K, ctypes.c_void_p(z),
+                                                           ctypes.byref(res))
+    for kw, msg in [(dict(q=0), "null"), (dict(z=0), "null"), (dict(n=0), "n must"),
+                    (dict(n=2**31), "n must"), (dict(K=1), "K must"), (dict(K=256), "K must"),
+                    (dict(), "not device memory")]:
+        assert call(**kw) == -1, kw
+        assert msg in lrqo.last_error(), (kw, lrqo.last_error())
+
+
+def test_graph_calls_reject_bad_arguments(lib):
+    q, c = ctypes.c_double(), ctypes.c_double()
+    assert lib.lrqo_graph_objective(None, 3, ctypes.c_void_p(1), ctypes.byref(q), ctypes.byref(c)) == -1
+    assert "null graph" in lrqo.last_error()
+    g = lrqo.Graph(ctypes.c_void_p(1), ctypes.c_void_p(1), None, 0, 0)
+    assert lib.lrqo_graph_objective(ctypes.byref(g), 3, ctypes.c_void_p(1), ctypes.byref(q), ctypes.byref(c)) == -1
+    assert "n must" in lrqo.last_error()
+    g = lrqo.Graph(ctypes.c_void_p(1), None, None, 5, 4)
+    assert lib.lrqo_refine_greedy(ctypes.byref(g), 3, ctypes.c_void_p(1), None, None) == -1
+    assert "null col" in lrqo.last_error()
+    g = lrqo.Graph(ctypes.c_void_p(1), ctypes.c_void_p(1), None, 5, 4)
+    assert lib.lrqo_refine_greedy(ctypes.byref(g), 3, ctypes.c_void_p(1), None, None) == -1
+    assert "device memory" in lrqo.last_error()
+    res = lrqo.EigsResult()
+    assert lib.lrqo_laplacian_factor(ctypes.byref(g), 3, None, None, ctypes.byref(res)) == -1
+    assert lib.lrqo_phase_sync_factor(None, 10, 3, 1.0, 1, 3, None, ctypes.c_void_p(1), ctypes.byref(res)) == -1
+    assert "null" in lrqo.last_error()
+    assert lib.lrqo_phase_sync_factor(ctypes.c_void_p(1), 10, 9, 1.0, 1, 3, None, ctypes.c_void_p(1),
+                                      ctypes.byref(res)) == -1
+    assert "p must" in lrqo.last_error()
+    assert lib.lrqo_phase_sync_factor(ctypes.c_void_p(1), 10, 3, float("nan"), 1, 3, None, ctypes.c_void_p(1),
+                                      ctypes.byref(res)) == -1
+    assert "sigma" in lrqo.last_error()
