@@ -78,15 +78,12 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
     ScratchPlan plan;
     plan_sampled(job, plan);
     LRQO_TRY(reserve_arena(ctx, plan.bytes));
-    const size_t host_need = sizeof(DevResult) + 4 * LRQO_MAX_K * sizeof(double) + 256;
-    LRQO_TRY(reserve_host(ctx, host_need));
+    LRQO_TRY(reserve_host(ctx, sizeof(DevResult)));
     hipStream_t st = current_stream();
-    char* hbase = static_cast<char*>(ctx->host);
-    DevResult* hres = reinterpret_cast<DevResult*>(hbase);
-    void* hroots = hbase + 256;
+    DevResult* hres = static_cast<DevResult*>(ctx->host);
 
     LRQO_HIP(hipEventRecord(ctx->ev_start, st));
-    LRQO_TRY(launch_sampled(job, plan, ctx->arena, hroots, st));
+    LRQO_TRY(launch_sampled(job, plan, ctx->arena, st));
     // the result block sits first in the arena
     LRQO_HIP(hipMemcpyAsync(hres, ctx->arena, sizeof(DevResult), hipMemcpyDeviceToHost, st));
     LRQO_HIP(hipEventRecord(ctx->ev_stop, st));

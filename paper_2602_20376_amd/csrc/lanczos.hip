@@ -10,7 +10,8 @@
 //                Philox4x32-10, key seed, counter (min, max, 0x57484D41, 0):
 //                off-diagonal sqrt(-log u0) e^{2 pi i u1}, conjugated below
 //                the diagonal; diagonal sqrt(-2 log u0) cos 2 pi u1), so the
-//                n x n matrix is never stored
+//                n x n matrix is never stored; each upper-triangle entry is
+//                generated once per product and serves its row and column
 //
 // Per Lanczos step j (basis columns q_0..q_j in HBM, column-major):
 //   w = A q_j; h = Q^H w (alpha_j = Re h_j); w -= Q h; a second pass of the
@@ -119,35 +120,106 @@ __device__ __forceinline__ float2 w_entry32(uint64_t seed, int64_t i, int64_t j)
     return make_float2(rad * cs, i <= j ? rad * sn : -rad * sn);
 }
 
-// y_i = sum_k U_ik c_k + sigma sum_j W_ij x_j; x staged through LDS
-__global__ __launch_bounds__(kBlock) void k_apply_phase(PhaseOp o, const double2* __restrict__ c,
-                                                        const double2* __restrict__ x, double2* __restrict__ y) {
-    __shared__ double2 xs[kBlock];
-    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+// Symmetric form of sigma W x: every entry of the upper triangle is
+// generated once and used for its row and, conjugated, for its column.
+// Rows come in stripes of kSymT = 256 (one block); a work item is stripe I
+// against a chunk of up to kSymChunk column stripes J >= I.  Lane l of wave w
+// (row I*256 + 64w + l) visits column (l + s) mod 256 of tile J at step s,
+// so the 64 lanes of a wave touch 64 different columns at every step and
+// each wave adds its column contributions into its own LDS row of cacc in a
+// fixed order; the four waves' sums are added in wave order.  Outputs:
+//   rowpart[item][t]        row sums of the item's tiles
+//   colpart[tri(J, I)][t]   column sums of tile (I, J), tri(J, I) = J(J+1)/2 + I
+// and k_w_combine adds, for row stripe I, the row sums of its items and the
+// column sums of the tiles (I', I), I' <= I, in that order.
+constexpr int kSymT = 256;
+constexpr int kSymChunk = 8;
+
+__device__ __forceinline__ int64_t tri_index(int64_t J, int64_t I) { return J * (J + 1) / 2 + I; }
+
+__global__ __launch_bounds__(kSymT) void k_w_tiles(PhaseOp o, const double2* __restrict__ x,
+                                                   const int2* __restrict__ items, int64_t P,
+                                                   double2* __restrict__ rowpart, double2* __restrict__ colpart) {
+    __shared__ double2 xs[kSymT];
+    __shared__ double2 cacc[kSymT / kWave][kSymT];
+    const int2 item = items[blockIdx.x];
+    const int64_t I = item.x;
+    const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+    const int64_t i = I * kSymT + t;
     const bool live = i < o.n;
+    const double2 xi = live ? x[i] : make_double2(0.0, 0.0);
     double ar = 0.0, ai = 0.0;
-    for (int64_t j0 = 0; j0 < o.n; j0 += kBlock) {
+    const int64_t J0 = I + (int64_t)item.y * kSymChunk, J1 = min(P, J0 + kSymChunk);
+    for (int64_t J = J0; J < J1; ++J) {
         __syncthreads();
-        xs[threadIdx.x] = j0 + threadIdx.x < o.n ? x[j0 + threadIdx.x] : make_double2(0.0, 0.0);
+        const int64_t jt = J * kSymT + t;
+        xs[t] = jt < o.n ? x[jt] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int v = 0; v < kSymT / kWave; ++v) cacc[v][t] = make_double2(0.0, 0.0);
         __syncthreads();
-        if (!live) continue;
-        const int cnt = (int)min((int64_t)kBlock, o.n - j0);
-        for (int t = 0; t < cnt; ++t) {
-            const float2 w = w_entry32(o.seed, i, j0 + t);
-            const double wr = (double)w.x, wi = (double)w.y;
-            const double2 xj = xs[t];
-            ar += wr * xj.x - wi * xj.y;
-            ai += wr * xj.y + wi * xj.x;
+        if (live) {
+            for (int st = 0; st < kSymT; ++st) {
+                const int jl = (lane + st) & (kSymT - 1);
+                const int64_t j = J * kSymT + jl;
+                if (j < o.n && (J != I || j >= i)) {
+                    const float2 w = w_entry32(o.seed, i, j);   // i <= j: the stored entry
+                    const double wr = (double)w.x, wi = (double)w.y;
+                    const double2 xj = xs[jl];
+                    ar += wr * xj.x - wi * xj.y;
+                    ai += wr * xj.y + wi * xj.x;
+                    if (j != i) {
+                        double2 ca = cacc[wv][jl];
+                        ca.x += wr * xi.x + wi * xi.y;           // conj(W_ij) x_i
+                        ca.y += wr * xi.y - wi * xi.x;
+                        cacc[wv][jl] = ca;
+                    }
+                }
+                // the next step's lane l reads the column lane l+1 wrote now
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
         }
+        __syncthreads();
+        double2 cs = cacc[0][t];
+#pragma unroll
+        for (int v = 1; v < kSymT / kWave; ++v) {
+            cs.x += cacc[v][t].x;
+            cs.y += cacc[v][t].y;
+        }
+        colpart[tri_index(J, I) * kSymT + t] = cs;
     }
-    if (!live) return;
+    rowpart[(int64_t)blockIdx.x * kSymT + t] = make_double2(ar, ai);
+}
+
+// y_i = sum_k U_ik c_k + sigma (row sums of the items of stripe I + column
+// sums of tiles (I', I), I' <= I); item_first[I] = first item of stripe I.
+__global__ __launch_bounds__(kSymT) void k_w_combine(PhaseOp o, const double2* __restrict__ c,
+                                                     const int32_t* __restrict__ item_first, int64_t P,
+                                                     const double2* __restrict__ rowpart,
+                                                     const double2* __restrict__ colpart, double2* __restrict__ y) {
+    const int64_t I = blockIdx.x;
+    const int t = threadIdx.x;
+    const int64_t i = I * kSymT + t;
+    if (i >= o.n) return;
+    double ar = 0.0, ai = 0.0;
+    for (int32_t it = item_first[I]; it < item_first[I + 1]; ++it) {
+        const double2 v = rowpart[(int64_t)it * kSymT + t];
+        ar += v.x;
+        ai += v.y;
+    }
+    for (int64_t Ip = 0; Ip <= I; ++Ip) {
+        const double2 v = colpart[tri_index(I, Ip) * kSymT + t];
+        ar += v.x;
+        ai += v.y;
+    }
     double yr = o.sigma * ar, yi = o.sigma * ai;
     for (int k = 0; k < o.p; ++k) {
-        const double2 t = cmul(o.U[i * o.p + k], c[k]);
-        yr += t.x;
-        yi += t.y;
+        const double2 u = cmul(o.U[i * o.p + k], c[k]);
+        yr += u.x;
+        yi += u.y;
     }
     y[i] = make_double2(yr, yi);
+    (void)P;
 }
 
 // ---------------------------------------------------------------- basis algebra
@@ -465,6 +537,22 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     cs.add<double2>((size_t)n * r);               // Ritz vectors
     cs.add<double>((size_t)nparts * LRQO_MAX_R);
     cs.add<int64_t>((size_t)nparts * LRQO_MAX_R);
+    // symmetric W tiles (phase-sync operator only)
+    const int64_t P = (n + kSymT - 1) / kSymT;
+    std::vector<int2> items;
+    std::vector<int32_t> item_first;
+    if (kind == kOpPhase) {
+        item_first.reserve(P + 1);
+        for (int64_t I = 0; I < P; ++I) {
+            item_first.push_back((int32_t)items.size());
+            for (int64_t cidx = 0; I + cidx * kSymChunk < P; ++cidx) items.push_back(make_int2((int)I, (int)cidx));
+        }
+        item_first.push_back((int32_t)items.size());
+        cs.add<int2>(items.size());
+        cs.add<int32_t>(item_first.size());
+        cs.add<double2>(items.size() * (size_t)kSymT);
+        cs.add<double2>((size_t)(P * (P + 1) / 2) * kSymT);
+    }
     CarveSize hs;
     hs.add<double>(2 * (kMaxIter + 1));
     hs.add<double>(2 * LRQO_MAX_R);
@@ -487,6 +575,20 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     double2* Uo = cv.take<double2>((size_t)n * r);
     double* pmax = cv.take<double>((size_t)nparts * LRQO_MAX_R);
     int64_t* pidx = cv.take<int64_t>((size_t)nparts * LRQO_MAX_R);
+    int2* d_items = nullptr;
+    int32_t* d_first = nullptr;
+    double2* rowpart = nullptr;
+    double2* colpart = nullptr;
+    if (kind == kOpPhase) {
+        d_items = cv.take<int2>(items.size());
+        d_first = cv.take<int32_t>(item_first.size());
+        rowpart = cv.take<double2>(items.size() * (size_t)kSymT);
+        colpart = cv.take<double2>((size_t)(P * (P + 1) / 2) * kSymT);
+        LRQO_HIP(hipMemcpyAsync(d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, st));
+        LRQO_HIP(hipMemcpyAsync(d_first, item_first.data(), sizeof(int32_t) * item_first.size(),
+                                hipMemcpyHostToDevice, st));
+        LRQO_HIP(hipStreamSynchronize(st));
+    }
     Carve hv(ctx->host);
     double* h_ab = hv.take<double>(2 * (kMaxIter + 1));     // alpha then beta
     double* h_tr = hv.take<double>(2 * LRQO_MAX_R);         // theta then resid
@@ -499,7 +601,10 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
             hipLaunchKernelGGL(k_apply_lap, dim3((unsigned)blocks), dim3(kBlock), 0, st, lap, x, y);
         } else {
             if (ph.p > 0) hipLaunchKernelGGL(k_utx, dim3(ph.p), dim3(kBlock), 0, st, ph, x, uc);
-            hipLaunchKernelGGL(k_apply_phase, dim3((unsigned)blocks), dim3(kBlock), 0, st, ph, uc, x, y);
+            hipLaunchKernelGGL(k_w_tiles, dim3((unsigned)items.size()), dim3(kSymT), 0, st, ph, x, d_items, P,
+                               rowpart, colpart);
+            hipLaunchKernelGGL(k_w_combine, dim3((unsigned)P), dim3(kSymT), 0, st, ph, uc, d_first, P, rowpart,
+                               colpart, y);
         }
         LRQO_HIP(hipGetLastError());
         return LRQO_OK;

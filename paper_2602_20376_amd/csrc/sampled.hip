@@ -47,7 +47,23 @@ struct Row {
     static constexpr int F = REAL ? R : 2 * R;  // floats per row of V
 };
 
-// ------------------------------------------------------------ checks
+// ------------------------------------------------------------ set-up and checks
+// Roots of unity omega^k = (cos, sin)(2 pi k / K) in FP64 and their FP32
+// roundings; zeroed result record and arg-max key.
+__global__ void k_init(int K, double2* __restrict__ roots64, float2* __restrict__ roots32,
+                       DevResult* __restrict__ res, unsigned long long* __restrict__ best_key) {
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)K, &sn, &cs);
+        roots64[k] = make_double2(cs, sn);
+        roots32[k] = make_float2((float)cs, (float)sn);
+    }
+    if (threadIdx.x == 0) {
+        *res = DevResult{};
+        *best_key = 0ull;
+    }
+}
+
 __global__ void k_check_finite(const float* __restrict__ V, int64_t count, DevResult* res) {
     bool bad = false;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
@@ -964,9 +980,7 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     plan.bytes = cs.bytes;
 }
 
-lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena,
-                           void* host_roots /* pinned, >= 4*LRQO_MAX_K doubles */,
-                           hipStream_t st) {
+lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena, hipStream_t st) {
     Carve cv(arena);
     Scratch sc{};
     sc.result = cv.take<DevResult>(1);
@@ -984,20 +998,7 @@ lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void*
     sc.rescore_rows = plan.rescore_rows;
     sc.rescore = cv.take<double>((size_t)plan.topk * plan.rescore_slices * 2 * job.r);
 
-    // roots of unity, FP64 from the host libm and their FP32 roundings
-    double* h64 = static_cast<double*>(host_roots);
-    float* h32 = reinterpret_cast<float*>(h64 + 2 * LRQO_MAX_K);
-    for (int k = 0; k < job.K; ++k) {
-        const double a = 6.283185307179586476925286766559 * (double)k / (double)job.K;
-        h64[2 * k] = std::cos(a);
-        h64[2 * k + 1] = std::sin(a);
-        h32[2 * k] = (float)h64[2 * k];
-        h32[2 * k + 1] = (float)h64[2 * k + 1];
-    }
-    LRQO_HIP(hipMemcpyAsync(sc.roots64, h64, sizeof(double) * 2 * job.K, hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(sc.roots32, h32, sizeof(float) * 2 * job.K, hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemsetAsync(sc.result, 0, sizeof(DevResult), st));
-    LRQO_HIP(hipMemsetAsync(sc.best_key, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, job.K, sc.roots64, sc.roots32, sc.result, sc.best_key);
 
     const int64_t vcount = job.n * job.r * (job.real ? 1 : 2);
     hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(256), 0, st, job.V, vcount, sc.result);

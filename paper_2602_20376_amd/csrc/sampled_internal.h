@@ -96,7 +96,6 @@ struct Scratch {
 };
 
 void plan_sampled(const SampledJob& job, ScratchPlan& plan);
-lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena,
-                           void* host_roots, hipStream_t st);
+lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena, hipStream_t st);
 
 }  // namespace lrqo
