@@ -394,11 +394,14 @@ def main():
     avg_score_ms = sum(score_ms) / len(score_ms)
     achieved = flops / (avg_score_ms / 1000.0) / 1e12
     kernel = f"k_score_rows<{r}, 4, true, {K if K in (2, 3, 4, 8, 16) else 0}>"
+    rows_at_peak = FP32_VECTOR_PEAK_TFLOPS * 1e12 / flops_per_rowcand
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": load_traffic(kernel), "kernel": kernel,
                 "kernel_ms": round(avg_score_ms, 4),
-                "algorithmic_flops_per_launch": flops}
+                "algorithmic_flops_per_launch": flops,
+                "candidate_rows_per_s_at_peak": rows_at_peak,
+                "end_to_end_frac": round(value / rows_at_peak, 4)}
 
     rec = {"metric": "candidate-rows scored/s", "value": value, "unit": "candidate-rows/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
