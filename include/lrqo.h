@@ -378,7 +378,8 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z,
 
 typedef struct lrqo_eigs_options {
     int32_t max_iter;        /* Lanczos steps, at most min(n, 2000); 0: 300 */
-    int32_t check_every;     /* steps between convergence checks; 0: 10 */
+    int32_t check_every;     /* steps between convergence checks; 0: 10 for the
+                                Laplacian, 1 for the phase-sync operator */
     double tol;              /* 0: 1e-10 */
     uint64_t seed;           /* start vector: complex Gaussian entries from Philox4x32-10,
                                 counter (i lo, i hi, 0x5354524C, 0) */
@@ -400,12 +401,14 @@ lrqo_status lrqo_laplacian_factor(const lrqo_graph* g, int32_t r, const lrqo_eig
 
 /* Top-r factor of Q = U U^H + sigma W (phase synchronisation), applied
  * matrix-free: U device complex128 n x p (row-major interleaved, 0 <= p <= 8)
- * and W the Hermitian Gaussian matrix defined by w_seed: for i <= j, words
- * (w0, w1) of Philox4x32-10 with key (w_seed lo, w_seed hi) and counter
- * (i, j, 0x57484D41, 0) give u = ((w >> 9) + 1/2) 2^-23 and
+ * and W the Hermitian Gaussian matrix defined by w_seed: for i <= j,
+ * Philox4x32-10 with key (w_seed lo, w_seed hi) and counter
+ * (i, j >> 1, 0x57484D41, 0) gives words (w0, w1, w2, w3); column j takes
+ * (w0, w1) for even j and (w2, w3) for odd j, as u = ((w >> 9) + 1/2) 2^-23;
  * W_ij = sqrt(-log u0) e^{2 pi i u1} (i < j), W_ii = sqrt(-2 log u0)
- * cos(2 pi u1), W_ji = conj(W_ij) (evaluated in FP32, accumulated in FP64).
- * Each product costs n^2 entry evaluations. */
+ * cos(2 pi u1), W_ji = conj(W_ij) (evaluated in FP32 with the hardware
+ * log2, sqrt, sin and cos, accumulated in FP64).  Each product costs n^2/2
+ * entry evaluations; check_every = 0 checks convergence after every step. */
 lrqo_status lrqo_phase_sync_factor(const double* U, int64_t n, int32_t p, double sigma, uint64_t w_seed, int32_t r,
                                    const lrqo_eigs_options* opt, double* V, lrqo_eigs_result* res);
 

@@ -11,8 +11,10 @@ Two matrices:
 
 W is regenerated from a counter-based definition (the paper fixes none; the
 library's matrix-free operator evaluates the same definition): for i <= j,
-words (w0, w1) of Philox4x32-10 with key (seed lo, seed hi) and counter
-(i, j, 0x57484D41, 0) give uniforms u = ((w >> 9) + 1/2) 2^-23 and
+Philox4x32-10 with key (seed lo, seed hi) and counter (i, j >> 1, 0x57484D41, 0)
+gives four words (w0, w1, w2, w3); column j takes (w0, w1) when j is even and
+(w2, w3) when j is odd, so one call serves the columns 2q and 2q + 1 of row i.
+The two words give uniforms u = ((w >> 9) + 1/2) 2^-23 and
   W_ij = sqrt(-log u0) (cos 2 pi u1 + i sin 2 pi u1)   (i < j)
   W_ii = sqrt(-2 log u0) cos 2 pi u1,                  W_ji = conj(W_ij).
 
@@ -34,9 +36,10 @@ W_STREAM = 0x57484D41
 def w_entry(seed: int, i: int, j: int) -> complex:
     """W_ij by the definition above, FP64."""
     a, b = (i, j) if i <= j else (j, i)
-    o = philox4x32_10([a & 0xFFFFFFFF, b & 0xFFFFFFFF, W_STREAM, 0],
+    o = philox4x32_10([a & 0xFFFFFFFF, (b >> 1) & 0xFFFFFFFF, W_STREAM, 0],
                       [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF])
-    u0, u1 = uniform(int(o[0])), uniform(int(o[1]))
+    h = 2 * (b & 1)
+    u0, u1 = uniform(int(o[h])), uniform(int(o[h + 1]))
     if a == b:
         return complex(math.sqrt(-2.0 * math.log(u0)) * math.cos(2.0 * math.pi * u1), 0.0)
     rad = math.sqrt(-math.log(u0))

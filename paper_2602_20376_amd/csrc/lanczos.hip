@@ -6,8 +6,9 @@
 //   Laplacian    L = D - A of a CSR graph (as for Max-K-Cut, Sec. 5):
 //                y_i = sum_j w_ij (x_i - x_j)
 //   phase sync   Q = U U^H + sigma W with W Hermitian Gaussian regenerated
-//                on the fly from a counter-based definition (W_ij from
-//                Philox4x32-10, key seed, counter (min, max, 0x57484D41, 0):
+//                on the fly from a counter-based definition (for i <= j,
+//                Philox4x32-10 with key seed and counter (i, j >> 1,
+//                0x57484D41, 0); words (x, y) for even j, (z, w) for odd j;
 //                off-diagonal sqrt(-log u0) e^{2 pi i u1}, conjugated below
 //                the diagonal; diagonal sqrt(-2 log u0) cos 2 pi u1), so the
 //                n x n matrix is never stored; each upper-triangle entry is
@@ -109,30 +110,56 @@ __global__ __launch_bounds__(kBlock) void k_utx(PhaseOp o, const double2* __rest
     if (threadIdx.x == 0) c[k] = make_double2(ar, ai);
 }
 
-__device__ __forceinline__ float2 w_entry32(uint64_t seed, int64_t i, int64_t j) {
-    const uint32_t a = (uint32_t)(i < j ? i : j), b = (uint32_t)(i < j ? j : i);
-    const U4 o = philox4x32_10(U4{a, b, kWStream, 0u}, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const float u0 = uniform_from_bits(o.x), u1 = uniform_from_bits(o.y);
-    float sn, cs;
-    sincospif(2.0f * u1, &sn, &cs);
-    if (a == b) return make_float2(sqrtf(-2.0f * logf(u0)) * cs, 0.0f);
-    const float rad = sqrtf(-logf(u0));
-    return make_float2(rad * cs, i <= j ? rad * sn : -rad * sn);
+// W entries in FP32 from the words of one Philox call, with the hardware
+// transcendentals: v_log_f32 is log2, v_sin_f32 / v_cos_f32 take the angle in
+// turns (sin 2 pi u).  u >= 2^-24 is never denormal, so none of the library
+// range reductions is needed.
+constexpr float kLn2 = 0.693147180559945309f;
+
+__device__ __forceinline__ float unit_from_bits(uint32_t x) {
+    // ((x >> 9) + 1/2) 2^-23, exact: one rounding of an exact value
+    return __builtin_fmaf(static_cast<float>(x >> 9), 0x1p-23f, 0x1p-24f);
+}
+// sqrt(-log u0) e^{2 pi i u1}
+__device__ __forceinline__ float2 w_off(uint32_t a, uint32_t b) {
+    const float u0 = unit_from_bits(a), u1 = unit_from_bits(b);
+    const float rad = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u0) * -kLn2);
+    return make_float2(rad * __builtin_amdgcn_cosf(u1), rad * __builtin_amdgcn_sinf(u1));
+}
+// sqrt(-2 log u0) cos 2 pi u1
+__device__ __forceinline__ float w_diag(uint32_t a, uint32_t b) {
+    const float u0 = unit_from_bits(a), u1 = unit_from_bits(b);
+    return __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u0) * (-2.0f * kLn2)) * __builtin_amdgcn_cosf(u1);
+}
+
+// One entry (row i, column j, i <= j) of the upper triangle against the
+// tile's x_j (row use) and, off the diagonal, conj(W_ij) x_i into the
+// column accumulator ca.
+__device__ __forceinline__ void w_use(float2 e, double2 xj, double2 xi, double& ar, double& ai, double2& ca) {
+    const double wr = (double)e.x, wi = (double)e.y;
+    ar = __builtin_fma(-wi, xj.y, __builtin_fma(wr, xj.x, ar));
+    ai = __builtin_fma(wi, xj.x, __builtin_fma(wr, xj.y, ai));
+    ca.x = __builtin_fma(wi, xi.y, __builtin_fma(wr, xi.x, ca.x));
+    ca.y = __builtin_fma(-wi, xi.x, __builtin_fma(wr, xi.y, ca.y));
 }
 
 // Symmetric form of sigma W x: every entry of the upper triangle is
 // generated once and used for its row and, conjugated, for its column.
 // Rows come in stripes of kSymT = 256 (one block); a work item is stripe I
-// against a chunk of up to kSymChunk column stripes J >= I.  Lane l of wave w
-// (row I*256 + 64w + l) visits column (l + s) mod 256 of tile J at step s,
-// so the 64 lanes of a wave touch 64 different columns at every step and
-// each wave adds its column contributions into its own LDS row of cacc in a
-// fixed order; the four waves' sums are added in wave order.  Outputs:
+// against a chunk of up to kSymChunk column stripes J >= I.  Columns are
+// taken in pairs (2q, 2q + 1), the two entries of one Philox call.  Lane l
+// of wave w (row I*256 + 64w + l) visits pair (l + s) mod 128 of tile J at
+// step s, so the 64 lanes of a wave touch 128 different columns at every
+// step and each wave adds its column contributions into its own LDS row of
+// cacc in a fixed order; the four waves' sums are added in wave order.
+// Tiles off the diagonal and inside the matrix need no per-entry test.
+// Outputs:
 //   rowpart[item][t]        row sums of the item's tiles
 //   colpart[tri(J, I)][t]   column sums of tile (I, J), tri(J, I) = J(J+1)/2 + I
 // and k_w_combine adds, for row stripe I, the row sums of its items and the
 // column sums of the tiles (I', I), I' <= I, in that order.
 constexpr int kSymT = 256;
+constexpr int kSymPairs = kSymT / 2;
 constexpr int kSymChunk = 8;
 
 __device__ __forceinline__ int64_t tri_index(int64_t J, int64_t I) { return J * (J + 1) / 2 + I; }
@@ -147,6 +174,8 @@ __global__ __launch_bounds__(kSymT) void k_w_tiles(PhaseOp o, const double2* __r
     const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
     const int64_t i = I * kSymT + t;
     const bool live = i < o.n;
+    const uint32_t iu = static_cast<uint32_t>(i);
+    const uint32_t k0 = static_cast<uint32_t>(o.seed), k1 = static_cast<uint32_t>(o.seed >> 32);
     const double2 xi = live ? x[i] : make_double2(0.0, 0.0);
     double ar = 0.0, ai = 0.0;
     const int64_t J0 = I + (int64_t)item.y * kSymChunk, J1 = min(P, J0 + kSymChunk);
@@ -157,24 +186,46 @@ __global__ __launch_bounds__(kSymT) void k_w_tiles(PhaseOp o, const double2* __r
 #pragma unroll
         for (int v = 0; v < kSymT / kWave; ++v) cacc[v][t] = make_double2(0.0, 0.0);
         __syncthreads();
-        if (live) {
-            for (int st = 0; st < kSymT; ++st) {
-                const int jl = (lane + st) & (kSymT - 1);
-                const int64_t j = J * kSymT + jl;
-                if (j < o.n && (J != I || j >= i)) {
-                    const float2 w = w_entry32(o.seed, i, j);   // i <= j: the stored entry
-                    const double wr = (double)w.x, wi = (double)w.y;
-                    const double2 xj = xs[jl];
-                    ar += wr * xj.x - wi * xj.y;
-                    ai += wr * xj.y + wi * xj.x;
-                    if (j != i) {
-                        double2 ca = cacc[wv][jl];
-                        ca.x += wr * xi.x + wi * xi.y;           // conj(W_ij) x_i
-                        ca.y += wr * xi.y - wi * xi.x;
-                        cacc[wv][jl] = ca;
+        const uint32_t qbase = static_cast<uint32_t>(J * kSymPairs);
+        if (J != I && (J + 1) * kSymT <= o.n) {
+            // J > I, so stripe I is full as well: every entry is strictly
+            // above the diagonal and inside the matrix
+            for (int st = 0; st < kSymPairs; ++st) {
+                const int q = (lane + st) & (kSymPairs - 1);
+                const U4 h = philox4x32_10(U4{iu, qbase + q, kWStream, 0u}, k0, k1);
+                double2 c0 = cacc[wv][2 * q], c1 = cacc[wv][2 * q + 1];
+                w_use(w_off(h.x, h.y), xs[2 * q], xi, ar, ai, c0);
+                w_use(w_off(h.z, h.w), xs[2 * q + 1], xi, ar, ai, c1);
+                cacc[wv][2 * q] = c0;
+                cacc[wv][2 * q + 1] = c1;
+                // the next step's lane l reads the pair lane l+1 wrote now
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        } else if (live) {
+            // diagonal tile or the last, partial column stripe
+            for (int st = 0; st < kSymPairs; ++st) {
+                const int q = (lane + st) & (kSymPairs - 1);
+                const int64_t j0 = J * kSymT + 2 * q;
+                if (j0 + 1 >= i && j0 < o.n) {
+                    const U4 h = philox4x32_10(U4{iu, qbase + q, kWStream, 0u}, k0, k1);
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int64_t j = j0 + e;
+                        if (j < i || j >= o.n) continue;
+                        const uint32_t a = e ? h.z : h.x, b = e ? h.w : h.y;
+                        const double2 xj = xs[2 * q + e];
+                        if (j == i) {
+                            const double d = (double)w_diag(a, b);
+                            ar = __builtin_fma(d, xj.x, ar);
+                            ai = __builtin_fma(d, xj.y, ai);
+                        } else {
+                            double2 c = cacc[wv][2 * q + e];
+                            w_use(w_off(a, b), xj, xi, ar, ai, c);
+                            cacc[wv][2 * q + e] = c;
+                        }
                     }
                 }
-                // the next step's lane l reads the column lane l+1 wrote now
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
@@ -512,7 +563,9 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     if (o.check_every < 0) return fail(LRQO_EINVAL, "check_every must be >= 0");
     if (!(o.tol >= 0.0) || o.tol >= 1.0) return fail(LRQO_EINVAL, "tol must be in [0, 1)");
     const int max_iter = (int)std::min<int64_t>(o.max_iter ? o.max_iter : 300, n);
-    const int every = o.check_every ? o.check_every : 10;
+    // a phase-sync product costs n^2/2 entry evaluations, far more than the
+    // tridiagonal Ritz step, so that operator is checked after every step
+    const int every = o.check_every ? o.check_every : (kind == kOpPhase ? 1 : 10);
     const double tol = o.tol > 0.0 ? o.tol : 1e-10;
     if (max_iter < r) return fail(LRQO_EINVAL, "max_iter (and n) must be at least r");
     DeviceCtx* ctx = device_ctx();

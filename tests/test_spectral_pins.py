@@ -22,6 +22,24 @@ def test_w_is_hermitian_with_the_stated_moments(oracle_lib):
     assert spectral.w_entry(77, 5, 3) == np.conj(spectral.w_entry(77, 3, 5))
 
 
+def test_entries_of_one_call_are_uncorrelated(oracle_lib):
+    """Columns 2q and 2q + 1 of a row take the two word pairs of one Philox
+    call: the pair must behave as two independent N_C(0,1) draws."""
+    n = 160
+    W = spectral.w_matrix(n, 91)
+    a, b = [], []
+    for i in range(n):
+        for q in range(n // 2):
+            if 2 * q > i:
+                a.append(W[i, 2 * q])
+                b.append(W[i, 2 * q + 1])
+    a, b = np.array(a), np.array(b)
+    assert len(a) > 5000
+    assert abs(np.mean(a * np.conj(b))) < 0.03
+    assert abs(np.mean(a * b)) < 0.03
+    assert abs(np.corrcoef(np.abs(a) ** 2, np.abs(b) ** 2)[0, 1]) < 0.05
+
+
 def test_semicircle_edge(oracle_lib):
     n = 300
     ev = np.linalg.eigvalsh(spectral.w_matrix(n, 5)) / np.sqrt(n)
