@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+HBM_PEAK_GBPS = 8000.0            # MI355X published HBM3E bandwidth
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_maxcut_er.json")
 
 
@@ -66,6 +67,24 @@ def cpu_baseline(inst, seconds: float):
             "kind": "oracle",
             "sample": f"first {count} of the {inst.S} directions (same stream, FP64, "
                       f"{res['threads']} threads, {dt:.1f} s)"}
+
+
+def _timed(fn):
+    t = time.perf_counter()
+    out = fn()
+    return (time.perf_counter() - t) * 1000.0, out
+
+
+def _alu_roofline(flops: float, ms: float, what: str) -> dict:
+    achieved = flops / (ms / 1000.0) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "algorithmic_flops": flops, "ms": ms, "what": what}
+
+
+def _hbm_roofline(nbytes: float, ms: float, what: str) -> dict:
+    achieved = nbytes / (ms / 1000.0) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "algorithmic_bytes": nbytes, "ms": ms, "what": what}
 
 
 def load_traffic(kernel: str):
@@ -113,7 +132,18 @@ def form_precision():
     run(0), run(1)
     ms32, o32 = _time(lambda: run(0), 3)
     ms16, o16 = _time(lambda: run(1), 3)
+    import oracle
+
+    oracle.build()
+    cnt = 64
+    oms, ores = _timed(lambda: oracle.sampled(inst.V, inst.K, cnt, inst.seed, want_f=False))
+    flops = 8 * inst.r * inst.n * inst.S
     return {"workload": "maxcut_ppm", "n": inst.n, "r": inst.r, "K": inst.K, "S": inst.S,
+            "roofline_fp32": _alu_roofline(flops, o32.score_ms, "k_score_rows, 8r flops per row-candidate"),
+            "roofline_bf16": _alu_roofline(flops, o16.score_ms, "k_score_bf16, same algorithmic flops"),
+            "oracle": {"kind": "oracle", "ms": oms, "candidate_rows_per_s": cnt * inst.n / (oms / 1000.0),
+                       "cores": ores["threads"],
+                       "sample": f"first {cnt} of the {inst.S} directions (FP64, {ores['threads']} threads)"},
             "fp32_ms": ms32, "bf16_ms": ms16, "bf16_speedup": ms32 / ms16,
             "fp32_score_ms": o32.score_ms, "bf16_score_ms": o16.score_ms,
             "obj_fp32": o32.obj, "obj_bf16": o16.obj,
@@ -137,7 +167,19 @@ def form_batched():
     first = run()
     ms, out = _time(run, 5)
     rows = int(b.n.sum()) * b.S
+    import oracle
+
+    oracle.build()
+    m = 128
+    oms, _ = _timed(lambda: [oracle.sampled(b.factor(t), b.K, b.S, b.seed, instance=t, want_f=False)
+                             for t in range(m)])
+    share = float(np.sum(b.n[:m] * b.r[:m])) / float(np.sum(b.n * b.r))
+    flops = 16.0 * float(np.sum(b.n * b.r)) * b.S
     return {"workload": "psk_batch", "instances": b.count, "K": b.K, "S": b.S,
+            "roofline": _alu_roofline(flops, out.device_ms, "16r flops per row-candidate (complex V) over the "
+                                      "whole batch (scorer, select, FP64 rescore, labels)"),
+            "oracle": {"kind": "oracle", "ms": oms, "ms_scaled_to_batch": oms / share,
+                       "sample": f"first {m} of the {b.count} instances, whole streams (FP64)"},
             "row_candidates": rows, "ms_per_batch": ms, "device_ms": out.device_ms,
             "candidate_rows_per_s": rows / (out.device_ms / 1000.0),
             "instances_per_s": b.count / (ms / 1000.0), "cpl": out.cpl,
@@ -174,7 +216,16 @@ def form_refine():
     # row_ptr twice, col twice, neighbour labels and gains gathered, own
     # label / gain / target / next label
     bytes_round = 16 * n + 4 * nnz + nnz + n + 8 * n + n + 8 * n + 4 * nnz + 8 * nnz + 3 * n
+    from oracle import graph as G
+
+    nb = G.adjacency(n, (i, j, np.ones(len(i))))
+    zr = np.random.default_rng(17).integers(0, inst.K, n)
+    oms, _ = _timed(lambda: G.greedy_round(n, nb, inst.K, zr))
     return {"workload": "maxcut_er graph", "n": n, "nnz": nnz, "K": inst.K,
+            "roofline": _hbm_roofline(bytes_round * res.launched, res.device_ms,
+                                      "k_gain + k_move, algorithmic bytes per round x rounds launched"),
+            "oracle": {"kind": "oracle", "ms_per_round": oms,
+                       "sample": "one round of the same rule from seeded random labels (pure Python loops)"},
             "cut_sampled": res.cut_before, "cut_refined": res.cut_after,
             "edges": nnz // 2, "cut_fraction_refined": res.cut_after / (nnz // 2),
             "rounds": res.rounds, "moves": res.moves, "converged": bool(res.converged),
@@ -214,7 +265,18 @@ def form_rank1_hybrid():
     Vd = torch.from_numpy(inputs.as_real_f32(inst.V)).cuda()
     zs = lrqo.solve_sampled(Vd, inst.K, inst.S, inst.seed, real=True).z
     _, cut_sampled = lrqo.graph_objective(rpd, cold, None, inst.K, zs)
+    from oracle import rank1 as R1
+
+    m = 1 << 16
+    oms, _ = _timed(lambda: R1.rank1_sweep(q[:m], inst.K))
+    dev = min(r[1] for r in runs)
+    # prep 16 B read + 29 B written per coordinate; a radix pass reads the
+    # 12 B pairs twice and writes them once; tiles and cells gather 20 B twice
+    sweep_bytes = (45 + 36 * res.sort_passes + 40) * float(inst.n)
     return {"workload": "maxcut_ppm", "n": inst.n, "K": inst.K, "edges": int(len(i)),
+            "roofline": _hbm_roofline(sweep_bytes, dev, "whole sweep: prep, radix passes, tile and cell scans"),
+            "oracle": {"kind": "oracle", "ms": oms, "ms_scaled_to_n": oms * inst.n / m,
+                       "sample": f"Alg. 1 on the first {m} coordinates of the same q (FP64, Python loop)"},
             "rank1_ms": min(r[0] for r in runs), "rank1_device_ms": min(r[1] for r in runs),
             "rank1_cells_per_s": (inst.n + 1) / (min(r[1] for r in runs) / 1000.0),
             "rank1_obj": res.obj, "rank1_sort_passes": res.sort_passes,
@@ -254,6 +316,11 @@ def form_samplers():
         _, cut_u = lrqo.graph_objective(rpd, cold, None, inst.K, u.z)
         _, cut_n = lrqo.graph_objective(rpd, cold, None, inst.K, zn)
         out[f"r{r}"] = {"uniform_obj": u.obj, "nullvec_obj": rn.obj,
+                        "nullvec_roofline": _alu_roofline(
+                            16.0 * r * inst.n * 2 * (rn.index_sets - rn.rank_deficient), rn.device_ms,
+                            "null-vector path: per feasible draw and sign, V c and V^H z over all rows "
+                            "(16r flops per row, complex V; label options of the drawn rows share them)"),
+
                         "uniform_over_nullvec": u.obj / rn.obj,
                         "cut_uniform": cut_u, "cut_nullvec": cut_n,
                         "nullvec_feasible": (rn.index_sets - rn.rank_deficient) / S,
@@ -291,7 +358,17 @@ def form_spectral():
                            ncv=max(4 * r + 1, 24))
         host_ms = (time.perf_counter() - t) * 1000.0
         lam = np.sort(lam)[::-1]
+        nnz = 2 * len(i)
+        m = res.iterations
+        # per step: Laplacian product (row pointers, columns, gathered and
+        # own entries, result), two Gram-Schmidt passes over the j + 1 basis
+        # columns (dots read them and w, subtraction reads them and updates
+        # w), norm and scaling
+        lap = 8.0 * (n + 1) + 20.0 * nnz + 32.0 * n
+        steps = sum(lap + 2 * (32.0 * n * (j + 1) + 48.0 * n) + 48.0 * n for j in range(m))
         out[name] = {"n": n, "r": r, "gpu_ms": gpu_ms, "device_ms": res.device_ms, "iterations": res.iterations,
+                     "roofline": _hbm_roofline(steps, res.device_ms, "Lanczos with two-pass reorthogonalisation, "
+                                               "algorithmic bytes of all steps"),
                      "eigenvalues": list(res.eigenvalues[:r]),
                      "max_rel_diff_vs_arpack": float(np.max(np.abs(np.array(res.eigenvalues[:r]) - lam) / lam)),
                      "arpack_host_ms": host_ms}
@@ -303,7 +380,9 @@ def form_spectral():
     torch.cuda.synchronize()
     out["phase_sync"] = {"n": n, "r": 3, "gpu_ms": (time.perf_counter() - t) * 1000.0, "device_ms": res.device_ms,
                          "iterations": res.iterations, "eigenvalues_over_n": [x / n for x in res.eigenvalues[:3]],
-                         "W_entries_per_s": res.iterations * float(n) * n / (res.device_ms / 1000.0)}
+                         "W_entries_generated_per_s":
+                             res.iterations * float(n) * (n + 1) / 2 / (res.device_ms / 1000.0),
+                         "ms_per_product": res.device_ms / res.iterations}
     return out
 
 
@@ -331,6 +410,15 @@ def form_learned(train_count):
     t_infer = (time.perf_counter() - t) * 1000.0
     ol = lrqo.solve_sampled(Vd, inst.K, SL, inst.seed, directions=dirs, f_out=fl)
     ref = max(ou.obj, ol.obj)
+    from oracle import proposal as OP
+
+    theta = prop.get_state()["theta"].astype(np.float64)
+
+    def oracle_infer():
+        G, s_ = OP.canonical_frame(inst.V, inst.K)
+        return OP.forward(theta, OP.features(inst.V, G, s_))
+
+    oms, _ = _timed(oracle_infer)
     ku = drv.knee(fu.cpu().numpy(), ref)
     kl = drv.knee(fl.cpu().numpy(), ref)
     row_rate = inst.n * SU / (ou.score_ms / 1000.0)
@@ -339,6 +427,8 @@ def form_learned(train_count):
             "samples_to_99.9pct_uniform": ku, "samples_to_99.9pct_learned": kl,
             "sample_ratio_uniform_over_learned": (ku / kl) if (ku and kl) else None,
             "learned_inference_ms": t_infer, "uniform_candidate_rows_per_s": row_rate,
+            "oracle": {"kind": "oracle", "inference_ms": oms,
+                       "sample": "gauge frame, features and network forward on the same factor (FP64)"},
             "train_instances": train_count, "train_final_loss": hist[-1], "train_first_loss": hist[0],
             **{k: round(v, 2) for k, v in phases.items()}}
 

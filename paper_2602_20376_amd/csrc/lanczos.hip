@@ -17,7 +17,8 @@
 // Per Lanczos step j (basis columns q_0..q_j in HBM, column-major):
 //   w = A q_j; h = Q^H w (alpha_j = Re h_j); w -= Q h; a second pass of the
 //   same (classical Gram-Schmidt, twice); beta_j = ||w||; q_{j+1} = w/beta_j.
-// Every check interval one block finds the r largest eigenvalues of the
+// alpha and beta are written on the device; the host reads them only at the
+// checks.  Every check interval one block finds the r largest eigenvalues of the
 // tridiagonal T_j by Sturm bisection and their vectors by inverse iteration;
 // |beta_j s_{j,k}| bounds the residual of Ritz pair k.  At convergence the
 // Ritz vectors U = Q S are formed, each is rotated so that its
@@ -96,19 +97,6 @@ struct PhaseOp {
     uint64_t seed;
     int64_t n;
 };
-
-// c[k] = sum_i conj(U_ik) x_i, one block per k
-__global__ __launch_bounds__(kBlock) void k_utx(PhaseOp o, const double2* __restrict__ x, double2* __restrict__ c) {
-    const int k = blockIdx.x;
-    double ar = 0.0, ai = 0.0;
-    for (int64_t i = threadIdx.x; i < o.n; i += kBlock) {
-        const double2 t = cdot1(o.U[i * o.p + k], x[i]);
-        ar += t.x;
-        ai += t.y;
-    }
-    block_sum2(ar, ai);
-    if (threadIdx.x == 0) c[k] = make_double2(ar, ai);
-}
 
 // W entries in FP32 from the words of one Philox call, with the hardware
 // transcendentals: v_log_f32 is log2, v_sin_f32 / v_cos_f32 take the angle in
@@ -274,19 +262,95 @@ __global__ __launch_bounds__(kSymT) void k_w_combine(PhaseOp o, const double2* _
 }
 
 // ---------------------------------------------------------------- basis algebra
-// h_j = q_j^H w for j < k (one block per column)
-__global__ __launch_bounds__(kBlock) void k_dots(const double2* __restrict__ Q, int64_t n, const double2* __restrict__ w,
-                                                 double2* __restrict__ h) {
-    const int j = blockIdx.x;
-    const double2* q = Q + (int64_t)j * n;
-    double ar = 0.0, ai = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
-        const double2 t = cdot1(q[i], w[i]);
-        ar += t.x;
-        ai += t.y;
+// h_j = q_j^H w for j < k in two fixed-order stages.  Block (b, c) takes
+// rows [b kDotRows, (b + 1) kDotRows) of columns kDotCols c .. kDotCols c + 7:
+// each thread sums its rows, the lanes of a wave are added by butterfly and
+// the four waves in order, giving part[j nb + b]; k_part_sum then adds the
+// nb partials of column j (lanes strided, then butterfly).  Q is read once,
+// by as many blocks as there are row chunks times column groups.
+constexpr int kDotRows = 4096;
+constexpr int kDotCols = 8;
+
+__device__ __forceinline__ void block_sums_to(double (&acc)[2 * kDotCols], int count, double* dst, int64_t stride) {
+    __shared__ double red[kBlock / kWave][2 * kDotCols];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+    for (int e = 0; e < 2 * kDotCols; ++e) {
+        const double v = wave_sum_f64(acc[e]);
+        if (lane == 0) red[wv][e] = v;
     }
-    block_sum2(ar, ai);
-    if (threadIdx.x == 0) h[j] = make_double2(ar, ai);
+    __syncthreads();
+    if ((int)threadIdx.x < 2 * count) {
+        double v = red[0][threadIdx.x];
+#pragma unroll
+        for (int q = 1; q < kBlock / kWave; ++q) v += red[q][threadIdx.x];
+        dst[(int64_t)(threadIdx.x >> 1) * stride + (threadIdx.x & 1)] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dots_part(const double2* __restrict__ Q, int64_t n,
+                                                      const double2* __restrict__ w, int k, int nb,
+                                                      double2* __restrict__ part) {
+    const int b = blockIdx.x, j0 = blockIdx.y * kDotCols;
+    const int nc = min(kDotCols, k - j0);
+    const int64_t i0 = (int64_t)b * kDotRows, i1 = min(n, i0 + kDotRows);
+    double acc[2 * kDotCols];
+#pragma unroll
+    for (int e = 0; e < 2 * kDotCols; ++e) acc[e] = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const double2 wi = w[i];
+#pragma unroll
+        for (int c = 0; c < kDotCols; ++c) {
+            if (c < nc) {
+                const double2 q = Q[(int64_t)(j0 + c) * n + i];      // conj(q) w
+                acc[2 * c] = __builtin_fma(q.y, wi.y, __builtin_fma(q.x, wi.x, acc[2 * c]));
+                acc[2 * c + 1] = __builtin_fma(-q.y, wi.x, __builtin_fma(q.x, wi.y, acc[2 * c + 1]));
+            }
+        }
+    }
+    block_sums_to(acc, nc, reinterpret_cast<double*>(part + (int64_t)j0 * nb + b), 2 * (int64_t)nb);
+}
+
+// part[k nb + b] = sum over rows of chunk b of conj(U_ik) x_i, k < p
+// (U row-major n x p, p <= 8)
+__global__ __launch_bounds__(kBlock) void k_utx_part(PhaseOp o, const double2* __restrict__ x, int nb,
+                                                     double2* __restrict__ part) {
+    const int b = blockIdx.x;
+    const int64_t i0 = (int64_t)b * kDotRows, i1 = min(o.n, i0 + kDotRows);
+    double acc[2 * kDotCols];
+#pragma unroll
+    for (int e = 0; e < 2 * kDotCols; ++e) acc[e] = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const double2 xi = x[i];
+#pragma unroll
+        for (int c = 0; c < kDotCols; ++c) {
+            if (c < o.p) {
+                const double2 u = o.U[i * o.p + c];
+                acc[2 * c] = __builtin_fma(u.y, xi.y, __builtin_fma(u.x, xi.x, acc[2 * c]));
+                acc[2 * c + 1] = __builtin_fma(-u.y, xi.x, __builtin_fma(u.x, xi.y, acc[2 * c + 1]));
+            }
+        }
+    }
+    block_sums_to(acc, o.p, reinterpret_cast<double*>(part + b), 2 * (int64_t)nb);
+}
+
+// h_j = sum_b part[j nb + b], one wave per column; Re h of the last column
+// also into last_re[0] when given
+__global__ __launch_bounds__(kWave) void k_part_sum(const double2* __restrict__ part, int nb,
+                                                    double2* __restrict__ h, double* __restrict__ last_re) {
+    const int j = blockIdx.x;
+    double ar = 0.0, ai = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kWave) {
+        const double2 v = part[(int64_t)j * nb + b];
+        ar += v.x;
+        ai += v.y;
+    }
+    ar = wave_sum_f64(ar);
+    ai = wave_sum_f64(ai);
+    if (threadIdx.x == 0) {
+        h[j] = make_double2(ar, ai);
+        if (last_re && j == (int)gridDim.x - 1) last_re[0] = ar;
+    }
 }
 
 // w -= sum_{j<k} q_j h_j
@@ -298,7 +362,21 @@ __global__ __launch_bounds__(kBlock) void k_sub(const double2* __restrict__ Q, i
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
     double ar = 0.0, ai = 0.0;
-    for (int j = 0; j < k; ++j) {
+    // eight column loads in flight per thread, the sum still in column order
+    constexpr int U = 8;
+    int j = 0;
+    for (; j + U <= k; j += U) {
+        double2 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = Q[(int64_t)(j + u) * n + i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double2 t = cmul(q[u], hs[j + u]);
+            ar += t.x;
+            ai += t.y;
+        }
+    }
+    for (; j < k; ++j) {
         const double2 t = cmul(Q[(int64_t)j * n + i], hs[j]);
         ar += t.x;
         ai += t.y;
@@ -317,11 +395,16 @@ __global__ __launch_bounds__(kBlock) void k_norm_part(const double2* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = a;
 }
 
-__global__ __launch_bounds__(kBlock) void k_norm_final(const double* __restrict__ part, int count, double* __restrict__ out) {
+// out[0] = sqrt(sum of the partials); also into copy[0] when given
+__global__ __launch_bounds__(kBlock) void k_norm_final(const double* __restrict__ part, int count, double* __restrict__ out,
+                                                       double* __restrict__ copy) {
     double a = 0.0, b = 0.0;
     for (int t = threadIdx.x; t < count; t += kBlock) a += part[t];
     block_sum2(a, b);
-    if (threadIdx.x == 0) out[0] = sqrt(a);
+    if (threadIdx.x == 0) {
+        out[0] = sqrt(a);
+        if (copy) copy[0] = sqrt(a);
+    }
 }
 
 // q = w / nrm (nrm read on the device)
@@ -329,7 +412,8 @@ __global__ __launch_bounds__(kBlock) void k_scale(const double2* __restrict__ w,
                                                   double2* __restrict__ q) {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
-    const double inv = 1.0 / nrm[0];
+    // a zero vector (breakdown, found by the host at the next check) stays zero
+    const double inv = nrm[0] > 0.0 ? 1.0 / nrm[0] : 0.0;
     const double2 t = w[i];
     q[i] = make_double2(t.x * inv, t.y * inv);
 }
@@ -347,87 +431,134 @@ __global__ __launch_bounds__(kBlock) void k_start(int64_t n, uint64_t seed, doub
 }
 
 // ---------------------------------------------------------------- tridiagonal
-// Number of eigenvalues of T (diagonal a, off-diagonal b) below x (Sturm).
-__device__ int sturm_below(const double* a, const double* b, int m, double x) {
+// Number of eigenvalues of T (diagonal a, squared off-diagonal bb) below x
+// (Sturm sequence of the pivots of T - x I).
+__device__ __forceinline__ int sturm_below(const double* a, const double* bb, int m, double x) {
     int cnt = 0;
-    double d = 1.0;
-    for (int i = 0; i < m; ++i) {
-        const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
-        d = a[i] - x - (i ? bb / d : 0.0);
+    double d = a[0] - x;
+    if (d == 0.0) d = -1e-300;
+    cnt += d < 0.0;
+    for (int i = 1; i < m; ++i) {
+        d = a[i] - x - bb[i - 1] / d;
         if (d == 0.0) d = -1e-300;
         cnt += d < 0.0;
     }
     return cnt;
 }
 
-// Thread t < r: eigenvalue theta_t (the t-th largest) by bisection and its
-// unit vector by inverse iteration (tridiagonal elimination with partial
-// pivoting); thread 0 then orthonormalises the r vectors in order and
-// forms the residual bounds |b_last s_{m-1,t}|.  S is m x r column-major.
-__global__ void k_tridiag_top(const double* __restrict__ a, const double* __restrict__ b, int m, int r,
-                              double b_last, double* __restrict__ theta, double* __restrict__ S,
-                              double* __restrict__ resid, double* __restrict__ work) {
-    const int t = threadIdx.x;
-    if (t < r) {
-        double lo = INFINITY, hi = -INFINITY;
-        for (int i = 0; i < m; ++i) {
-            const double rad = (i ? fabs(b[i - 1]) : 0.0) + (i + 1 < m ? fabs(b[i]) : 0.0);
-            lo = fmin(lo, a[i] - rad);
-            hi = fmax(hi, a[i] + rad);
+// Top r eigenpairs of the m x m tridiagonal T (diagonal a, off-diagonal b).
+// a, b and b^2 are staged in LDS.  Eigenvalue t (the t-th largest, ascending
+// index k = m-1-t) is found by wave t mod 4 by multisection: the 64 lanes
+// count the eigenvalues below 64 interior points of the bracket, and the
+// first point whose count exceeds k becomes the upper end (a factor of 65
+// per round).  Thread t < r then computes the unit vector by inverse
+// iteration on T - mu I, mu just off theta (one elimination with partial
+// pivoting, three solves); wave 0 orthonormalises the r vectors in order
+// (two Gram-Schmidt passes, lane-strided dots added by butterfly) and forms
+// the residual bounds |b_last s_{m-1,t}|.  S is m x r column-major; the
+// elimination works in LDS for m <= kTriLds, else in `work`.
+constexpr int kTriThreads = 256;
+constexpr int kTriLds = 224;
+
+__global__ __launch_bounds__(kTriThreads) void k_tridiag_top(const double* __restrict__ a_g,
+                                                             const double* __restrict__ b_g, int m, int r,
+                                                             double b_last, double* __restrict__ theta,
+                                                             double* __restrict__ S, double* __restrict__ resid,
+                                                             double* __restrict__ work) {
+    __shared__ double a[kMaxIter + 1], b[kMaxIter + 1], bb[kMaxIter + 1];
+    __shared__ double wl[LRQO_MAX_R][6 * kTriLds];
+    __shared__ double red_lo[kTriThreads / kWave], red_hi[kTriThreads / kWave];
+    __shared__ double th_s[LRQO_MAX_R];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int i = tid; i < m; i += kTriThreads) {
+        const double ai = a_g[i], bi = i + 1 < m ? b_g[i] : 0.0, bp = i ? b_g[i - 1] : 0.0;
+        a[i] = ai;
+        b[i] = bi;
+        bb[i] = bi * bi;
+        const double rad = fabs(bp) + fabs(bi);           // Gershgorin disc of row i
+        lo = fmin(lo, ai - rad);
+        hi = fmax(hi, ai + rad);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, kWave));
+        hi = fmax(hi, __shfl_xor(hi, off, kWave));
+    }
+    if (lane == 0) {
+        red_lo[wv] = lo;
+        red_hi[wv] = hi;
+    }
+    __syncthreads();
+    lo = red_lo[0];
+    hi = red_hi[0];
+#pragma unroll
+    for (int q = 1; q < kTriThreads / kWave; ++q) {
+        lo = fmin(lo, red_lo[q]);
+        hi = fmax(hi, red_hi[q]);
+    }
+    const double span = fmax(hi - lo, 1e-300);
+    lo -= 1e-12 * span;
+    hi += 1e-12 * span;
+    for (int t = wv; t < r; t += kTriThreads / kWave) {
+        const int k = m - 1 - t;
+        double l0 = lo, h0 = hi;
+        for (int round = 0; round < 40 && h0 - l0 > 4e-16 * fmax(fabs(l0), fabs(h0)); ++round) {
+            const double step = (h0 - l0) / 65.0;
+            const bool above = sturm_below(a, bb, m, l0 + step * (double)(lane + 1)) > k;
+            const unsigned long long mask = __ballot(above);
+            const int first = mask ? __ffsll(mask) - 1 : kWave;
+            const double nh = first < kWave ? l0 + step * (double)(first + 1) : h0;
+            l0 = first > 0 ? l0 + step * (double)first : l0;
+            h0 = nh;
         }
-        const double span = fmax(hi - lo, 1e-300);
-        lo -= 1e-12 * span;
-        hi += 1e-12 * span;
-        const int k = m - 1 - t;      // ascending index
-        for (int it = 0; it < 200 && hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)); ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (sturm_below(a, b, m, mid) > k) hi = mid;
-            else lo = mid;
+        if (lane == 0) {
+            th_s[t] = 0.5 * (l0 + h0);
+            theta[t] = th_s[t];
         }
-        const double th = 0.5 * (lo + hi);
-        theta[t] = th;
-        // inverse iteration on (T - mu I), mu just off th
-        const double mu = th + 1e-13 * span;
-        double* d0 = work + (size_t)t * 6 * m;   // diagonal after elimination
-        double* d1 = d0 + m;                      // first superdiagonal
-        double* d2 = d1 + m;                      // second superdiagonal (fill-in)
-        double* lm = d2 + m;                      // multipliers
-        double* pv = lm + m;                      // pivot swap flags
-        double* x = pv + m;
-        for (int i = 0; i < m; ++i) x[i] = 1.0 + 0.001 * (double)((i * 7919 + t * 104729) % 97);
-        for (int iter = 0; iter < 4; ++iter) {
-            // factor: rows i, i+1 with partial pivoting
-            double cd = a[0] - mu, cu = m > 1 ? b[0] : 0.0;
-            for (int i = 0; i < m; ++i) {
-                if (i + 1 < m) {
-                    const double nl = b[i], nd = a[i + 1] - mu, nu = i + 2 < m ? b[i + 1] : 0.0;
-                    if (fabs(nl) > fabs(cd)) {   // swap rows i and i+1
-                        d0[i] = nl;
-                        d1[i] = nd;
-                        d2[i] = nu;
-                        const double l = cd / nl;
-                        lm[i] = l;
-                        pv[i] = 1.0;
-                        cd = cu - l * nd;
-                        cu = -l * nu;
-                    } else {
-                        const double piv = cd != 0.0 ? cd : 1e-300;
-                        d0[i] = piv;
-                        d1[i] = cu;
-                        d2[i] = 0.0;
-                        const double l = nl / piv;
-                        lm[i] = l;
-                        pv[i] = 0.0;
-                        cd = nd - l * cu;
-                        cu = nu;
-                    }
-                } else {
-                    d0[i] = cd != 0.0 ? cd : 1e-300;
-                    d1[i] = 0.0;
-                    d2[i] = 0.0;
-                }
+    }
+    __syncthreads();
+    if (tid < r) {
+        const int t = tid;
+        const double mu = th_s[t] + 1e-13 * span;
+        double* base = m <= kTriLds ? &wl[t][0] : work + (size_t)t * 6 * m;
+        const int ld = m <= kTriLds ? kTriLds : m;
+        double* rd0 = base;                       // reciprocal pivots
+        double* d1 = base + ld;                   // first superdiagonal
+        double* d2 = base + 2 * ld;               // second superdiagonal (fill-in)
+        double* lm = base + 3 * ld;               // multipliers
+        double* pv = base + 4 * ld;               // 1 where rows i, i+1 were swapped
+        double* x = base + 5 * ld;
+        // eliminate once: rows i, i+1 with partial pivoting
+        double cd = a[0] - mu, cu = m > 1 ? b[0] : 0.0;
+        for (int i = 0; i + 1 < m; ++i) {
+            const double nl = b[i], nd = a[i + 1] - mu, nu = i + 2 < m ? b[i + 1] : 0.0;
+            if (fabs(nl) > fabs(cd)) {            // swap rows i and i+1
+                const double l = cd / nl;
+                rd0[i] = 1.0 / nl;
+                d1[i] = nd;
+                d2[i] = nu;
+                lm[i] = l;
+                pv[i] = 1.0;
+                cd = cu - l * nd;
+                cu = -l * nu;
+            } else {
+                const double piv = cd != 0.0 ? cd : 1e-300;
+                const double l = nl / piv;
+                rd0[i] = 1.0 / piv;
+                d1[i] = cu;
+                d2[i] = 0.0;
+                lm[i] = l;
+                pv[i] = 0.0;
+                cd = nd - l * cu;
+                cu = nu;
             }
-            // forward: apply swaps and multipliers to x
+        }
+        rd0[m - 1] = 1.0 / (cd != 0.0 ? cd : 1e-300);
+        d1[m - 1] = 0.0;
+        d2[m - 1] = 0.0;
+        for (int i = 0; i < m; ++i) x[i] = 1.0 + 0.001 * (double)((i * 7919 + t * 104729) % 97);
+        if (m == 1) x[0] = 1.0;                   // the 1 x 1 case needs no solve
+        for (int iter = 0; iter < (m > 1 ? 3 : 0); ++iter) {
             for (int i = 0; i + 1 < m; ++i) {
                 if (pv[i] != 0.0) {
                     const double tmp = x[i];
@@ -436,36 +567,39 @@ __global__ void k_tridiag_top(const double* __restrict__ a, const double* __rest
                 }
                 x[i + 1] -= lm[i] * x[i];
             }
-            // back substitution
+            double x1 = 0.0, x2 = 0.0, nrm = 0.0;   // x[i+1], x[i+2]
             for (int i = m - 1; i >= 0; --i) {
-                double s = x[i];
-                if (i + 1 < m) s -= d1[i] * x[i + 1];
-                if (i + 2 < m) s -= d2[i] * x[i + 2];
-                x[i] = s / d0[i];
+                const double v = (x[i] - d1[i] * x1 - d2[i] * x2) * rd0[i];
+                x[i] = v;
+                x2 = x1;
+                x1 = v;
+                nrm += v * v;
             }
-            double nrm = 0.0;
-            for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
-            nrm = sqrt(nrm);
-            for (int i = 0; i < m; ++i) x[i] /= nrm;
+            const double inv = 1.0 / sqrt(nrm);
+            for (int i = 0; i < m; ++i) x[i] *= inv;
         }
         for (int i = 0; i < m; ++i) S[(size_t)t * m + i] = x[i];
     }
     __syncthreads();
-    if (t == 0) {
+    if (wv == 0) {
         for (int u = 0; u < r; ++u) {
             double* su = S + (size_t)u * m;
             for (int pass = 0; pass < 2; ++pass)
                 for (int v = 0; v < u; ++v) {
                     const double* sv = S + (size_t)v * m;
                     double d = 0.0;
-                    for (int i = 0; i < m; ++i) d += sv[i] * su[i];
-                    for (int i = 0; i < m; ++i) su[i] -= d * sv[i];
+                    for (int i = lane; i < m; i += kWave) d += sv[i] * su[i];
+                    d = wave_sum_f64(d);
+                    for (int i = lane; i < m; i += kWave) su[i] -= d * sv[i];
                 }
             double nrm = 0.0;
-            for (int i = 0; i < m; ++i) nrm += su[i] * su[i];
-            nrm = sqrt(nrm);
-            for (int i = 0; i < m; ++i) su[i] /= nrm;
-            resid[u] = fabs(b_last * su[m - 1]);
+            for (int i = lane; i < m; i += kWave) nrm += su[i] * su[i];
+            nrm = wave_sum_f64(nrm);
+            const double inv = 1.0 / sqrt(nrm);
+            for (int i = lane; i < m; i += kWave) {
+                su[i] *= inv;
+                if (i == m - 1) resid[u] = fabs(b_last * su[i]);
+            }
         }
     }
 }
@@ -578,6 +712,8 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     cs.add<double2>((size_t)n * (max_iter + 1));   // basis
     cs.add<double2>(n);                           // w
     cs.add<double2>(kMaxIter + 1);                // h
+    const int nbd = (int)((n + kDotRows - 1) / kDotRows);
+    cs.add<double2>((size_t)(kMaxIter + 1) * nbd);  // partial dots
     cs.add<double2>(LRQO_MAX_R);                  // U^H x
     cs.add<double>(nparts);                       // norm partials
     cs.add<double>(4);                            // norm
@@ -609,13 +745,13 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     CarveSize hs;
     hs.add<double>(2 * (kMaxIter + 1));
     hs.add<double>(2 * LRQO_MAX_R);
-    hs.add<double2>(2);
     LRQO_TRY(reserve_arena(ctx, cs.bytes));
     LRQO_TRY(reserve_host(ctx, hs.bytes));
     Carve cv(ctx->arena);
     double2* Q = cv.take<double2>((size_t)n * (max_iter + 1));
     double2* w = cv.take<double2>(n);
     double2* h = cv.take<double2>(kMaxIter + 1);
+    double2* dpart = cv.take<double2>((size_t)(kMaxIter + 1) * nbd);
     double2* uc = cv.take<double2>(LRQO_MAX_R);
     double* npart = cv.take<double>(nparts);
     double* nrm = cv.take<double>(4);
@@ -645,7 +781,6 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     Carve hv(ctx->host);
     double* h_ab = hv.take<double>(2 * (kMaxIter + 1));     // alpha then beta
     double* h_tr = hv.take<double>(2 * LRQO_MAX_R);         // theta then resid
-    double2* h_h = hv.take<double2>(2);
     double* h_alpha = h_ab;
     double* h_beta = h_ab + (kMaxIter + 1);
 
@@ -653,7 +788,10 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
         if (kind == kOpLap) {
             hipLaunchKernelGGL(k_apply_lap, dim3((unsigned)blocks), dim3(kBlock), 0, st, lap, x, y);
         } else {
-            if (ph.p > 0) hipLaunchKernelGGL(k_utx, dim3(ph.p), dim3(kBlock), 0, st, ph, x, uc);
+            if (ph.p > 0) {
+                hipLaunchKernelGGL(k_utx_part, dim3(nbd), dim3(kBlock), 0, st, ph, x, nbd, dpart);
+                hipLaunchKernelGGL(k_part_sum, dim3(ph.p), dim3(kWave), 0, st, dpart, nbd, uc, nullptr);
+            }
             hipLaunchKernelGGL(k_w_tiles, dim3((unsigned)items.size()), dim3(kSymT), 0, st, ph, x, d_items, P,
                                rowpart, colpart);
             hipLaunchKernelGGL(k_w_combine, dim3((unsigned)P), dim3(kSymT), 0, st, ph, uc, d_first, P, rowpart,
@@ -664,7 +802,7 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     };
     auto normalize_into = [&](double2* dst) -> lrqo_status {
         hipLaunchKernelGGL(k_norm_part, dim3(nparts), dim3(kBlock), 0, st, w, n, npart);
-        hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, npart, nparts, nrm);
+        hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, npart, nparts, nrm, nullptr);
         hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(kBlock), 0, st, w, n, nrm, dst);
         LRQO_HIP(hipGetLastError());
         return LRQO_OK;
@@ -675,36 +813,41 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     LRQO_TRY(normalize_into(Q));
     int m = 0;              // Lanczos vectors q_0..q_{m-1} complete, T is m x m
     bool converged = false, breakdown = false;
-    double b_last = 0.0;
+    // alpha and beta stay on the device; the host reads them at each check,
+    // where it also finds a breakdown (the first beta_t not above 1e-13
+    // times the largest |alpha_u| + |beta_u|, u <= t) and truncates there
     for (int j = 0; j < max_iter; ++j) {
         double2* qj = Q + (int64_t)j * n;
         LRQO_TRY(apply(qj, w));
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(kBlock), 0, st, Q, n, w, h);
-            if (pass == 0) LRQO_HIP(hipMemcpyAsync(h_h, h + j, sizeof(double2), hipMemcpyDeviceToHost, st));
+            hipLaunchKernelGGL(k_dots_part, dim3(nbd, (j + kDotCols) / kDotCols), dim3(kBlock), 0, st, Q, n, w,
+                               j + 1, nbd, dpart);
+            hipLaunchKernelGGL(k_part_sum, dim3(j + 1), dim3(kWave), 0, st, dpart, nbd, h,
+                               pass == 0 ? alpha + j : nullptr);
             hipLaunchKernelGGL(k_sub, dim3((unsigned)blocks), dim3(kBlock), 0, st, Q, n, j + 1, h, w);
-            LRQO_HIP(hipGetLastError());
-            if (pass == 0) {
-                LRQO_HIP(hipStreamSynchronize(st));
-                h_alpha[j] = h_h[0].x;
-            }
         }
         hipLaunchKernelGGL(k_norm_part, dim3(nparts), dim3(kBlock), 0, st, w, n, npart);
-        hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, npart, nparts, nrm);
+        hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, st, npart, nparts, nrm, beta + j);
         LRQO_HIP(hipGetLastError());
-        LRQO_HIP(hipMemcpyAsync(h_beta + j, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
-        LRQO_HIP(hipStreamSynchronize(st));
         m = j + 1;
-        b_last = h_beta[j];
-        double amax = 0.0;
-        for (int i = 0; i <= j; ++i) amax = std::max(amax, std::fabs(h_alpha[i]) + std::fabs(h_beta[i]));
-        breakdown = !(b_last > 1e-13 * amax) || m == n;
-        const bool check = m >= r && (breakdown || m % every == 0 || j + 1 == max_iter);
+        const bool check = m >= r && (m % every == 0 || j + 1 == max_iter || m == n);
         if (check) {
-            LRQO_HIP(hipMemcpyAsync(alpha, h_alpha, sizeof(double) * m, hipMemcpyHostToDevice, st));
-            LRQO_HIP(hipMemcpyAsync(beta, h_beta, sizeof(double) * m, hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(k_tridiag_top, dim3(1), dim3(64), 0, st, alpha, beta, m, r, breakdown ? 0.0 : b_last,
-                               theta, S, resid, work);
+            LRQO_HIP(hipMemcpyAsync(h_alpha, alpha, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+            LRQO_HIP(hipMemcpyAsync(h_beta, beta, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+            LRQO_HIP(hipStreamSynchronize(st));
+            double amax = 0.0;
+            for (int t = 0; t < m; ++t) {
+                amax = std::max(amax, std::fabs(h_alpha[t]) + std::fabs(h_beta[t]));
+                if (!(h_beta[t] > 1e-13 * amax)) {
+                    m = t + 1;
+                    breakdown = true;
+                    break;
+                }
+            }
+            breakdown = breakdown || m == n;
+            if (m < r) break;
+            hipLaunchKernelGGL(k_tridiag_top, dim3(1), dim3(kTriThreads), 0, st, alpha, beta, m, r,
+                               breakdown ? 0.0 : h_beta[m - 1], theta, S, resid, work);
             LRQO_HIP(hipGetLastError());
             LRQO_HIP(hipMemcpyAsync(h_tr, theta, sizeof(double) * r, hipMemcpyDeviceToHost, st));
             LRQO_HIP(hipMemcpyAsync(h_tr + LRQO_MAX_R, resid, sizeof(double) * r, hipMemcpyDeviceToHost, st));
@@ -714,8 +857,9 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
             for (int k = 0; k < r; ++k) converged &= h_tr[LRQO_MAX_R + k] <= tol * scale;
             if (converged || breakdown) break;
         }
-        if (breakdown) break;
-        LRQO_TRY(normalize_into(Q + (int64_t)(j + 1) * n));
+        hipLaunchKernelGGL(k_scale, dim3((unsigned)blocks), dim3(kBlock), 0, st, w, n, nrm,
+                           Q + (int64_t)(j + 1) * n);
+        LRQO_HIP(hipGetLastError());
     }
     if (m < r) return fail(LRQO_EINVAL, "the Krylov space is smaller than r (graph or operator too small)");
     hipLaunchKernelGGL(k_ritz, dim3((unsigned)blocks), dim3(kBlock), 0, st, Q, n, m, r, S, Uo);
