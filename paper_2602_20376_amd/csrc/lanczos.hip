@@ -263,13 +263,19 @@ __global__ __launch_bounds__(kSymT) void k_w_combine(PhaseOp o, const double2* _
 
 // ---------------------------------------------------------------- basis algebra
 // h_j = q_j^H w for j < k in two fixed-order stages.  Block (b, c) takes
-// rows [b kDotRows, (b + 1) kDotRows) of columns kDotCols c .. kDotCols c + 7:
+// rows [b rows, (b + 1) rows) of columns kDotCols c .. kDotCols c + 7 (rows a
+// multiple of 256, sized on the host for at least 256 row chunks up to 4096):
 // each thread sums its rows, the lanes of a wave are added by butterfly and
 // the four waves in order, giving part[j nb + b]; k_part_sum then adds the
 // nb partials of column j (lanes strided, then butterfly).  Q is read once,
 // by as many blocks as there are row chunks times column groups.
-constexpr int kDotRows = 4096;
+constexpr int kDotRowsMax = 4096;
 constexpr int kDotCols = 8;
+
+int dot_rows(int64_t n) {
+    int64_t rows = ((n + 255) / 256 + 255) / 256 * 256;
+    return (int)std::min<int64_t>(std::max<int64_t>(rows, 256), kDotRowsMax);
+}
 
 __device__ __forceinline__ void block_sums_to(double (&acc)[2 * kDotCols], int count, double* dst, int64_t stride) {
     __shared__ double red[kBlock / kWave][2 * kDotCols];
@@ -289,11 +295,11 @@ __device__ __forceinline__ void block_sums_to(double (&acc)[2 * kDotCols], int c
 }
 
 __global__ __launch_bounds__(kBlock) void k_dots_part(const double2* __restrict__ Q, int64_t n,
-                                                      const double2* __restrict__ w, int k, int nb,
+                                                      const double2* __restrict__ w, int k, int rows, int nb,
                                                       double2* __restrict__ part) {
     const int b = blockIdx.x, j0 = blockIdx.y * kDotCols;
     const int nc = min(kDotCols, k - j0);
-    const int64_t i0 = (int64_t)b * kDotRows, i1 = min(n, i0 + kDotRows);
+    const int64_t i0 = (int64_t)b * rows, i1 = min(n, i0 + rows);
     double acc[2 * kDotCols];
 #pragma unroll
     for (int e = 0; e < 2 * kDotCols; ++e) acc[e] = 0.0;
@@ -313,10 +319,10 @@ __global__ __launch_bounds__(kBlock) void k_dots_part(const double2* __restrict_
 
 // part[k nb + b] = sum over rows of chunk b of conj(U_ik) x_i, k < p
 // (U row-major n x p, p <= 8)
-__global__ __launch_bounds__(kBlock) void k_utx_part(PhaseOp o, const double2* __restrict__ x, int nb,
+__global__ __launch_bounds__(kBlock) void k_utx_part(PhaseOp o, const double2* __restrict__ x, int rows, int nb,
                                                      double2* __restrict__ part) {
     const int b = blockIdx.x;
-    const int64_t i0 = (int64_t)b * kDotRows, i1 = min(o.n, i0 + kDotRows);
+    const int64_t i0 = (int64_t)b * rows, i1 = min(o.n, i0 + rows);
     double acc[2 * kDotCols];
 #pragma unroll
     for (int e = 0; e < 2 * kDotCols; ++e) acc[e] = 0.0;
@@ -712,7 +718,8 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     cs.add<double2>((size_t)n * (max_iter + 1));   // basis
     cs.add<double2>(n);                           // w
     cs.add<double2>(kMaxIter + 1);                // h
-    const int nbd = (int)((n + kDotRows - 1) / kDotRows);
+    const int drows = dot_rows(n);
+    const int nbd = (int)((n + drows - 1) / drows);
     cs.add<double2>((size_t)(kMaxIter + 1) * nbd);  // partial dots
     cs.add<double2>(LRQO_MAX_R);                  // U^H x
     cs.add<double>(nparts);                       // norm partials
@@ -789,7 +796,7 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
             hipLaunchKernelGGL(k_apply_lap, dim3((unsigned)blocks), dim3(kBlock), 0, st, lap, x, y);
         } else {
             if (ph.p > 0) {
-                hipLaunchKernelGGL(k_utx_part, dim3(nbd), dim3(kBlock), 0, st, ph, x, nbd, dpart);
+                hipLaunchKernelGGL(k_utx_part, dim3(nbd), dim3(kBlock), 0, st, ph, x, drows, nbd, dpart);
                 hipLaunchKernelGGL(k_part_sum, dim3(ph.p), dim3(kWave), 0, st, dpart, nbd, uc, nullptr);
             }
             hipLaunchKernelGGL(k_w_tiles, dim3((unsigned)items.size()), dim3(kSymT), 0, st, ph, x, d_items, P,
@@ -821,7 +828,7 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
         LRQO_TRY(apply(qj, w));
         for (int pass = 0; pass < 2; ++pass) {
             hipLaunchKernelGGL(k_dots_part, dim3(nbd, (j + kDotCols) / kDotCols), dim3(kBlock), 0, st, Q, n, w,
-                               j + 1, nbd, dpart);
+                               j + 1, drows, nbd, dpart);
             hipLaunchKernelGGL(k_part_sum, dim3(j + 1), dim3(kWave), 0, st, dpart, nbd, h,
                                pass == 0 ? alpha + j : nullptr);
             hipLaunchKernelGGL(k_sub, dim3((unsigned)blocks), dim3(kBlock), 0, st, Q, n, j + 1, h, w);
