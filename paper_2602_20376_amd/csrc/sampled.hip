@@ -10,7 +10,8 @@
 //                   w = V_i c, rounds arg(w) to the nearest K-th root and
 //                   accumulates s += conj(V_i) z_i.  With several row slices
 //                   (gridDim.y > 1) it writes partial sums instead.
-//   k_finalize      sums the slice partials in a fixed order -> f = ||s||^2
+//   k_finalize      sums the slice partials in a fixed order -> f = ||s||^2,
+//                   and sorts each wave's 64 keys for the selection
 //   topk_select     best T packed (f, index) keys (select.hip)
 //   k_rescore       FP64 re-evaluation of each kept direction, row-sliced
 //   k_pick          FP64 arg-max of the rescored candidates (ties -> lowest index)
@@ -680,25 +681,46 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16(ScoreParams p) {
     }
 }
 
+// Slice sums: f of each candidate from the scorer's per-slice partial sums
+// (slices in order, then the components in order).  Each wave also sorts its
+// 64 keys across its lanes, so the first top-T pass merges sorted lists.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ partial, int P,
                                                      uint32_t S, float* __restrict__ f_out,
-                                                     unsigned long long* best_key) {
+                                                     unsigned long long* __restrict__ best_key,
+                                                     unsigned long long* __restrict__ lists) {
+    constexpr int U = R <= 4 ? 8 : 4;      // slices loaded together
     const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
-    unsigned long long best = 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    unsigned long long key = 0;
     if (idx < S) {
+        float acc[2 * R];
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) acc[j] = 0.0f;
+        for (int p0 = 0; p0 < P; p0 += U) {
+            float v[U][2 * R];
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+#pragma unroll
+                for (int j = 0; j < 2 * R; ++j)
+                    v[q][j] = p0 + q < P ? partial[((size_t)(p0 + q) * (2 * R) + j) * S + idx] : 0.0f;
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                if (p0 + q < P) {
+#pragma unroll
+                    for (int j = 0; j < 2 * R; ++j) acc[j] += v[q][j];
+                }
+        }
         float f = 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2 * R; ++j) {
-            float a = 0.0f;
-            for (int p = 0; p < P; ++p) a += partial[((size_t)p * (2 * R) + j) * S + idx];
-            f = fmaf(a, a, f);
-        }
+        for (int j = 0; j < 2 * R; ++j) f = fmaf(acc[j], acc[j], f);
         f_out[idx] = f;
-        best = pack_key(f, idx);
+        key = pack_key(f, idx);
     }
-    best = wave_max_u64(best);
-    if ((threadIdx.x & (kWave - 1)) == 0 && best) atomicMax(best_key, best);
+    const unsigned long long sorted = wave_sort_desc(key, lane);
+    lists[idx] = sorted;
+    const unsigned long long best = __shfl(sorted, 0, kWave);
+    if (lane == 0 && best) atomicMax(best_key, best);
 }
 
 // ------------------------------------------------------------ FP64 rescore
@@ -891,16 +913,18 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     launch_score_k<R, REAL>(p, dim3((unsigned)cand_blocks, (unsigned)sc.slices), st, job.precision);
     LRQO_HIP(hipGetLastError());
     LRQO_HIP(hipEventRecord(job.ev_score1, st));
-    if (sc.slices > 1) {
-        hipLaunchKernelGGL((k_finalize<R>), dim3((S + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
-                           sc.partial, sc.slices, S, sc.f32, sc.best_key);
-        LRQO_HIP(hipGetLastError());
-    }
-
     // ---- top-T
     const int T = sc.topk;
     const unsigned long long* keys = nullptr;
-    LRQO_TRY(topk_select(sc.f32, S, T, sc.keys_a, sc.keys_b, st, &keys));
+    if (sc.slices > 1) {
+        const uint32_t fblocks = (S + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL((k_finalize<R>), dim3(fblocks), dim3(kBlock), 0, st, sc.partial, sc.slices, S, sc.f32,
+                           sc.best_key, sc.lists);
+        LRQO_HIP(hipGetLastError());
+        LRQO_TRY(topk_select_lists(sc.lists, fblocks * kBlock, T, sc.keys_a, sc.keys_b, st, &keys));
+    } else {
+        LRQO_TRY(topk_select(sc.f32, S, T, sc.keys_a, sc.keys_b, st, &keys));
+    }
 
     // ---- FP64 rescore of the T kept keys
     RescoreParams rp{};
@@ -976,6 +1000,7 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     cs.add<float>(slices > 1 ? (size_t)slices * 2 * R * job.S : 0);
     cs.add<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
     cs.add<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
+    cs.add<unsigned long long>(slices > 1 ? (size_t)(job.S + kBlock - 1) / kBlock * kBlock : 0);
     cs.add<double>((size_t)plan.topk * plan.rescore_slices * 2 * R);
     plan.bytes = cs.bytes;
 }
@@ -994,6 +1019,8 @@ lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void*
     sc.topk = plan.topk;
     sc.keys_a = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
     sc.keys_b = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
+    sc.lists = plan.slices > 1 ? cv.take<unsigned long long>((size_t)(job.S + kBlock - 1) / kBlock * kBlock)
+                               : nullptr;
     sc.rescore_slices = plan.rescore_slices;
     sc.rescore_rows = plan.rescore_rows;
     sc.rescore = cv.take<double>((size_t)plan.topk * plan.rescore_slices * 2 * job.r);

@@ -90,6 +90,7 @@ struct Scratch {
     int topk;
     unsigned long long* keys_a;
     unsigned long long* keys_b;
+    unsigned long long* lists;  // per-wave sorted keys from the slice sum
     double* rescore;
     int rescore_slices;
     int64_t rescore_rows;

@@ -19,4 +19,10 @@ lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long lon
                         unsigned long long* buf_b, hipStream_t st,
                         const unsigned long long** out);
 
+// The same from keys already sorted in lists of 64 (lists[64 q + l] the
+// l-th largest of list q, padding keys 0); count a multiple of 64.
+lrqo_status topk_select_lists(const unsigned long long* lists, uint32_t count, int T,
+                              unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
+                              const unsigned long long** out);
+
 }  // namespace lrqo

@@ -3,9 +3,10 @@
 // sorts a tile across its lanes (bitonic network over lane shuffles) and
 // merges it into the running list (half-cleaner against the reversed tile,
 // then a bitonic merge); tiles with no key above the running 64th are
-// skipped.  The four lists of a block are merged the same way, the block
-// writes its best T, and passes repeat over the survivors until one block
-// remains.
+// skipped; input already sorted in lists of 64 (the slice sum's per-wave
+// lists, or a previous pass's block lists when T = 64) is merged without the
+// sort.  The four lists of a block are merged the same way, the block writes
+// its best T, and passes repeat over the survivors until one block remains.
 #include "lrqo_device.h"
 #include "lrqo_runtime.h"
 #include "select.h"
@@ -23,7 +24,7 @@ constexpr int kChunk = 2048;  // keys per block, kChunk / kWaves per wave
 // word is nonzero).
 __global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
                                                  const unsigned long long* __restrict__ keys_in,
-                                                 uint32_t count, int T,
+                                                 uint32_t count, int T, int sorted,
                                                  unsigned long long* __restrict__ keys_out) {
     __shared__ unsigned long long top[kWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
         if (g < count) key = f ? pack_key(f[g], g) : keys_in[g];
         const unsigned long long floor64 = __shfl(run, 63, 64);
         if (__ballot(key > floor64) == 0) continue;  // uniform across the wave
-        run = wave_top_union(run, wave_sort_desc(key, lane), lane);
+        run = wave_top_union(run, sorted ? key : wave_sort_desc(key, lane), lane);
     }
     top[w][lane] = run;
     __syncthreads();
@@ -50,27 +51,43 @@ size_t topk_buffer_keys(uint32_t count, int T) {
     return ((size_t)count + kChunk - 1) / kChunk * (size_t)T;
 }
 
-lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long long* buf_a,
-                        unsigned long long* buf_b, hipStream_t st,
+namespace {
+
+lrqo_status topk_passes(const float* f, const unsigned long long* keys, bool sorted, uint32_t count, int T,
+                        unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
                         const unsigned long long** out) {
-    const unsigned long long* keys = nullptr;
     uint32_t n = count;
     int ping = 0;
-    bool from_f = true;
+    bool from_f = f != nullptr;
     for (;;) {
         const uint32_t blocks = (n + kChunk - 1) / kChunk;
         unsigned long long* dst = ping ? buf_b : buf_a;
         hipLaunchKernelGGL(k_topk, dim3(blocks), dim3(kBlock), 0, st, from_f ? f : nullptr, keys, n,
-                           T, dst);
+                           T, sorted ? 1 : 0, dst);
         LRQO_HIP(hipGetLastError());
         keys = dst;
         n = blocks * (uint32_t)T;
         ping ^= 1;
         from_f = false;
+        sorted = T == 64;       // a block writes its list sorted, 64 apart
         if (blocks == 1) break;
     }
     *out = keys;
     return LRQO_OK;
+}
+
+}  // namespace
+
+lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long long* buf_a,
+                        unsigned long long* buf_b, hipStream_t st,
+                        const unsigned long long** out) {
+    return topk_passes(f, nullptr, false, count, T, buf_a, buf_b, st, out);
+}
+
+lrqo_status topk_select_lists(const unsigned long long* lists, uint32_t count, int T,
+                              unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
+                              const unsigned long long** out) {
+    return topk_passes(nullptr, lists, true, count, T, buf_a, buf_b, st, out);
 }
 
 }  // namespace lrqo
