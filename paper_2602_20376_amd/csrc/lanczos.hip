@@ -615,16 +615,23 @@ __global__ __launch_bounds__(kBlock) void k_ritz(const double2* __restrict__ Q, 
                                                  const double* __restrict__ S, double2* __restrict__ Uo) {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
-    for (int k = 0; k < r; ++k) {
-        double ar = 0.0, ai = 0.0;
-        for (int j = 0; j < m; ++j) {
-            const double s = S[(size_t)k * m + j];
-            const double2 q = Q[(int64_t)j * n + i];
-            ar += q.x * s;
-            ai += q.y * s;
+    double ar[LRQO_MAX_R], ai[LRQO_MAX_R];
+#pragma unroll
+    for (int k = 0; k < LRQO_MAX_R; ++k) ar[k] = ai[k] = 0.0;
+    for (int j = 0; j < m; ++j) {          // the basis is read once
+        const double2 q = Q[(int64_t)j * n + i];
+#pragma unroll
+        for (int k = 0; k < LRQO_MAX_R; ++k) {
+            if (k < r) {
+                const double s = S[(size_t)k * m + j];
+                ar[k] += q.x * s;
+                ai[k] += q.y * s;
+            }
         }
-        Uo[i * r + k] = make_double2(ar, ai);
     }
+#pragma unroll
+    for (int k = 0; k < LRQO_MAX_R; ++k)
+        if (k < r) Uo[i * r + k] = make_double2(ar[k], ai[k]);
 }
 
 // per block: (max |u_ik|^2, lowest index) for each column k
@@ -665,11 +672,11 @@ __global__ __launch_bounds__(kBlock) void k_colmax(const double2* __restrict__ U
     }
 }
 
-// phase of each column from the block partials, then V = U phase sqrt(theta)
-__global__ __launch_bounds__(kBlock) void k_factor(const double2* __restrict__ Uo, int64_t n, int r, int parts,
-                                                   const double* __restrict__ pmax, const int64_t* __restrict__ pidx,
-                                                   const double* __restrict__ theta, double2* __restrict__ V) {
-    __shared__ double2 ph[LRQO_MAX_R];
+// phase of each column from the block partials (one block, thread k):
+// ph_k = conj(u) / |u| sqrt(max(theta_k, 0)) at the column's largest entry
+__global__ void k_phase(const double2* __restrict__ Uo, int r, int parts, const double* __restrict__ pmax,
+                        const int64_t* __restrict__ pidx, const double* __restrict__ theta,
+                        double2* __restrict__ ph) {
     if ((int)threadIdx.x < r) {
         const int k = threadIdx.x;
         double best = -1.0;
@@ -685,9 +692,13 @@ __global__ __launch_bounds__(kBlock) void k_factor(const double2* __restrict__ U
         const double2 u = Uo[bi * r + k];
         const double mod = sqrt(u.x * u.x + u.y * u.y);
         const double sc = sqrt(fmax(theta[k], 0.0)) / (mod > 0.0 ? mod : 1.0);
-        ph[k] = make_double2(u.x * sc, -u.y * sc);     // conj(u) / |u| sqrt(theta)
+        ph[k] = make_double2(u.x * sc, -u.y * sc);
     }
-    __syncthreads();
+}
+
+// V = U ph (column k times ph_k)
+__global__ __launch_bounds__(kBlock) void k_factor(const double2* __restrict__ Uo, int64_t n, int r,
+                                                   const double2* __restrict__ ph, double2* __restrict__ V) {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= n) return;
     for (int k = 0; k < r; ++k) V[i * r + k] = cmul(Uo[i * r + k], ph[k]);
@@ -871,7 +882,8 @@ lrqo_status lanczos_factor(int kind, const LapOp& lap, const PhaseOp& ph, int64_
     if (m < r) return fail(LRQO_EINVAL, "the Krylov space is smaller than r (graph or operator too small)");
     hipLaunchKernelGGL(k_ritz, dim3((unsigned)blocks), dim3(kBlock), 0, st, Q, n, m, r, S, Uo);
     hipLaunchKernelGGL(k_colmax, dim3(nparts), dim3(kBlock), 0, st, Uo, n, r, pmax, pidx);
-    hipLaunchKernelGGL(k_factor, dim3((unsigned)blocks), dim3(kBlock), 0, st, Uo, n, r, nparts, pmax, pidx, theta,
+    hipLaunchKernelGGL(k_phase, dim3(1), dim3(64), 0, st, Uo, r, nparts, pmax, pidx, theta, uc);
+    hipLaunchKernelGGL(k_factor, dim3((unsigned)blocks), dim3(kBlock), 0, st, Uo, n, r, uc,
                        reinterpret_cast<double2*>(Vout));
     LRQO_HIP(hipGetLastError());
     LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
