@@ -126,6 +126,32 @@ def test_sampled_parity_small(lrqo_mod, n, r, K, S, real):
     check_result(V, K, S, seed, out, real=real, f32=f32.cpu().numpy())
 
 
+@pytest.mark.parametrize("n,r,K,S,real,topk", [
+    (5000, 4, 8, 1000, False, 64),      # ragged S
+    (4096, 3, 3, 50, True, 64),         # S < 64: T = 50
+    (3000, 2, 3, 70000, True, 64),      # three selection levels
+    (4096, 3, 5, 3000, False, 7),       # T < 64: later passes take unsorted lists
+    (4096, 2, 3, 3000, True, 1),
+])
+def test_sliced_selection(lrqo_mod, n, r, K, S, real, topk):
+    """Several row slices: the slice sums sort each wave's 64 keys and the
+    top-T passes merge those lists.  The winner must be in the top T of the
+    returned FP32 scores (f descending, index ascending) and hold the largest
+    FP64 objective among them (up to the FP32 rounding of the directions)."""
+    seed = 9100 + n + S + topk
+    V = inputs.random_V(n, r, seed, real=real)
+    f32 = torch.empty(S, dtype=torch.float32, device="cuda")
+    out = lrqo_mod.solve_sampled(_to_dev(V, real), K, S, seed, real=real, f_out=f32, topk=topk)
+    assert out.slices > 1 and out.rescored == min(topk, S)
+    f = f32.cpu().numpy()
+    kept = np.lexsort((np.arange(S), -f.astype(np.float64)))[:min(topk, S)]
+    assert out.best_index in set(int(x) for x in kept)
+    Vx = _fp32_exact(V)
+    f64 = [oracle.f_of_c(Vx, K, oracle.direction(seed, int(s), r))[0] for s in kept]
+    assert out.obj >= max(f64) * (1 - 1e-6)
+    check_result(V, K, S, seed, out, real=real, f32=f, full_oracle=topk == 64)
+
+
 def test_exact_small_config_sampled(lrqo_mod):
     """The 12 x 2 complex workload: best-of-4096 reaches the brute-force OPT."""
     from oracle import brute
