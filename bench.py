@@ -317,9 +317,10 @@ def form_samplers():
         _, cut_n = lrqo.graph_objective(rpd, cold, None, inst.K, zn)
         out[f"r{r}"] = {"uniform_obj": u.obj, "nullvec_obj": rn.obj,
                         "nullvec_roofline": _alu_roofline(
-                            16.0 * r * inst.n * 2 * (rn.index_sets - rn.rank_deficient), rn.device_ms,
-                            "null-vector path: per feasible draw and sign, V c and V^H z over all rows "
-                            "(16r flops per row, complex V; label options of the drawn rows share them)"),
+                            24.0 * r * inst.n * (rn.index_sets - rn.rank_deficient), rn.device_ms,
+                            "null-vector path: per feasible draw and row, V c once (8r flops, complex V; "
+                            "-c gives -V c) and V^H z for each sign (2 x 8r); the label options of the "
+                            "drawn rows share them"),
 
                         "uniform_over_nullvec": u.obj / rn.obj,
                         "cut_uniform": cut_u, "cut_nullvec": cut_n,

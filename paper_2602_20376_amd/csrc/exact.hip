@@ -11,11 +11,14 @@
 //
 // Kernels:
 //   k_to_f32        FP32 copy of V for the scorer
-//   k_exact_score   one thread per index set (grid-stride): colex unranking,
-//                   FP64 null vector by twice-orthogonalised Gram-Schmidt,
-//                   both signs scored in FP32 over all rows (row tiles in
-//                   LDS), coordinates in the set tried with every label the
-//                   vertex leaves open; best FP32 score per set -> fbuf
+//   k_exact_score   one thread per index set (grid-stride) and row slice:
+//                   colex unranking (or a random draw), FP64 null vector by
+//                   twice-orthogonalised Gram-Schmidt, both signs scored in
+//                   FP32 over the slice's rows (row tiles in LDS);
+//                   coordinates in the set tried with every label the vertex
+//                   leaves open; best FP32 score per set -> fbuf
+//   k_exact_combine with several row slices: the slice sums in order, then
+//                   the label combinations
 //   topk_select     best 64 sets (select.hip)
 //   k_exact_rescore FP64 re-evaluation of each kept set (both signs, all
 //                   label combinations), rows split over the block
@@ -38,10 +41,18 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kTile = 256;
 constexpr int kMaxR = 4;
-constexpr int kMaxM = 2 * kMaxR - 1;
 constexpr int kTopT = 64;
 constexpr double kRankTol = 1e-10;
 constexpr int64_t kMaxCombos = 1 << 20;
+
+// A vertex as the split scorer reads it: FP32 direction (re, im per
+// column), the coordinates of its index set (-1 when it has none), and
+// whether the set gave a full-rank vertex.
+struct VertexRec {
+    float c[2 * 4];
+    int32_t g[2 * 4 - 1];
+    int32_t ok;
+};
 
 struct ExactParams {
     const double* V64;   // n x r complex128, interleaved
@@ -61,6 +72,9 @@ struct ExactParams {
     unsigned long long* stats;          // valid sets, rank deficient, candidates
     int random;                         // 1: index sets drawn at random (null-vector sampler)
     uint64_t draw_seed;
+    int64_t rows_per_slice;             // rows of one slice of the split scorer's grid
+    float* part;                        // split form: slice sums
+    VertexRec* recs;                    // split form: one record per set
 };
 
 struct LevelTable {
@@ -301,6 +315,140 @@ __global__ void k_to_f32(const double* __restrict__ V64, float* __restrict__ V32
     }
 }
 
+// Sums conj(V_i) z_i over rows [r0, r1) for both signs +c and -c of a
+// direction (V_i c formed once), skipping the rows of the set (g, sorted,
+// -1 for none): rows in
+// LDS tiles, every lane of a wave reading the same row (broadcast).  All
+// threads of the block take part in the tile loads.
+template <int R, int D, int KS>
+__device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c)[2 * D],
+                                           const int32_t (&g)[2 * D - 1], int64_t r0, int64_t r1,
+                                           float* tile, const float2* roots_s, float (&acc)[2][2 * R]) {
+    constexpr int M = 2 * D - 1;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) acc[s][j] = 0.0f;
+    int64_t next = INT64_MAX;                  // next touched row at or after r0
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+        if (g[t] >= r0 && g[t] < next) next = g[t];
+    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
+        const int cnt = (int)min((int64_t)kTile, r1 - t0);
+        __syncthreads();
+        const float* __restrict__ src = p.V32 + t0 * 2 * R;
+        for (int e = threadIdx.x; e < cnt * 2 * R; e += kBlock) tile[e] = src[e];
+        __syncthreads();
+        for (int i = 0; i < cnt; ++i) {
+            const int64_t row = t0 + i;
+            float vv[2 * R];
+#pragma unroll
+            for (int e = 0; e < 2 * R; ++e) vv[e] = tile[i * 2 * R + e];
+            const bool touched = row == next;
+            if (touched) {          // rare: advance the cursor
+                int64_t nn = INT64_MAX;
+#pragma unroll
+                for (int t = 0; t < M; ++t)
+                    if (g[t] > row && g[t] < nn) nn = g[t];
+                next = nn;
+            }
+            // V_i c once: for -c it is exactly -(V_i c)
+            float wr = 0.0f, wi = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                const float vr = vv[2 * j], vi = vv[2 * j + 1];
+                wr = fmaf(vr, c[2 * j], fmaf(-vi, c[2 * j + 1], wr));
+                wi = fmaf(vr, c[2 * j + 1], fmaf(vi, c[2 * j], wi));
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                float zr, zi;
+                nearest_root<KS>(s ? -wr : wr, s ? -wi : wi, p.K, roots_s, zr, zi);
+                zr = touched ? 0.0f : zr;
+                zi = touched ? 0.0f : zi;
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const float vr = vv[2 * j], vi = vv[2 * j + 1];
+                    acc[s][2 * j] = fmaf(vr, zr, fmaf(vi, zi, acc[s][2 * j]));
+                    acc[s][2 * j + 1] = fmaf(vr, zi, fmaf(-vi, zr, acc[s][2 * j + 1]));
+                }
+            }
+        }
+    }
+}
+
+// Best FP32 score over both signs and every open-label combination of the
+// set's coordinates, from the sums acc[s] of the untouched rows; also the
+// number of combinations tried.
+template <int R, int D>
+__device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1], const int (&mm)[2 * D - 1],
+                             const double (&v)[2 * D], const float (&acc)[2][2 * R],
+                             unsigned long long& ncand) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    float best = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        double cs[C2];
+#pragma unroll
+        for (int k = 0; k < C2; ++k) cs[k] = s ? -v[k] : v[k];
+        int o[M], cn[M];
+        open_labels<D>(p, g, mm, cs, o, cn);
+        int64_t total = 1;
+#pragma unroll
+        for (int t = 0; t < M; ++t) total *= cn[t];
+        ncand += (unsigned long long)total;
+        for (int64_t combo = 0; combo < total; ++combo) {
+            float sr[2 * R];
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) sr[j] = acc[s][j];
+            int64_t rest = combo;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
+                const int q = (int)(rest % cn[t]);
+                rest /= cn[t];
+                int k = o[t] + q;
+                k = k >= p.K ? k - p.K : k;
+                const float2 z = p.roots32[k];
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const float vr = p.V32[(g[t] * R + j) * 2], vi = p.V32[(g[t] * R + j) * 2 + 1];
+                    sr[2 * j] = fmaf(vr, z.x, fmaf(vi, z.y, sr[2 * j]));
+                    sr[2 * j + 1] = fmaf(vr, z.y, fmaf(-vi, z.x, sr[2 * j + 1]));
+                }
+            }
+            float f = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) f = fmaf(sr[j], sr[j], f);
+            best = fmaxf(best, f);
+        }
+    }
+    return best;
+}
+
+// Per-wave sums of the set statistics (valid sets, rank deficient,
+// candidates) into p.stats.
+__device__ __forceinline__ void add_stats(const ExactParams& p, bool active, bool valid, bool ok,
+                                          unsigned long long ncand) {
+    unsigned long long a0 = (active && valid) ? 1ull : 0ull;
+    unsigned long long a1 = (active && valid && !ok) ? 1ull : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a0 += __shfl_xor(a0, off, kWave);
+        a1 += __shfl_xor(a1, off, kWave);
+        ncand += __shfl_xor(ncand, off, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (a0) atomicAdd(&p.stats[0], a0);
+        if (a1) atomicAdd(&p.stats[1], a1);
+        if (ncand) atomicAdd(&p.stats[2], ncand);
+    }
+}
+
+// Fused form (one pass per set, all rows): vertex, both signs scored over
+// every row the set does not touch (row tiles in LDS, the touched rows found
+// with a cursor over their sorted list), then the label combinations.  Used
+// when the sets are too many for the split form's buffers.
 template <int R, int D, int KS>
 __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
@@ -323,114 +471,126 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
 #pragma unroll
             for (int t = 0; t < M; ++t) g[t] = -1;
         }
-        // FP32 directions for both signs
-        float c[2][2 * D];
+        float c[2 * D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            c[0][2 * j] = ok ? (float)v[j] : 0.0f;
-            c[0][2 * j + 1] = ok ? (float)v[D + j] : 0.0f;
-            c[1][2 * j] = -c[0][2 * j];
-            c[1][2 * j + 1] = -c[0][2 * j + 1];
+            c[2 * j] = ok ? (float)v[j] : 0.0f;
+            c[2 * j + 1] = ok ? (float)v[D + j] : 0.0f;
+        }
+        int32_t g32[M];
+#pragma unroll
+        for (int t = 0; t < M; ++t) g32[t] = (int32_t)g[t];
+        float acc[2][2 * R];
+        score_rows<R, D, KS>(p, c, g32, 0, p.n, tile, roots_s, acc);
+        unsigned long long ncand = 0;
+        const float best = ok ? combos_best<R, D>(p, g, mm, v, acc, ncand) : 0.0f;
+        if (active) p.fbuf[p.offset + rank] = best;
+        add_stats(p, active, valid, ok, ncand);
+    }
+}
+
+// Split form, stage 1: the vertex of each set in FP64, kept as its FP32
+// direction and its touched rows (-1 where the set has no full-rank vertex).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_exact_vertex(ExactParams p, VertexRec* __restrict__ recs) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t rank = (uint64_t)blockIdx.x * kBlock + threadIdx.x; rank < p.count; rank += stride) {
+        int64_t g[M];
+        int mm[M];
+        double v[C2];
+        bool valid = false;
+        const bool ok = vertex<D>(p, rank, g, mm, v, valid);
+        VertexRec rec;
+#pragma unroll
+        for (int j = 0; j < 2 * kMaxR; ++j) rec.c[j] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 2 * kMaxR - 1; ++t) rec.g[t] = -1;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            rec.c[2 * j] = ok ? (float)v[j] : 0.0f;
+            rec.c[2 * j + 1] = ok ? (float)v[D + j] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < M; ++t) rec.g[t] = ok ? (int32_t)g[t] : -1;
+        rec.ok = ok ? 1 : 0;
+        recs[rank] = rec;
+    }
+}
+
+// Split form, stage 2: grid (set blocks, row slices); each thread scores its
+// set's two signs over the slice's rows from the stored record (no FP64
+// state, so many waves fit on a SIMD) and writes the slice sums to p.part.
+template <int R, int D, int KS>
+__global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const VertexRec* __restrict__ recs) {
+    constexpr int M = 2 * D - 1;
+    __shared__ __align__(16) float tile[kTile * 2 * R];
+    __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
+    if constexpr (KS == 0) {
+        for (int k = threadIdx.x; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
+    }
+    const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
+    const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
+        const uint64_t rank = base + threadIdx.x;
+        const bool active = rank < p.count;
+        float c[2 * D];
+        int32_t g[M];
+        if (active) {
+            const VertexRec rec = recs[rank];
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) c[j] = rec.c[j];
+#pragma unroll
+            for (int t = 0; t < M; ++t) g[t] = rec.g[t];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) c[j] = 0.0f;
+#pragma unroll
+            for (int t = 0; t < M; ++t) g[t] = -1;
         }
         float acc[2][2 * R];
+        score_rows<R, D, KS>(p, c, g, r0, r1, tile, roots_s, acc);
+        if (active) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
-            for (int j = 0; j < 2 * R; ++j) acc[s][j] = 0.0f;
-
-        for (int64_t t0 = 0; t0 < p.n; t0 += kTile) {
-            const int cnt = (int)min((int64_t)kTile, p.n - t0);
-            __syncthreads();
-            const float* __restrict__ src = p.V32 + t0 * 2 * R;
-            for (int e = tid; e < cnt * 2 * R; e += kBlock) tile[e] = src[e];
-            __syncthreads();
-            for (int i = 0; i < cnt; ++i) {
-                const int64_t row = t0 + i;
-                float vv[2 * R];
-#pragma unroll
-                for (int e = 0; e < 2 * R; ++e) vv[e] = tile[i * 2 * R + e];
-                bool touched = false;
-#pragma unroll
-                for (int t = 0; t < M; ++t) touched |= (row == g[t]);
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    float wr = 0.0f, wi = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        const float vr = vv[2 * j], vi = vv[2 * j + 1];
-                        wr = fmaf(vr, c[s][2 * j], fmaf(-vi, c[s][2 * j + 1], wr));
-                        wi = fmaf(vr, c[s][2 * j + 1], fmaf(vi, c[s][2 * j], wi));
-                    }
-                    float zr, zi;
-                    nearest_root<KS>(wr, wi, p.K, roots_s, zr, zi);
-                    zr = touched ? 0.0f : zr;
-                    zi = touched ? 0.0f : zi;
-#pragma unroll
-                    for (int j = 0; j < R; ++j) {
-                        const float vr = vv[2 * j], vi = vv[2 * j + 1];
-                        acc[s][2 * j] = fmaf(vr, zr, fmaf(vi, zi, acc[s][2 * j]));
-                        acc[s][2 * j + 1] = fmaf(vr, zi, fmaf(-vi, zr, acc[s][2 * j + 1]));
-                    }
-                }
-            }
+                for (int j = 0; j < 2 * R; ++j)
+                    p.part[(((uint64_t)blockIdx.y * 2 + s) * (2 * R) + j) * p.count + rank] = acc[s][j];
         }
+    }
+}
 
-        float best = 0.0f;
+// Row slices of k_exact_score: per set, the slice sums in slice order, then
+// the label combinations and the statistics.
+template <int R, int D>
+__global__ __launch_bounds__(kBlock) void k_exact_combine(ExactParams p, int slices) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
+        const uint64_t rank = base + threadIdx.x;
+        const bool active = rank < p.count;
+        int64_t g[M];
+        int mm[M];
+        double v[C2];
+        bool valid = false, ok = false;
+        if (active) ok = vertex<D>(p, rank, g, mm, v, valid);
         unsigned long long ncand = 0;
+        float best = 0.0f;
         if (ok) {
+            float acc[2][2 * R];
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                double cs[C2];
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
-                for (int k = 0; k < C2; ++k) cs[k] = s ? -v[k] : v[k];
-                int o[M], cn[M];
-                open_labels<D>(p, g, mm, cs, o, cn);
-                int64_t total = 1;
-#pragma unroll
-                for (int t = 0; t < M; ++t) total *= cn[t];
-                ncand += (unsigned long long)total;
-                for (int64_t combo = 0; combo < total; ++combo) {
-                    float sr[2 * R];
-#pragma unroll
-                    for (int j = 0; j < 2 * R; ++j) sr[j] = acc[s][j];
-                    int64_t rest = combo;
-#pragma unroll
-                    for (int t = 0; t < M; ++t) {
-                        if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
-                        const int q = (int)(rest % cn[t]);
-                        rest /= cn[t];
-                        int k = o[t] + q;
-                        k = k >= p.K ? k - p.K : k;
-                        const float2 z = p.roots32[k];
-#pragma unroll
-                        for (int j = 0; j < R; ++j) {
-                            const float vr = p.V32[(g[t] * R + j) * 2], vi = p.V32[(g[t] * R + j) * 2 + 1];
-                            sr[2 * j] = fmaf(vr, z.x, fmaf(vi, z.y, sr[2 * j]));
-                            sr[2 * j + 1] = fmaf(vr, z.y, fmaf(-vi, z.x, sr[2 * j + 1]));
-                        }
-                    }
-                    float f = 0.0f;
-#pragma unroll
-                    for (int j = 0; j < 2 * R; ++j) f = fmaf(sr[j], sr[j], f);
-                    best = fmaxf(best, f);
+                for (int j = 0; j < 2 * R; ++j) {
+                    float a = 0.0f;
+                    for (int q = 0; q < slices; ++q) a += p.part[(((uint64_t)q * 2 + s) * (2 * R) + j) * p.count + rank];
+                    acc[s][j] = a;
                 }
-            }
+            best = combos_best<R, D>(p, g, mm, v, acc, ncand);
         }
         if (active) p.fbuf[p.offset + rank] = best;
-        // statistics
-        unsigned long long a0 = (active && valid) ? 1ull : 0ull;
-        unsigned long long a1 = (active && valid && !ok) ? 1ull : 0ull;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            a0 += __shfl_xor(a0, off, kWave);
-            a1 += __shfl_xor(a1, off, kWave);
-            ncand += __shfl_xor(ncand, off, kWave);
-        }
-        if ((tid & (kWave - 1)) == 0) {
-            if (a0) atomicAdd(&p.stats[0], a0);
-            if (a1) atomicAdd(&p.stats[1], a1);
-            if (ncand) atomicAdd(&p.stats[2], ncand);
-        }
+        add_stats(p, active, valid, ok, ncand);
     }
 }
 
@@ -656,6 +816,12 @@ __global__ __launch_bounds__(kBlock) void k_exact_labels(ExactParams p, LevelTab
 }
 
 // ---------------------------------------------------------------- host
+// Bytes of the split form's buffers: one record per set, and the slice sums
+// (two signs, 2r components) per set and slice.
+uint64_t split_bytes(uint64_t count, int slices, int r) {
+    return count * (sizeof(VertexRec) + (uint64_t)slices * 2 * (2 * r) * sizeof(float));
+}
+
 unsigned __int128 binom128(int64_t x, int k) {
     if (k < 0 || x < k) return 0;
     unsigned __int128 c = 1;
@@ -668,15 +834,44 @@ unsigned __int128 binom128(int64_t x, int k) {
 
 int boundary_count(int K) { return (K % 2 == 0) ? K / 2 : K; }
 
+// Split form for a level of `count` sets when its buffers fit in
+// kSplitBytes: row slices so that the grid fills the chip several times
+// over, slices of at least 1024 rows.  Returns the slice count (0: fused).
+constexpr uint64_t kSplitBytes = 128ull << 20;
+
+int exact_slices(uint64_t count, int64_t n, int r, int64_t& rows) {
+    const uint64_t blocks = std::min<uint64_t>((count + kBlock - 1) / kBlock, 8192);
+    int64_t slices = std::max<int64_t>(1, (int64_t)((2048 + blocks - 1) / blocks));
+    slices = std::min<int64_t>(slices, std::max<int64_t>(1, n / 1024));
+    rows = (n + slices - 1) / slices;
+    rows = ((rows + 63) / 64) * 64;
+    slices = (n + rows - 1) / rows;
+    if (split_bytes(count, (int)slices, r) > kSplitBytes) return 0;
+    return (int)slices;
+}
+
 template <int R, int D>
-void launch_level(const ExactParams& p, hipStream_t st) {
+void launch_level(ExactParams p, hipStream_t st) {
     const uint64_t blocks = std::min<uint64_t>((p.count + kBlock - 1) / kBlock, 8192);
-    switch (p.K) {
-        case 2: hipLaunchKernelGGL((k_exact_score<R, D, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
-        case 3: hipLaunchKernelGGL((k_exact_score<R, D, 3>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
-        case 4: hipLaunchKernelGGL((k_exact_score<R, D, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
-        default: hipLaunchKernelGGL((k_exact_score<R, D, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+    const int slices = exact_slices(p.count, p.n, R, p.rows_per_slice);
+    if (slices == 0) {
+        switch (p.K) {
+            case 2: hipLaunchKernelGGL((k_exact_score<R, D, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+            case 3: hipLaunchKernelGGL((k_exact_score<R, D, 3>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+            case 4: hipLaunchKernelGGL((k_exact_score<R, D, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+            default: hipLaunchKernelGGL((k_exact_score<R, D, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+        }
+        return;
     }
+    hipLaunchKernelGGL((k_exact_vertex<D>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p, p.recs);
+    const dim3 grid((unsigned)blocks, (unsigned)slices);
+    switch (p.K) {
+        case 2: hipLaunchKernelGGL((k_exact_rows<R, D, 2>), grid, dim3(kBlock), 0, st, p, p.recs); break;
+        case 3: hipLaunchKernelGGL((k_exact_rows<R, D, 3>), grid, dim3(kBlock), 0, st, p, p.recs); break;
+        case 4: hipLaunchKernelGGL((k_exact_rows<R, D, 4>), grid, dim3(kBlock), 0, st, p, p.recs); break;
+        default: hipLaunchKernelGGL((k_exact_rows<R, D, 0>), grid, dim3(kBlock), 0, st, p, p.recs); break;
+    }
+    hipLaunchKernelGGL((k_exact_combine<R, D>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p, slices);
 }
 
 template <int R>
@@ -769,6 +964,17 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     cs.add<unsigned long long>(topk_buffer_keys(total, T));
     cs.add<unsigned long long>(topk_buffer_keys(total, T));
     cs.add<RescoreEntry>(T);
+    uint64_t rec_count = 0, part_floats = 0;     // the largest split level's needs
+    for (int d = r; d >= 1; --d) {
+        if (lt.count[d] == 0) continue;
+        int64_t rows = 0;
+        const int sl = exact_slices(lt.count[d], n, r, rows);
+        if (sl == 0) continue;
+        rec_count = std::max<uint64_t>(rec_count, lt.count[d]);
+        part_floats = std::max<uint64_t>(part_floats, lt.count[d] * (uint64_t)sl * 2 * (2 * r));
+    }
+    cs.add<VertexRec>(rec_count);
+    cs.add<float>(part_floats);
     const size_t host_bytes = 4096 + binom_entries * sizeof(unsigned long long) +
                               LRQO_MAX_K * (2 * sizeof(double2) + sizeof(float2));
 
@@ -788,6 +994,8 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     unsigned long long* ka = cv.take<unsigned long long>(topk_buffer_keys(total, T));
     unsigned long long* kb = cv.take<unsigned long long>(topk_buffer_keys(total, T));
     RescoreEntry* entries = cv.take<RescoreEntry>(T);
+    VertexRec* recs = cv.take<VertexRec>(rec_count);
+    float* part = cv.take<float>(part_floats);
 
     // host tables (pinned staging): result block, binomials, rho, roots
     char* hb = static_cast<char*>(ctx->host);
@@ -848,6 +1056,8 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     p.stats = stats;
     p.random = random ? 1 : 0;
     p.draw_seed = seed;
+    p.part = part;
+    p.recs = recs;
 
     const int64_t vcount = n * r * 2;
     int* nonfinite = &dres->nonfinite;
