@@ -166,14 +166,27 @@ __global__ __launch_bounds__(kBlock) void k_batch_score(BatchDevParams p) {
 }
 
 // Per instance (one block of four waves):
-//   select   best T of its S FP32 scores as packed keys: each wave keeps a
-//            64-key list over a quarter of the scores, wave 0 merges the four
-//   rescore  FP64 objective of each kept direction; wave w takes rows
-//            w, w+4, ..., and the four partial sums are added in wave order
+//   select   best T of its S FP32 scores as packed keys.  Threshold pass:
+//            every lane takes the largest key of its scores, and tau = the
+//            64th largest of the block's 256 lane maxima (64 distinct keys are
+//            >= tau, so the best 64 all are); the keys >= tau (about 75 of
+//            4,096 for scattered scores) are gathered in LDS and wave 0 keeps
+//            the best 64 of them.  If more than kStage keys pass, each wave
+//            instead keeps a 64-key list over a quarter of the scores and
+//            wave 0 merges the four.
+//   rescore  FP64 objective of each kept direction from V_t staged in LDS;
+//            wave w takes rows w, w+4, ..., and the four partial sums are
+//            added in wave order
 //   pick     FP64 arg-max over the kept directions, ties to the lower index
 //   labels   FP64 decision rule of the winner for every row
+constexpr int kStage = 512;          // keys the threshold pass may keep
+
 struct SelectShared {
+    float Vs[kMaxRows * 8];         // V_t as stored (real: n x r, complex: n x 2r floats)
     unsigned long long top[kBlock / 64][64];
+    unsigned long long stage[kStage];
+    unsigned long long tau;
+    unsigned int cnt;
     double part[kBlock / 64][kTopT][8];
     double2 roots[LRQO_MAX_K];
     double cbest[8];
@@ -185,24 +198,57 @@ __device__ void select_rescore(const BatchDevParams& p, int t, SelectShared& sh)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int S = p.S, T = p.T, n = p.n[t];
     const float* f = p.f + (size_t)t * S;
-    const float* V = p.V + p.voff[t];
+    const float* V = sh.Vs;         // staged by the caller before the selection
 
     // ---- select
     const int per = (S + NW * 64 - 1) / (NW * 64) * 64;
     const int lo = w * per, hi = min(S, lo + per);
-    unsigned long long run = 0;
-    for (int b = lo; b < hi; b += 64) {
-        const int s = b + lane;
-        const unsigned long long key = s < hi ? pack_key(f[s], (uint32_t)s) : 0ull;
-        const unsigned long long floor64 = __shfl(run, 63, 64);
-        if (__ballot(key > floor64) == 0) continue;  // uniform across the wave
-        run = wave_top_union(run, wave_sort_desc(key, lane), lane);
-    }
-    sh.top[w][lane] = run;
+    // threshold: the 64th largest of the lane maxima
+    unsigned long long lmax = 0;
+    for (int s = lo + lane; s < hi; s += 64) lmax = key_max(lmax, pack_key(f[s], (uint32_t)s));
+    sh.top[w][lane] = wave_sort_desc(lmax, lane);
     __syncthreads();
     if (w == 0) {
-        for (int v = 1; v < NW; ++v) run = wave_top_union(run, sh.top[v][lane], lane);
-        sh.top[0][lane] = run;
+        unsigned long long u = sh.top[0][lane];
+        for (int v = 1; v < NW; ++v) u = wave_top_union(u, sh.top[v][lane], lane);
+        const unsigned long long tau = __shfl(u, 63, 64);
+        if (lane == 0) sh.tau = tau;
+    }
+    __syncthreads();
+    const unsigned long long tau = sh.tau;
+    for (int s = lo + lane; s < hi; s += 64) {
+        const unsigned long long key = pack_key(f[s], (uint32_t)s);
+        if (key >= tau) {
+            const unsigned int pos = atomicAdd(&sh.cnt, 1u);
+            if (pos < (unsigned)kStage) sh.stage[pos] = key;
+        }
+    }
+    __syncthreads();
+    const unsigned int cnt = sh.cnt;
+    unsigned long long run = 0;
+    if (cnt <= (unsigned)kStage) {
+        if (w == 0) {
+            for (unsigned int b = 0; b < cnt; b += 64) {
+                const unsigned long long key = b + lane < cnt ? sh.stage[b + lane] : 0ull;
+                run = wave_top_union(run, wave_sort_desc(key, lane), lane);
+            }
+            sh.top[0][lane] = run;
+        }
+    } else {
+        for (int b = lo; b < hi; b += 64) {
+            const int s = b + lane;
+            const unsigned long long key = s < hi ? pack_key(f[s], (uint32_t)s) : 0ull;
+            const unsigned long long floor64 = __shfl(run, 63, 64);
+            if (__ballot(key > floor64) == 0) continue;  // uniform across the wave
+            run = wave_top_union(run, wave_sort_desc(key, lane), lane);
+        }
+        __syncthreads();        // every wave has read sh.top (threshold pass)
+        sh.top[w][lane] = run;
+        __syncthreads();
+        if (w == 0) {
+            for (int v = 1; v < NW; ++v) run = wave_top_union(run, sh.top[v][lane], lane);
+            sh.top[0][lane] = run;
+        }
     }
     __syncthreads();
 
@@ -291,6 +337,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_select(BatchDevParams p) {
     __shared__ SelectShared sh;
     const int t = blockIdx.x;
     for (int k = threadIdx.x; k < p.K; k += kBlock) sh.roots[k] = p.roots64[k];
+    const int nf = p.n[t] * p.r[t] * (p.real ? 1 : 2);
+    const float* src = p.V + p.voff[t];
+    for (int e = threadIdx.x; e < nf; e += kBlock) sh.Vs[e] = src[e];
+    if (threadIdx.x == 0) sh.cnt = 0u;
     __syncthreads();
     switch (p.r[t]) {
         case 1: select_rescore<1, KS>(p, t, sh); break;
