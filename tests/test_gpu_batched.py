@@ -77,6 +77,30 @@ def test_batched_parity_small(lrqo_mod, K, S, real, tmp_path, monkeypatch):
         _check_instance(lrqo_mod, V, K, S, 77, t, out.obj[t], out.best_index[t], z[zo[t]:zo[t + 1]], real)
 
 
+def test_equal_scores_take_the_merge_fallback(lrqo_mod, tmp_path, monkeypatch):
+    """A zero factor scores every direction 0, so the keys differ only by
+    index and far more than the threshold pass's 512 keys reach its
+    threshold: the selection falls back to the full merge and must still
+    keep the lowest indices (winner 0, objective 0).  Its neighbours in the
+    batch keep the sampled-path bar."""
+    monkeypatch.setenv("LRQO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    Vs, cat, offs, ns, rs = _small_batch(count=6, seed=21)
+    zero = 2
+    a = offs[zero]
+    b = offs[zero + 1]
+    cat = cat.copy()
+    cat[a:b] = 0.0
+    Vs[zero] = np.zeros_like(Vs[zero])
+    S = 4096
+    out = lrqo_mod.solve_batched(torch.from_numpy(cat).cuda(), offs, ns, rs, 8, S, 31)
+    assert out.best_index[zero] == 0 and out.obj[zero] == 0.0
+    z = out.z.cpu().numpy()
+    zo = np.concatenate([[0], np.cumsum(ns)])
+    for t, V in enumerate(Vs):
+        if t != zero:
+            _check_instance(lrqo_mod, V, 8, S, 31, t, out.obj[t], out.best_index[t], z[zo[t]:zo[t + 1]])
+
+
 def test_batched_equals_single_solves(lrqo_mod, tmp_path, monkeypatch):
     """Instance t of a batch is the single solve with instance = t (same
     stream); objectives agree to the 1e-5 objective bar and usually exactly."""
