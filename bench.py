@@ -40,7 +40,7 @@ def parse():
                     help="skip the precision / batched / learned-proposal measurements")
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
-    ap.add_argument("--form", choices=("precision_bf16", "batched", "learned_proposal", "refine",
+    ap.add_argument("--form", choices=("exact", "precision_bf16", "batched", "learned_proposal", "refine",
                                        "rank1_hybrid", "samplers", "spectral"),
                     help="measure only this form and print its record (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -149,6 +149,50 @@ def form_precision():
             "obj_fp32": o32.obj, "obj_bf16": o16.obj,
             "obj_rel_diff": abs(o16.obj - o32.obj) / o32.obj,
             "flagged_fraction": o16.flagged_rows / float(inst.n * inst.S)}
+
+
+def form_exact():
+    """Exact vertex enumeration (Alg. 2 with its recursion over leading
+    columns): the parity configuration exact_small (n = 12, r = 2, K = 3)
+    beside the FP64 oracle (Alg. 2 in numpy) and brute force over the 3^12
+    assignments, and two larger enumerations of the same kind (n = 64: the
+    split scorer; n = 160: C(480, 3) index sets, the fused scorer)."""
+    import torch
+
+    import oracle
+    from oracle import brute as BR
+    from oracle import exact as EX
+    from paper_2602_20376_amd import inputs, lrqo
+
+    oracle.build()
+
+    def device(V, K):
+        Vd = torch.from_numpy(V).cuda()
+        lrqo.solve_exact(Vd, K)
+        return min((lrqo.solve_exact(Vd, K)[1] for _ in range(3)), key=lambda x: x.device_ms)
+
+    inst = inputs.exact_small()
+    res = device(inst.V, inst.K)
+    oms, ref = _timed(lambda: EX.solve_exact(inst.V, inst.K))
+    bms, bf = _timed(lambda: BR.brute_force(inst.V, inst.K))
+    n, r = inst.V.shape
+    out = {"exact_small": {"n": n, "r": r, "K": inst.K, "obj": res.obj, "oracle_opt": ref["opt"],
+                           "brute_force_opt": bf[0], "index_sets": res.index_sets,
+                           "rank_deficient": res.rank_deficient, "candidates": res.candidates,
+                           "device_ms": res.device_ms,
+                           "oracle": {"kind": "oracle", "ms": oms, "sample": "whole enumeration (FP64, numpy)"},
+                           "brute_force_ms": bms}}
+    for n in (64, 160):
+        V = inputs.random_V(n, 2, 4000 + n)
+        res = device(V, 3)
+        flops = 24.0 * 2 * n * res.index_sets
+        out[f"n{n}"] = {"n": n, "r": 2, "K": 3, "obj": res.obj, "index_sets": res.index_sets,
+                        "candidates": res.candidates, "device_ms": res.device_ms,
+                        "sets_per_s": res.index_sets / (res.device_ms / 1000.0),
+                        "roofline": _alu_roofline(flops, res.device_ms,
+                                                  "per index set and row, V c once and V^H z for each sign "
+                                                  "(24r flops, complex V) over the whole solve")}
+    return out
 
 
 def form_batched():
@@ -448,7 +492,7 @@ def main():
     from paper_2602_20376_amd import inputs, lrqo
 
     if args.form:
-        fn = {"precision_bf16": form_precision, "batched": form_batched, "refine": form_refine,
+        fn = {"precision_bf16": form_precision, "batched": form_batched, "exact": form_exact, "refine": form_refine,
               "rank1_hybrid": form_rank1_hybrid, "samplers": form_samplers, "spectral": form_spectral,
               "learned_proposal": lambda: form_learned(args.train_count)}[args.form]
         print(json.dumps({"form": args.form, **fn()}), flush=True)
@@ -507,7 +551,7 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     if not args.no_forms:
         forms = {}
-        for name, fn in (("precision_bf16", form_precision), ("batched", form_batched),
+        for name, fn in (("exact", form_exact), ("precision_bf16", form_precision), ("batched", form_batched),
                          ("refine", form_refine), ("rank1_hybrid", form_rank1_hybrid),
                          ("samplers", form_samplers), ("spectral", form_spectral),
                          ("learned_proposal", lambda: form_learned(args.train_count))):

@@ -73,6 +73,25 @@ def test_exact_larger_n(lrqo_mod):
     _check(V, 3, z, res)
 
 
+def test_exact_fused_form_at_scale(lrqo_mod):
+    """n = 80, r = 2, K = 3: C(240, 3) + 240 index sets (2.3 million), more
+    than the split scorer's buffers take, so the fused scorer runs.  Too
+    large for the oracle's enumeration; held to what holds at any size: the
+    FP64 objective of the returned labels is the returned objective, and the
+    exact optimum is at least the best of 2^18 sampled directions on the same
+    factor."""
+    V = inputs.random_V(80, 2, 8080)
+    z, res = _solve(lrqo_mod, V, 3)
+    assert res.index_sets > 2_000_000
+    assert abs(oracle.objective(V, 3, z) - res.obj) <= 1e-12 * res.obj
+    samp = lrqo_mod.solve_sampled(torch.from_numpy(V.astype(np.complex64)).cuda(), 3, 1 << 18, 80)
+    V32 = V.astype(np.complex64).astype(np.complex128)
+    f_samp = oracle.objective(V32, 3, samp.z.cpu().numpy())
+    f_exact_on_32 = oracle.objective(V32, 3, z)
+    assert res.obj >= samp.obj * (1 - 1e-6), (res.obj, samp.obj)
+    assert f_exact_on_32 >= f_samp * (1 - 1e-6)
+
+
 def test_exact_real_factor(lrqo_mod):
     """A real factor violates general position (Assumption 1): at vertices
     c ~ exp(i pi(2m+1)/K) x, x real, every row lies on boundary line m.  The
