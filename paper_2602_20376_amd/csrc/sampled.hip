@@ -778,49 +778,63 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
 }
 
 // Thread (t, j) sums component j of kept candidate t over the slices
-// (fixed order); thread t forms f_t; thread 0 takes the FP64 arg-max, ties
-// to the lowest index.
+// (fixed order, eight loads in flight); lane t of wave 0 forms f_t, and a
+// butterfly over the wave takes the FP64 arg-max, ties to the lowest index.
 template <int R>
 __global__ __launch_bounds__(64 * 2 * R) void k_pick(const double* __restrict__ partial, int T, int P,
                                                      const unsigned long long* __restrict__ keys,
                                                      uint64_t seed, uint32_t instance, uint64_t first,
                                                      const float* dirs, DevResult* res) {
     __shared__ double comp[64][2 * R];
-    __shared__ double fs[64];
     const int t = threadIdx.x / (2 * R), j = threadIdx.x % (2 * R);
     if (t < T) {
+        const double* src = partial + (size_t)t * P * (2 * R) + j;
         double a = 0.0;
-        for (int q = 0; q < P; ++q) a += partial[((size_t)t * P + q) * (2 * R) + j];
+        int q = 0;
+        for (; q + 8 <= P; q += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(q + u) * (2 * R)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a += v[u];
+        }
+        for (; q < P; ++q) a += src[(size_t)q * (2 * R)];
         comp[t][j] = a;
     }
     __syncthreads();
-    if (threadIdx.x < T) {
-        double f = 0.0;
-        for (int jj = 0; jj < 2 * R; ++jj) f += comp[threadIdx.x][jj] * comp[threadIdx.x][jj];
-        fs[threadIdx.x] = f;
+    if (threadIdx.x >= kWave) return;
+    const int lane = threadIdx.x;
+    double f = -1.0;
+    unsigned long long key = 0ull;
+    uint32_t idx = 0xFFFFFFFFu;
+    if (lane < T) {
+        double s = 0.0;
+        for (int jj = 0; jj < 2 * R; ++jj) s += comp[lane][jj] * comp[lane][jj];
+        key = keys[lane];
+        idx = key_index(key);
+        f = s >= 0.0 ? s : -1.0;      // a non-finite score is never picked
     }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    int bt = -1;
-    double bf = -1.0;
-    uint32_t bidx = 0xFFFFFFFFu;
-    for (int u = 0; u < T; ++u) {
-        const uint32_t idx = key_index(keys[u]);
-        if (fs[u] > bf || (fs[u] == bf && idx < bidx)) {
-            bf = fs[u];
-            bt = u;
-            bidx = idx;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double fo = __shfl_xor(f, off, kWave);
+        const uint32_t io = __shfl_xor(idx, off, kWave);
+        const unsigned long long ko = __shfl_xor(key, off, kWave);
+        if (fo > f || (fo == f && io < idx)) {
+            f = fo;
+            idx = io;
+            key = ko;
         }
     }
-    if (bt < 0) {  // only with non-finite scores; the host reports the error
-        bt = 0;
-        bidx = key_index(keys[0]);
+    if (lane != 0) return;
+    if (f < 0.0) {  // only with non-finite scores; the host reports the error
+        key = keys[0];
+        idx = key_index(key);
     }
     float cf[2 * R];
-    direction_any<R>(dirs, seed, first + bidx, instance, cf);
-    res->best_index = (int64_t)(first + bidx);
-    res->obj = bf;
-    res->fp32_obj = (double)key_value(keys[bt]);
+    direction_any<R>(dirs, seed, first + idx, instance, cf);
+    res->best_index = (int64_t)(first + idx);
+    res->obj = f;
+    res->fp32_obj = (double)key_value(key);
     for (int jj = 0; jj < 2 * LRQO_MAX_R; ++jj) res->c[jj] = jj < 2 * R ? (double)cf[jj] : 0.0;
 }
 
