@@ -50,9 +50,9 @@ struct Row {
 
 // ------------------------------------------------------------ set-up and checks
 // Roots of unity omega^k = (cos, sin)(2 pi k / K) in FP64 and their FP32
-// roundings; zeroed result record and arg-max key.
+// roundings; zeroed result record.
 __global__ void k_init(int K, double2* __restrict__ roots64, float2* __restrict__ roots32,
-                       DevResult* __restrict__ res, unsigned long long* __restrict__ best_key) {
+                       DevResult* __restrict__ res) {
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
         double sn, cs;
         sincospi(2.0 * (double)k / (double)K, &sn, &cs);
@@ -61,7 +61,6 @@ __global__ void k_init(int K, double2* __restrict__ roots64, float2* __restrict_
     }
     if (threadIdx.x == 0) {
         *res = DevResult{};
-        *best_key = 0ull;
     }
 }
 
@@ -150,7 +149,6 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreParams p) {
     }
 
     if (gridDim.y == 1) {
-        unsigned long long best = 0;
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const uint32_t idx = base + q * kBlock;
@@ -159,12 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_score(ScoreParams p) {
 #pragma unroll
                 for (int j = 0; j < 2 * R; ++j) f = fmaf(acc[q][j], acc[q][j], f);
                 p.f_out[idx] = f;
-                const unsigned long long key = pack_key(f, idx);
-                best = key > best ? key : best;
             }
         }
-        best = wave_max_u64(best);
-        if ((tid & (kWave - 1)) == 0 && best) atomicMax(p.best_key, best);
     } else {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
@@ -345,7 +339,6 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
             for (int j = 0; j < 2 * R; ++j) acc[q][j] += red[w][q * 2 * R + j][lane];
 
     if (gridDim.y == 1) {
-        unsigned long long best = 0;
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const uint32_t idx = base + q * kWave;
@@ -354,12 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
 #pragma unroll
                 for (int j = 0; j < 2 * R; ++j) f = fmaf(acc[q][j], acc[q][j], f);
                 p.f_out[idx] = f;
-                const unsigned long long key = pack_key(f, idx);
-                best = key > best ? key : best;
             }
         }
-        best = wave_max_u64(best);
-        if (lane == 0 && best) atomicMax(p.best_key, best);
     } else {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
@@ -653,7 +642,6 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16(ScoreParams p) {
             for (int j = 0; j < 2 * R; ++j) acc[q][j] += red[w][q * 2 * R + j][lane];
 
     if (gridDim.y == 1) {
-        unsigned long long best = 0;
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
             const uint32_t idx = base + q * kWave;
@@ -662,12 +650,8 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16(ScoreParams p) {
 #pragma unroll
                 for (int j = 0; j < 2 * R; ++j) f = fmaf(acc[q][j], acc[q][j], f);
                 p.f_out[idx] = f;
-                const unsigned long long key = pack_key(f, idx);
-                best = key > best ? key : best;
             }
         }
-        best = wave_max_u64(best);
-        if (lane == 0 && best) atomicMax(p.best_key, best);
     } else {
 #pragma unroll
         for (int q = 0; q < CPL; ++q) {
@@ -687,7 +671,6 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16(ScoreParams p) {
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ partial, int P,
                                                      uint32_t S, float* __restrict__ f_out,
-                                                     unsigned long long* __restrict__ best_key,
                                                      unsigned long long* __restrict__ lists) {
     constexpr int U = R <= 4 ? 8 : 4;      // slices loaded together
     const uint32_t idx = blockIdx.x * kBlock + threadIdx.x;
@@ -697,30 +680,28 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const float* __restrict__ p
         float acc[2 * R];
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) acc[j] = 0.0f;
-        for (int p0 = 0; p0 < P; p0 += U) {
+        int p0 = 0;
+        for (; p0 + U <= P; p0 += U) {          // whole groups: every load issued before the adds
             float v[U][2 * R];
 #pragma unroll
             for (int q = 0; q < U; ++q)
 #pragma unroll
-                for (int j = 0; j < 2 * R; ++j)
-                    v[q][j] = p0 + q < P ? partial[((size_t)(p0 + q) * (2 * R) + j) * S + idx] : 0.0f;
+                for (int j = 0; j < 2 * R; ++j) v[q][j] = partial[((size_t)(p0 + q) * (2 * R) + j) * S + idx];
 #pragma unroll
             for (int q = 0; q < U; ++q)
-                if (p0 + q < P) {
 #pragma unroll
-                    for (int j = 0; j < 2 * R; ++j) acc[j] += v[q][j];
-                }
+                for (int j = 0; j < 2 * R; ++j) acc[j] += v[q][j];
         }
+        for (; p0 < P; ++p0)
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) acc[j] += partial[((size_t)p0 * (2 * R) + j) * S + idx];
         float f = 0.0f;
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) f = fmaf(acc[j], acc[j], f);
         f_out[idx] = f;
         key = pack_key(f, idx);
     }
-    const unsigned long long sorted = wave_sort_desc(key, lane);
-    lists[idx] = sorted;
-    const unsigned long long best = __shfl(sorted, 0, kWave);
-    if (lane == 0 && best) atomicMax(best_key, best);
+    lists[idx] = wave_sort_desc(key, lane);
 }
 
 // ------------------------------------------------------------ FP64 rescore
@@ -918,7 +899,6 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     p.S = S;
     p.f_out = sc.f32;
     p.partial = sc.partial;
-    p.best_key = sc.best_key;
     p.roots32 = sc.roots32;
     p.rows_per_slice = sc.rows_per_slice;
     LRQO_HIP(hipEventRecord(job.ev_score0, st));
@@ -933,7 +913,7 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     if (sc.slices > 1) {
         const uint32_t fblocks = (S + kBlock - 1) / kBlock;
         hipLaunchKernelGGL((k_finalize<R>), dim3(fblocks), dim3(kBlock), 0, st, sc.partial, sc.slices, S, sc.f32,
-                           sc.best_key, sc.lists);
+                           sc.lists);
         LRQO_HIP(hipGetLastError());
         LRQO_TRY(topk_select_lists(sc.lists, fblocks * kBlock, T, sc.keys_a, sc.keys_b, st, &keys));
     } else {
@@ -1007,7 +987,6 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     plan.rescore_slices = (int)((job.n + rrows - 1) / rrows);
     CarveSize cs;
     cs.add<DevResult>(1);
-    cs.add<unsigned long long>(1);
     cs.add<float2>(LRQO_MAX_K);
     cs.add<double2>(LRQO_MAX_K);
     cs.add<float>(job.f_out ? 0 : job.S);
@@ -1023,7 +1002,6 @@ lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void*
     Carve cv(arena);
     Scratch sc{};
     sc.result = cv.take<DevResult>(1);
-    sc.best_key = cv.take<unsigned long long>(1);
     sc.roots32 = cv.take<float2>(LRQO_MAX_K);
     sc.roots64 = cv.take<double2>(LRQO_MAX_K);
     sc.f32 = job.f_out ? job.f_out : cv.take<float>(job.S);
@@ -1039,7 +1017,7 @@ lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void*
     sc.rescore_rows = plan.rescore_rows;
     sc.rescore = cv.take<double>((size_t)plan.topk * plan.rescore_slices * 2 * job.r);
 
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, job.K, sc.roots64, sc.roots32, sc.result, sc.best_key);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, job.K, sc.roots64, sc.roots32, sc.result);
 
     const int64_t vcount = job.n * job.r * (job.real ? 1 : 2);
     hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(256), 0, st, job.V, vcount, sc.result);

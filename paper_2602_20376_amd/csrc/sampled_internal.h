@@ -30,7 +30,6 @@ struct ScoreParams {
     int64_t rows_per_slice;
     float* f_out;
     float* partial;
-    unsigned long long* best_key;
     const float2* roots32;
     unsigned long long* flagged;   // precision form: row-candidates recomputed in FP32
     const float* dirs;             // optional [S][2r] directions in place of the stream
@@ -80,7 +79,6 @@ struct ScratchPlan {
 
 struct Scratch {
     DevResult* result;
-    unsigned long long* best_key;
     float2* roots32;
     double2* roots64;
     float* f32;
