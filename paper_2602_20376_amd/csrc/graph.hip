@@ -14,7 +14,7 @@
 //                   other label and its gain 2 sum_k c_k (cos(a-k) - cos(b-k))
 //   k_move          per candidate: moves when its (gain, -index) beats every
 //                   neighbouring candidate; labels go to the other buffer;
-//                   moves counted per round
+//                   moves counted per round (per block, into eight counters)
 // One thread per vertex; the CSR entries of a vertex are read in order, so
 // every per-vertex sum has a fixed order.
 #include <algorithm>
@@ -148,6 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_
     target[i] = (uint8_t)(cand ? bl : a);
 }
 
+constexpr int kMoveLanes = 8;
+
 __global__ __launch_bounds__(kBlock) void k_move(GraphDev g, const uint8_t* __restrict__ z,
                                                  const double* __restrict__ gain,
                                                  const uint8_t* __restrict__ target,
@@ -165,8 +167,17 @@ __global__ __launch_bounds__(kBlock) void k_move(GraphDev g, const uint8_t* __re
         }
         z_next[i] = win ? target[i] : z[i];
     }
-    const unsigned long long wave_moves = __popcll(__ballot(win));
-    if ((threadIdx.x & (kWave - 1)) == 0 && wave_moves) atomicAdd(moves, wave_moves);
+    // the block's count into one of kMoveLanes counters (block index mod
+    // kMoveLanes), so that same-address atomics stay few
+    __shared__ unsigned int wm[kBlock / kWave];
+    const unsigned long long bal = __ballot(win);
+    if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = (unsigned)__popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long b = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) b += wm[w];
+        if (b) atomicAdd(&moves[blockIdx.x % kMoveLanes], b);
+    }
 }
 
 struct GraphScratch {
@@ -185,7 +196,7 @@ constexpr int kMaxCheck = 64;
 struct HostScratch {
     double* out;                  // [4]
     int* flag;                    // [16]
-    unsigned long long* moves;    // [kMaxCheck]
+    unsigned long long* moves;    // [kMaxCheck][kMoveLanes]
     double* table;                // [2 * LRQO_MAX_K]
 };
 
@@ -200,12 +211,12 @@ lrqo_status reserve_graph(DeviceCtx* ctx, int64_t n, bool refine, GraphScratch& 
         cs.add<double>(n);
         cs.add<uint8_t>(n);
         cs.add<uint8_t>(n);
-        cs.add<unsigned long long>(kMaxCheck);
+        cs.add<unsigned long long>(kMaxCheck * kMoveLanes);
     }
     CarveSize hs;
     hs.add<double>(4);
     hs.add<int>(16);
-    hs.add<unsigned long long>(kMaxCheck);
+    hs.add<unsigned long long>(kMaxCheck * kMoveLanes);
     hs.add<double>(2 * LRQO_MAX_K);
     LRQO_TRY(reserve_arena(ctx, cs.bytes));
     LRQO_TRY(reserve_host(ctx, hs.bytes));
@@ -217,11 +228,11 @@ lrqo_status reserve_graph(DeviceCtx* ctx, int64_t n, bool refine, GraphScratch& 
     s.gain = refine ? cv.take<double>(n) : nullptr;
     s.target = refine ? cv.take<uint8_t>(n) : nullptr;
     s.zb = refine ? cv.take<uint8_t>(n) : nullptr;
-    s.moves = refine ? cv.take<unsigned long long>(kMaxCheck) : nullptr;
+    s.moves = refine ? cv.take<unsigned long long>(kMaxCheck * kMoveLanes) : nullptr;
     Carve hv(ctx->host);
     h.out = hv.take<double>(4);
     h.flag = hv.take<int>(16);
-    h.moves = hv.take<unsigned long long>(kMaxCheck);
+    h.moves = hv.take<unsigned long long>(kMaxCheck * kMoveLanes);
     h.table = hv.take<double>(2 * LRQO_MAX_K);
     return LRQO_OK;
 }
@@ -357,31 +368,34 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
     float total_ms = 0.0f;
     while (!converged && rounds < max_rounds) {
         const int todo = (int)std::min<int64_t>(chunk, max_rounds - rounds);
-        LRQO_HIP(hipMemsetAsync(s.moves, 0, sizeof(unsigned long long) * todo, st));
+        LRQO_HIP(hipMemsetAsync(s.moves, 0, sizeof(unsigned long long) * todo * kMoveLanes, st));
         LRQO_HIP(hipEventRecord(ctx->ev_start, st));
         for (int t = 0; t < todo; ++t) {
             hipLaunchKernelGGL(k_gain, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd, s.gain,
                                s.target);
             hipLaunchKernelGGL(k_move, dim3(blocks), dim3(kBlock), 0, st, gd, zbuf[cur], s.gain, s.target,
-                               zbuf[cur ^ 1], s.moves + t);
+                               zbuf[cur ^ 1], s.moves + (size_t)t * kMoveLanes);
             cur ^= 1;
         }
         LRQO_HIP(hipGetLastError());
         LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
         launched += todo;
-        LRQO_HIP(hipMemcpyAsync(h.moves, s.moves, sizeof(unsigned long long) * todo, hipMemcpyDeviceToHost, st));
+        LRQO_HIP(hipMemcpyAsync(h.moves, s.moves, sizeof(unsigned long long) * todo * kMoveLanes,
+                                hipMemcpyDeviceToHost, st));
         LRQO_HIP(hipStreamSynchronize(st));
         float ms = 0.0f;
         LRQO_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
         total_ms += ms;
         // a round without moves leaves the labels as they were, and so do all after it
         for (int t = 0; t < todo; ++t) {
-            if (h.moves[t] == 0) {
+            unsigned long long m = 0;
+            for (int l = 0; l < kMoveLanes; ++l) m += h.moves[(size_t)t * kMoveLanes + l];
+            if (m == 0) {
                 converged = true;
                 break;
             }
             ++rounds;
-            moves += (int64_t)h.moves[t];
+            moves += (int64_t)m;
         }
     }
     if (cur == 1) LRQO_HIP(hipMemcpyAsync(z, s.zb, (size_t)gd.n, hipMemcpyDeviceToDevice, st));
