@@ -99,26 +99,38 @@ __device__ void hermitian_eig3(const double (&Mr)[3][3], const double (&Mi)[3][3
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) Q[i][j] = i == j ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 30; ++sweep) {
-        double off = 0.0;
-        for (int i = 0; i < 6; ++i)
+        double off = 0.0, dia = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            dia += A[i][i] * A[i][i];
+#pragma unroll
             for (int j = i + 1; j < 6; ++j) off += A[i][j] * A[i][j];
-        if (off < 1e-30) break;
+        }
+        // converged when the off-diagonal part is at FP64 rounding of the
+        // diagonal (an absolute bound would never be met for large M)
+        if (off <= 1e-32 * dia || off < 1e-300) break;
+        // fully unrolled: every index is a constant, so A and Q stay in registers
+#pragma unroll
         for (int p = 0; p < 6; ++p)
+#pragma unroll
             for (int q = p + 1; q < 6; ++q) {
                 if (fabs(A[p][q]) < 1e-300) continue;
                 const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
                 const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
                 const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     const double akp = A[k][p], akq = A[k][q];
                     A[k][p] = c * akp - s * akq;
                     A[k][q] = s * akp + c * akq;
                 }
+#pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     const double apk = A[p][k], aqk = A[q][k];
                     A[p][k] = c * apk - s * aqk;
                     A[q][k] = s * apk + c * aqk;
                 }
+#pragma unroll
                 for (int k = 0; k < 6; ++k) {
                     const double qkp = Q[k][p], qkq = Q[k][q];
                     Q[k][p] = c * qkp - s * qkq;
@@ -126,41 +138,72 @@ __device__ void hermitian_eig3(const double (&Mr)[3][3], const double (&Mi)[3][3
                 }
             }
     }
+    // Everything below indexes A, Q, U only with constants (unrolled loops
+    // and selects), so that they stay in registers.
+    double ev[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) ev[c] = A[c][c];
+    auto pick6 = [](const double (&a)[6], int idx) {
+        double v = a[0];
+#pragma unroll
+        for (int c = 1; c < 6; ++c) v = idx == c ? a[c] : v;
+        return v;
+    };
     int order[6] = {0, 1, 2, 3, 4, 5};
+#pragma unroll
     for (int i = 0; i < 6; ++i)
+#pragma unroll
         for (int j = i + 1; j < 6; ++j)
-            if (A[order[j]][order[j]] > A[order[i]][order[i]]) {
+            if (pick6(ev, order[j]) > pick6(ev, order[i])) {
                 const int t = order[i];
                 order[i] = order[j];
                 order[j] = t;
             }
     int got = 0;
-    for (int oi = 0; oi < 6 && got < 3; ++oi) {
+#pragma unroll
+    for (int oi = 0; oi < 6; ++oi) {
+        if (got >= 3) break;
         const int col = order[oi];
         double ur[3], ui[3];
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
-            ur[k] = Q[k][col];
-            ui[k] = Q[k + 3][col];
+            ur[k] = Q[k][0];
+            ui[k] = Q[k + 3][0];
+#pragma unroll
+            for (int c = 1; c < 6; ++c) {
+                ur[k] = col == c ? Q[k][c] : ur[k];
+                ui[k] = col == c ? Q[k + 3][c] : ui[k];
+            }
         }
-        for (int prev = 0; prev < got; ++prev) {   // remove <u_prev, u> u_prev
+#pragma unroll
+        for (int prev = 0; prev < 3; ++prev) {     // remove <u_prev, u> u_prev
+            if (prev >= got) break;
             double dr = 0.0, di = 0.0;
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 dr += Ur[k][prev] * ur[k] + Ui[k][prev] * ui[k];
                 di += Ur[k][prev] * ui[k] - Ui[k][prev] * ur[k];
             }
+#pragma unroll
             for (int k = 0; k < 3; ++k) {
                 ur[k] -= dr * Ur[k][prev] - di * Ui[k][prev];
                 ui[k] -= dr * Ui[k][prev] + di * Ur[k][prev];
             }
         }
         double nrm = 0.0;
+#pragma unroll
         for (int k = 0; k < 3; ++k) nrm += ur[k] * ur[k] + ui[k] * ui[k];
         nrm = sqrt(nrm);
         if (nrm < 0.5) continue;                   // the i * u twin of an earlier vector
-        for (int k = 0; k < 3; ++k) {
-            Ur[k][got] = ur[k] / nrm;
-            Ui[k][got] = ui[k] / nrm;
-        }
+#pragma unroll
+        for (int g = 0; g < 3; ++g)
+            if (g == got) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    Ur[k][g] = ur[k] / nrm;
+                    Ui[k][g] = ui[k] / nrm;
+                }
+            }
         ++got;
     }
 }
@@ -176,16 +219,31 @@ __device__ double block_sum(double x, double* red) {
     return t;
 }
 
-// One block per instance: two passes over the rows (FP64).
-__global__ __launch_bounds__(kBlock) void k_frame(const float* __restrict__ V, const int64_t* voff,
-                                                 const int64_t* nrows, int K, Frame* frames) {
+// Canonical frame of each instance in four stages, the two row passes split
+// over `splits` blocks per instance (row range q of ceil(n / splits) rows),
+// their partial sums added in split order (FP64):
+//   k_frame_m    per split: sum_i |v_i|^2 conj(v_ia) v_ib and sum_i |v_i|^2
+//   k_frame_eig  per instance: M, its eigenvectors (descending) -> g, scale s
+//   k_frame_p    per split: sum_i (s V U)_ib^K (binary exponentiation of the
+//                complex number) and sum_i (s V U)_ib
+//   k_frame_fin  per instance: column phases from the two sums -> g
+constexpr int kFrameM = 19, kFrameP = 12;
+
+__device__ __forceinline__ void split_rows(int64_t n, int q, int splits, int64_t& r0, int64_t& r1) {
+    const int64_t per = (n + splits - 1) / splits;
+    r0 = min(n, (int64_t)q * per);
+    r1 = min(n, r0 + per);
+}
+
+__global__ __launch_bounds__(kBlock) void k_frame_m(const float* __restrict__ V, const int64_t* voff,
+                                                   const int64_t* nrows, int splits, double* __restrict__ work) {
     __shared__ double red[kBlock / kWave];
-    __shared__ double Us[18];
-    const int t = blockIdx.x;
+    const int t = blockIdx.x, q = blockIdx.y;
     const float* Vt = V + voff[t];
-    const int64_t n = nrows[t];
-    double acc[19] = {0};   // 9 complex entries of M, then sum |v|^2
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    int64_t r0, r1;
+    split_rows(nrows[t], q, splits, r0, r1);
+    double acc[kFrameM] = {0};   // 9 complex entries of M, then sum |v|^2
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
         double vr[3], vi[3], w = 0.0;
         for (int j = 0; j < 3; ++j) {
             vr[j] = Vt[i * 6 + 2 * j];
@@ -199,27 +257,91 @@ __global__ __launch_bounds__(kBlock) void k_frame(const float* __restrict__ V, c
             }
         acc[18] += w;
     }
-    double tot[19];
-    for (int e = 0; e < 19; ++e) tot[e] = block_sum(acc[e], red);
-    if (threadIdx.x == 0) {
-        double Mr[3][3], Mi[3][3], Ur[3][3], Ui[3][3];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                Mr[a][b] = tot[2 * (3 * a + b)];
-                Mi[a][b] = tot[2 * (3 * a + b) + 1];
-            }
-        hermitian_eig3(Mr, Mi, Ur, Ui);
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) {
-                Us[2 * (3 * a + b)] = Ur[a][b];
-                Us[2 * (3 * a + b) + 1] = Ui[a][b];
-            }
+    for (int e = 0; e < kFrameM; ++e) {
+        const double v = block_sum(acc[e], red);
+        if (threadIdx.x == 0) work[((size_t)t * splits + q) * kFrameM + e] = v;
+    }
+}
+
+// Thread e < count of a block sums entry e of instance t over the splits
+// (in split order, eight loads in flight) into tot[e].
+__device__ __forceinline__ void sum_splits(const double* __restrict__ work, int t, int splits, int width,
+                                           double* tot) {
+    const int e = threadIdx.x;
+    if (e < width) {
+        const double* src = work + (size_t)t * splits * width + e;
+        double a = 0.0;
+        int q = 0;
+        for (; q + 8 <= splits; q += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(q + u) * width];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a += v[u];
+        }
+        for (; q < splits; ++q) a += src[(size_t)q * width];
+        tot[e] = a;
     }
     __syncthreads();
-    // pass 2: sum_i (V U)_ij^K and sum_i (V U)_ij on rows of unit RMS norm
-    const double s = sqrt((double)n / tot[18]);
+}
+
+__global__ __launch_bounds__(kWave) void k_frame_eig(const double* __restrict__ work, const int64_t* nrows, int splits,
+                            Frame* __restrict__ frames) {
+    __shared__ double tot[kFrameM];
+    const int t = blockIdx.x;
+    sum_splits(work, t, splits, kFrameM, tot);
+    if (threadIdx.x != 0) return;
+    double Mr[3][3], Mi[3][3], Ur[3][3], Ui[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            Mr[a][b] = tot[2 * (3 * a + b)];
+            Mi[a][b] = tot[2 * (3 * a + b) + 1];
+        }
+    hermitian_eig3(Mr, Mi, Ur, Ui);
+    Frame f;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            f.g[2 * (3 * a + b)] = Ur[a][b];
+            f.g[2 * (3 * a + b) + 1] = Ui[a][b];
+        }
+    f.s = sqrt((double)nrows[t] / tot[18]);
+    f.pad = 0.0;
+    frames[t] = f;
+}
+
+// w^K for an integer K >= 1 by binary exponentiation
+__device__ __forceinline__ void cpow_int(double wr, double wi, int K, double& pr, double& pi) {
+    double rr = 1.0, ri = 0.0, br = wr, bi = wi;
+    for (int e = K; e > 0; e >>= 1) {
+        if (e & 1) {
+            const double x = rr * br - ri * bi;
+            ri = rr * bi + ri * br;
+            rr = x;
+        }
+        if (e > 1) {
+            const double x = br * br - bi * bi;
+            bi = 2.0 * br * bi;
+            br = x;
+        }
+    }
+    pr = rr;
+    pi = ri;
+}
+
+__global__ __launch_bounds__(kBlock) void k_frame_p(const float* __restrict__ V, const int64_t* voff,
+                                                   const int64_t* nrows, int splits, int K,
+                                                   const Frame* __restrict__ frames, double* __restrict__ work) {
+    __shared__ double red[kBlock / kWave];
+    __shared__ double Us[18];
+    const int t = blockIdx.x, q = blockIdx.y;
+    if (threadIdx.x < 18) Us[threadIdx.x] = frames[t].g[threadIdx.x];
+    __syncthreads();
+    const double s = frames[t].s;
+    const float* Vt = V + voff[t];
+    int64_t r0, r1;
+    split_rows(nrows[t], q, splits, r0, r1);
     double pk[6] = {0}, p1[6] = {0};
-    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
         double vr[3], vi[3];
         for (int j = 0; j < 3; ++j) {
             vr[j] = s * Vt[i * 6 + 2 * j];
@@ -234,40 +356,74 @@ __global__ __launch_bounds__(kBlock) void k_frame(const float* __restrict__ V, c
             }
             p1[2 * b] += wr;
             p1[2 * b + 1] += wi;
-            const double rho = sqrt(wr * wr + wi * wi), th = atan2(wi, wr);
-            const double rk = pow(rho, (double)K);
-            pk[2 * b] += rk * cos(K * th);
-            pk[2 * b + 1] += rk * sin(K * th);
+            double pr, pim;
+            cpow_int(wr, wi, K, pr, pim);
+            pk[2 * b] += pr;
+            pk[2 * b + 1] += pim;
         }
     }
+    for (int e = 0; e < 6; ++e) {
+        const double a = block_sum(pk[e], red);
+        const double b = block_sum(p1[e], red);
+        if (threadIdx.x == 0) {
+            work[((size_t)t * splits + q) * kFrameP + e] = a;
+            work[((size_t)t * splits + q) * kFrameP + 6 + e] = b;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_frame_fin(const double* __restrict__ work, int splits, int K, Frame* __restrict__ frames) {
+    __shared__ double tot[kFrameP];
+    const int t = blockIdx.x;
+    sum_splits(work, t, splits, kFrameP, tot);
+    if (threadIdx.x != 0) return;
     double PK[6], P1[6];
     for (int e = 0; e < 6; ++e) {
-        PK[e] = block_sum(pk[e], red);
-        P1[e] = block_sum(p1[e], red);
+        PK[e] = tot[e];
+        P1[e] = tot[6 + e];
     }
-    if (threadIdx.x == 0) {
-        Frame f;
-        const double two_pi = 6.283185307179586476925286766559;
-        for (int b = 0; b < 3; ++b) {
-            const double phi = atan2(PK[2 * b + 1], PK[2 * b]) / K;
-            // first moment after the K-th-moment phase: rotate into [-pi/K, pi/K)
-            const double c1 = cos(-phi), s1 = sin(-phi);
-            const double fr = P1[2 * b] * c1 - P1[2 * b + 1] * s1;
-            const double fi = P1[2 * b] * s1 + P1[2 * b + 1] * c1;
-            const double psi = atan2(fi, fr);
-            const double m = floor(psi * K / two_pi + 0.5);
-            const double ang = -phi - two_pi * m / K;
-            const double cr = cos(ang), ci = sin(ang);
-            for (int a = 0; a < 3; ++a) {
-                const double ur = Us[2 * (3 * a + b)], ui = Us[2 * (3 * a + b) + 1];
-                f.g[2 * (3 * a + b)] = ur * cr - ui * ci;
-                f.g[2 * (3 * a + b) + 1] = ur * ci + ui * cr;
-            }
+    Frame f = frames[t];
+    double Us[18];
+    for (int e = 0; e < 18; ++e) Us[e] = f.g[e];
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int b = 0; b < 3; ++b) {
+        const double phi = atan2(PK[2 * b + 1], PK[2 * b]) / K;
+        // first moment after the K-th-moment phase: rotate into [-pi/K, pi/K)
+        const double c1 = cos(-phi), s1 = sin(-phi);
+        const double fr = P1[2 * b] * c1 - P1[2 * b + 1] * s1;
+        const double fi = P1[2 * b] * s1 + P1[2 * b + 1] * c1;
+        const double psi = atan2(fi, fr);
+        const double m = floor(psi * K / two_pi + 0.5);
+        const double ang = -phi - two_pi * m / K;
+        const double cr = cos(ang), ci = sin(ang);
+        for (int a = 0; a < 3; ++a) {
+            const double ur = Us[2 * (3 * a + b)], ui = Us[2 * (3 * a + b) + 1];
+            f.g[2 * (3 * a + b)] = ur * cr - ui * ci;
+            f.g[2 * (3 * a + b) + 1] = ur * ci + ui * cr;
         }
-        f.s = s;
-        f.pad = 0.0;
-        frames[t] = f;
     }
+    frames[t] = f;
+}
+
+// Row splits for frames of `count` instances of at most max_n rows: about
+// 1024 blocks in all, at least 1024 rows per split.
+int frame_splits(int count, int64_t max_n) {
+    int64_t sp = (1024 + count - 1) / count;
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, max_n / 1024));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sp, 256));
+}
+
+// Work doubles the frame stages need.
+size_t frame_work(int count, int splits) { return (size_t)count * splits * (kFrameM + kFrameP); }
+
+void launch_frames(const float* V, const int64_t* voff, const int64_t* n, int count, int splits, int K,
+                   Frame* frames, double* work, hipStream_t st) {
+    double* wm = work;
+    double* wp = work + (size_t)count * splits * kFrameM;
+    hipLaunchKernelGGL(k_frame_m, dim3(count, splits), dim3(kBlock), 0, st, V, voff, n, splits, wm);
+    hipLaunchKernelGGL(k_frame_eig, dim3(count), dim3(64), 0, st, wm, n, splits, frames);
+    hipLaunchKernelGGL(k_frame_p, dim3(count, splits), dim3(kBlock), 0, st, V, voff, n, splits, K, frames, wp);
+    hipLaunchKernelGGL(k_frame_fin, dim3(count), dim3(64), 0, st, wp, splits, K, frames);
 }
 
 __device__ __forceinline__ void feature_row(const float* Vt, int64_t i, const Frame& f, float (&x)[DIN]) {
@@ -800,6 +956,8 @@ struct FwdBufs {
     int32_t* first;
     float* partial;
     float* mvec;
+    double* fwork;              // frame stages' partial sums
+    int fsplits;
 };
 
 lrqo_status run_embed(lrqo_proposal* P, const float* V, int count, const int64_t* hvoff, const int64_t* hn,
@@ -810,7 +968,7 @@ lrqo_status run_embed(lrqo_proposal* P, const float* V, int count, const int64_t
     LRQO_HIP(hipMemcpyAsync(b.inst, rp.inst.data(), sizeof(int32_t) * rp.inst.size(), hipMemcpyHostToDevice, st));
     LRQO_HIP(hipMemcpyAsync(b.start, rp.start.data(), sizeof(int64_t) * rp.start.size(), hipMemcpyHostToDevice, st));
     LRQO_HIP(hipMemcpyAsync(b.first, rp.first.data(), sizeof(int32_t) * rp.first.size(), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_frame, dim3(count), dim3(kBlock), 0, st, V, b.voff, b.n, P->K, b.frames);
+    launch_frames(V, b.voff, b.n, count, b.fsplits, P->K, b.frames, b.fwork, st);
     LRQO_HIP(hipGetLastError());
     RowItems items{b.inst, b.start, (int32_t)rp.inst.size()};
     hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)rp.inst.size()), dim3(kBlock), 0, st, V, b.voff, b.n,
@@ -922,6 +1080,8 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     cs.add<float>((size_t)count * (OUT * H + OUT));
     cs.add<float>(bp.inst.size() * NG);
     cs.add<float>((size_t)kGradChunks * NP);
+    const int fsplits = frame_splits(count, *std::max_element(n, n + count));
+    cs.add<double>(frame_work(count, fsplits));
     LRQO_TRY(ensure_scratch(P, cs.bytes));
     Carve cv(P->scratch);
     FwdBufs b{};
@@ -940,6 +1100,8 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     float* headp = cv.take<float>((size_t)count * (OUT * H + OUT));
     float* mlpp = cv.take<float>(bp.inst.size() * NG);
     float* gpart = cv.take<float>((size_t)kGradChunks * NP);
+    b.fwork = cv.take<double>(frame_work(count, fsplits));
+    b.fsplits = fsplits;
     hipStream_t st = current_stream();
     LRQO_TRY(run_embed(P, V, count, v_offset, n, fp, b, st));
     LRQO_HIP(hipMemcpyAsync(tin, targets, sizeof(float) * count * 6, hipMemcpyHostToDevice, st));
@@ -998,6 +1160,8 @@ lrqo_status lrqo_proposal_sample(lrqo_proposal* P, const float* V, int64_t n, in
     cs.add<int32_t>(2);
     cs.add<float>(fp.inst.size() * H);
     cs.add<float>(H);
+    const int fsplits = frame_splits(1, n);
+    cs.add<double>(frame_work(1, fsplits));
     LRQO_TRY(ensure_scratch(P, cs.bytes));
     Carve cv(P->scratch);
     FwdBufs b{};
@@ -1009,6 +1173,8 @@ lrqo_status lrqo_proposal_sample(lrqo_proposal* P, const float* V, int64_t n, in
     b.first = cv.take<int32_t>(2);
     b.partial = cv.take<float>(fp.inst.size() * H);
     b.mvec = cv.take<float>(H);
+    b.fwork = cv.take<double>(frame_work(1, fsplits));
+    b.fsplits = fsplits;
     hipStream_t st = current_stream();
     LRQO_TRY(run_embed(P, V, 1, &zero, &n, fp, b, st));
     const int period = uniform_fraction > 0.0f ? std::max(1, (int)lrintf(1.0f / uniform_fraction)) : 0;
@@ -1026,13 +1192,20 @@ lrqo_status lrqo_proposal_frame(lrqo_proposal* P, const float* V, int64_t n, dou
     if (!P || !V || !frame_out) return fail(LRQO_EINVAL, "null pointer argument");
     if (n < 1 || n > (1 << 24)) return fail(LRQO_EINVAL, "n must be in [1, 2^24]");
     if (!is_device_pointer(V)) return fail(LRQO_EINVAL, "V is not device memory");
-    LRQO_TRY(ensure_scratch(P, 4096));
-    int64_t* d = static_cast<int64_t*>(P->scratch);
-    Frame* fr = reinterpret_cast<Frame*>(static_cast<char*>(P->scratch) + 256);
+    const int fsplits = frame_splits(1, n);
+    CarveSize cs;
+    cs.add<int64_t>(2);
+    cs.add<Frame>(1);
+    cs.add<double>(frame_work(1, fsplits));
+    LRQO_TRY(ensure_scratch(P, cs.bytes));
+    Carve cv(P->scratch);
+    int64_t* d = cv.take<int64_t>(2);
+    Frame* fr = cv.take<Frame>(1);
+    double* work = cv.take<double>(frame_work(1, fsplits));
     const int64_t h[2] = {0, n};
     hipStream_t st = current_stream();
     LRQO_HIP(hipMemcpyAsync(d, h, sizeof h, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_frame, dim3(1), dim3(kBlock), 0, st, V, d, d + 1, P->K, fr);
+    launch_frames(V, d, d + 1, 1, fsplits, P->K, fr, work, st);
     LRQO_HIP(hipGetLastError());
     Frame hf;
     LRQO_HIP(hipMemcpyAsync(&hf, fr, sizeof hf, hipMemcpyDeviceToHost, st));
