@@ -39,7 +39,8 @@ constexpr int NP = H * DIN + H + H * H + H + OUT * H + OUT;   // 21,248 paramete
 constexpr int OFF_W1 = 0, OFF_B1 = H * DIN, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H,
               OFF_W3 = OFF_B2 + H, OFF_B3 = OFF_W3 + OUT * H;
 constexpr int kBlock = 256;
-constexpr int kRowTile = 64;   // rows per backward tile
+constexpr int kRowTile = 64;   // rows per backward tile (one per lane)
+static_assert(kRowTile == kWave, "the backward maps lane l to row l of the tile");
 constexpr int kMaxRetry = 32;  // rejection-sampler attempts before falling back to the mean
 
 struct Frame {                 // canonical gauge of one instance
@@ -645,7 +646,9 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bwd(const float* __restrict__ V,
                                                    float* __restrict__ partial) {
     constexpr int NG = H * DIN + H + H * H + H;
     __shared__ float W1[H * DIN], b1[H], W2[H * H], b2[H];
-    __shared__ float X[kRowTile][DIN], A1[kRowTile][H], D2[kRowTile][H], D1[kRowTile][H];
+    // rows padded to H + 1 floats: lanes that hold different rows of one
+    // column fall in different LDS banks
+    __shared__ float X[kRowTile][DIN + 1], A1[kRowTile][H + 1], D2[kRowTile][H + 1], D1[kRowTile][H + 1];
     __shared__ float dh2[H];
     for (int e = threadIdx.x; e < H * DIN; e += kBlock) W1[e] = theta[OFF_W1 + e];
     for (int e = threadIdx.x; e < H * H; e += kBlock) W2[e] = theta[OFF_W2 + e];
@@ -659,57 +662,93 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bwd(const float* __restrict__ V,
     }
     __syncthreads();
     const int64_t i0 = items.start[it];
-    // forward recompute and d pre-activations, one row per thread (first 64
-    // threads); activations go to LDS (h1 > 0 exactly where pre1 > 0)
-    if (threadIdx.x < kRowTile) {
-        const int rr = threadIdx.x;
-        const int64_t i = i0 + rr;
-        const bool live = i < n;
-        float x[DIN], h1[H];
+    // forward recompute and d pre-activations: thread (row rr = lane, part =
+    // wave) takes neurons 16 part .. 16 part + 15 of each layer
+    constexpr int HP = H / (kBlock / kWave);
+    const int rr = threadIdx.x & (kWave - 1), o0 = (threadIdx.x / kWave) * HP;
+    const int64_t i = i0 + rr;
+    const bool live = i < n;
+    {
+        float x[DIN];
 #pragma unroll
         for (int k = 0; k < DIN; ++k) x[k] = 0.0f;
         if (live) feature_row(V + voff[t], i, frames[t], x);
+        if (o0 == 0) {
 #pragma unroll
-        for (int k = 0; k < DIN; ++k) X[rr][k] = x[k];
+            for (int k = 0; k < DIN; ++k) X[rr][k] = x[k];
+        }
 #pragma unroll
-        for (int o = 0; o < H; ++o) {
+        for (int oo = 0; oo < HP; ++oo) {
+            const int o = o0 + oo;
             float a = b1[o];
 #pragma unroll
             for (int k = 0; k < DIN; ++k) a = fmaf(W1[o * DIN + k], x[k], a);
-            h1[o] = live ? fmaxf(a, 0.0f) : 0.0f;
-            A1[rr][o] = h1[o];
-        }
-        for (int o = 0; o < H; ++o) {
-            float a = b2[o];
-#pragma unroll
-            for (int k = 0; k < H; ++k) a = fmaf(W2[o * H + k], h1[k], a);
-            D2[rr][o] = (live && a > 0.0f) ? dh2[o] : 0.0f;
-        }
-        for (int k = 0; k < H; ++k) {
-            float a = 0.0f;
-            for (int o = 0; o < H; ++o) a = fmaf(W2[o * H + k], D2[rr][o], a);
-            D1[rr][k] = A1[rr][k] > 0.0f ? a : 0.0f;
+            A1[rr][o] = live ? fmaxf(a, 0.0f) : 0.0f;
         }
     }
     __syncthreads();
-    // weight gradients over the tile's rows: thread e owns entries e, e+256, ...
+    for (int oo = 0; oo < HP; ++oo) {
+        const int o = o0 + oo;
+        float a = b2[o];
+#pragma unroll 16
+        for (int k = 0; k < H; ++k) a = fmaf(W2[o * H + k], A1[rr][k], a);
+        D2[rr][o] = (live && a > 0.0f) ? dh2[o] : 0.0f;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < HP; ++kk) {
+        const int k = o0 + kk;
+        float a = 0.0f;
+#pragma unroll 16
+        for (int o = 0; o < H; ++o) a = fmaf(W2[o * H + k], D2[rr][o], a);
+        D1[rr][k] = A1[rr][k] > 0.0f ? a : 0.0f;
+    }
+    __syncthreads();
+    // weight gradients over the tile's rows, each entry summed over the rows
+    // in order.  dW2[o][k] = sum_r D2[r][o] A1[r][k]: thread (to, tk) of a
+    // 16 x 16 grid owns the 4 x 4 block o in 4to.., k in 4tk.. (eight LDS
+    // reads per sixteen FMAs)
     float* out = partial + (size_t)it * NG;
-    for (int e = threadIdx.x; e < NG; e += kBlock) {
+    static_assert(kBlock == 256 && H == 64, "the dW2 tiling assumes 256 threads and H = 64");
+    {
+        const int to = threadIdx.x / 16, tk = threadIdx.x % 16;
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0f;
+        for (int r = 0; r < kRowTile; ++r) {
+            float d[4], h[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                d[a] = D2[r][4 * to + a];
+                h[a] = A1[r][4 * tk + a];
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(d[a], h[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) out[H * DIN + H + (4 * to + a) * H + 4 * tk + b] = acc[a][b];
+    }
+    // dW1, db1 and db2: thread e owns entries e, e + 256 of those 512
+    for (int e = threadIdx.x; e < H * DIN + 2 * H; e += kBlock) {
         float a = 0.0f;
         if (e < H * DIN) {                       // dW1[o][k] = sum_r D1[r][o] X[r][k]
             const int o = e / DIN, k = e % DIN;
             for (int r = 0; r < kRowTile; ++r) a = fmaf(D1[r][o], X[r][k], a);
+            out[e] = a;
         } else if (e < H * DIN + H) {            // db1
             const int o = e - H * DIN;
             for (int r = 0; r < kRowTile; ++r) a += D1[r][o];
-        } else if (e < H * DIN + H + H * H) {    // dW2[o][k] = sum_r D2[r][o] A1[r][k]
-            const int q = e - H * DIN - H, o = q / H, k = q % H;
-            for (int r = 0; r < kRowTile; ++r) a = fmaf(D2[r][o], A1[r][k], a);
+            out[e] = a;
         } else {                                 // db2
-            const int o = e - H * DIN - H - H * H;
+            const int o = e - H * DIN - H;
             for (int r = 0; r < kRowTile; ++r) a += D2[r][o];
+            out[H * DIN + H + H * H + o] = a;
         }
-        out[e] = a;
     }
 }
 
