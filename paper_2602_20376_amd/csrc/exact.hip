@@ -69,7 +69,7 @@ struct ExactParams {
     uint64_t count;                     // index sets at this level
     uint64_t offset;                    // global index of this level's first set
     float* fbuf;
-    unsigned long long* stats;          // valid sets, rank deficient, candidates
+    unsigned long long* stats;          // valid sets, rank deficient, candidates: kStatSlots slots each
     int random;                         // 1: index sets drawn at random (null-vector sampler)
     uint64_t draw_seed;
     int64_t rows_per_slice;             // rows of one slice of the split scorer's grid
@@ -397,17 +397,19 @@ __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1]
 #pragma unroll
         for (int t = 0; t < M; ++t) total *= cn[t];
         ncand += (unsigned long long)total;
+        // the combinations in mixed radix cn[0], cn[1], ... (digit t least
+        // significant first), stepped by a counter instead of divisions
+        int dig[M];
+#pragma unroll
+        for (int t = 0; t < M; ++t) dig[t] = 0;
         for (int64_t combo = 0; combo < total; ++combo) {
             float sr[2 * R];
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) sr[j] = acc[s][j];
-            int64_t rest = combo;
 #pragma unroll
             for (int t = 0; t < M; ++t) {
                 if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
-                const int q = (int)(rest % cn[t]);
-                rest /= cn[t];
-                int k = o[t] + q;
+                int k = o[t] + dig[t];
                 k = k >= p.K ? k - p.K : k;
                 const float2 z = p.roots32[k];
 #pragma unroll
@@ -421,15 +423,27 @@ __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1]
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) f = fmaf(sr[j], sr[j], f);
             best = fmaxf(best, f);
+            bool carry = true;
+#pragma unroll
+            for (int t = 0; t < M; ++t) {
+                if (carry) {
+                    carry = ++dig[t] == cn[t];
+                    if (carry) dig[t] = 0;
+                }
+            }
         }
     }
     return best;
 }
 
-// Per-wave sums of the set statistics (valid sets, rank deficient,
-// candidates) into p.stats.
+// Statistics of the sets (valid, rank deficient, candidates) summed over
+// the block, then added into slot (block index mod kStatSlots) of each
+// counter, so that same-address atomics stay few; the host adds the slots.
+constexpr int kStatSlots = 64;
+
 __device__ __forceinline__ void add_stats(const ExactParams& p, bool active, bool valid, bool ok,
                                           unsigned long long ncand) {
+    __shared__ unsigned long long sred[3][kBlock / kWave];
     unsigned long long a0 = (active && valid) ? 1ull : 0ull;
     unsigned long long a1 = (active && valid && !ok) ? 1ull : 0ull;
 #pragma unroll
@@ -438,11 +452,19 @@ __device__ __forceinline__ void add_stats(const ExactParams& p, bool active, boo
         a1 += __shfl_xor(a1, off, kWave);
         ncand += __shfl_xor(ncand, off, kWave);
     }
+    const int w = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        if (a0) atomicAdd(&p.stats[0], a0);
-        if (a1) atomicAdd(&p.stats[1], a1);
-        if (ncand) atomicAdd(&p.stats[2], ncand);
+        sred[0][w] = a0;
+        sred[1][w] = a1;
+        sred[2][w] = ncand;
     }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long v = 0;
+        for (int q = 0; q < kBlock / kWave; ++q) v += sred[threadIdx.x][q];
+        if (v) atomicAdd(&p.stats[threadIdx.x * kStatSlots + blockIdx.x % kStatSlots], v);
+    }
+    __syncthreads();
 }
 
 // Fused form (one pass per set, all rows): vertex, both signs scored over
@@ -675,12 +697,12 @@ __device__ void rescore_one(ExactParams p, uint64_t rank, RescoreEntry* out) {
             double sr[2 * R];
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) sr[j] = base[j];
-            int64_t rest = combo;
+            uint32_t rest = (uint32_t)combo;     // total <= 2^20 (checked on the host)
 #pragma unroll
             for (int t = 0; t < M; ++t) {
                 if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
-                const int q = (int)(rest % cn[t]);
-                rest /= cn[t];
+                const int q = (int)(rest % (uint32_t)cn[t]);
+                rest /= (uint32_t)cn[t];
                 int k = o[t] + q;
                 k = k >= p.K ? k - p.K : k;
                 const double2 z = p.roots64[k];
@@ -954,7 +976,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     const size_t binom_entries = random ? 1 : (size_t)(Mmax + 1) * (size_t)(N + 1);
     CarveSize cs;
     cs.add<ExactDevResult>(1);
-    cs.add<unsigned long long>(4);
+    cs.add<unsigned long long>(3 * kStatSlots);
     cs.add<float>((size_t)n * r * 2);
     cs.add<unsigned long long>(binom_entries);
     cs.add<double2>(LRQO_MAX_K);
@@ -984,7 +1006,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     hipStream_t st = current_stream();
     Carve cv(ctx->arena);
     ExactDevResult* dres = cv.take<ExactDevResult>(1);
-    unsigned long long* stats = cv.take<unsigned long long>(4);
+    unsigned long long* stats = cv.take<unsigned long long>(3 * kStatSlots);
     float* V32 = cv.take<float>((size_t)n * r * 2);
     unsigned long long* binom = cv.take<unsigned long long>(binom_entries);
     double2* rho = cv.take<double2>(LRQO_MAX_K);
@@ -1038,7 +1060,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     LRQO_HIP(hipMemcpyAsync(roots64, hr64, sizeof(double2) * K, hipMemcpyHostToDevice, st));
     LRQO_HIP(hipMemcpyAsync(roots32, hr32, sizeof(float2) * K, hipMemcpyHostToDevice, st));
     LRQO_HIP(hipMemsetAsync(dres, 0, sizeof(ExactDevResult), st));
-    LRQO_HIP(hipMemsetAsync(stats, 0, 4 * sizeof(unsigned long long), st));
+    LRQO_HIP(hipMemsetAsync(stats, 0, 3 * kStatSlots * sizeof(unsigned long long), st));
 
     ExactParams p{};
     p.V64 = V;
@@ -1083,7 +1105,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     }
     if (s != LRQO_OK) return s;
     LRQO_HIP(hipMemcpyAsync(hres, dres, sizeof(ExactDevResult), hipMemcpyDeviceToHost, st));
-    LRQO_HIP(hipMemcpyAsync(hstats, stats, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipMemcpyAsync(hstats, stats, 3 * kStatSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
     LRQO_HIP(hipStreamSynchronize(st));
     float ms = 0.0f;
@@ -1095,9 +1117,12 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     if (res) {
         std::memset(res, 0, sizeof *res);
         res->obj = hres->obj;
-        res->index_sets = (int64_t)hstats[0];
-        res->rank_deficient = (int64_t)hstats[1];
-        res->candidates = (int64_t)hstats[2];
+        int64_t sum3[3] = {0, 0, 0};
+        for (int c = 0; c < 3; ++c)
+            for (int q = 0; q < kStatSlots; ++q) sum3[c] += (int64_t)hstats[c * kStatSlots + q];
+        res->index_sets = sum3[0];
+        res->rank_deficient = sum3[1];
+        res->candidates = sum3[2];
         res->device_ms = ms;
     }
     return LRQO_OK;
