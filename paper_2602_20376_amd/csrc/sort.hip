@@ -1,11 +1,12 @@
 // Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits.
 //
 // Per pass (one 8-bit digit):
-//   k_digit_hist     per tile of 2048 pairs: digit counts -> hist[digit][tile],
-//                    and the digit totals
-//   k_scan_rows      one block per digit: the first output slot of (digit,
-//                    tile) = totals of the lower digits + prefix along the row
-//   k_digit_scatter  per tile: four waves take consecutive quarters; each
+//   k_digit_hist     per tile of 2048 pairs: digit counts -> hist[digit][tile]
+//   k_scan_rows      one block per digit: exclusive prefix along the row, and
+//                    the row's total
+//   k_digit_scatter  per tile: the digits' first output slots (exclusive
+//                    scan of the row totals, done by every block, plus the
+//                    row prefix); four waves take consecutive quarters; each
 //                    wave counts its digits, the waves' counts are offset
 //                    in wave order, then every wave walks its quarter in
 //                    64-pair steps: lanes holding the same digit are found
@@ -37,7 +38,7 @@ __device__ __forceinline__ int digit_of(unsigned long long key, int shift) {
 
 __global__ __launch_bounds__(kBlock) void k_digit_hist(const unsigned long long* __restrict__ keys,
                                                        int64_t n, int shift, uint32_t* __restrict__ hist,
-                                                       int64_t tiles, uint32_t* __restrict__ totals) {
+                                                       int64_t tiles) {
     __shared__ uint32_t h[kBins];
     h[threadIdx.x] = 0;
     __syncthreads();
@@ -48,26 +49,16 @@ __global__ __launch_bounds__(kBlock) void k_digit_hist(const unsigned long long*
     }
     __syncthreads();
     hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
-    if (h[threadIdx.x]) atomicAdd(&totals[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_zero_u32(uint32_t* __restrict__ a, int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) a[i] = 0u;
-}
-
-// Block d turns row d of hist (one count per tile) into first output slots:
-// (sum of the totals of the digits below d) + exclusive prefix along the row.
+// Block d turns row d of hist (one count per tile) into its exclusive prefix
+// along the row and writes the row's total to rowtot[d].
 __global__ __launch_bounds__(kScanBlock) void k_scan_rows(uint32_t* __restrict__ hist, int64_t tiles,
-                                                         const uint32_t* __restrict__ totals) {
+                                                         uint32_t* __restrict__ rowtot) {
     __shared__ uint32_t buf[kScanBlock];
     __shared__ uint32_t carry;
     const int d = blockIdx.x;
-    if (threadIdx.x == 0) {
-        uint32_t b = 0;
-        for (int e = 0; e < d; ++e) b += totals[e];
-        carry = b;
-    }
+    if (threadIdx.x == 0) carry = 0u;
     uint32_t* row = hist + (int64_t)d * tiles;
     for (int64_t c0 = 0; c0 < tiles; c0 += kScanBlock) {
         const int64_t t = c0 + threadIdx.x;
@@ -87,6 +78,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_rows(uint32_t* __restrict__
         if (threadIdx.x == kScanBlock - 1) carry = base + buf[kScanBlock - 1];
         __syncthreads();
     }
+    if (threadIdx.x == 0) rowtot[d] = carry;
 }
 
 __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long long* __restrict__ keys_in,
@@ -94,12 +86,24 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
                                                           unsigned long long* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, int64_t n,
                                                           int shift, const uint32_t* __restrict__ offs,
-                                                          int64_t tiles) {
+                                                          int64_t tiles, const uint32_t* __restrict__ rowtot) {
     __shared__ uint32_t cnt[kWaves][kBins];
     __shared__ uint32_t base[kWaves][kBins];
+    __shared__ uint32_t wsum[kWaves];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     for (int v = 0; v < kWaves; ++v) cnt[v][threadIdx.x] = 0;
+    // first slot of digit threadIdx.x: exclusive scan of the row totals
+    // (inclusive over the wave by shuffles, then the lower waves' sums)
+    const uint32_t tot = rowtot[threadIdx.x];
+    uint32_t incl = tot;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
     __syncthreads();
+    uint32_t dbase = incl - tot;
+    for (int v = 0; v < w; ++v) dbase += wsum[v];
     const int64_t chunk = blockIdx.x * (int64_t)kTile + (int64_t)w * (kSteps * kWave);
     for (int t = 0; t < kSteps; ++t) {
         const int64_t idx = chunk + t * kWave + lane;
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
     }
     __syncthreads();
     {
-        uint32_t run = offs[(int64_t)threadIdx.x * tiles + blockIdx.x];
+        uint32_t run = dbase + offs[(int64_t)threadIdx.x * tiles + blockIdx.x];
         for (int v = 0; v < kWaves; ++v) {
             base[v][threadIdx.x] = run;
             run += cnt[v][threadIdx.x];
@@ -154,16 +158,14 @@ lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned 
     unsigned long long* kout = keys_tmp;
     uint32_t* vout = vals_tmp;
     bool tmp = false;
-    uint32_t* totals = hist + (size_t)kBins * tiles;
+    uint32_t* rowtot = hist + (size_t)kBins * tiles;
     for (int d = 0; d < 8; ++d) {
         if (!((digit_mask >> d) & 1u)) continue;
         const int shift = 8 * d;
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kBins), 0, st, totals, kBins);
-        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist, tiles,
-                           totals);
-        hipLaunchKernelGGL(k_scan_rows, dim3(kBins), dim3(kScanBlock), 0, st, hist, tiles, totals);
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_scan_rows, dim3(kBins), dim3(kScanBlock), 0, st, hist, tiles, rowtot);
         hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
-                           shift, hist, tiles);
+                           shift, hist, tiles, rowtot);
         LRQO_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);
