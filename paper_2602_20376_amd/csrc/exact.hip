@@ -20,8 +20,10 @@
 //   k_exact_combine with several row slices: the slice sums in order, then
 //                   the label combinations
 //   topk_select     best 64 sets (select.hip)
-//   k_exact_rescore FP64 re-evaluation of each kept set (both signs, all
-//                   label combinations), rows split over the block
+//   k_exact_rescore_rows  FP64 row sums of each kept set (both signs),
+//                   grid (kept sets, row slices)
+//   k_exact_rescore FP64 re-evaluation of each kept set from the slice sums
+//                   (in slice order), all label combinations over the block
 //   k_exact_pick    FP64 arg-max (ties -> lowest set index)
 //   k_exact_labels  labels of the winner
 #include <algorithm>
@@ -42,6 +44,7 @@ constexpr int kBlock = 256;
 constexpr int kTile = 256;
 constexpr int kMaxR = 4;
 constexpr int kTopT = 64;
+constexpr int kRescoreSlices = 64;   // row slices of the FP64 rescore, at most
 constexpr double kRankTol = 1e-10;
 constexpr int64_t kMaxCombos = 1 << 20;
 
@@ -383,8 +386,14 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
 template <int R, int D>
 __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1], const int (&mm)[2 * D - 1],
                              const double (&v)[2 * D], const float (&acc)[2][2 * R],
-                             unsigned long long& ncand) {
+                             const float2* roots_s, unsigned long long& ncand) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
+    // the set's rows in registers once (every combination reads them)
+    float vt[M][2 * R];
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) vt[t][j] = g[t] >= 0 ? p.V32[g[t] * 2 * R + j] : 0.0f;
     float best = 0.0f;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -411,10 +420,10 @@ __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1]
                 if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
                 int k = o[t] + dig[t];
                 k = k >= p.K ? k - p.K : k;
-                const float2 z = p.roots32[k];
+                const float2 z = roots_s[k];
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    const float vr = p.V32[(g[t] * R + j) * 2], vi = p.V32[(g[t] * R + j) * 2 + 1];
+                    const float vr = vt[t][2 * j], vi = vt[t][2 * j + 1];
                     sr[2 * j] = fmaf(vr, z.x, fmaf(vi, z.y, sr[2 * j]));
                     sr[2 * j + 1] = fmaf(vr, z.y, fmaf(-vi, z.x, sr[2 * j + 1]));
                 }
@@ -476,10 +485,12 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
     __shared__ __align__(16) float tile[kTile * 2 * R];
     __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
+    __shared__ float2 roots_all[LRQO_MAX_K];      // the label combinations' roots
     const int tid = threadIdx.x;
     if constexpr (KS == 0) {
         for (int k = tid; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
     }
+    for (int k = tid; k < p.K; k += kBlock) roots_all[k] = p.roots32[k];   // read after the tile barriers
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
         const uint64_t rank = base + tid;
@@ -505,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
         float acc[2][2 * R];
         score_rows<R, D, KS>(p, c, g32, 0, p.n, tile, roots_s, acc);
         unsigned long long ncand = 0;
-        const float best = ok ? combos_best<R, D>(p, g, mm, v, acc, ncand) : 0.0f;
+        const float best = ok ? combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand) : 0.0f;
         if (active) p.fbuf[p.offset + rank] = best;
         add_stats(p, active, valid, ok, ncand);
     }
@@ -588,6 +599,9 @@ __global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const Vert
 template <int R, int D>
 __global__ __launch_bounds__(kBlock) void k_exact_combine(ExactParams p, int slices) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
+    __shared__ float2 roots_all[LRQO_MAX_K];
+    for (int k = threadIdx.x; k < p.K; k += kBlock) roots_all[k] = p.roots32[k];
+    __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
         const uint64_t rank = base + threadIdx.x;
@@ -609,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_combine(ExactParams p, int sli
                     for (int q = 0; q < slices; ++q) a += p.part[(((uint64_t)q * 2 + s) * (2 * R) + j) * p.count + rank];
                     acc[s][j] = a;
                 }
-            best = combos_best<R, D>(p, g, mm, v, acc, ncand);
+            best = combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand);
         }
         if (active) p.fbuf[p.offset + rank] = best;
         add_stats(p, active, valid, ok, ncand);
@@ -629,21 +643,21 @@ __device__ __forceinline__ int level_of(const LevelTable& lt, int r, uint64_t gi
     return 0;
 }
 
+// Row pass of the FP64 rescore, split over row slices: for both signs of
+// the set's vertex, the sum over rows [r0, r1) that the set does not touch
+// of conj(V_i) omega^{label(V_i c)} -> out[s * 2R + j] (zeros without a
+// full-rank vertex).
 template <int R, int D>
-__device__ void rescore_one(ExactParams p, uint64_t rank, RescoreEntry* out) {
+__device__ void rescore_rows_one(const ExactParams& p, uint64_t rank, int64_t r0, int64_t r1, double* out) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
     __shared__ double red[kBlock / kWave][2 * R];
-    __shared__ double base[2 * R];
-    __shared__ double bf[kBlock];
-    __shared__ long long bc[kBlock];
     int64_t g[M];
     int mm[M];
     double v[C2];
     bool valid;
     const bool ok = vertex<D>(p, rank, g, mm, v, valid);
-    RescoreEntry best{-1.0, 0, 0, 0};
     if (!ok) {
-        if (threadIdx.x == 0) *out = best;
+        if (threadIdx.x < 4 * R) out[threadIdx.x] = 0.0;
         return;
     }
     for (int s = 0; s < 2; ++s) {
@@ -653,7 +667,7 @@ __device__ void rescore_one(ExactParams p, uint64_t rank, RescoreEntry* out) {
         double acc[2 * R];
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) acc[j] = 0.0;
-        for (int64_t i = threadIdx.x; i < p.n; i += kBlock) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
             bool touched = false;
 #pragma unroll
             for (int t = 0; t < M; ++t) touched |= (i == g[t]);
@@ -683,6 +697,36 @@ __device__ void rescore_one(ExactParams p, uint64_t rank, RescoreEntry* out) {
         if (threadIdx.x < 2 * R) {
             double x = 0.0;
             for (int w = 0; w < kBlock / kWave; ++w) x += red[w][threadIdx.x];
+            out[s * 2 * R + threadIdx.x] = x;
+        }
+        __syncthreads();
+    }
+}
+
+template <int R, int D>
+__device__ void rescore_one(ExactParams p, uint64_t rank, const double* part, int slices, RescoreEntry* out) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    __shared__ double base[2 * R];
+    __shared__ double bf[kBlock];
+    __shared__ long long bc[kBlock];
+    int64_t g[M];
+    int mm[M];
+    double v[C2];
+    bool valid;
+    const bool ok = vertex<D>(p, rank, g, mm, v, valid);
+    RescoreEntry best{-1.0, 0, 0, 0};
+    if (!ok) {
+        if (threadIdx.x == 0) *out = best;
+        return;
+    }
+    for (int s = 0; s < 2; ++s) {
+        double cs[C2];
+#pragma unroll
+        for (int k = 0; k < C2; ++k) cs[k] = s ? -v[k] : v[k];
+        // rows the set does not touch: the slice sums in slice order
+        if (threadIdx.x < 2 * R) {
+            double x = 0.0;
+            for (int q = 0; q < slices; ++q) x += part[((size_t)q * 2 + s) * (2 * R) + threadIdx.x];
             base[threadIdx.x] = x;
         }
         __syncthreads();
@@ -739,18 +783,40 @@ __device__ void rescore_one(ExactParams p, uint64_t rank, RescoreEntry* out) {
     if (threadIdx.x == 0) *out = best;
 }
 
+// Grid (kept sets, row slices): part[(t * slices + q) * 2 * 2R ..] holds
+// both signs' sums over slice q of the rows.
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_exact_rescore(ExactParams p, LevelTable lt,
-                                                          const unsigned long long* keys,
-                                                          RescoreEntry* out) {
-    const int t = blockIdx.x;
+__global__ __launch_bounds__(kBlock) void k_exact_rescore_rows(ExactParams p, LevelTable lt,
+                                                               const unsigned long long* keys, int64_t rows,
+                                                               double* part) {
+    const int t = blockIdx.x, q = blockIdx.y;
+    const int64_t r0 = min(p.n, (int64_t)q * rows), r1 = min(p.n, r0 + rows);
+    double* out = part + ((size_t)t * gridDim.y + q) * 2 * (2 * R);
     uint64_t rank;
     const int d = level_of(lt, R, key_index(keys[t]), rank);
     switch (d) {
-        case 1: rescore_one<R, 1>(p, rank, out + t); break;
-        case 2: if constexpr (R >= 2) rescore_one<R, 2>(p, rank, out + t); break;
-        case 3: if constexpr (R >= 3) rescore_one<R, 3>(p, rank, out + t); break;
-        case 4: if constexpr (R >= 4) rescore_one<R, 4>(p, rank, out + t); break;
+        case 1: rescore_rows_one<R, 1>(p, rank, r0, r1, out); break;
+        case 2: if constexpr (R >= 2) rescore_rows_one<R, 2>(p, rank, r0, r1, out); break;
+        case 3: if constexpr (R >= 3) rescore_rows_one<R, 3>(p, rank, r0, r1, out); break;
+        case 4: if constexpr (R >= 4) rescore_rows_one<R, 4>(p, rank, r0, r1, out); break;
+        default:
+            if (threadIdx.x < 4 * R) out[threadIdx.x] = 0.0;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_exact_rescore(ExactParams p, LevelTable lt,
+                                                          const unsigned long long* keys, const double* part,
+                                                          int slices, RescoreEntry* out) {
+    const int t = blockIdx.x;
+    const double* pt = part + (size_t)t * slices * 2 * (2 * R);
+    uint64_t rank;
+    const int d = level_of(lt, R, key_index(keys[t]), rank);
+    switch (d) {
+        case 1: rescore_one<R, 1>(p, rank, pt, slices, out + t); break;
+        case 2: if constexpr (R >= 2) rescore_one<R, 2>(p, rank, pt, slices, out + t); break;
+        case 3: if constexpr (R >= 3) rescore_one<R, 3>(p, rank, pt, slices, out + t); break;
+        case 4: if constexpr (R >= 4) rescore_one<R, 4>(p, rank, pt, slices, out + t); break;
         default:
             if (threadIdx.x == 0) out[t] = RescoreEntry{-1.0, 0, 0, 0};
     }
@@ -898,7 +964,7 @@ void launch_level(ExactParams p, hipStream_t st) {
 
 template <int R>
 lrqo_status run_exact(ExactParams p, const LevelTable& lt, const unsigned long long** keys_out,
-                      unsigned long long* ka, unsigned long long* kb, RescoreEntry* entries,
+                      unsigned long long* ka, unsigned long long* kb, RescoreEntry* entries, double* rpart,
                       ExactDevResult* dres, uint8_t* z, uint32_t total, int T, hipStream_t st) {
     for (int d = R; d >= 1; --d) {
         if (lt.count[d] == 0) continue;
@@ -915,7 +981,11 @@ lrqo_status run_exact(ExactParams p, const LevelTable& lt, const unsigned long l
     }
     const unsigned long long* keys = nullptr;
     LRQO_TRY(topk_select(p.fbuf, total, T, ka, kb, st, &keys));
-    hipLaunchKernelGGL((k_exact_rescore<R>), dim3(T), dim3(kBlock), 0, st, p, lt, keys, entries);
+    const int64_t rrows = std::max<int64_t>(4096, (p.n + kRescoreSlices - 1) / kRescoreSlices);
+    const int rslices = (int)((p.n + rrows - 1) / rrows);
+    hipLaunchKernelGGL((k_exact_rescore_rows<R>), dim3(T, rslices), dim3(kBlock), 0, st, p, lt, keys, rrows,
+                       rpart);
+    hipLaunchKernelGGL((k_exact_rescore<R>), dim3(T), dim3(kBlock), 0, st, p, lt, keys, rpart, rslices, entries);
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_exact_pick, dim3(1), dim3(64), 0, st, entries, keys, T, lt, R, dres);
     LRQO_HIP(hipGetLastError());
@@ -986,6 +1056,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     cs.add<unsigned long long>(topk_buffer_keys(total, T));
     cs.add<unsigned long long>(topk_buffer_keys(total, T));
     cs.add<RescoreEntry>(T);
+    cs.add<double>((size_t)T * kRescoreSlices * 2 * (2 * r));
     uint64_t rec_count = 0, part_floats = 0;     // the largest split level's needs
     for (int d = r; d >= 1; --d) {
         if (lt.count[d] == 0) continue;
@@ -1016,6 +1087,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     unsigned long long* ka = cv.take<unsigned long long>(topk_buffer_keys(total, T));
     unsigned long long* kb = cv.take<unsigned long long>(topk_buffer_keys(total, T));
     RescoreEntry* entries = cv.take<RescoreEntry>(T);
+    double* rpart = cv.take<double>((size_t)T * kRescoreSlices * 2 * (2 * r));
     VertexRec* recs = cv.take<VertexRec>(rec_count);
     float* part = cv.take<float>(part_floats);
 
@@ -1088,19 +1160,19 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     switch (r) {
         case 1:
             hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
-            s = run_exact<1>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            s = run_exact<1>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
         case 2:
             hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
-            s = run_exact<2>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            s = run_exact<2>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
         case 3:
             hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
-            s = run_exact<3>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            s = run_exact<3>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
         case 4:
             hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
-            s = run_exact<4>(p, lt, &keys, ka, kb, entries, dres, z, total, T, st);
+            s = run_exact<4>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
     }
     if (s != LRQO_OK) return s;
