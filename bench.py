@@ -475,6 +475,10 @@ def form_learned(train_count):
             "samples_to_99.9pct_uniform": ku, "samples_to_99.9pct_learned": kl,
             "sample_ratio_uniform_over_learned": (ku / kl) if (ku and kl) else None,
             "learned_inference_ms": t_infer, "uniform_candidate_rows_per_s": row_rate,
+            # time to 99.9% of the best: the knee's samples at the measured
+            # scoring rate on this factor, plus inference for the learned side
+            "time_to_99.9pct_uniform_ms": (ku * inst.n / row_rate * 1000.0) if ku else None,
+            "time_to_99.9pct_learned_ms": (t_infer + kl * inst.n / row_rate * 1000.0) if kl else None,
             "oracle": {"kind": "oracle", "inference_ms": oms,
                        "sample": "gauge frame, features and network forward on the same factor (FP64)"},
             "train_instances": train_count, "train_final_loss": hist[-1], "train_first_loss": hist[0],
@@ -569,6 +573,8 @@ def main():
             "metric": "samples to 99.9% of best obj, learned vs uniform",
             "uniform": lp.get("samples_to_99.9pct_uniform"),
             "learned": lp.get("samples_to_99.9pct_learned"),
+            "time_ms_uniform": lp.get("time_to_99.9pct_uniform_ms"),
+            "time_ms_learned_with_inference": lp.get("time_to_99.9pct_learned_ms"),
             "workload": "phase_sync n=262144 r=3 K=16"}
     print(json.dumps(rec), flush=True)
 
