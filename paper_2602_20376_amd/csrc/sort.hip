@@ -2,7 +2,7 @@
 //
 // Per pass (one 8-bit digit):
 //   k_digit_hist     per tile of 2048 pairs: digit counts -> hist[digit][tile]
-//   k_scan_rows      one block per digit: exclusive prefix along the row, and
+//   k_scan_rows      one wave per digit: exclusive prefix along the row, and
 //                    the row's total
 //   k_digit_scatter  per tile: the digits' first output slots (exclusive
 //                    scan of the row totals, done by every block, plus the
@@ -14,6 +14,9 @@
 //                    offset plus the number of such lanes below it, and the
 //                    lowest of them advances the offset.  Slots therefore
 //                    follow input order within a digit: the pass is stable.
+//                    The pairs are first placed in a digit-ordered LDS copy
+//                    of the tile and written out from it, so that each
+//                    digit's run is written to consecutive addresses.
 #include <algorithm>
 
 #include "lrqo_device.h"
@@ -29,7 +32,6 @@ constexpr int kBlock = kWaves * kWave;   // 256
 constexpr int kSteps = 8;                // 64-pair steps per wave
 constexpr int kTile = kWaves * kSteps * kWave;  // 2048 pairs per block
 constexpr int kBins = 256;
-constexpr int kScanBlock = 1024;
 static_assert(kBlock == kBins, "one thread per digit bin");
 
 __device__ __forceinline__ int digit_of(unsigned long long key, int shift) {
@@ -51,34 +53,60 @@ __global__ __launch_bounds__(kBlock) void k_digit_hist(const unsigned long long*
     hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Block d turns row d of hist (one count per tile) into its exclusive prefix
-// along the row and writes the row's total to rowtot[d].
-__global__ __launch_bounds__(kScanBlock) void k_scan_rows(uint32_t* __restrict__ hist, int64_t tiles,
-                                                         uint32_t* __restrict__ rowtot) {
-    __shared__ uint32_t buf[kScanBlock];
-    __shared__ uint32_t carry;
-    const int d = blockIdx.x;
-    if (threadIdx.x == 0) carry = 0u;
+// Wave d turns row d of hist (one count per tile) into its exclusive prefix
+// along the row and writes the row's total to rowtot[d]: chunks of 64 x 8
+// entries, lane l holding 8 consecutive ones; prefix = carry + the wave's
+// exclusive scan of the lanes' sums (shuffles) + the lane's running sum.
+constexpr int kScanWaves = 4;
+
+__global__ __launch_bounds__(kScanWaves * kWave) void k_scan_rows(uint32_t* __restrict__ hist, int64_t tiles,
+                                                                  uint32_t* __restrict__ rowtot) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int d = blockIdx.x * kScanWaves + threadIdx.x / kWave;
     uint32_t* row = hist + (int64_t)d * tiles;
-    for (int64_t c0 = 0; c0 < tiles; c0 += kScanBlock) {
-        const int64_t t = c0 + threadIdx.x;
-        const uint32_t v = t < tiles ? row[t] : 0u;
-        buf[threadIdx.x] = v;
-        __syncthreads();
-        // inclusive scan in LDS (Hillis-Steele)
-        for (int off = 1; off < kScanBlock; off <<= 1) {
-            const uint32_t add = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
-            __syncthreads();
-            buf[threadIdx.x] += add;
-            __syncthreads();
+    uint32_t carry = 0u;
+    for (int64_t c0 = 0; c0 < tiles; c0 += 8 * kWave) {
+        uint32_t v[8], sum = 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t idx = c0 + lane * 8 + u;
+            v[u] = idx < tiles ? row[idx] : 0u;
+            sum += v[u];
         }
-        const uint32_t base = carry;
-        if (t < tiles) row[t] = base + buf[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == kScanBlock - 1) carry = base + buf[kScanBlock - 1];
-        __syncthreads();
+        uint32_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += y;
+        }
+        uint32_t run = carry + incl - sum;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t idx = c0 + lane * 8 + u;
+            if (idx < tiles) row[idx] = run;
+            run += v[u];
+        }
+        carry += __shfl(incl, kWave - 1, kWave);
     }
-    if (threadIdx.x == 0) rowtot[d] = carry;
+    if (lane == 0) rowtot[d] = carry;
+}
+
+// Exclusive prefix over the block of one value per thread (256 threads):
+// inclusive scan across each wave by shuffles, then the lower waves' sums.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* wsum) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += y;
+    }
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    uint32_t ex = incl - x;
+    for (int v = 0; v < w; ++v) ex += wsum[v];
+    __syncthreads();
+    return ex;
 }
 
 __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long long* __restrict__ keys_in,
@@ -90,34 +118,38 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
     __shared__ uint32_t cnt[kWaves][kBins];
     __shared__ uint32_t base[kWaves][kBins];
     __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t lstart[kBins], gbase[kBins];
+    __shared__ unsigned long long lkeys[kTile];
+    __shared__ uint32_t lvals[kTile];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     for (int v = 0; v < kWaves; ++v) cnt[v][threadIdx.x] = 0;
     // first slot of digit threadIdx.x: exclusive scan of the row totals
-    // (inclusive over the wave by shuffles, then the lower waves' sums)
-    const uint32_t tot = rowtot[threadIdx.x];
-    uint32_t incl = tot;
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += y;
-    }
-    if (lane == kWave - 1) wsum[w] = incl;
-    __syncthreads();
-    uint32_t dbase = incl - tot;
-    for (int v = 0; v < w; ++v) dbase += wsum[v];
-    const int64_t chunk = blockIdx.x * (int64_t)kTile + (int64_t)w * (kSteps * kWave);
+    const uint32_t dbase = block_excl_scan(rowtot[threadIdx.x], wsum);
+    const int64_t tile0 = blockIdx.x * (int64_t)kTile;
+    const int64_t chunk = tile0 + (int64_t)w * (kSteps * kWave);
     for (int t = 0; t < kSteps; ++t) {
         const int64_t idx = chunk + t * kWave + lane;
         if (idx < n) atomicAdd(&cnt[w][digit_of(keys_in[idx], shift)], 1u);
     }
     __syncthreads();
+    uint32_t tile_count = 0;
     {
-        uint32_t run = dbase + offs[(int64_t)threadIdx.x * tiles + blockIdx.x];
+        const uint32_t g0 = dbase + offs[(int64_t)threadIdx.x * tiles + blockIdx.x];
+        gbase[threadIdx.x] = g0;
+        uint32_t run = g0;
         for (int v = 0; v < kWaves; ++v) {
             base[v][threadIdx.x] = run;
             run += cnt[v][threadIdx.x];
         }
+        tile_count = run - g0;
     }
+    // where each digit's pairs start in the tile's digit-ordered LDS copy
+    lstart[threadIdx.x] = block_excl_scan(tile_count, wsum);
     __syncthreads();
+    // rank every pair (its global slot), and place it at the same offset in
+    // the LDS copy: lanes holding the same digit are found with eight
+    // ballots, a lane's slot is the digit's running offset plus the number of
+    // such lanes below it, and the lowest of them advances the offset
     const unsigned long long below = (1ull << lane) - 1ull;
     for (int t = 0; t < kSteps; ++t) {
         const int64_t idx = chunk + t * kWave + lane;
@@ -135,11 +167,22 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
         const uint32_t lower = (uint32_t)__popcll(match & below);
         const uint32_t slot = base[w][d] + lower;   // every lane reads before the update below
         if (valid) {
-            keys_out[slot] = key;
-            vals_out[slot] = val;
+            const uint32_t local = lstart[d] + (slot - gbase[d]);
+            lkeys[local] = key;
+            lvals[local] = val;
         }
         if (valid && lower == 0) base[w][d] += (uint32_t)__popcll(match);
         __builtin_amdgcn_wave_barrier();  // the next step's reads stay after this update
+    }
+    __syncthreads();
+    // write out in the LDS order: runs of one digit go to consecutive slots
+    const int count = (int)min((int64_t)kTile, n - tile0);
+    for (int j = threadIdx.x; j < count; j += kBlock) {
+        const unsigned long long key = lkeys[j];
+        const int d = digit_of(key, shift);
+        const uint32_t g = gbase[d] + ((uint32_t)j - lstart[d]);
+        keys_out[g] = key;
+        vals_out[g] = lvals[j];
     }
 }
 
@@ -163,7 +206,8 @@ lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned 
         if (!((digit_mask >> d) & 1u)) continue;
         const int shift = 8 * d;
         hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist, tiles);
-        hipLaunchKernelGGL(k_scan_rows, dim3(kBins), dim3(kScanBlock), 0, st, hist, tiles, rowtot);
+        hipLaunchKernelGGL(k_scan_rows, dim3(kBins / kScanWaves), dim3(kScanWaves * kWave), 0, st, hist, tiles,
+                           rowtot);
         hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
                            shift, hist, tiles, rowtot);
         LRQO_HIP(hipGetLastError());
