@@ -314,11 +314,15 @@ def form_rank1_hybrid():
     m = 1 << 16
     oms, _ = _timed(lambda: R1.rank1_sweep(q[:m], inst.K))
     dev = min(r[1] for r in runs)
-    # prep 16 B read + 29 B written per coordinate; a radix pass reads the
-    # 12 B pairs twice and writes them once; tiles and cells gather 20 B twice
-    sweep_bytes = (45 + 36 * res.sort_passes + 40) * float(inst.n)
+    # per coordinate: prep reads q (16 B) and writes key, label and d (25 B);
+    # a radix pass reads the 12 B pairs twice and writes them once (the first
+    # reads no values: 4 B less); the tile pass reads the order (4 B), gathers
+    # d (16 B) and writes it in sorted order (16 B); the cell pass reads that
+    # (16 B); the label pass reads key, label and q (25 B) and writes z (1 B)
+    sweep_bytes = (41 + 36 * res.sort_passes - 4 + 36 + 16 + 26) * float(inst.n)
     return {"workload": "maxcut_ppm", "n": inst.n, "K": inst.K, "edges": int(len(i)),
-            "roofline": _hbm_roofline(sweep_bytes, dev, "whole sweep: prep, radix passes, tile and cell scans"),
+            "roofline": _hbm_roofline(sweep_bytes, dev, "whole sweep: prep, radix passes, tile, cell and "
+                                      "label passes"),
             "oracle": {"kind": "oracle", "ms": oms, "ms_scaled_to_n": oms * inst.n / m,
                        "sample": f"Alg. 1 on the first {m} coordinates of the same q (FP64, Python loop)"},
             "rank1_ms": min(r[0] for r in runs), "rank1_device_ms": min(r[1] for r in runs),

@@ -14,15 +14,21 @@
 //                 sortable key, k_0, d, block partials of s_0 and of the
 //                 OR / AND of the keys (digits that never change skip a
 //                 pass), finiteness
+//   k_r1_reduce0  s_0 and the OR / AND from the block partials
 //   radix sort    stable by key (sort.hip): ties keep coordinate order
-//   k_r1_tiles    per tile of 2048 sorted positions: sum of d
+//   k_r1_tiles    per tile of 2048 sorted positions: gathers d into sorted
+//                 order (coalesced write) and sums the tile
 //   k_r1_tilepre  s_0 plus the tile sums before each tile (fixed order)
 //   k_r1_cells    per tile: running s through its positions, |s|^2 per cell,
 //                 best cell of the tile (ties to the earlier cell)
-//   k_r1_pick     best cell over the tiles and cell 0
-//   k_r1_labels   labels of the best cell: k_0 advanced by one for the
-//                 coordinates whose boundary comes at or before it
-//   k_r1_obj      FP64 |z^H q|^2 of the returned labels (block partials)
+//   k_r1_pick     best cell over the tiles and cell 0, and the (key,
+//                 coordinate) pair of its last boundary point
+//   k_r1_labels   labels of the best cell, in coordinate order: k_0 advanced
+//                 by one where (key, coordinate) is at or below that pair,
+//                 which is where the stable sort put the coordinate at or
+//                 before the cell; block partials of z^H q
+// All sums run in a fixed order (shuffle trees and block scans of fixed
+// shape), so a run is reproducible.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -54,20 +60,45 @@ __device__ __forceinline__ double2 cconj_mul(double2 q, double2 w) {
     return make_double2(q.x * w.x + q.y * w.y, q.x * w.y - q.y * w.x);
 }
 
-// Fixed-order block sum of a complex value per thread.
+__device__ __forceinline__ double2 shfl_xor_c(double2 v, int m) {
+    return make_double2(__shfl_xor(v.x, m, kWave), __shfl_xor(v.y, m, kWave));
+}
+
+__device__ __forceinline__ double2 shfl_up_c(double2 v, int off) {
+    return make_double2(__shfl_up(v.x, off, kWave), __shfl_up(v.y, off, kWave));
+}
+
+// Fixed-order block sum of a complex value per thread: a shuffle tree in
+// each wave, then the waves' sums in wave order.  Every thread gets it.
 __device__ __forceinline__ double2 block_sum_c(double2 v) {
-    __shared__ double sx[kBlock], sy[kBlock];
-    sx[threadIdx.x] = v.x;
-    sy[threadIdx.x] = v.y;
+    __shared__ double2 ws[kBlock / kWave];
+#pragma unroll
+    for (int m = kWave / 2; m > 0; m >>= 1) v = cadd(v, shfl_xor_c(v, m));
+    if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = v;
     __syncthreads();
-    for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            sx[threadIdx.x] += sx[threadIdx.x + h];
-            sy[threadIdx.x] += sy[threadIdx.x + h];
-        }
-        __syncthreads();
+    double2 r = ws[0];
+    for (int w = 1; w < kBlock / kWave; ++w) r = cadd(r, ws[w]);
+    __syncthreads();
+    return r;
+}
+
+// init + the sum of the values of the threads before this one (fixed
+// order: a shuffle scan in each wave, the lower waves' totals before it).
+__device__ __forceinline__ double2 block_excl_scan_c(double2 v, double2 init) {
+    __shared__ double2 ws[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    double2 incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double2 y = shfl_up_c(incl, off);
+        if (lane >= off) incl = cadd(y, incl);
     }
-    const double2 r = make_double2(sx[0], sy[0]);
+    if (lane == kWave - 1) ws[w] = incl;
+    const double2 below = shfl_up_c(incl, 1);
+    __syncthreads();
+    double2 r = init;
+    for (int u = 0; u < w; ++u) r = cadd(r, ws[u]);
+    if (lane > 0) r = cadd(r, below);
     __syncthreads();
     return r;
 }
@@ -78,7 +109,6 @@ struct R1Dev {
     int K;
     const double2* roots;            // [K]
     unsigned long long* keys;
-    uint32_t* vals;
     uint8_t* k0;
     double2* d;
     double2* part;                   // block partials
@@ -103,23 +133,17 @@ __global__ __launch_bounds__(kBlock) void k_r1_prep(R1Dev p) {
         k += k < 0 ? p.K : 0;
         key = order_key(phi);
         p.keys[i] = key;
-        p.vals[i] = (uint32_t)i;
         p.k0[i] = (uint8_t)k;
         const int k1 = k + 1 == p.K ? 0 : k + 1;
         const double2 a = p.roots[k], b = p.roots[k1];
         p.d[i] = cconj_mul(q, make_double2(b.x - a.x, b.y - a.y));
         c0 = cconj_mul(q, a);
     }
-    const unsigned long long wor = [&] {
-        unsigned long long v = live ? key : 0ull;
-        for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, kWave);
-        return v;
-    }();
-    const unsigned long long wand = [&] {
-        unsigned long long v = live ? key : ~0ull;
-        for (int off = 32; off > 0; off >>= 1) v &= __shfl_xor(v, off, kWave);
-        return v;
-    }();
+    unsigned long long wor = live ? key : 0ull, wand = live ? key : ~0ull;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        wor |= __shfl_xor(wor, off, kWave);
+        wand &= __shfl_xor(wand, off, kWave);
+    }
     __shared__ unsigned long long wo[kBlock / kWave], wa[kBlock / kWave];
     if ((threadIdx.x & (kWave - 1)) == 0) {
         wo[threadIdx.x / kWave] = wor;
@@ -138,28 +162,6 @@ __global__ __launch_bounds__(kBlock) void k_r1_prep(R1Dev p) {
     }
 }
 
-// OR and AND over the block partials (one block).
-__global__ __launch_bounds__(kBlock) void k_r1_orand(const unsigned long long* __restrict__ part, int64_t blocks,
-                                                     unsigned long long* __restrict__ out) {
-    __shared__ unsigned long long so[kBlock], sa[kBlock];
-    unsigned long long o = 0ull, a = ~0ull;
-    for (int64_t t = threadIdx.x; t < blocks; t += kBlock) {
-        o |= part[2 * t];
-        a &= part[2 * t + 1];
-    }
-    so[threadIdx.x] = o;
-    sa[threadIdx.x] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int t = 1; t < kBlock; ++t) {
-            o |= so[t];
-            a &= sa[t];
-        }
-        out[0] = o;
-        out[1] = a;
-    }
-}
-
 // Fixed-order sum of `count` complex partials into out[0] (one block).
 __global__ __launch_bounds__(kBlock) void k_r1_sum(const double2* __restrict__ part, int64_t count,
                                                    double2* __restrict__ out) {
@@ -169,39 +171,81 @@ __global__ __launch_bounds__(kBlock) void k_r1_sum(const double2* __restrict__ p
     if (threadIdx.x == 0) out[0] = s;
 }
 
-// Thread t of tile b owns sorted positions b*kTile + t*kItems .. + kItems-1.
-__global__ __launch_bounds__(kBlock) void k_r1_tiles(const double2* __restrict__ d, const uint32_t* __restrict__ order,
-                                                     int64_t n, double2* __restrict__ tile_sum) {
-    const int64_t p0 = blockIdx.x * (int64_t)kTile + (int64_t)threadIdx.x * kItems;
+// s_0 from the prep's block partials, and the OR / AND of its key partials
+// (one block).
+__global__ __launch_bounds__(kBlock) void k_r1_reduce0(const double2* __restrict__ part,
+                                                       const unsigned long long* __restrict__ orand_part,
+                                                       int64_t blocks, double2* __restrict__ s0,
+                                                       unsigned long long* __restrict__ orand) {
     double2 a = make_double2(0.0, 0.0);
-    for (int e = 0; e < kItems; ++e)
-        if (p0 + e < n) a = cadd(a, d[order[p0 + e]]);
+    unsigned long long o = 0ull, m = ~0ull;
+    for (int64_t t = threadIdx.x; t < blocks; t += kBlock) {
+        a = cadd(a, part[t]);
+        o |= orand_part[2 * t];
+        m &= orand_part[2 * t + 1];
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        o |= __shfl_xor(o, off, kWave);
+        m &= __shfl_xor(m, off, kWave);
+    }
+    __shared__ unsigned long long wo[kBlock / kWave], wa[kBlock / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        wo[threadIdx.x / kWave] = o;
+        wa[threadIdx.x / kWave] = m;
+    }
+    const double2 s = block_sum_c(a);   // synchronises the block
+    if (threadIdx.x == 0) {
+        s0[0] = s;
+        for (int w = 1; w < kBlock / kWave; ++w) {
+            o |= wo[w];
+            m &= wa[w];
+        }
+        orand[0] = o;
+        orand[1] = m;
+    }
+}
+
+// Tile b holds sorted positions b*kTile .. b*kTile + kTile-1; here thread t
+// takes positions b*kTile + e*kBlock + t (coalesced), gathers their d into
+// d_sorted and sums them.
+__global__ __launch_bounds__(kBlock) void k_r1_tiles(const double2* __restrict__ d, const uint32_t* __restrict__ order,
+                                                     int64_t n, double2* __restrict__ d_sorted,
+                                                     double2* __restrict__ tile_sum) {
+    const int64_t b0 = blockIdx.x * (int64_t)kTile + threadIdx.x;
+    uint32_t idx[kItems];
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int64_t p = b0 + (int64_t)e * kBlock;
+        idx[e] = p < n ? order[p] : 0u;
+    }
+    double2 v[kItems];
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int64_t p = b0 + (int64_t)e * kBlock;
+        v[e] = p < n ? d[idx[e]] : make_double2(0.0, 0.0);
+    }
+    double2 a = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int64_t p = b0 + (int64_t)e * kBlock;
+        if (p < n) d_sorted[p] = v[e];
+        a = cadd(a, v[e]);
+    }
     const double2 s = block_sum_c(a);
     if (threadIdx.x == 0) tile_sum[blockIdx.x] = s;
 }
 
-// tile_pre[b] = s_0 + sum of tile_sum[0..b-1] (one block, sequential by
-// segments: each thread a contiguous run of tiles, thread 0 chains them).
+// tile_pre[b] = s_0 + sum of tile_sum[0..b-1] (one block): each thread sums
+// a contiguous run of tiles, a block scan offsets the runs, and each thread
+// then walks its run.
 __global__ __launch_bounds__(kBlock) void k_r1_tilepre(const double2* __restrict__ tile_sum, int64_t tiles,
                                                        const double2* __restrict__ s0,
                                                        double2* __restrict__ tile_pre) {
-    __shared__ double2 seg[kBlock];
     const int64_t per = (tiles + kBlock - 1) / kBlock;
-    const int64_t lo = threadIdx.x * per, hi = min(tiles, lo + per);
+    const int64_t lo = min(tiles, (int64_t)threadIdx.x * per), hi = min(tiles, lo + per);
     double2 a = make_double2(0.0, 0.0);
     for (int64_t t = lo; t < hi; ++t) a = cadd(a, tile_sum[t]);
-    seg[threadIdx.x] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double2 run = s0[0];
-        for (int t = 0; t < kBlock; ++t) {
-            const double2 v = seg[t];
-            seg[t] = run;
-            run = cadd(run, v);
-        }
-    }
-    __syncthreads();
-    double2 run = seg[threadIdx.x];
+    double2 run = block_excl_scan_c(a, s0[0]);
     for (int64_t t = lo; t < hi; ++t) {
         tile_pre[t] = run;
         run = cadd(run, tile_sum[t]);
@@ -211,38 +255,60 @@ __global__ __launch_bounds__(kBlock) void k_r1_tilepre(const double2* __restrict
 struct Best {
     double f;
     int64_t cell;
+    unsigned long long key;   // key of the cell's last boundary point (cell >= 1)
+    uint32_t coord;           // and its coordinate
+    int32_t pad;
 };
 
 __device__ __forceinline__ bool better(double f, int64_t c, double g, int64_t e) {
     return f > g || (f == g && c < e);
 }
 
-__global__ __launch_bounds__(kBlock) void k_r1_cells(const double2* __restrict__ d, const uint32_t* __restrict__ order,
-                                                     int64_t n, const double2* __restrict__ tile_pre,
+__device__ __forceinline__ int64_t shfl_xor_i64(int64_t v, int m) {
+    const int lo = __shfl_xor((int)(uint32_t)v, m, kWave);
+    const int hi = __shfl_xor((int)(v >> 32), m, kWave);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Best (value, cell) over the block, ties to the lower cell; thread 0 gets it.
+__device__ __forceinline__ void block_best(double& f, int64_t& c) {
+    __shared__ double wf[kBlock / kWave];
+    __shared__ int64_t wc[kBlock / kWave];
+#pragma unroll
+    for (int m = kWave / 2; m > 0; m >>= 1) {
+        const double g = __shfl_xor(f, m, kWave);
+        const int64_t e = shfl_xor_i64(c, m);
+        if (better(g, e, f, c)) {
+            f = g;
+            c = e;
+        }
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        wf[threadIdx.x / kWave] = f;
+        wc[threadIdx.x / kWave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < kBlock / kWave; ++w)
+            if (better(wf[w], wc[w], f, c)) {
+                f = wf[w];
+                c = wc[w];
+            }
+}
+
+// Thread t of tile b owns sorted positions b*kTile + t*kItems .. + kItems-1.
+__global__ __launch_bounds__(kBlock) void k_r1_cells(const double2* __restrict__ d_sorted, int64_t n,
+                                                     const double2* __restrict__ tile_pre,
                                                      Best* __restrict__ tile_best) {
-    __shared__ double2 tp[kBlock];
-    __shared__ double bf[kBlock];
-    __shared__ int64_t bc[kBlock];
     const int64_t p0 = blockIdx.x * (int64_t)kTile + (int64_t)threadIdx.x * kItems;
     double2 dv[kItems];
     double2 a = make_double2(0.0, 0.0);
+#pragma unroll
     for (int e = 0; e < kItems; ++e) {
-        dv[e] = p0 + e < n ? d[order[p0 + e]] : make_double2(0.0, 0.0);
+        dv[e] = p0 + e < n ? d_sorted[p0 + e] : make_double2(0.0, 0.0);
         a = cadd(a, dv[e]);
     }
-    // exclusive prefix of the thread sums in thread order (fixed order)
-    tp[threadIdx.x] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double2 run = tile_pre[blockIdx.x];
-        for (int t = 0; t < kBlock; ++t) {
-            const double2 v = tp[t];
-            tp[t] = run;
-            run = cadd(run, v);
-        }
-    }
-    __syncthreads();
-    double2 s = tp[threadIdx.x];
+    double2 s = block_excl_scan_c(a, tile_pre[blockIdx.x]);
     double best = -1.0;
     int64_t cell = INT64_MAX;
     for (int e = 0; e < kItems; ++e) {
@@ -254,23 +320,14 @@ __global__ __launch_bounds__(kBlock) void k_r1_cells(const double2* __restrict__
             cell = p0 + e + 1;   // cell l follows the l-th boundary point
         }
     }
-    bf[threadIdx.x] = best;
-    bc[threadIdx.x] = cell;
-    __syncthreads();
-    for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h && better(bf[threadIdx.x + h], bc[threadIdx.x + h], bf[threadIdx.x], bc[threadIdx.x])) {
-            bf[threadIdx.x] = bf[threadIdx.x + h];
-            bc[threadIdx.x] = bc[threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) tile_best[blockIdx.x] = Best{bf[0], bc[0]};
+    block_best(best, cell);
+    if (threadIdx.x == 0) tile_best[blockIdx.x] = Best{best, cell, 0ull, 0u, 0};
 }
 
 __global__ __launch_bounds__(kBlock) void k_r1_pick(const Best* __restrict__ tile_best, int64_t tiles,
-                                                    const double2* __restrict__ s0, Best* __restrict__ out) {
-    __shared__ double bf[kBlock];
-    __shared__ int64_t bc[kBlock];
+                                                    const double2* __restrict__ s0,
+                                                    const unsigned long long* __restrict__ skeys,
+                                                    const uint32_t* __restrict__ order, Best* __restrict__ out) {
     double best = -1.0;
     int64_t cell = INT64_MAX;
     if (threadIdx.x == 0) {
@@ -282,34 +339,37 @@ __global__ __launch_bounds__(kBlock) void k_r1_pick(const Best* __restrict__ til
             best = tile_best[t].f;
             cell = tile_best[t].cell;
         }
-    bf[threadIdx.x] = best;
-    bc[threadIdx.x] = cell;
-    __syncthreads();
-    for (unsigned h = kBlock / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h && better(bf[threadIdx.x + h], bc[threadIdx.x + h], bf[threadIdx.x], bc[threadIdx.x])) {
-            bf[threadIdx.x] = bf[threadIdx.x + h];
-            bc[threadIdx.x] = bc[threadIdx.x + h];
+    block_best(best, cell);
+    if (threadIdx.x == 0) {
+        Best b{best, cell, 0ull, 0u, 0};
+        if (cell >= 1) {
+            b.key = skeys[cell - 1];
+            b.coord = order[cell - 1];
         }
-        __syncthreads();
+        out[0] = b;
     }
-    if (threadIdx.x == 0) out[0] = Best{bf[0], bc[0]};
 }
 
-__global__ __launch_bounds__(kBlock) void k_r1_labels(const uint32_t* __restrict__ order, const uint8_t* __restrict__ k0,
-                                                      int64_t n, int K, const Best* __restrict__ best,
-                                                      uint8_t* __restrict__ z) {
-    const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t i = order[p];
-    int k = k0[i] + (p + 1 <= best->cell ? 1 : 0);
-    z[i] = (uint8_t)(k == K ? 0 : k);
-}
-
-__global__ __launch_bounds__(kBlock) void k_r1_obj(const double2* __restrict__ q, const uint8_t* __restrict__ z,
-                                                   int64_t n, const double2* __restrict__ roots,
-                                                   double2* __restrict__ part) {
+// Coordinate i moves to k_0 + 1 when its boundary point sits at a sorted
+// position below the best cell; the sort is stable, so that is when
+// (key_i, i) <= (key, coordinate) of the cell's last point.  Also the block
+// partials of z^H q.
+__global__ __launch_bounds__(kBlock) void k_r1_labels(const unsigned long long* __restrict__ keys,
+                                                      const uint8_t* __restrict__ k0, const double2* __restrict__ q,
+                                                      const double2* __restrict__ roots, int64_t n, int K,
+                                                      const Best* __restrict__ best, uint8_t* __restrict__ z,
+                                                      double2* __restrict__ part) {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    const double2 v = i < n ? cconj_mul(q[i], roots[z[i]]) : make_double2(0.0, 0.0);
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n) {
+        const Best b = best[0];
+        const unsigned long long key = keys[i];
+        const bool adv = b.cell >= 1 && (key < b.key || (key == b.key && (uint32_t)i <= b.coord));
+        int k = k0[i] + (adv ? 1 : 0);
+        k = k == K ? 0 : k;
+        z[i] = (uint8_t)k;
+        v = cconj_mul(q[i], roots[k]);
+    }
     const double2 s = block_sum_c(v);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -334,8 +394,8 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
 
     const int64_t blocks = (n + kBlock - 1) / kBlock;
     const int64_t tiles = (n + kTile - 1) / kTile;
-    const int64_t nparts = std::max(blocks, tiles);
     CarveSize cs;
+    cs.add<unsigned long long>(n);
     cs.add<unsigned long long>(n);
     cs.add<uint32_t>(n);
     cs.add<unsigned long long>(n);
@@ -343,7 +403,8 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     cs.add<uint32_t>(radix_hist_entries(n));
     cs.add<uint8_t>(n);
     cs.add<double2>(n);
-    cs.add<double2>(nparts);
+    cs.add<double2>(n);
+    cs.add<double2>(blocks);
     cs.add<double2>(tiles);
     cs.add<double2>(tiles);
     cs.add<Best>(tiles);
@@ -363,13 +424,15 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     LRQO_TRY(reserve_host(ctx, hs.bytes));
     Carve cv(ctx->arena);
     unsigned long long* keys = cv.take<unsigned long long>(n);
-    uint32_t* vals = cv.take<uint32_t>(n);
-    unsigned long long* keys_t = cv.take<unsigned long long>(n);
-    uint32_t* vals_t = cv.take<uint32_t>(n);
+    unsigned long long* keys_a = cv.take<unsigned long long>(n);
+    uint32_t* vals_a = cv.take<uint32_t>(n);
+    unsigned long long* keys_b = cv.take<unsigned long long>(n);
+    uint32_t* vals_b = cv.take<uint32_t>(n);
     uint32_t* hist = cv.take<uint32_t>(radix_hist_entries(n));
     uint8_t* k0 = cv.take<uint8_t>(n);
     double2* d = cv.take<double2>(n);
-    double2* part = cv.take<double2>(nparts);
+    double2* d_sorted = cv.take<double2>(n);
+    double2* part = cv.take<double2>(blocks);
     double2* tile_sum = cv.take<double2>(tiles);
     double2* tile_pre = cv.take<double2>(tiles);
     Best* tile_best = cv.take<Best>(tiles);
@@ -395,10 +458,9 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     LRQO_HIP(hipEventRecord(ctx->ev_start, st));
     LRQO_HIP(hipMemcpyAsync(roots, h_roots, sizeof(double2) * K, hipMemcpyHostToDevice, st));
     LRQO_HIP(hipMemcpyAsync(flag, h_flag, sizeof(int), hipMemcpyHostToDevice, st));
-    R1Dev p{reinterpret_cast<const double2*>(q), n, K, roots, keys, vals, k0, d, part, orand_part, flag};
+    R1Dev p{reinterpret_cast<const double2*>(q), n, K, roots, keys, k0, d, part, orand_part, flag};
     hipLaunchKernelGGL(k_r1_prep, dim3((unsigned)blocks), dim3(kBlock), 0, st, p);
-    hipLaunchKernelGGL(k_r1_sum, dim3(1), dim3(kBlock), 0, st, part, blocks, s0);
-    hipLaunchKernelGGL(k_r1_orand, dim3(1), dim3(kBlock), 0, st, orand_part, blocks, orand);
+    hipLaunchKernelGGL(k_r1_reduce0, dim3(1), dim3(kBlock), 0, st, part, orand_part, blocks, s0, orand);
     LRQO_HIP(hipGetLastError());
     LRQO_HIP(hipMemcpyAsync(h_orand, orand, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, st));
     LRQO_HIP(hipMemcpyAsync(h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -409,16 +471,18 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     const unsigned long long varying = h_orand[0] ^ h_orand[1];
     for (int dgt = 0; dgt < 8; ++dgt)
         if ((varying >> (8 * dgt)) & 0xFFull) mask |= 1u << dgt;
-    bool in_tmp = false;
-    LRQO_TRY(radix_sort_pairs(keys, vals, keys_t, vals_t, hist, n, mask, st, &in_tmp));
-    const uint32_t* order = in_tmp ? vals_t : vals;
+    if (!mask) mask = 1u;   // the sort runs one pass at least
+    SortedPairs sorted{};
+    LRQO_TRY(radix_sort_pairs(keys, keys_a, vals_a, keys_b, vals_b, hist, n, mask, st, &sorted));
 
-    hipLaunchKernelGGL(k_r1_tiles, dim3((unsigned)tiles), dim3(kBlock), 0, st, d, order, n, tile_sum);
+    hipLaunchKernelGGL(k_r1_tiles, dim3((unsigned)tiles), dim3(kBlock), 0, st, d, sorted.vals, n, d_sorted,
+                       tile_sum);
     hipLaunchKernelGGL(k_r1_tilepre, dim3(1), dim3(kBlock), 0, st, tile_sum, tiles, s0, tile_pre);
-    hipLaunchKernelGGL(k_r1_cells, dim3((unsigned)tiles), dim3(kBlock), 0, st, d, order, n, tile_pre, tile_best);
-    hipLaunchKernelGGL(k_r1_pick, dim3(1), dim3(kBlock), 0, st, tile_best, tiles, s0, best);
-    hipLaunchKernelGGL(k_r1_labels, dim3((unsigned)blocks), dim3(kBlock), 0, st, order, k0, n, K, best, z);
-    hipLaunchKernelGGL(k_r1_obj, dim3((unsigned)blocks), dim3(kBlock), 0, st, p.q, z, n, roots, part);
+    hipLaunchKernelGGL(k_r1_cells, dim3((unsigned)tiles), dim3(kBlock), 0, st, d_sorted, n, tile_pre, tile_best);
+    hipLaunchKernelGGL(k_r1_pick, dim3(1), dim3(kBlock), 0, st, tile_best, tiles, s0, sorted.keys, sorted.vals,
+                       best);
+    hipLaunchKernelGGL(k_r1_labels, dim3((unsigned)blocks), dim3(kBlock), 0, st, keys, k0, p.q, roots, n, K, best,
+                       z, part);
     hipLaunchKernelGGL(k_r1_sum, dim3(1), dim3(kBlock), 0, st, part, blocks, s0 + 1);
     LRQO_HIP(hipGetLastError());
     LRQO_HIP(hipEventRecord(ctx->ev_stop, st));

@@ -11,14 +11,22 @@ namespace lrqo {
 // Entries of the digit-count scratch radix_sort_pairs needs for n keys.
 size_t radix_hist_entries(int64_t n);
 
+// Where the sorted pairs ended up (one of the two work buffers).
+struct SortedPairs {
+    const unsigned long long* keys;
+    const uint32_t* vals;
+};
+
 // Ascending, stable (equal keys keep their input order) LSD radix sort with
-// 8-bit digits.  Pass d (bits 8d .. 8d+7) runs only when bit d of
-// digit_mask is set: a digit that is the same in every key leaves the order
-// unchanged.  Input in (keys, vals); the sorted pairs end in (keys, vals)
-// or in (keys_tmp, vals_tmp), as *in_tmp reports.  hist holds
-// radix_hist_entries(n) counters.  1 <= n <= 2^31 - 1.
-lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp,
-                             uint32_t* vals_tmp, uint32_t* hist, int64_t n, unsigned digit_mask,
-                             hipStream_t st, bool* in_tmp);
+// 8-bit digits of the n keys in `keys`, which stay as they are; the value
+// paired with each key is its position 0 .. n-1.  Pass d (bits 8d .. 8d+7)
+// runs only when bit d of digit_mask is set: a digit that is the same in
+// every key leaves the order unchanged.  The passes alternate between the
+// work buffers (keys_a, vals_a) and (keys_b, vals_b); *out names the one
+// holding the result.  hist holds radix_hist_entries(n) counters.
+// 1 <= n <= 2^31 - 1.
+lrqo_status radix_sort_pairs(const unsigned long long* keys, unsigned long long* keys_a, uint32_t* vals_a,
+                             unsigned long long* keys_b, uint32_t* vals_b, uint32_t* hist, int64_t n,
+                             unsigned digit_mask, hipStream_t st, SortedPairs* out);
 
 }  // namespace lrqo

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
         const int64_t idx = chunk + t * kWave + lane;
         const bool valid = idx < n;
         const unsigned long long key = valid ? keys_in[idx] : 0ull;
-        const uint32_t val = valid ? vals_in[idx] : 0u;
+        const uint32_t val = !valid ? 0u : vals_in ? vals_in[idx] : (uint32_t)idx;
         const int d = digit_of(key, shift);
         unsigned long long match = __ballot(valid);
 #pragma unroll
@@ -192,15 +192,19 @@ size_t radix_hist_entries(int64_t n) {
     return (size_t)kBins * (size_t)((n + kTile - 1) / kTile) + kBins;
 }
 
-lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned long long* keys_tmp,
-                             uint32_t* vals_tmp, uint32_t* hist, int64_t n, unsigned digit_mask,
-                             hipStream_t st, bool* in_tmp) {
+lrqo_status radix_sort_pairs(const unsigned long long* keys, unsigned long long* keys_a, uint32_t* vals_a,
+                             unsigned long long* keys_b, uint32_t* vals_b, uint32_t* hist, int64_t n,
+                             unsigned digit_mask, hipStream_t st, SortedPairs* out) {
     const int64_t tiles = (n + kTile - 1) / kTile;
-    unsigned long long* kin = keys;
-    uint32_t* vin = vals;
-    unsigned long long* kout = keys_tmp;
-    uint32_t* vout = vals_tmp;
-    bool tmp = false;
+    // one pass at least, so that the positions are written out even when
+    // every digit is the same in all keys (that pass keeps the order)
+    if (!(digit_mask & 0xFFu)) digit_mask = 1u;
+    const unsigned long long* kin = keys;
+    const uint32_t* vin = nullptr;   // first pass: the values are the positions
+    unsigned long long* kout = keys_a;
+    uint32_t* vout = vals_a;
+    unsigned long long* knext = keys_b;
+    uint32_t* vnext = vals_b;
     uint32_t* rowtot = hist + (size_t)kBins * tiles;
     for (int d = 0; d < 8; ++d) {
         if (!((digit_mask >> d) & 1u)) continue;
@@ -211,11 +215,13 @@ lrqo_status radix_sort_pairs(unsigned long long* keys, uint32_t* vals, unsigned 
         hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
                            shift, hist, tiles, rowtot);
         LRQO_HIP(hipGetLastError());
-        std::swap(kin, kout);
-        std::swap(vin, vout);
-        tmp = !tmp;
+        kin = kout;
+        vin = vout;
+        std::swap(kout, knext);
+        std::swap(vout, vnext);
     }
-    *in_tmp = tmp;
+    out->keys = kin;
+    out->vals = vin;
     return LRQO_OK;
 }
 
