@@ -15,7 +15,15 @@
 //                 OR / AND of the keys (digits that never change skip a
 //                 pass), finiteness
 //   k_r1_reduce0  s_0 and the OR / AND from the block partials
-//   radix sort    stable by key (sort.hip): ties keep coordinate order
+//   radix sort    stable (sort.hip), first by a 32-bit fixed-point image of
+//                 phi (four passes; it never reverses the order of two
+//                 points), so equal images keep coordinate order
+//   k_r1_fixup    runs of equal images whose exact keys differ (rare: points
+//                 closer than 2^-32 of the range) are put in (key,
+//                 coordinate) order by insertion; a run longer than 16 with
+//                 differing keys makes the host sort the exact 64-bit keys
+//                 instead (eight passes), so the order is always that of
+//                 (key, coordinate)
 //   k_r1_tiles    per tile of 2048 sorted positions: gathers d into sorted
 //                 order (coalesced write) and sums the tile
 //   k_r1_tilepre  s_0 plus the tile sums before each tile (fixed order)
@@ -51,6 +59,15 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 __device__ __forceinline__ unsigned long long order_key(double v) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// A 32-bit image of phi in (-pi/K, pi/K] that never reverses the order of
+// two values: (phi K/(2 pi) + 1/2) 2^32, truncated and clamped; every step
+// is non-decreasing in phi.
+__device__ __forceinline__ uint32_t fixed_key(double phi, int K) {
+    double u = fma(phi, (double)K / (2.0 * kPi), 0.5) * 4294967296.0;
+    u = u > 0.0 ? u : 0.0;   // also maps a NaN to 0 (reported separately)
+    return u >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)u;
 }
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -108,7 +125,8 @@ struct R1Dev {
     int64_t n;
     int K;
     const double2* roots;            // [K]
-    unsigned long long* keys;
+    unsigned long long* keys;        // exact order keys of phi
+    uint32_t* k32;                   // fixed-point images of phi
     uint8_t* k0;
     double2* d;
     double2* part;                   // block partials
@@ -133,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_r1_prep(R1Dev p) {
         k += k < 0 ? p.K : 0;
         key = order_key(phi);
         p.keys[i] = key;
+        p.k32[i] = fixed_key(phi, p.K);
         p.k0[i] = (uint8_t)k;
         const int k1 = k + 1 == p.K ? 0 : k + 1;
         const double2 a = p.roots[k], b = p.roots[k1];
@@ -252,6 +271,50 @@ __global__ __launch_bounds__(kBlock) void k_r1_tilepre(const double2* __restrict
     }
 }
 
+constexpr int kRunMax = 16;   // longest run of equal images sorted in place
+
+// After the stable sort by image, position p starts a run of equal images
+// or sits inside one.  A run start with a run of at most kRunMax puts it in
+// (key, coordinate) order by insertion (a run of equal keys is already in
+// coordinate order and costs one comparison per member).  An inside
+// position whose key differs from its predecessor's, in a run longer than
+// kRunMax, sets *overflow; such runs are never touched here.
+__global__ __launch_bounds__(kBlock) void k_r1_fixup(const uint32_t* __restrict__ img, uint32_t* __restrict__ order,
+                                                     const unsigned long long* __restrict__ keys, int64_t n,
+                                                     int* __restrict__ overflow) {
+    const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t q = img[p];
+    const bool start = p == 0 || img[p - 1] != q;
+    if (start) {
+        if (p + 1 >= n || img[p + 1] != q) return;
+        int64_t e = p + 1;
+        while (e < n && img[e] == q && e - p <= kRunMax) ++e;
+        if (e - p > kRunMax) return;     // long run: checked by its members
+        for (int64_t a = p + 1; a < e; ++a) {
+            const uint32_t v = order[a];
+            const unsigned long long kv = keys[v];
+            int64_t b = a;
+            while (b > p) {
+                const uint32_t u = order[b - 1];
+                const unsigned long long ku = keys[u];
+                if (ku < kv || (ku == kv && u < v)) break;
+                order[b] = u;
+                --b;
+            }
+            order[b] = v;
+        }
+        return;
+    }
+    // inside a run; order[] of a run of at most kRunMax may be changing
+    // under this read, but then the length test below ends it
+    if (keys[order[p]] == keys[order[p - 1]]) return;
+    int64_t lo = p, hi = p + 1;
+    while (lo > 0 && img[lo - 1] == q && hi - lo <= kRunMax) --lo;
+    while (hi < n && img[hi] == q && hi - lo <= kRunMax) ++hi;
+    if (hi - lo > kRunMax) *overflow = 1;   // every writer stores the same value
+}
+
 struct Best {
     double f;
     int64_t cell;
@@ -326,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_r1_cells(const double2* __restrict__
 
 __global__ __launch_bounds__(kBlock) void k_r1_pick(const Best* __restrict__ tile_best, int64_t tiles,
                                                     const double2* __restrict__ s0,
-                                                    const unsigned long long* __restrict__ skeys,
+                                                    const unsigned long long* __restrict__ keys,
                                                     const uint32_t* __restrict__ order, Best* __restrict__ out) {
     double best = -1.0;
     int64_t cell = INT64_MAX;
@@ -343,8 +406,8 @@ __global__ __launch_bounds__(kBlock) void k_r1_pick(const Best* __restrict__ til
     if (threadIdx.x == 0) {
         Best b{best, cell, 0ull, 0u, 0};
         if (cell >= 1) {
-            b.key = skeys[cell - 1];
             b.coord = order[cell - 1];
+            b.key = keys[b.coord];
         }
         out[0] = b;
     }
@@ -396,6 +459,7 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     const int64_t tiles = (n + kTile - 1) / kTile;
     CarveSize cs;
     cs.add<unsigned long long>(n);
+    cs.add<uint32_t>(n);
     cs.add<unsigned long long>(n);
     cs.add<uint32_t>(n);
     cs.add<unsigned long long>(n);
@@ -424,6 +488,7 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
     LRQO_TRY(reserve_host(ctx, hs.bytes));
     Carve cv(ctx->arena);
     unsigned long long* keys = cv.take<unsigned long long>(n);
+    uint32_t* k32 = cv.take<uint32_t>(n);
     unsigned long long* keys_a = cv.take<unsigned long long>(n);
     uint32_t* vals_a = cv.take<uint32_t>(n);
     unsigned long long* keys_b = cv.take<unsigned long long>(n);
@@ -454,33 +519,47 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
         const double a = (2.0 * kPi * (double)k) / (double)K;
         h_roots[k] = make_double2(std::cos(a), std::sin(a));
     }
-    h_flag[0] = 0;
+    h_flag[0] = 0;   // non-finite q
+    h_flag[1] = 0;   // a long run with differing keys
     LRQO_HIP(hipEventRecord(ctx->ev_start, st));
     LRQO_HIP(hipMemcpyAsync(roots, h_roots, sizeof(double2) * K, hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(flag, h_flag, sizeof(int), hipMemcpyHostToDevice, st));
-    R1Dev p{reinterpret_cast<const double2*>(q), n, K, roots, keys, k0, d, part, orand_part, flag};
+    LRQO_HIP(hipMemcpyAsync(flag, h_flag, 2 * sizeof(int), hipMemcpyHostToDevice, st));
+    R1Dev p{reinterpret_cast<const double2*>(q), n, K, roots, keys, k32, k0, d, part, orand_part, flag};
     hipLaunchKernelGGL(k_r1_prep, dim3((unsigned)blocks), dim3(kBlock), 0, st, p);
     hipLaunchKernelGGL(k_r1_reduce0, dim3(1), dim3(kBlock), 0, st, part, orand_part, blocks, s0, orand);
     LRQO_HIP(hipGetLastError());
+    // images first (the 64-bit work buffers hold the 32-bit pairs)
+    SortedPairs32 by_img{};
+    LRQO_TRY(radix_sort_pairs32(k32, reinterpret_cast<uint32_t*>(keys_a), vals_a, reinterpret_cast<uint32_t*>(keys_b),
+                                vals_b, hist, n, 0xFu, st, &by_img));
+    uint32_t* order_img = const_cast<uint32_t*>(by_img.vals);   // a work buffer of this call
+    hipLaunchKernelGGL(k_r1_fixup, dim3((unsigned)blocks), dim3(kBlock), 0, st, by_img.keys, order_img, keys, n,
+                       flag + 1);
+    LRQO_HIP(hipGetLastError());
     LRQO_HIP(hipMemcpyAsync(h_orand, orand, sizeof(unsigned long long) * 2, hipMemcpyDeviceToHost, st));
-    LRQO_HIP(hipMemcpyAsync(h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipMemcpyAsync(h_flag, flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     LRQO_HIP(hipStreamSynchronize(st));
     if (h_flag[0]) return fail(LRQO_ENOTFINITE, "q holds a NaN or an infinity");
 
-    unsigned mask = 0;
-    const unsigned long long varying = h_orand[0] ^ h_orand[1];
-    for (int dgt = 0; dgt < 8; ++dgt)
-        if ((varying >> (8 * dgt)) & 0xFFull) mask |= 1u << dgt;
-    if (!mask) mask = 1u;   // the sort runs one pass at least
-    SortedPairs sorted{};
-    LRQO_TRY(radix_sort_pairs(keys, keys_a, vals_a, keys_b, vals_b, hist, n, mask, st, &sorted));
+    int passes = 4;
+    const uint32_t* order = order_img;
+    if (h_flag[1]) {
+        // the exact keys, skipping digits that are the same in all of them
+        unsigned mask = 0;
+        const unsigned long long varying = h_orand[0] ^ h_orand[1];
+        for (int dgt = 0; dgt < 8; ++dgt)
+            if ((varying >> (8 * dgt)) & 0xFFull) mask |= 1u << dgt;
+        if (!mask) mask = 1u;   // the sort runs one pass at least
+        SortedPairs exact{};
+        LRQO_TRY(radix_sort_pairs(keys, keys_a, vals_a, keys_b, vals_b, hist, n, mask, st, &exact));
+        order = exact.vals;
+        passes += __builtin_popcount(mask);
+    }
 
-    hipLaunchKernelGGL(k_r1_tiles, dim3((unsigned)tiles), dim3(kBlock), 0, st, d, sorted.vals, n, d_sorted,
-                       tile_sum);
+    hipLaunchKernelGGL(k_r1_tiles, dim3((unsigned)tiles), dim3(kBlock), 0, st, d, order, n, d_sorted, tile_sum);
     hipLaunchKernelGGL(k_r1_tilepre, dim3(1), dim3(kBlock), 0, st, tile_sum, tiles, s0, tile_pre);
     hipLaunchKernelGGL(k_r1_cells, dim3((unsigned)tiles), dim3(kBlock), 0, st, d_sorted, n, tile_pre, tile_best);
-    hipLaunchKernelGGL(k_r1_pick, dim3(1), dim3(kBlock), 0, st, tile_best, tiles, s0, sorted.keys, sorted.vals,
-                       best);
+    hipLaunchKernelGGL(k_r1_pick, dim3(1), dim3(kBlock), 0, st, tile_best, tiles, s0, keys, order, best);
     hipLaunchKernelGGL(k_r1_labels, dim3((unsigned)blocks), dim3(kBlock), 0, st, keys, k0, p.q, roots, n, K, best,
                        z, part);
     hipLaunchKernelGGL(k_r1_sum, dim3(1), dim3(kBlock), 0, st, part, blocks, s0 + 1);
@@ -497,7 +576,7 @@ lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, 
         res->sweep_obj = h_best[0].f;
         res->best_cell = h_best[0].cell;
         res->device_ms = ms;
-        res->sort_passes = __builtin_popcount(mask);
+        res->sort_passes = passes;
     }
     return LRQO_OK;
 }

@@ -16,6 +16,10 @@ struct SortedPairs {
     const unsigned long long* keys;
     const uint32_t* vals;
 };
+struct SortedPairs32 {
+    const uint32_t* keys;
+    const uint32_t* vals;
+};
 
 // Ascending, stable (equal keys keep their input order) LSD radix sort with
 // 8-bit digits of the n keys in `keys`, which stay as they are; the value
@@ -28,5 +32,10 @@ struct SortedPairs {
 lrqo_status radix_sort_pairs(const unsigned long long* keys, unsigned long long* keys_a, uint32_t* vals_a,
                              unsigned long long* keys_b, uint32_t* vals_b, uint32_t* hist, int64_t n,
                              unsigned digit_mask, hipStream_t st, SortedPairs* out);
+
+// The same for 32-bit keys (four digits; bits 0-3 of digit_mask).
+lrqo_status radix_sort_pairs32(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                               uint32_t* vals_b, uint32_t* hist, int64_t n, unsigned digit_mask, hipStream_t st,
+                               SortedPairs32* out);
 
 }  // namespace lrqo

@@ -1,4 +1,5 @@
-// Stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit digits.
+// Stable LSD radix sort of (uint64 or uint32 key, uint32 value) pairs,
+// 8-bit digits.
 //
 // Per pass (one 8-bit digit):
 //   k_digit_hist     per tile of 2048 pairs: digit counts -> hist[digit][tile]
@@ -34,11 +35,13 @@ constexpr int kTile = kWaves * kSteps * kWave;  // 2048 pairs per block
 constexpr int kBins = 256;
 static_assert(kBlock == kBins, "one thread per digit bin");
 
-__device__ __forceinline__ int digit_of(unsigned long long key, int shift) {
-    return (int)((key >> shift) & 0xFFull);
+template <typename Key>
+__device__ __forceinline__ int digit_of(Key key, int shift) {
+    return (int)((key >> shift) & 0xFFu);
 }
 
-__global__ __launch_bounds__(kBlock) void k_digit_hist(const unsigned long long* __restrict__ keys,
+template <typename Key>
+__global__ __launch_bounds__(kBlock) void k_digit_hist(const Key* __restrict__ keys,
                                                        int64_t n, int shift, uint32_t* __restrict__ hist,
                                                        int64_t tiles) {
     __shared__ uint32_t h[kBins];
@@ -109,9 +112,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* wsum) 
     return ex;
 }
 
-__global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long long* __restrict__ keys_in,
+template <typename Key>
+__global__ __launch_bounds__(kBlock) void k_digit_scatter(const Key* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
-                                                          unsigned long long* __restrict__ keys_out,
+                                                          Key* __restrict__ keys_out,
                                                           uint32_t* __restrict__ vals_out, int64_t n,
                                                           int shift, const uint32_t* __restrict__ offs,
                                                           int64_t tiles, const uint32_t* __restrict__ rowtot) {
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
     __shared__ uint32_t base[kWaves][kBins];
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t lstart[kBins], gbase[kBins];
-    __shared__ unsigned long long lkeys[kTile];
+    __shared__ Key lkeys[kTile];
     __shared__ uint32_t lvals[kTile];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     for (int v = 0; v < kWaves; ++v) cnt[v][threadIdx.x] = 0;
@@ -154,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
     for (int t = 0; t < kSteps; ++t) {
         const int64_t idx = chunk + t * kWave + lane;
         const bool valid = idx < n;
-        const unsigned long long key = valid ? keys_in[idx] : 0ull;
+        const Key key = valid ? keys_in[idx] : Key(0);
         const uint32_t val = !valid ? 0u : vals_in ? vals_in[idx] : (uint32_t)idx;
         const int d = digit_of(key, shift);
         unsigned long long match = __ballot(valid);
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_digit_scatter(const unsigned long lo
     // write out in the LDS order: runs of one digit go to consecutive slots
     const int count = (int)min((int64_t)kTile, n - tile0);
     for (int j = threadIdx.x; j < count; j += kBlock) {
-        const unsigned long long key = lkeys[j];
+        const Key key = lkeys[j];
         const int d = digit_of(key, shift);
         const uint32_t g = gbase[d] + ((uint32_t)j - lstart[d]);
         keys_out[g] = key;
@@ -192,36 +196,57 @@ size_t radix_hist_entries(int64_t n) {
     return (size_t)kBins * (size_t)((n + kTile - 1) / kTile) + kBins;
 }
 
-lrqo_status radix_sort_pairs(const unsigned long long* keys, unsigned long long* keys_a, uint32_t* vals_a,
-                             unsigned long long* keys_b, uint32_t* vals_b, uint32_t* hist, int64_t n,
-                             unsigned digit_mask, hipStream_t st, SortedPairs* out) {
+namespace {
+
+template <typename Key>
+void sort_passes(const Key* keys, Key* keys_a, uint32_t* vals_a, Key* keys_b, uint32_t* vals_b, uint32_t* hist,
+                 int64_t n, unsigned digit_mask, hipStream_t st, const Key** out_keys, const uint32_t** out_vals) {
+    constexpr int kDigits = (int)sizeof(Key);
     const int64_t tiles = (n + kTile - 1) / kTile;
     // one pass at least, so that the positions are written out even when
     // every digit is the same in all keys (that pass keeps the order)
-    if (!(digit_mask & 0xFFu)) digit_mask = 1u;
-    const unsigned long long* kin = keys;
+    digit_mask &= (1u << kDigits) - 1u;
+    if (!digit_mask) digit_mask = 1u;
+    const Key* kin = keys;
     const uint32_t* vin = nullptr;   // first pass: the values are the positions
-    unsigned long long* kout = keys_a;
+    Key* kout = keys_a;
     uint32_t* vout = vals_a;
-    unsigned long long* knext = keys_b;
+    Key* knext = keys_b;
     uint32_t* vnext = vals_b;
     uint32_t* rowtot = hist + (size_t)kBins * tiles;
-    for (int d = 0; d < 8; ++d) {
+    for (int d = 0; d < kDigits; ++d) {
         if (!((digit_mask >> d) & 1u)) continue;
         const int shift = 8 * d;
-        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist, tiles);
+        hipLaunchKernelGGL(k_digit_hist<Key>, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, n, shift, hist,
+                           tiles);
         hipLaunchKernelGGL(k_scan_rows, dim3(kBins / kScanWaves), dim3(kScanWaves * kWave), 0, st, hist, tiles,
                            rowtot);
-        hipLaunchKernelGGL(k_digit_scatter, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, vin, kout, vout, n,
-                           shift, hist, tiles, rowtot);
-        LRQO_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_digit_scatter<Key>, dim3((unsigned)tiles), dim3(kBlock), 0, st, kin, vin, kout, vout,
+                           n, shift, hist, tiles, rowtot);
         kin = kout;
         vin = vout;
         std::swap(kout, knext);
         std::swap(vout, vnext);
     }
-    out->keys = kin;
-    out->vals = vin;
+    *out_keys = kin;
+    *out_vals = vin;
+}
+
+}  // namespace
+
+lrqo_status radix_sort_pairs(const unsigned long long* keys, unsigned long long* keys_a, uint32_t* vals_a,
+                             unsigned long long* keys_b, uint32_t* vals_b, uint32_t* hist, int64_t n,
+                             unsigned digit_mask, hipStream_t st, SortedPairs* out) {
+    sort_passes(keys, keys_a, vals_a, keys_b, vals_b, hist, n, digit_mask, st, &out->keys, &out->vals);
+    LRQO_HIP(hipGetLastError());
+    return LRQO_OK;
+}
+
+lrqo_status radix_sort_pairs32(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                               uint32_t* vals_b, uint32_t* hist, int64_t n, unsigned digit_mask, hipStream_t st,
+                               SortedPairs32* out) {
+    sort_passes(keys, keys_a, vals_a, keys_b, vals_b, hist, n, digit_mask, st, &out->keys, &out->vals);
+    LRQO_HIP(hipGetLastError());
     return LRQO_OK;
 }
 

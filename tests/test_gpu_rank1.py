@@ -72,6 +72,35 @@ def test_rank1_real_vector_ties(lrqo_mod, K):
         assert abs(res.obj - np.sum(np.abs(q)) ** 2) <= 1e-10 * res.obj
 
 
+def _clustered(groups, size, seed, K):
+    """Groups of boundary points 1e-13 apart in angle: distinct FP64 keys
+    that fall in one 2^-32 step of the fixed-point image, with magnitudes
+    and coordinate order shuffled so that coordinate order is not key
+    order inside a group."""
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(-np.pi, np.pi, groups)[:, None] + 1e-13 * np.arange(size)[None, :]
+    q = rng.uniform(0.5, 2.0, theta.shape) * np.exp(1j * theta)
+    return rng.permutation(q.ravel())
+
+
+@pytest.mark.parametrize("K", [3, 5])
+def test_rank1_close_points_sorted_in_place(lrqo_mod, K):
+    """Runs of at most 16 equal images with distinct keys: put in key order
+    after the image sort, without the 64-bit sort."""
+    q = _clustered(6, 12, 11 + K, K)
+    res = _check(lrqo_mod, q, K)
+    assert res.sort_passes == 4
+
+
+@pytest.mark.parametrize("K", [3, 5])
+def test_rank1_long_close_runs_take_the_exact_sort(lrqo_mod, K):
+    """A run of more than 16 equal images with distinct keys: the host sorts
+    the exact 64-bit keys instead."""
+    q = np.concatenate([_clustered(3, 40, 21 + K, K), inputs.random_V(500, 1, 7)[:, 0]])
+    res = _check(lrqo_mod, q, K)
+    assert res.sort_passes > 4
+
+
 def test_rank1_equals_the_exact_path(lrqo_mod):
     q = inputs.random_V(300, 1, 42)
     z, res = lrqo_mod.solve_rank1(torch.from_numpy(q[:, 0]).cuda(), 3)
