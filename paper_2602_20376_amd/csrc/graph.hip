@@ -112,6 +112,49 @@ __global__ __launch_bounds__(kBlock) void k_sum2(const double* __restrict__ part
     block_sum2(a, b, out);
 }
 
+// Label weights of the entries [e, e1) in chunks of U: the U column and
+// weight loads, then the U label loads, are issued together; the additions
+// keep entry order.  Leaves e at the first entry of an incomplete chunk.
+template <int U>
+__device__ __forceinline__ void gain_chunk(const GraphDev& g, const uint8_t* __restrict__ z, int64_t& e,
+                                           int64_t e1, double (*cnt)[kBlock], double& wdeg) {
+    for (; e + U <= e1; e += U) {
+        int32_t c[U];
+        double w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = g.col[e + u];
+            w[u] = g.w ? g.w[e + u] : 1.0;
+        }
+        uint8_t l[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) l[u] = z[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cnt[l[u]][threadIdx.x] += w[u];
+            wdeg += fabs(w[u]);
+        }
+    }
+}
+
+// Whether a neighbour in [e, e1) beats (gi, i), U neighbours' gains in
+// flight at a time; stops at the first chunk that holds one.
+template <int U>
+__device__ __forceinline__ void move_chunk(const GraphDev& g, const double* __restrict__ gain, int64_t i, double gi,
+                                           int64_t& e, int64_t e1, bool& win) {
+    for (; win && e + U <= e1; e += U) {
+        int32_t j[U];
+        double gj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) j[u] = g.col[e + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) gj[u] = gain[j[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (gj[u] > 0.0 && (gj[u] > gi || (gj[u] == gi && j[u] < i))) win = false;
+    }
+}
+
 // cosd[d] = cos(2 pi d / K).  Gain of moving i from a to b:
 // 2 sum_k c_k (cosd[(a-k) mod K] - cosd[(b-k) mod K]).
 __global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_t* __restrict__ z,
@@ -122,7 +165,13 @@ __global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_
     if (i >= g.n) return;
     for (int k = 0; k < K; ++k) cnt[k][threadIdx.x] = 0.0;
     double wdeg = 0.0;
-    for (int64_t e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
+    int64_t e = g.row_ptr[i];
+    const int64_t e1 = g.row_ptr[i + 1];
+    // eight, then four entries' loads in flight at a time; the sums stay in
+    // entry order
+    gain_chunk<8>(g, z, e, e1, cnt, wdeg);
+    gain_chunk<4>(g, z, e, e1, cnt, wdeg);
+    for (; e < e1; ++e) {
         const double w = g.w ? g.w[e] : 1.0;
         cnt[z[g.col[e]]][threadIdx.x] += w;
         wdeg += fabs(w);
@@ -160,7 +209,12 @@ __global__ __launch_bounds__(kBlock) void k_move(GraphDev g, const uint8_t* __re
     if (i < g.n) {
         const double gi = gain[i];
         win = gi > 0.0;
-        for (int64_t e = g.row_ptr[i]; win && e < g.row_ptr[i + 1]; ++e) {
+        int64_t e = g.row_ptr[i];
+        const int64_t e1 = g.row_ptr[i + 1];
+        // eight, then four neighbours' gains in flight at a time
+        move_chunk<8>(g, gain, i, gi, e, e1, win);
+        move_chunk<4>(g, gain, i, gi, e, e1, win);
+        for (; win && e < e1; ++e) {
             const int32_t j = g.col[e];
             const double gj = gain[j];
             if (gj > 0.0 && (gj > gi || (gj == gi && j < i))) win = false;
