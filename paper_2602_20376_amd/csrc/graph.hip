@@ -83,6 +83,35 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* out) {
 }
 
 // sqd[d] = |1 - omega^d|^2 for the label difference d = (k_i - k_j) mod K.
+// The terms of the entries [e, e1) of vertex i (label a) in chunks of U:
+// the U column and weight loads, then the U label loads, are issued
+// together; the additions keep entry order.  Leaves e at the first entry of
+// an incomplete chunk.
+template <int U>
+__device__ __forceinline__ void objective_chunk(const GraphDev& g, int K, const uint8_t* __restrict__ z,
+                                                const double* __restrict__ sqd, int a, int64_t& e, int64_t e1,
+                                                double& q, double& cut) {
+    for (; e + U <= e1; e += U) {
+        int32_t c[U];
+        double w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = g.col[e + u];
+            w[u] = g.w ? g.w[e + u] : 1.0;
+        }
+        int b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) b[u] = z[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int d = a - b[u];
+            d += d < 0 ? K : 0;
+            q += w[u] * sqd[d];
+            cut += a != b[u] ? w[u] : 0.0;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_objective(GraphDev g, int K, const uint8_t* __restrict__ z,
                                                       const double* __restrict__ sqd,
                                                       double* __restrict__ partial) {
@@ -90,7 +119,11 @@ __global__ __launch_bounds__(kBlock) void k_objective(GraphDev g, int K, const u
     double q = 0.0, cut = 0.0;
     if (i < g.n) {
         const int a = z[i];
-        for (int64_t e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
+        int64_t e = g.row_ptr[i];
+        const int64_t e1 = g.row_ptr[i + 1];
+        objective_chunk<8>(g, K, z, sqd, a, e, e1, q, cut);
+        objective_chunk<4>(g, K, z, sqd, a, e, e1, q, cut);
+        for (; e < e1; ++e) {
             const int b = z[g.col[e]];
             const double w = g.w ? g.w[e] : 1.0;
             int d = a - b;
@@ -157,10 +190,11 @@ __device__ __forceinline__ void move_chunk(const GraphDev& g, const double* __re
 
 // cosd[d] = cos(2 pi d / K).  Gain of moving i from a to b:
 // 2 sum_k c_k (cosd[(a-k) mod K] - cosd[(b-k) mod K]).
+template <int KM>
 __global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_t* __restrict__ z,
                                                  const double* __restrict__ cosd,
                                                  double* __restrict__ gain, uint8_t* __restrict__ target) {
-    __shared__ double cnt[kMaxKRefine][kBlock];
+    __shared__ double cnt[KM][kBlock];   // KM >= K rows
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= g.n) return;
     for (int k = 0; k < K; ++k) cnt[k][threadIdx.x] = 0.0;
@@ -425,8 +459,12 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
         LRQO_HIP(hipMemsetAsync(s.moves, 0, sizeof(unsigned long long) * todo * kMoveLanes, st));
         LRQO_HIP(hipEventRecord(ctx->ev_start, st));
         for (int t = 0; t < todo; ++t) {
-            hipLaunchKernelGGL(k_gain, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd, s.gain,
-                               s.target);
+            if (K <= 4)
+                hipLaunchKernelGGL(k_gain<4>, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd, s.gain,
+                                   s.target);
+            else
+                hipLaunchKernelGGL(k_gain<kMaxKRefine>, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd,
+                                   s.gain, s.target);
             hipLaunchKernelGGL(k_move, dim3(blocks), dim3(kBlock), 0, st, gd, zbuf[cur], s.gain, s.target,
                                zbuf[cur ^ 1], s.moves + (size_t)t * kMoveLanes);
             cur ^= 1;
