@@ -15,6 +15,9 @@
 //   k_move          per candidate: moves when its (gain, -index) beats every
 //                   neighbouring candidate; labels go to the other buffer;
 //                   moves counted per round (per block, into eight counters)
+// Rounds go out in batches between host checks; a round whose predecessor
+// moved nothing returns at once, so a batch that converges early costs a
+// launch per remaining round.
 // One thread per vertex; the CSR entries of a vertex are read in order, so
 // every per-vertex sum has a fixed order.
 #include <algorithm>
@@ -145,6 +148,19 @@ __global__ __launch_bounds__(kBlock) void k_sum2(const double* __restrict__ part
     block_sum2(a, b, out);
 }
 
+constexpr int kMoveLanes = 8;
+
+// Whether the previous round (its kMoveLanes counters; none for the first
+// round of a batch) moved nothing: then this round and every later one of
+// the batch would leave the labels unchanged, and is skipped.
+__device__ __forceinline__ bool no_moves(const unsigned long long* __restrict__ prev) {
+    if (!prev) return false;
+    unsigned long long m = 0;
+#pragma unroll
+    for (int l = 0; l < kMoveLanes; ++l) m += prev[l];
+    return m == 0;
+}
+
 // Label weights of the entries [e, e1) in chunks of U: the U column and
 // weight loads, then the U label loads, are issued together; the additions
 // keep entry order.  Leaves e at the first entry of an incomplete chunk.
@@ -193,10 +209,11 @@ __device__ __forceinline__ void move_chunk(const GraphDev& g, const double* __re
 template <int KM>
 __global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_t* __restrict__ z,
                                                  const double* __restrict__ cosd,
-                                                 double* __restrict__ gain, uint8_t* __restrict__ target) {
+                                                 double* __restrict__ gain, uint8_t* __restrict__ target,
+                                                 const unsigned long long* __restrict__ prev) {
     __shared__ double cnt[KM][kBlock];   // KM >= K rows
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (i >= g.n) return;
+    if (i >= g.n || no_moves(prev)) return;
     for (int k = 0; k < K; ++k) cnt[k][threadIdx.x] = 0.0;
     double wdeg = 0.0;
     int64_t e = g.row_ptr[i];
@@ -231,14 +248,15 @@ __global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_
     target[i] = (uint8_t)(cand ? bl : a);
 }
 
-constexpr int kMoveLanes = 8;
 
 __global__ __launch_bounds__(kBlock) void k_move(GraphDev g, const uint8_t* __restrict__ z,
                                                  const double* __restrict__ gain,
                                                  const uint8_t* __restrict__ target,
                                                  uint8_t* __restrict__ z_next,
-                                                 unsigned long long* __restrict__ moves) {
+                                                 unsigned long long* __restrict__ moves,
+                                                 const unsigned long long* __restrict__ prev) {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (no_moves(prev)) return;   // uniform over the grid
     bool win = false;
     if (i < g.n) {
         const double gi = gain[i];
@@ -459,14 +477,16 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
         LRQO_HIP(hipMemsetAsync(s.moves, 0, sizeof(unsigned long long) * todo * kMoveLanes, st));
         LRQO_HIP(hipEventRecord(ctx->ev_start, st));
         for (int t = 0; t < todo; ++t) {
+            // the batch runs only after rounds that all moved something
+            const unsigned long long* prev = t ? s.moves + (size_t)(t - 1) * kMoveLanes : nullptr;
             if (K <= 4)
                 hipLaunchKernelGGL(k_gain<4>, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd, s.gain,
-                                   s.target);
+                                   s.target, prev);
             else
                 hipLaunchKernelGGL(k_gain<kMaxKRefine>, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd,
-                                   s.gain, s.target);
+                                   s.gain, s.target, prev);
             hipLaunchKernelGGL(k_move, dim3(blocks), dim3(kBlock), 0, st, gd, zbuf[cur], s.gain, s.target,
-                               zbuf[cur ^ 1], s.moves + (size_t)t * kMoveLanes);
+                               zbuf[cur ^ 1], s.moves + (size_t)t * kMoveLanes, prev);
             cur ^= 1;
         }
         LRQO_HIP(hipGetLastError());
@@ -490,7 +510,10 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
             moves += (int64_t)m;
         }
     }
-    if (cur == 1) LRQO_HIP(hipMemcpyAsync(z, s.zb, (size_t)gd.n, hipMemcpyDeviceToDevice, st));
+    // round t reads labels from buffer t mod 2 and writes the other; rounds
+    // after the first one without moves were skipped, so the result is in
+    // buffer rounds mod 2 (the caller's z is buffer 0)
+    if (rounds % 2 == 1) LRQO_HIP(hipMemcpyAsync(z, s.zb, (size_t)gd.n, hipMemcpyDeviceToDevice, st));
     LRQO_TRY(objective(gd, K, z, s, h.out, st, &r.quad_after, &r.cut_after));
     r.moves = moves;
     r.rounds = (int32_t)rounds;
