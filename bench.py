@@ -359,6 +359,7 @@ def form_samplers():
     out = {"workload": "maxcut_er", "n": inst.n, "K": inst.K, "S": S}
     for r in (2, 4):
         V = np.ascontiguousarray(inst.V[:, :r])
+        real_v = bool(np.all(V.imag == 0))
         Vr = torch.from_numpy(inputs.as_real_f32(V)).cuda()
         Vc = torch.from_numpy(V).cuda()
         lrqo.solve_sampled(Vr, inst.K, S, inst.seed, real=True)       # warm-up (scratch, clocks)
@@ -376,10 +377,12 @@ def form_samplers():
         _, cut_n = lrqo.graph_objective(rpd, cold, None, inst.K, zn)
         out[f"r{r}"] = {"uniform_obj": u.obj, "nullvec_obj": rn.obj,
                         "nullvec_roofline": _alu_roofline(
-                            24.0 * r * inst.n * (rn.index_sets - rn.rank_deficient), rn.device_ms,
-                            "null-vector path: per feasible draw and row, V c once (8r flops, complex V; "
-                            "-c gives -V c) and V^H z for each sign (2 x 8r); the label options of the "
-                            "drawn rows share them"),
+                            (12.0 if real_v else 24.0) * r * inst.n * (rn.index_sets - rn.rank_deficient),
+                            rn.device_ms,
+                            "null-vector path: per feasible draw and row, V c once and V^H z for each sign "
+                            "(-c gives -V c): 4r + 2 x 4r = 12r flops for a real V (the imaginary parts are "
+                            "zero and the row scorer leaves them out), 24r for a complex one; the label "
+                            "options of the drawn rows share them"),
 
                         "uniform_over_nullvec": u.obj / rn.obj,
                         "cut_uniform": cut_u, "cut_nullvec": cut_n,

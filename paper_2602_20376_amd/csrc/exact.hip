@@ -10,7 +10,9 @@
 // recursion), and every candidate is scored with the full factor.
 //
 // Kernels:
-//   k_to_f32        FP32 copy of V for the scorer
+//   k_to_f32        FP32 copy of V for the scorer, and a flag when some
+//                   imaginary part is not zero (the row scorers take real
+//                   arithmetic, half the FMAs, when none is)
 //   k_exact_score   one thread per index set (grid-stride) and row slice:
 //                   colex unranking (or a random draw), FP64 null vector by
 //                   twice-orthogonalised Gram-Schmidt, both signs scored in
@@ -78,6 +80,7 @@ struct ExactParams {
     int64_t rows_per_slice;             // rows of one slice of the split scorer's grid
     float* part;                        // split form: slice sums
     VertexRec* recs;                    // split form: one record per set
+    const int32_t* complex_v;           // nonzero: V has an imaginary part (else real arithmetic)
 };
 
 struct LevelTable {
@@ -99,7 +102,7 @@ struct ExactDevResult {
     int32_t sign;
     int64_t combo;
     int32_t nonfinite;
-    int32_t pad;
+    int32_t complex_v;   // some imaginary part of V is not zero
 };
 
 // ---------------------------------------------------------------- vertex
@@ -309,25 +312,29 @@ __device__ void open_labels(const ExactParams& p, const int64_t (&g)[2 * D - 1],
 // ---------------------------------------------------------------- FP32 scoring
 template <int R>
 __global__ void k_to_f32(const double* __restrict__ V64, float* __restrict__ V32, int64_t count,
-                         int* nonfinite) {
+                         int* nonfinite, int* complex_v) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
          e += (int64_t)gridDim.x * blockDim.x) {
         const double x = V64[e];
         if (!isfinite(x)) *nonfinite = 1;
+        if ((e & 1) && x != 0.0) *complex_v = 1;   // every writer stores the same value
         V32[e] = (float)x;
     }
 }
 
 // Sums conj(V_i) z_i over rows [r0, r1) for both signs +c and -c of a
 // direction (V_i c formed once), skipping the rows of the set (g, sorted,
-// -1 for none): rows in
-// LDS tiles, every lane of a wave reading the same row (broadcast).  All
-// threads of the block take part in the tile loads.
-template <int R, int D, int KS>
+// -1 for none): rows in LDS tiles, every lane of a wave reading the same row
+// (broadcast).  All threads of the block take part in the tile loads.
+// REAL: V has no imaginary part; the tiles hold the real parts only and
+// the terms with Im V are left out (they are exact zeros, so the sums are
+// the same numbers).
+template <int R, int D, int KS, bool REAL>
 __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c)[2 * D],
                                            const int32_t (&g)[2 * D - 1], int64_t r0, int64_t r1,
                                            float* tile, const float2* roots_s, float (&acc)[2][2 * R]) {
     constexpr int M = 2 * D - 1;
+    constexpr int RW = REAL ? R : 2 * R;   // floats per staged row
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -340,13 +347,13 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
         const int cnt = (int)min((int64_t)kTile, r1 - t0);
         __syncthreads();
         const float* __restrict__ src = p.V32 + t0 * 2 * R;
-        for (int e = threadIdx.x; e < cnt * 2 * R; e += kBlock) tile[e] = src[e];
+        for (int e = threadIdx.x; e < cnt * RW; e += kBlock) tile[e] = REAL ? src[2 * e] : src[e];
         __syncthreads();
         for (int i = 0; i < cnt; ++i) {
             const int64_t row = t0 + i;
-            float vv[2 * R];
+            float vv[RW];
 #pragma unroll
-            for (int e = 0; e < 2 * R; ++e) vv[e] = tile[i * 2 * R + e];
+            for (int e = 0; e < RW; ++e) vv[e] = tile[i * RW + e];
             const bool touched = row == next;
             if (touched) {          // rare: advance the cursor
                 int64_t nn = INT64_MAX;
@@ -359,9 +366,14 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
             float wr = 0.0f, wi = 0.0f;
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const float vr = vv[2 * j], vi = vv[2 * j + 1];
-                wr = fmaf(vr, c[2 * j], fmaf(-vi, c[2 * j + 1], wr));
-                wi = fmaf(vr, c[2 * j + 1], fmaf(vi, c[2 * j], wi));
+                if constexpr (REAL) {
+                    wr = fmaf(vv[j], c[2 * j], wr);
+                    wi = fmaf(vv[j], c[2 * j + 1], wi);
+                } else {
+                    const float vr = vv[2 * j], vi = vv[2 * j + 1];
+                    wr = fmaf(vr, c[2 * j], fmaf(-vi, c[2 * j + 1], wr));
+                    wi = fmaf(vr, c[2 * j + 1], fmaf(vi, c[2 * j], wi));
+                }
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
@@ -371,9 +383,14 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
                 zi = touched ? 0.0f : zi;
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    const float vr = vv[2 * j], vi = vv[2 * j + 1];
-                    acc[s][2 * j] = fmaf(vr, zr, fmaf(vi, zi, acc[s][2 * j]));
-                    acc[s][2 * j + 1] = fmaf(vr, zi, fmaf(-vi, zr, acc[s][2 * j + 1]));
+                    if constexpr (REAL) {
+                        acc[s][2 * j] = fmaf(vv[j], zr, acc[s][2 * j]);
+                        acc[s][2 * j + 1] = fmaf(vv[j], zi, acc[s][2 * j + 1]);
+                    } else {
+                        const float vr = vv[2 * j], vi = vv[2 * j + 1];
+                        acc[s][2 * j] = fmaf(vr, zr, fmaf(vi, zi, acc[s][2 * j]));
+                        acc[s][2 * j + 1] = fmaf(vr, zi, fmaf(-vi, zr, acc[s][2 * j + 1]));
+                    }
                 }
             }
         }
@@ -491,6 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
         for (int k = tid; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
     }
     for (int k = tid; k < p.K; k += kBlock) roots_all[k] = p.roots32[k];   // read after the tile barriers
+    const bool cplx = *p.complex_v != 0;   // the same in every thread
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
         const uint64_t rank = base + tid;
@@ -514,7 +532,10 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
 #pragma unroll
         for (int t = 0; t < M; ++t) g32[t] = (int32_t)g[t];
         float acc[2][2 * R];
-        score_rows<R, D, KS>(p, c, g32, 0, p.n, tile, roots_s, acc);
+        if (cplx)
+            score_rows<R, D, KS, false>(p, c, g32, 0, p.n, tile, roots_s, acc);
+        else
+            score_rows<R, D, KS, true>(p, c, g32, 0, p.n, tile, roots_s, acc);
         unsigned long long ncand = 0;
         const float best = ok ? combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand) : 0.0f;
         if (active) p.fbuf[p.offset + rank] = best;
@@ -564,6 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const Vert
     }
     const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
     const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
+    const bool cplx = *p.complex_v != 0;   // the same in every thread
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
         const uint64_t rank = base + threadIdx.x;
@@ -583,7 +605,10 @@ __global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const Vert
             for (int t = 0; t < M; ++t) g[t] = -1;
         }
         float acc[2][2 * R];
-        score_rows<R, D, KS>(p, c, g, r0, r1, tile, roots_s, acc);
+        if (cplx)
+            score_rows<R, D, KS, false>(p, c, g, r0, r1, tile, roots_s, acc);
+        else
+            score_rows<R, D, KS, true>(p, c, g, r0, r1, tile, roots_s, acc);
         if (active) {
 #pragma unroll
             for (int s = 0; s < 2; ++s)
@@ -1155,23 +1180,29 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
 
     const int64_t vcount = n * r * 2;
     int* nonfinite = &dres->nonfinite;
+    int* complex_v = &dres->complex_v;
+    p.complex_v = complex_v;
     const unsigned long long* keys = nullptr;
     lrqo_status s = LRQO_OK;
     switch (r) {
         case 1:
-            hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
+                               complex_v);
             s = run_exact<1>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
         case 2:
-            hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
+                               complex_v);
             s = run_exact<2>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
         case 3:
-            hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
+                               complex_v);
             s = run_exact<3>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
         case 4:
-            hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite);
+            hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
+                               complex_v);
             s = run_exact<4>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
             break;
     }

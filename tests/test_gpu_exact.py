@@ -105,6 +105,20 @@ def test_exact_real_factor(lrqo_mod):
         assert abs(res.obj - opt) <= 1e-12 * opt
 
 
+@pytest.mark.parametrize("n,r,K", [(40, 2, 3), (14, 3, 4), (300, 1, 5)])
+def test_exact_real_and_rotated_factor_agree(lrqo_mod, n, r, K):
+    """A real factor (all imaginary parts zero: the row scorers take real
+    arithmetic) and the same factor times a global phase (complex
+    arithmetic) have the same optimum, since |(e^{it} V)^H z| = |V^H z|."""
+    V = inputs.random_V(n, r, 70 + n, real=True)
+    _, r1 = _solve(lrqo_mod, V, K)
+    _, r2 = _solve(lrqo_mod, V * np.exp(0.7j), K)
+    assert abs(r1.obj - r2.obj) <= 1e-12 * r1.obj
+    if r == 1:   # against Alg. 1, an independent exact algorithm
+        opt = rank1.rank1_sweep(V[:, 0], K)[0]
+        assert abs(r1.obj - opt) <= 1e-12 * opt
+
+
 def test_exact_rank1_long(lrqo_mod):
     """r = 1, n = 3000 against Alg. 1 (independent exact algorithm)."""
     q = inputs.random_V(3000, 1, 31)
