@@ -265,10 +265,12 @@ __global__ __launch_bounds__(kSymT) void k_w_combine(PhaseOp o, const double2* _
 // h_j = q_j^H w for j < k in two fixed-order stages.  Block (b, c) takes
 // rows [b rows, (b + 1) rows) of columns kDotCols c .. kDotCols c + 7 (rows a
 // multiple of 256, sized on the host for at least 256 row chunks up to 4096):
-// each thread sums its rows, the lanes of a wave are added by butterfly and
-// the four waves in order, giving part[j nb + b]; k_part_sum then adds the
-// nb partials of column j (lanes strided, then butterfly).  Q is read once,
-// by as many blocks as there are row chunks times column groups.
+// each thread sums its rows (two rows' loads in flight), the 16 sums of a
+// wave are added by a transposing butterfly (each exchange halves the
+// values a lane holds: 17 shuffles instead of 16 x 6) and the four waves in
+// order, giving part[j nb + b]; k_part_sum then adds the nb partials of
+// column j (lanes strided, then butterfly).  Q is read once, by as many
+// blocks as there are row chunks times column groups.
 constexpr int kDotRowsMax = 4096;
 constexpr int kDotCols = 8;
 
@@ -277,14 +279,38 @@ int dot_rows(int64_t n) {
     return (int)std::min<int64_t>(std::max<int64_t>(rows, 256), kDotRowsMax);
 }
 
+// Wave sums of the 16 values acc[0..15]: at the exchange with lane
+// distance o = 32, 16, 8, 4 a lane keeps one half of its values (the upper
+// one when its bit o is set) and adds its partner's copy of that half; the
+// one value left, index lane / 4, is then summed over the four lanes of the
+// group.  Returns the wave sum of value lane / 4 (the same in those lanes).
+static_assert(2 * kDotCols == 16 && kWave == 64, "the exchange pattern is for 16 values on 64 lanes");
+__device__ __forceinline__ double wave_sums16(double (&v)[16]) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        const int o = 32 >> st, h = 8 >> st;
+        const bool hi = (lane & o) != 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k < h) {
+                const double send = hi ? v[k] : v[k + h];
+                const double keep = hi ? v[k + h] : v[k];
+                v[k] = keep + __shfl_xor(send, o, kWave);
+            }
+        }
+    }
+    double r = v[0];
+    r += __shfl_xor(r, 2, kWave);
+    r += __shfl_xor(r, 1, kWave);
+    return r;
+}
+
 __device__ __forceinline__ void block_sums_to(double (&acc)[2 * kDotCols], int count, double* dst, int64_t stride) {
     __shared__ double red[kBlock / kWave][2 * kDotCols];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-#pragma unroll
-    for (int e = 0; e < 2 * kDotCols; ++e) {
-        const double v = wave_sum_f64(acc[e]);
-        if (lane == 0) red[wv][e] = v;
-    }
+    const double v = wave_sums16(acc);
+    if ((lane & 3) == 0) red[wv][lane >> 2] = v;
     __syncthreads();
     if ((int)threadIdx.x < 2 * count) {
         double v = red[0][threadIdx.x];
@@ -303,7 +329,29 @@ __global__ __launch_bounds__(kBlock) void k_dots_part(const double2* __restrict_
     double acc[2 * kDotCols];
 #pragma unroll
     for (int e = 0; e < 2 * kDotCols; ++e) acc[e] = 0.0;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    int64_t i = i0 + threadIdx.x;
+    // two rows' loads in flight; each column's sum still runs in row order
+    for (; i + kBlock < i1; i += 2 * kBlock) {
+        const double2 wa = w[i], wb = w[i + kBlock];
+        double2 qa[kDotCols], qb[kDotCols];
+#pragma unroll
+        for (int c = 0; c < kDotCols; ++c) {
+            if (c < nc) {
+                qa[c] = Q[(int64_t)(j0 + c) * n + i];
+                qb[c] = Q[(int64_t)(j0 + c) * n + i + kBlock];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kDotCols; ++c) {
+            if (c < nc) {                                            // conj(q) w
+                acc[2 * c] = __builtin_fma(qa[c].y, wa.y, __builtin_fma(qa[c].x, wa.x, acc[2 * c]));
+                acc[2 * c + 1] = __builtin_fma(-qa[c].y, wa.x, __builtin_fma(qa[c].x, wa.y, acc[2 * c + 1]));
+                acc[2 * c] = __builtin_fma(qb[c].y, wb.y, __builtin_fma(qb[c].x, wb.x, acc[2 * c]));
+                acc[2 * c + 1] = __builtin_fma(-qb[c].y, wb.x, __builtin_fma(qb[c].x, wb.y, acc[2 * c + 1]));
+            }
+        }
+    }
+    for (; i < i1; i += kBlock) {
         const double2 wi = w[i];
 #pragma unroll
         for (int c = 0; c < kDotCols; ++c) {
