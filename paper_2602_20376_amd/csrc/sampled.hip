@@ -2,7 +2,9 @@
 // directions, top-T selection, FP64 rescore of the T best, label write-out.
 //
 // Kernels, in launch order:
-//   k_check_finite  flags a NaN/Inf in V
+//   k_prologue      roots of unity and the zeroed result record (block 0);
+//                   per block, whether its share of V holds a NaN or an
+//                   infinity (k_pick gathers the blocks' flags)
 //   k_score         fused candidate generation + scoring (A1, A3-A6): each
 //                   lane owns CPL directions in registers; the block streams
 //                   row tiles of V through LDS (every lane of a wave reads the
@@ -49,27 +51,29 @@ struct Row {
 };
 
 // ------------------------------------------------------------ set-up and checks
-// Roots of unity omega^k = (cos, sin)(2 pi k / K) in FP64 and their FP32
-// roundings; zeroed result record.
-__global__ void k_init(int K, double2* __restrict__ roots64, float2* __restrict__ roots32,
-                       DevResult* __restrict__ res) {
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
-        double sn, cs;
-        sincospi(2.0 * (double)k / (double)K, &sn, &cs);
-        roots64[k] = make_double2(cs, sn);
-        roots32[k] = make_float2((float)cs, (float)sn);
+// Block 0: roots of unity omega^k = (cos, sin)(2 pi k / K) in FP64 and their
+// FP32 roundings, and the zeroed result record.  Every block: whether its
+// share of V holds a NaN or an infinity, into bad[blockIdx.x] (so that no
+// block writes the record while block 0 clears it; k_pick gathers them).
+__global__ __launch_bounds__(kBlock) void k_prologue(int K, double2* __restrict__ roots64,
+                                                     float2* __restrict__ roots32, DevResult* __restrict__ res,
+                                                     const float* __restrict__ V, int64_t count,
+                                                     int* __restrict__ bad) {
+    if (blockIdx.x == 0) {
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            double sn, cs;
+            sincospi(2.0 * (double)k / (double)K, &sn, &cs);
+            roots64[k] = make_double2(cs, sn);
+            roots32[k] = make_float2((float)cs, (float)sn);
+        }
+        if (threadIdx.x == 0) *res = DevResult{};
     }
-    if (threadIdx.x == 0) {
-        *res = DevResult{};
-    }
-}
-
-__global__ void k_check_finite(const float* __restrict__ V, int64_t count, DevResult* res) {
-    bool bad = false;
+    bool b = false;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
          e += (int64_t)gridDim.x * blockDim.x)
-        bad |= !isfinite(V[e]);
-    if (bad) res->nonfinite = 1;
+        b |= !isfinite(V[e]);
+    const int any = __syncthreads_or(b);
+    if (threadIdx.x == 0) bad[blockIdx.x] = any;
 }
 
 // ------------------------------------------------------------ fused scorer
@@ -765,7 +769,8 @@ template <int R>
 __global__ __launch_bounds__(64 * 2 * R) void k_pick(const double* __restrict__ partial, int T, int P,
                                                      const unsigned long long* __restrict__ keys,
                                                      uint64_t seed, uint32_t instance, uint64_t first,
-                                                     const float* dirs, DevResult* res) {
+                                                     const float* dirs, const int* __restrict__ bad, int nbad,
+                                                     DevResult* res) {
     __shared__ double comp[64][2 * R];
     const int t = threadIdx.x / (2 * R), j = threadIdx.x % (2 * R);
     if (t < T) {
@@ -782,7 +787,9 @@ __global__ __launch_bounds__(64 * 2 * R) void k_pick(const double* __restrict__ 
         for (; q < P; ++q) a += src[(size_t)q * (2 * R)];
         comp[t][j] = a;
     }
-    __syncthreads();
+    int b = 0;                                   // the prologue's finiteness flags
+    for (int q = threadIdx.x; q < nbad; q += blockDim.x) b |= bad[q];
+    const int any_bad = __syncthreads_or(b);
     if (threadIdx.x >= kWave) return;
     const int lane = threadIdx.x;
     double f = -1.0;
@@ -813,6 +820,7 @@ __global__ __launch_bounds__(64 * 2 * R) void k_pick(const double* __restrict__ 
     }
     float cf[2 * R];
     direction_any<R>(dirs, seed, first + idx, instance, cf);
+    res->nonfinite = any_bad ? 1 : 0;
     res->best_index = (int64_t)(first + idx);
     res->obj = f;
     res->fp32_obj = (double)key_value(key);
@@ -944,7 +952,7 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     }
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_pick<R>), dim3(1), dim3(64 * 2 * R), 0, st, sc.rescore, T, sc.rescore_slices, keys,
-                       job.seed, job.instance, job.first, job.dirs, sc.result);
+                       job.seed, job.instance, job.first, job.dirs, sc.bad_blocks, kCheckBlocks, sc.result);
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_labels<R, REAL>), dim3((unsigned)((job.n + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, job.V, job.n, job.K, sc.result, job.z);
@@ -995,6 +1003,7 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     cs.add<unsigned long long>(topk_buffer_keys((uint32_t)job.S, plan.topk));
     cs.add<unsigned long long>(slices > 1 ? (size_t)(job.S + kBlock - 1) / kBlock * kBlock : 0);
     cs.add<double>((size_t)plan.topk * plan.rescore_slices * 2 * R);
+    cs.add<int>(kCheckBlocks);
     plan.bytes = cs.bytes;
 }
 
@@ -1017,10 +1026,11 @@ lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void*
     sc.rescore_rows = plan.rescore_rows;
     sc.rescore = cv.take<double>((size_t)plan.topk * plan.rescore_slices * 2 * job.r);
 
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(256), 0, st, job.K, sc.roots64, sc.roots32, sc.result);
+    sc.bad_blocks = cv.take<int>(kCheckBlocks);
 
     const int64_t vcount = job.n * job.r * (job.real ? 1 : 2);
-    hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(256), 0, st, job.V, vcount, sc.result);
+    hipLaunchKernelGGL(k_prologue, dim3(kCheckBlocks), dim3(kBlock), 0, st, job.K, sc.roots64, sc.roots32,
+                       sc.result, job.V, vcount, sc.bad_blocks);
     LRQO_HIP(hipGetLastError());
     return job.real ? dispatch_r<true>(job, sc, st) : dispatch_r<false>(job, sc, st);
 }

@@ -92,7 +92,10 @@ struct Scratch {
     double* rescore;
     int rescore_slices;
     int64_t rescore_rows;
+    int* bad_blocks;            // [kCheckBlocks] finiteness flags of the prologue's blocks
 };
+
+constexpr int kCheckBlocks = 256;   // blocks of the prologue's finiteness check
 
 void plan_sampled(const SampledJob& job, ScratchPlan& plan);
 lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena, hipStream_t st);
