@@ -11,9 +11,10 @@
 //
 // Kernels:
 //   k_r1_prep     per coordinate: phi (same FP64 expression as Alg. 1),
-//                 sortable key, k_0, d, block partials of s_0 and of the
-//                 OR / AND of the keys (digits that never change skip a
-//                 pass), finiteness
+//                 its exact sortable key and 32-bit image, k_0, d, block
+//                 partials of s_0 and of the OR / AND of the keys (digits
+//                 that never change skip a pass of the exact-key sort),
+//                 finiteness
 //   k_r1_reduce0  s_0 and the OR / AND from the block partials
 //   radix sort    stable (sort.hip), first by a 32-bit fixed-point image of
 //                 phi (four passes; it never reverses the order of two
