@@ -508,7 +508,17 @@ __global__ void k_pool(const float* __restrict__ partial, const int32_t* first_i
     const int o = threadIdx.x;
     if (t >= count || o >= H) return;
     float v = 0.0f;
-    for (int it = first_item[t]; it < first_item[t + 1]; ++it) v += partial[(size_t)it * H + o];
+    int it = first_item[t];
+    const int end = first_item[t + 1];
+    // sixteen loads in flight; the additions keep item order
+    for (; it + 16 <= end; it += 16) {
+        float p[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) p[u] = partial[(size_t)(it + u) * H + o];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v += p[u];
+    }
+    for (; it < end; ++it) v += partial[(size_t)it * H + o];
     mvec[(size_t)t * H + o] = v / (float)nrows[t];
 }
 
