@@ -995,6 +995,29 @@ void plan_rows(int count, const int64_t* n, int tile, RowPlan& rp) {
     rp.first[count] = (int32_t)rp.inst.size();
 }
 
+// The host-to-device data of one call in one copy: its pieces are carved one
+// after another, so their device offsets (alignment padding included) lay
+// out one host image of the whole range.
+struct Upload {
+    char* base = nullptr;
+    std::vector<char> img;
+    template <class T>
+    T* take(lrqo::Carve& cv, const T* src, size_t count) {
+        T* d = cv.take<T>(count);
+        if (!base) base = reinterpret_cast<char*>(d);
+        const size_t off = (size_t)(reinterpret_cast<char*>(d) - base), bytes = sizeof(T) * count;
+        if (img.size() < off + bytes) img.resize(off + bytes);
+        if (bytes) std::memcpy(img.data() + off, src, bytes);
+        return d;
+    }
+    lrqo_status send(hipStream_t st) {
+        using namespace lrqo;
+        if (base && !img.empty())
+            LRQO_HIP(hipMemcpyAsync(base, img.data(), img.size(), hipMemcpyHostToDevice, st));
+        return LRQO_OK;
+    }
+};
+
 // Shared by training and inference: frames, pooled embeddings.
 struct FwdBufs {
     int64_t* voff;
@@ -1009,14 +1032,9 @@ struct FwdBufs {
     int fsplits;
 };
 
-lrqo_status run_embed(lrqo_proposal* P, const float* V, int count, const int64_t* hvoff, const int64_t* hn,
-                      const RowPlan& rp, FwdBufs& b, hipStream_t st) {
+// b's descriptors (offsets, sizes, the row plan) are on the device already.
+lrqo_status run_embed(lrqo_proposal* P, const float* V, int count, const RowPlan& rp, FwdBufs& b, hipStream_t st) {
     using namespace lrqo;
-    LRQO_HIP(hipMemcpyAsync(b.voff, hvoff, sizeof(int64_t) * count, hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(b.n, hn, sizeof(int64_t) * count, hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(b.inst, rp.inst.data(), sizeof(int32_t) * rp.inst.size(), hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(b.start, rp.start.data(), sizeof(int64_t) * rp.start.size(), hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(b.first, rp.first.data(), sizeof(int32_t) * rp.first.size(), hipMemcpyHostToDevice, st));
     launch_frames(V, b.voff, b.n, count, b.fsplits, P->K, b.frames, b.fwork, st);
     LRQO_HIP(hipGetLastError());
     RowItems items{b.inst, b.start, (int32_t)rp.inst.size()};
@@ -1114,16 +1132,18 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     plan_rows(count, n, kRowTile, bp);
     constexpr int NG = H * DIN + H + H * H + H;
     CarveSize cs;
+    cs.add<int64_t>(count);                  // uploaded: offsets, sizes,
     cs.add<int64_t>(count);
-    cs.add<int64_t>(count);
-    cs.add<Frame>(count);
-    cs.add<int32_t>(std::max(fp.inst.size(), bp.inst.size()));
-    cs.add<int64_t>(std::max(fp.start.size(), bp.start.size()));
+    cs.add<int32_t>(fp.inst.size());         // forward row plan,
+    cs.add<int64_t>(fp.start.size());
     cs.add<int32_t>(count + 1);
+    cs.add<float>((size_t)count * 6);        // host targets,
+    cs.add<int32_t>(bp.inst.size());         // backward row plan
+    cs.add<int64_t>(bp.start.size());
+    cs.add<Frame>(count);
     cs.add<float>(fp.inst.size() * H);
     cs.add<float>((size_t)count * H);        // m
     cs.add<float>((size_t)count * H);        // dm
-    cs.add<float>((size_t)count * 6);        // host targets
     cs.add<float>((size_t)count * 6);        // canonical targets
     cs.add<float>(count);                    // loss
     cs.add<float>((size_t)count * (OUT * H + OUT));
@@ -1134,16 +1154,19 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     LRQO_TRY(ensure_scratch(P, cs.bytes));
     Carve cv(P->scratch);
     FwdBufs b{};
-    b.voff = cv.take<int64_t>(count);
-    b.n = cv.take<int64_t>(count);
+    Upload up;
+    b.voff = up.take(cv, v_offset, count);
+    b.n = up.take(cv, n, count);
+    b.inst = up.take(cv, fp.inst.data(), fp.inst.size());
+    b.start = up.take(cv, fp.start.data(), fp.start.size());
+    b.first = up.take(cv, fp.first.data(), fp.first.size());
+    float* tin = up.take(cv, targets, (size_t)count * 6);
+    int32_t* inst_b = up.take(cv, bp.inst.data(), bp.inst.size());
+    int64_t* start_b = up.take(cv, bp.start.data(), bp.start.size());
     b.frames = cv.take<Frame>(count);
-    b.inst = cv.take<int32_t>(std::max(fp.inst.size(), bp.inst.size()));
-    b.start = cv.take<int64_t>(std::max(fp.start.size(), bp.start.size()));
-    b.first = cv.take<int32_t>(count + 1);
     b.partial = cv.take<float>(fp.inst.size() * H);
     b.mvec = cv.take<float>((size_t)count * H);
     float* dm = cv.take<float>((size_t)count * H);
-    float* tin = cv.take<float>((size_t)count * 6);
     float* tcan = cv.take<float>((size_t)count * 6);
     float* loss = cv.take<float>(count);
     float* headp = cv.take<float>((size_t)count * (OUT * H + OUT));
@@ -1152,14 +1175,12 @@ lrqo_status lrqo_proposal_train_step(lrqo_proposal* P, const float* V, int32_t c
     b.fwork = cv.take<double>(frame_work(count, fsplits));
     b.fsplits = fsplits;
     hipStream_t st = current_stream();
-    LRQO_TRY(run_embed(P, V, count, v_offset, n, fp, b, st));
-    LRQO_HIP(hipMemcpyAsync(tin, targets, sizeof(float) * count * 6, hipMemcpyHostToDevice, st));
+    LRQO_TRY(up.send(st));
+    LRQO_TRY(run_embed(P, V, count, fp, b, st));
     hipLaunchKernelGGL(k_targets, dim3((count + 255) / 256), dim3(256), 0, st, tin, b.frames, count, tcan);
     hipLaunchKernelGGL(k_head_loss, dim3(count), dim3(kBlock), 0, st, P->theta, b.mvec, tcan, P->K, loss, dm, headp);
     LRQO_HIP(hipGetLastError());
-    LRQO_HIP(hipMemcpyAsync(b.inst, bp.inst.data(), sizeof(int32_t) * bp.inst.size(), hipMemcpyHostToDevice, st));
-    LRQO_HIP(hipMemcpyAsync(b.start, bp.start.data(), sizeof(int64_t) * bp.start.size(), hipMemcpyHostToDevice, st));
-    RowItems items{b.inst, b.start, (int32_t)bp.inst.size()};
+    RowItems items{inst_b, start_b, (int32_t)bp.inst.size()};
     hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)bp.inst.size()), dim3(kBlock), 0, st, V, b.voff, b.n, b.frames,
                        P->theta, dm, items, mlpp);
     LRQO_HIP(hipGetLastError());
@@ -1201,12 +1222,12 @@ lrqo_status lrqo_proposal_sample(lrqo_proposal* P, const float* V, int64_t n, in
     const int64_t zero = 0;
     plan_rows(1, &n, kBlock, fp);
     CarveSize cs;
+    cs.add<int64_t>(1);                      // uploaded: offset, size, row plan
     cs.add<int64_t>(1);
-    cs.add<int64_t>(1);
-    cs.add<Frame>(1);
     cs.add<int32_t>(fp.inst.size());
     cs.add<int64_t>(fp.start.size());
     cs.add<int32_t>(2);
+    cs.add<Frame>(1);
     cs.add<float>(fp.inst.size() * H);
     cs.add<float>(H);
     const int fsplits = frame_splits(1, n);
@@ -1214,18 +1235,20 @@ lrqo_status lrqo_proposal_sample(lrqo_proposal* P, const float* V, int64_t n, in
     LRQO_TRY(ensure_scratch(P, cs.bytes));
     Carve cv(P->scratch);
     FwdBufs b{};
-    b.voff = cv.take<int64_t>(1);
-    b.n = cv.take<int64_t>(1);
+    Upload up;
+    b.voff = up.take(cv, &zero, 1);
+    b.n = up.take(cv, &n, 1);
+    b.inst = up.take(cv, fp.inst.data(), fp.inst.size());
+    b.start = up.take(cv, fp.start.data(), fp.start.size());
+    b.first = up.take(cv, fp.first.data(), fp.first.size());
     b.frames = cv.take<Frame>(1);
-    b.inst = cv.take<int32_t>(fp.inst.size());
-    b.start = cv.take<int64_t>(fp.start.size());
-    b.first = cv.take<int32_t>(2);
     b.partial = cv.take<float>(fp.inst.size() * H);
     b.mvec = cv.take<float>(H);
     b.fwork = cv.take<double>(frame_work(1, fsplits));
     b.fsplits = fsplits;
     hipStream_t st = current_stream();
-    LRQO_TRY(run_embed(P, V, 1, &zero, &n, fp, b, st));
+    LRQO_TRY(up.send(st));
+    LRQO_TRY(run_embed(P, V, 1, fp, b, st));
     const int period = uniform_fraction > 0.0f ? std::max(1, (int)lrintf(1.0f / uniform_fraction)) : 0;
     const unsigned blocks = (unsigned)std::min<int64_t>((S + kBlock - 1) / kBlock, 4096);
     hipLaunchKernelGGL(k_sample, dim3(blocks), dim3(kBlock), 0, st, P->theta, b.mvec, b.frames, S, seed, instance,
