@@ -728,8 +728,8 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
     const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
     const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
     constexpr int RF = Row<R, REAL>::F;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-        const float* row = p.V + i * RF;
+    // one row's FP64 terms, added to acc
+    auto add_row = [&](const float (&row)[RF]) {
         double wr = 0.0, wi = 0.0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
@@ -747,6 +747,23 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
             acc[2 * j] += vr * zr + vi * zi;
             acc[2 * j + 1] += vr * zi - vi * zr;
         }
+    };
+    // four rows' loads in flight; the rows are still added in order
+    int64_t i = r0 + threadIdx.x;
+    for (; i + 3 * kBlock < r1; i += 4 * kBlock) {
+        float rows[4][RF];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e = 0; e < RF; ++e) rows[u][e] = p.V[(i + (int64_t)u * kBlock) * RF + e];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add_row(rows[u]);
+    }
+    for (; i < r1; i += kBlock) {
+        float row[RF];
+#pragma unroll
+        for (int e = 0; e < RF; ++e) row[e] = p.V[i * RF + e];
+        add_row(row);
     }
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
