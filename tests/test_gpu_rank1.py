@@ -101,6 +101,15 @@ def test_rank1_long_close_runs_take_the_exact_sort(lrqo_mod, K):
     assert res.sort_passes > 4
 
 
+@pytest.mark.parametrize("size,exact_sort", [(16, False), (17, True)])
+def test_rank1_run_length_limit(lrqo_mod, size, exact_sort):
+    """The in-place limit: a run of 16 equal images with distinct keys is
+    sorted in place, one of 17 sends the call to the exact-key sort."""
+    q = np.concatenate([_clustered(1, size, 31 + size, 3), inputs.random_V(200, 1, 9)[:, 0]])
+    res = _check(lrqo_mod, q, 3)
+    assert (res.sort_passes > 4) == exact_sort
+
+
 def test_rank1_equals_the_exact_path(lrqo_mod):
     q = inputs.random_V(300, 1, 42)
     z, res = lrqo_mod.solve_rank1(torch.from_numpy(q[:, 0]).cuda(), 3)
