@@ -506,7 +506,7 @@ def main():
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): "
               "the candidate stream shards by index range across GPUs with a single 8-byte "
-              "arg-max exchange, which this build does not run.", file=sys.stderr)
+              "arg-max exchange, which this benchmark does not run.", file=sys.stderr)
         sys.exit(2)
 
     import torch
