@@ -729,23 +729,34 @@ __global__ __launch_bounds__(kBlock) void k_rescore(RescoreParams p) {
     const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
     constexpr int RF = Row<R, REAL>::F;
     // one row's FP64 terms, added to acc
+    // (a real V leaves out the products with Im V: half the FP64 work)
     auto add_row = [&](const float (&row)[RF]) {
         double wr = 0.0, wi = 0.0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const double vr = REAL ? (double)row[j] : (double)row[2 * j];
-            const double vi = REAL ? 0.0 : (double)row[2 * j + 1];
-            wr += vr * c[2 * j] - vi * c[2 * j + 1];
-            wi += vr * c[2 * j + 1] + vi * c[2 * j];
+            if constexpr (REAL) {
+                const double vr = (double)row[j];
+                wr += vr * c[2 * j];
+                wi += vr * c[2 * j + 1];
+            } else {
+                const double vr = (double)row[2 * j], vi = (double)row[2 * j + 1];
+                wr += vr * c[2 * j] - vi * c[2 * j + 1];
+                wi += vr * c[2 * j + 1] + vi * c[2 * j];
+            }
         }
         double zr, zi;
         nearest_root64<KS>(wr, wi, p.K, roots_s, zr, zi);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const double vr = REAL ? (double)row[j] : (double)row[2 * j];
-            const double vi = REAL ? 0.0 : (double)row[2 * j + 1];
-            acc[2 * j] += vr * zr + vi * zi;
-            acc[2 * j + 1] += vr * zi - vi * zr;
+            if constexpr (REAL) {
+                const double vr = (double)row[j];
+                acc[2 * j] += vr * zr;
+                acc[2 * j + 1] += vr * zi;
+            } else {
+                const double vr = (double)row[2 * j], vi = (double)row[2 * j + 1];
+                acc[2 * j] += vr * zr + vi * zi;
+                acc[2 * j + 1] += vr * zi - vi * zr;
+            }
         }
     };
     // four rows' loads in flight; the rows are still added in order
