@@ -297,7 +297,9 @@ typedef struct lrqo_rank1_result {
     double sweep_obj;        /* the chosen cell's value from the sweep's prefix sums */
     int64_t best_cell;       /* 0: assignment at phi = -pi/K; l: after the l-th boundary point */
     float device_ms;
-    int32_t sort_passes;     /* 8-bit radix passes run (digits that differ between keys; one at least) */
+    int32_t sort_passes;     /* 8-bit radix passes run: 4 over 32-bit images of the points, plus
+                                those over the exact 64-bit keys (digits that differ) when a run
+                                of more than 16 equal images holds distinct points */
 } lrqo_rank1_result;
 
 lrqo_status lrqo_solve_rank1(const double* q, int64_t n, int32_t K, uint8_t* z, lrqo_rank1_result* res);
