@@ -218,6 +218,21 @@ def test_nonfinite_is_rejected(lrqo_mod):
         lrqo_mod.solve_sampled(torch.from_numpy(V).cuda(), 3, 100, 1)
 
 
+def test_nonfinite_flag_is_per_call(lrqo_mod):
+    """The prologue's finiteness flags are rewritten by every call: after a
+    factor rejected for an infinity in its last entry, the clean factor gives
+    the same result as before."""
+    V = inputs.random_V(3000, 3, 61).astype(np.complex64)
+    good = lrqo_mod.solve_sampled(torch.from_numpy(V).cuda(), 3, 500, 2)
+    bad = V.copy()
+    bad[-1, -1] = np.inf
+    with pytest.raises(lrqo_mod.LrqoError, match="ENOTFINITE"):
+        lrqo_mod.solve_sampled(torch.from_numpy(bad).cuda(), 3, 500, 2)
+    again = lrqo_mod.solve_sampled(torch.from_numpy(V).cuda(), 3, 500, 2)
+    assert again.obj == good.obj and again.best_index == good.best_index
+    assert torch.equal(again.z, good.z)
+
+
 def test_host_pointer_is_rejected(lrqo_mod):
     import ctypes
 
