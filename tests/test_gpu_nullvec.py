@@ -52,6 +52,20 @@ def test_nullvec_real_factor_statistics(lrqo_mod):
     assert abs(oracle.objective(V, 3, z.cpu().numpy()) - res.obj) <= 1e-12 * res.obj
 
 
+@pytest.mark.parametrize("r", [2, 4])
+def test_nullvec_full_size_statistics(lrqo_mod, r):
+    """The samplers comparison's configuration: the maxcut_er factor
+    (n = 10^5, real, K = 3), its leading r columns, S = 65,536 draws.  The
+    oracle counts the valid and the rank-deficient draws (no scoring at this
+    size); the returned objective is the FP64 value of the returned labels."""
+    inst = inputs.maxcut_er()
+    V = np.ascontiguousarray(inst.V[:, :r])
+    z, res = lrqo_mod.solve_nullvec(torch.from_numpy(V).cuda(), inst.K, inst.S, inst.seed)
+    ref = nullvec.nullvec_sampler(V, inst.K, inst.S, inst.seed, score=False)
+    assert (res.index_sets, res.rank_deficient) == (ref["valid"], ref["rank_deficient"])
+    assert abs(oracle.objective(V, inst.K, z.cpu().numpy()) - res.obj) <= 1e-12 * res.obj
+
+
 def test_nullvec_rejects_bad_arguments(lrqo_mod):
     V = torch.from_numpy(inputs.random_V(10, 2, 1)).cuda()
     with pytest.raises(lrqo_mod.LrqoError, match="S must be"):
