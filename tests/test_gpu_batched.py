@@ -66,7 +66,8 @@ def _check_instance(lrqo_mod, V, K, S, seed, t, obj, best, z, real=False, full=T
         assert abs(obj - ref["best_f"]) <= 1e-5 * ref["best_f"], (t, obj, ref["best_f"])
 
 
-@pytest.mark.parametrize("K,S,real", [(8, 1000, False), (3, 600, True), (16, 257, False)])
+@pytest.mark.parametrize("K,S,real", [(8, 1000, False), (3, 600, True), (16, 257, False),
+                                      (5, 700, False), (2, 300, True), (4, 513, False), (7, 64, True)])
 def test_batched_parity_small(lrqo_mod, K, S, real, tmp_path, monkeypatch):
     monkeypatch.setenv("LRQO_TUNE_CACHE", str(tmp_path / "tune.json"))
     Vs, cat, offs, ns, rs = _small_batch(real=real)
