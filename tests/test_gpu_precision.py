@@ -59,6 +59,7 @@ CASES = [
     (777, 2, 8, 2500, False),
     (513, 3, 16, 2000, False),
     (200, 4, 4, 1024, False),
+    (400, 2, 2, 1000, True),
     (129, 2, 2, 999, True),
 ]
 
