@@ -34,6 +34,10 @@ namespace lrqo {
 namespace {
 
 constexpr int kBlock = 256;
+#ifndef LRQO_REFINE_BLOCK
+#define LRQO_REFINE_BLOCK 512
+#endif
+constexpr int kRefineBlock = LRQO_REFINE_BLOCK;   // threads per block of the gain and move kernels
 constexpr int kMaxKRefine = 16;
 
 enum : int { kBadPtr = 1, kBadCol = 2, kBadWeight = 4, kBadLabel = 8 };
@@ -166,7 +170,7 @@ __device__ __forceinline__ bool no_moves(const unsigned long long* __restrict__ 
 // keep entry order.  Leaves e at the first entry of an incomplete chunk.
 template <int U>
 __device__ __forceinline__ void gain_chunk(const GraphDev& g, const uint8_t* __restrict__ z, int64_t& e,
-                                           int64_t e1, double (*cnt)[kBlock], double& wdeg) {
+                                           int64_t e1, double (*cnt)[kRefineBlock], double& wdeg) {
     for (; e + U <= e1; e += U) {
         int32_t c[U];
         double w[U];
@@ -207,12 +211,12 @@ __device__ __forceinline__ void move_chunk(const GraphDev& g, const double* __re
 // cosd[d] = cos(2 pi d / K).  Gain of moving i from a to b:
 // 2 sum_k c_k (cosd[(a-k) mod K] - cosd[(b-k) mod K]).
 template <int KM>
-__global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_t* __restrict__ z,
+__global__ __launch_bounds__(kRefineBlock) void k_gain(GraphDev g, int K, const uint8_t* __restrict__ z,
                                                  const double* __restrict__ cosd,
                                                  double* __restrict__ gain, uint8_t* __restrict__ target,
                                                  const unsigned long long* __restrict__ prev) {
-    __shared__ double cnt[KM][kBlock];   // KM >= K rows
-    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    __shared__ double cnt[KM][kRefineBlock];   // KM >= K rows
+    const int64_t i = blockIdx.x * (int64_t)kRefineBlock + threadIdx.x;
     if (i >= g.n || no_moves(prev)) return;
     for (int k = 0; k < K; ++k) cnt[k][threadIdx.x] = 0.0;
     double wdeg = 0.0;
@@ -249,13 +253,13 @@ __global__ __launch_bounds__(kBlock) void k_gain(GraphDev g, int K, const uint8_
 }
 
 
-__global__ __launch_bounds__(kBlock) void k_move(GraphDev g, const uint8_t* __restrict__ z,
+__global__ __launch_bounds__(kRefineBlock) void k_move(GraphDev g, const uint8_t* __restrict__ z,
                                                  const double* __restrict__ gain,
                                                  const uint8_t* __restrict__ target,
                                                  uint8_t* __restrict__ z_next,
                                                  unsigned long long* __restrict__ moves,
                                                  const unsigned long long* __restrict__ prev) {
-    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const int64_t i = blockIdx.x * (int64_t)kRefineBlock + threadIdx.x;
     if (no_moves(prev)) return;   // uniform over the grid
     bool win = false;
     if (i < g.n) {
@@ -275,13 +279,13 @@ __global__ __launch_bounds__(kBlock) void k_move(GraphDev g, const uint8_t* __re
     }
     // the block's count into one of kMoveLanes counters (block index mod
     // kMoveLanes), so that same-address atomics stay few
-    __shared__ unsigned int wm[kBlock / kWave];
+    __shared__ unsigned int wm[kRefineBlock / kWave];
     const unsigned long long bal = __ballot(win);
     if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = (unsigned)__popcll(bal);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long b = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) b += wm[w];
+        for (int w = 0; w < kRefineBlock / kWave; ++w) b += wm[w];
         if (b) atomicAdd(&moves[blockIdx.x % kMoveLanes], b);
     }
 }
@@ -465,7 +469,7 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
     lrqo_refine_result r{};
     LRQO_TRY(objective(gd, K, z, s, h.out, st, &r.quad_before, &r.cut_before));
 
-    const unsigned blocks = (unsigned)((gd.n + kBlock - 1) / kBlock);
+    const unsigned blocks = (unsigned)((gd.n + kRefineBlock - 1) / kRefineBlock);
     const double* cosd = s.table + LRQO_MAX_K;
     uint8_t* zbuf[2] = {z, s.zb};
     int cur = 0;
@@ -480,12 +484,12 @@ lrqo_status lrqo_refine_greedy(const lrqo_graph* g, int32_t K, uint8_t* z, const
             // the batch runs only after rounds that all moved something
             const unsigned long long* prev = t ? s.moves + (size_t)(t - 1) * kMoveLanes : nullptr;
             if (K <= 4)
-                hipLaunchKernelGGL(k_gain<4>, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd, s.gain,
+                hipLaunchKernelGGL(k_gain<4>, dim3(blocks), dim3(kRefineBlock), 0, st, gd, K, zbuf[cur], cosd, s.gain,
                                    s.target, prev);
             else
-                hipLaunchKernelGGL(k_gain<kMaxKRefine>, dim3(blocks), dim3(kBlock), 0, st, gd, K, zbuf[cur], cosd,
+                hipLaunchKernelGGL(k_gain<kMaxKRefine>, dim3(blocks), dim3(kRefineBlock), 0, st, gd, K, zbuf[cur], cosd,
                                    s.gain, s.target, prev);
-            hipLaunchKernelGGL(k_move, dim3(blocks), dim3(kBlock), 0, st, gd, zbuf[cur], s.gain, s.target,
+            hipLaunchKernelGGL(k_move, dim3(blocks), dim3(kRefineBlock), 0, st, gd, zbuf[cur], s.gain, s.target,
                                zbuf[cur ^ 1], s.moves + (size_t)t * kMoveLanes, prev);
             cur ^= 1;
         }
