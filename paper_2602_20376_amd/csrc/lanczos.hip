@@ -75,12 +75,42 @@ struct LapOp {
     int64_t n;
 };
 
+// The entries [e, e1) of a row in chunks of U: the U column and weight
+// loads, then the U gathers of x, are issued together; the additions keep
+// entry order.  Leaves e at the first entry of an incomplete chunk.
+template <int U>
+__device__ __forceinline__ void lap_chunk(const LapOp& g, const double2* __restrict__ x, int64_t& e, int64_t e1,
+                                          double& ar, double& ai, double& deg) {
+    for (; e + U <= e1; e += U) {
+        int32_t c[U];
+        double w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = g.col[e + u];
+            w[u] = g.w ? g.w[e + u] : 1.0;
+        }
+        double2 xj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xj[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ar += w[u] * xj[u].x;
+            ai += w[u] * xj[u].y;
+            deg += w[u];
+        }
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_apply_lap(LapOp g, const double2* __restrict__ x, double2* __restrict__ y) {
     const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (i >= g.n) return;
     const double2 xi = x[i];
     double ar = 0.0, ai = 0.0, deg = 0.0;
-    for (int64_t e = g.row_ptr[i]; e < g.row_ptr[i + 1]; ++e) {
+    int64_t e = g.row_ptr[i];
+    const int64_t e1 = g.row_ptr[i + 1];
+    lap_chunk<8>(g, x, e, e1, ar, ai, deg);
+    lap_chunk<4>(g, x, e, e1, ar, ai, deg);
+    for (; e < e1; ++e) {
         const double w = g.w ? g.w[e] : 1.0;
         const double2 xj = x[g.col[e]];
         ar += w * xj.x;
