@@ -65,6 +65,9 @@ def _load():
     lib.oracle_sampled.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, u64, u32, u64, i64,
                                    ctypes.c_int, vp, vp, vp, vp]
     lib.oracle_sampled.restype = ctypes.c_int
+    lib.oracle_score_dirs.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, vp, i64, d, ctypes.c_int,
+                                      vp, vp, vp, vp]
+    lib.oracle_score_dirs.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -164,6 +167,27 @@ def sampled(V, K: int, S: int, seed: int, instance: int = 0, s0: int = 0, nthrea
                                   _ptr(best_s), _ptr(best_f))
     return {"f": f, "margin": m, "best_s": int(best_s[0]), "best_f": float(best_f[0]),
             "threads": int(used)}
+
+
+def score_dirs(V, K: int, dirs, reach: float, nthreads: int = 0) -> dict:
+    """f at each given direction (rows of `dirs`, complex (S, r)) with the
+    interval [lo, hi] holding every labelling that differs from the FP64
+    decision rule only on rows within `reach` (relative to sum_j |V_ij||c_j|)
+    of a decision-boundary line; `nambig` counts those rows."""
+    V = _V64(V)
+    n, r = V.shape
+    D = np.ascontiguousarray(np.asarray(dirs, dtype=np.complex128).reshape(-1, r))
+    S = D.shape[0]
+    dd = np.empty((S, 2 * r), dtype=np.float64)
+    dd[:, 0::2] = D.real
+    dd[:, 1::2] = D.imag
+    f = np.zeros(S)
+    lo = np.zeros(S)
+    hi = np.zeros(S)
+    na = np.zeros(S, dtype=np.int64)
+    used = _load().oracle_score_dirs(_ptr(V), n, r, int(K), _ptr(dd), S, float(reach), int(nthreads),
+                                     _ptr(f), _ptr(lo), _ptr(hi), _ptr(na))
+    return {"f": f, "lo": lo, "hi": hi, "nambig": na, "threads": int(used)}
 
 
 def canonical(z, K: int, real_V: bool = False) -> np.ndarray:

@@ -209,3 +209,104 @@ int oracle_sampled(const double* V, int64_t n, int r, int K, uint64_t seed, uint
     if (!f_out) free(f);
     return used;
 }
+
+/* ------------------------------------------------ near-boundary interval
+ * f at each of `count` given directions (dirs[t*2r + 2j] = Re c_j,
+ * dirs[t*2r + 2j + 1] = Im c_j), with an interval [lo, hi] holding the
+ * objective of every labelling that differs from the FP64 decision rule only
+ * on ambiguous rows.  A row is ambiguous when a label other than its own
+ * borders w_i = V_i c within `reach` times its scale sum_j |V_ij||c_j|:
+ *   - |w_i| <= reach * scale: every label;
+ *   - otherwise each decision-boundary ray pi(2m+1)/K at angle delta < pi/2
+ *     from arg(w_i) whose line lies within |w_i| sin(delta) <= reach * scale
+ *     adds its two neighbouring labels.
+ * Changing ambiguous row a moves s = V^H z by conj(V_a)(z'_a - z_a), of norm
+ * at most D_a = ||V_a|| max |omega^k' - omega^k| over its options, so every
+ * such labelling has ||s|| within ||s_0|| +- sum_a D_a:
+ *   lo = max(0, ||s_0|| - sum D)^2,  hi = (||s_0|| + sum D)^2.
+ * This is a tolerance device for comparing a lower-precision evaluation of
+ * the decision rule (whose rounding can move w_i by a bounded amount) with
+ * the FP64 one; it adds nothing to the method.  Returns the threads used. */
+static double chord(int a, int b, int K) {
+    /* |omega^a - omega^b| = 2 |sin(pi (a - b) / K)| */
+    return 2.0 * fabs(sin(0.5 * TWO_PI * (double)(a - b) / (double)K));
+}
+
+static void score_one_dir(const double* V, int64_t n, int r, int K, const double* c, double reach,
+                          double* f, double* lo, double* hi, int64_t* nambig) {
+    double sr[8] = {0}, si[8] = {0};
+    double spread = 0.0;
+    int64_t na = 0;
+    const double step = TWO_PI / (double)K;
+    for (int64_t i = 0; i < n; ++i) {
+        double wr = 0.0, wi = 0.0, scale = 0.0, vn2 = 0.0;
+        for (int j = 0; j < r; ++j) {
+            const double vr = V[(i * r + j) * 2], vi = V[(i * r + j) * 2 + 1];
+            wr += vr * c[2 * j] - vi * c[2 * j + 1];
+            wi += vr * c[2 * j + 1] + vi * c[2 * j];
+            scale += hypot(vr, vi) * hypot(c[2 * j], c[2 * j + 1]);
+            vn2 += vr * vr + vi * vi;
+        }
+        const int k = oracle_label(wr, wi, K);
+        const double aw = hypot(wr, wi);
+        const double lim = reach * scale;
+        double dmax = 0.0;                 /* largest chord to an open label */
+        if (lim > 0.0 && aw <= lim) {
+            for (int o = 0; o < K; ++o) dmax = fmax(dmax, chord(o, k, K));
+        } else if (lim > 0.0) {
+            const double x = (double)K * atan2(wi, wr) / TWO_PI + 0.5;
+            const double fr = x - floor(x);
+            /* rays below arg(w): between labels k-j-1 and k-j, at fr*step + j*step */
+            for (int j = 0;; ++j) {
+                const double delta = fr * step + (double)j * step;
+                if (delta >= (0.25 * TWO_PI) || aw * sin(delta) > lim) break;
+                dmax = fmax(dmax, chord(((k - j - 1) % K + K) % K, k, K));
+                dmax = fmax(dmax, chord(((k - j) % K + K) % K, k, K));
+            }
+            /* rays above: between labels k+j and k+j+1, at (1-fr)*step + j*step */
+            for (int j = 0;; ++j) {
+                const double delta = (1.0 - fr) * step + (double)j * step;
+                if (delta >= (0.25 * TWO_PI) || aw * sin(delta) > lim) break;
+                dmax = fmax(dmax, chord((k + j) % K, k, K));
+                dmax = fmax(dmax, chord((k + j + 1) % K, k, K));
+            }
+        }
+        if (dmax > 0.0) {
+            ++na;
+            spread += sqrt(vn2) * dmax;
+        }
+        const double ang = TWO_PI * (double)k / (double)K;
+        const double zr = cos(ang), zi = sin(ang);
+        for (int j = 0; j < r; ++j) {
+            const double vr = V[(i * r + j) * 2], vi = V[(i * r + j) * 2 + 1];
+            sr[j] += vr * zr + vi * zi;
+            si[j] += vr * zi - vi * zr;
+        }
+    }
+    double ff = 0.0;
+    for (int j = 0; j < r; ++j) ff += sr[j] * sr[j] + si[j] * si[j];
+    const double ns = sqrt(ff);
+    const double a = ns - spread > 0.0 ? ns - spread : 0.0;
+    *f = ff;
+    *lo = spread > 0.0 ? a * a : ff;
+    *hi = spread > 0.0 ? (ns + spread) * (ns + spread) : ff;
+    *nambig = na;
+}
+
+int oracle_score_dirs(const double* V, int64_t n, int r, int K, const double* dirs, int64_t count,
+                      double reach, int nthreads, double* f_out, double* lo_out, double* hi_out,
+                      int64_t* nambig_out) {
+    int used = 1;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+    for (int64_t t = 0; t < count; ++t) {
+        score_one_dir(V, n, r, K, dirs + t * 2 * r, reach, &f_out[t], &lo_out[t], &hi_out[t],
+                      &nambig_out[t]);
+#ifdef _OPENMP
+        if (t == 0) used = omp_get_num_threads();
+#endif
+    }
+    return used;
+}

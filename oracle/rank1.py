@@ -1,57 +1,98 @@
-"""Alg. 1: exact rank-1 sweep (Sec. 2.5, Thm. rank1).  Test infrastructure only.
+"""Exact rank-1 maximisation (Sec. 2.5, Alg. 1, Thm. rank1).  Test
+infrastructure only.
 
-For Q = q q^H the optimum is reached in one of the n+1 cells of the sweep of
-the auxiliary angle phi over (-pi/K, pi/K]: start from k = floor(K theta/2pi)
-(the assignment at phi = -pi/K) and advance one coordinate by one label at
-each boundary point phi_i = (2pi/K)(1/2 + floor(K theta_i/2pi) - K theta_i/2pi),
-taken in sorted order.
+For V = q (one column) the objective is |sum_i conj(q_i) z_i|^2.  Rotating the
+direction c = e^{i phi} moves every w_i = q_i e^{i phi} by the same angle, and
+the decision rule changes the label of coordinate i exactly when
+arg(q_i) + phi crosses a boundary pi(2m+1)/K.  Inside the window
+phi in (-pi/K, pi/K] (one label step; a wider window only rotates every
+label, Lemma phase_equiv) each coordinate crosses exactly one boundary, at
+
+    phi_i = (2 pi / K) (1/2 + floor(x_i) - x_i),   x_i = K arg(q_i) / (2 pi),
+
+where its label advances from floor(x_i) to floor(x_i) + 1 (mod K).  The
+window is thus cut into at most n + 1 cells on which the labels are constant,
+and Thm. rank1 says the optimum is the labelling of one of them.
+
+Two forms, each checked against the other and against brute force:
+
+* ``rank1_cells_direct`` is the definition: one representative angle inside
+  each cell, the decision rule applied there, the objective summed from the
+  labels (O(n^2), small n only).
+* ``rank1_cells`` takes the cells in boundary order and forms every cell's
+  sum V^H z from the first cell's by cumulative sums of the label steps
+  (O(n log n)); ``rank1_sweep`` returns its best cell (ties to the earlier
+  cell).  These are the references of the GPU sweep.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def rank1_sweep(q: np.ndarray, K: int):
-    """(OPT, labels) of max |z^H q|^2 over z in A_K^n, by Alg. 1."""
+def _roots(K: int) -> np.ndarray:
+    return np.exp(2j * np.pi * np.arange(K) / K)
+
+
+def boundary_points(q: np.ndarray, K: int):
+    """(phi, start labels): phi_i as above, and floor(x_i) mod K, the label of
+    coordinate i at the left end phi = -pi/K of the window."""
     q = np.asarray(q, dtype=np.complex128).ravel()
-    n = q.size
-    theta = np.angle(q)                                    # (-pi, pi]
-    x = K * theta / (2.0 * np.pi)
-    phi = (2.0 * np.pi / K) * (0.5 + np.floor(x) - x)     # boundary points
-    order = np.argsort(phi, kind="stable")
-    k = np.mod(np.floor(x).astype(np.int64), K)
-    roots = np.exp(2j * np.pi * np.arange(K) / K)
-    s = np.sum(np.conj(q) * roots[k])                      # z^H q conjugated: sum conj(q_i) z_i
-    best, best_k = abs(s) ** 2, k.copy()
-    for i in order:
-        new = (k[i] + 1) % K
-        s += np.conj(q[i]) * (roots[new] - roots[k[i]])
-        k[i] = new
-        f = abs(s) ** 2
-        if f > best:
-            best, best_k = f, k.copy()
-    return float(best), best_k.astype(np.uint8)
+    x = K * np.angle(q) / (2.0 * np.pi)
+    fl = np.floor(x)
+    phi = (2.0 * np.pi / K) * (0.5 + fl - x)
+    return phi, np.mod(fl.astype(np.int64), K)
 
 
 def rank1_cells(q: np.ndarray, K: int):
-    """Objective of every cell of the sweep, in sweep order: f[0] is the
-    assignment at phi = -pi/K, f[l] the one after the l-th boundary point.
-    Returns (f, order, k0) with `order` the stable argsort of the boundary
-    points and k0 the starting labels."""
+    """Objective of every cell, in boundary order: f[0] is the labelling at
+    phi = -pi/K, f[l] the one after the l-th boundary point (equal points in
+    coordinate order).  Returns (f, order, k0): the stable order of the
+    boundary points and the start labels."""
     q = np.asarray(q, dtype=np.complex128).ravel()
-    theta = np.angle(q)
-    x = K * theta / (2.0 * np.pi)
-    phi = (2.0 * np.pi / K) * (0.5 + np.floor(x) - x)
+    phi, k0 = boundary_points(q, K)
     order = np.argsort(phi, kind="stable")
-    k0 = np.mod(np.floor(x).astype(np.int64), K)
-    roots = np.exp(2j * np.pi * np.arange(K) / K)
-    k = k0.copy()
-    s = np.sum(np.conj(q) * roots[k])
-    f = np.empty(q.size + 1)
-    f[0] = abs(s) ** 2
-    for l, i in enumerate(order, start=1):
-        new = (k[i] + 1) % K
-        s += np.conj(q[i]) * (roots[new] - roots[k[i]])
-        k[i] = new
-        f[l] = abs(s) ** 2
-    return f, order, k0
+    w = _roots(K)
+    # crossing the point of coordinate i changes z_i from w[k0] to w[k0 + 1]
+    step = np.conj(q[order]) * (w[(k0[order] + 1) % K] - w[k0[order]])
+    s = np.empty(q.size + 1, dtype=np.complex128)
+    s[0] = np.sum(np.conj(q) * w[k0])
+    s[1:] = s[0] + np.cumsum(step)
+    return np.abs(s) ** 2, order, k0
+
+
+def cell_labels(k0: np.ndarray, order: np.ndarray, l: int, K: int) -> np.ndarray:
+    """Labels of cell l: the start labels with the first l coordinates of the
+    boundary order advanced by one."""
+    k = np.array(k0, dtype=np.int64)
+    k[order[:l]] = (k[order[:l]] + 1) % K
+    return k.astype(np.uint8)
+
+
+def rank1_sweep(q: np.ndarray, K: int):
+    """(OPT, labels): the best cell of rank1_cells, ties to the earlier cell."""
+    f, order, k0 = rank1_cells(q, K)
+    l = int(np.argmax(f))
+    return float(f[l]), cell_labels(k0, order, l, K)
+
+
+def rank1_cells_direct(q: np.ndarray, K: int):
+    """The definition, cell by cell: for the sorted distinct boundary points
+    p_1 < ... < p_m, one angle inside each cell (the midpoints, and for the
+    cell that wraps around the window end the midpoint of (p_m, p_1 + 2pi/K),
+    taken modulo the window); labels from the decision rule at
+    w = q e^{i phi}; objective |sum conj(q_i) z_i|^2 summed directly.
+    Returns (f, labels) with one row per cell."""
+    q = np.asarray(q, dtype=np.complex128).ravel()
+    phi, _ = boundary_points(q, K)
+    p = np.unique(phi)
+    width = 2.0 * np.pi / K
+    mids = list(0.5 * (p[:-1] + p[1:])) + [0.5 * (p[-1] + p[0] + width)]
+    w = _roots(K)
+    fs, zs = [], []
+    for a in mids:
+        wi = q * np.exp(1j * a)
+        k = np.mod(np.floor(K * np.angle(wi) / (2.0 * np.pi) + 0.5).astype(np.int64), K)
+        k[wi == 0] = 0
+        fs.append(abs(np.sum(np.conj(q) * w[k])) ** 2)
+        zs.append(k.astype(np.uint8))
+    return np.array(fs), np.array(zs)
