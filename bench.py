@@ -1,16 +1,20 @@
 #!/usr/bin/env python
 """Throughput of the sampled low-rank K-ary quadratic maximizer on one MI355X.
 
-Workload: Max-3-Cut on an Erdos-Renyi graph, n = 100,000, mean degree 10;
-V = top-4 Laplacian eigenvectors scaled by sqrt(eigenvalue) (FP64 Lanczos,
-stored FP32, real); K = 3; S = 65,536 uniform sphere directions.  One step is
-one full solve through the C-ABI: direction generation, fused FP32 scoring,
-top-64 selection, FP64 rescore, label write-out (inputs resident in HBM).
+Headline workload (the largest single-GPU configuration): Max-3-Cut on a
+3-block planted-partition graph, n = 1,000,000, p_in = 8/n, p_out = 2/n;
+V = top-3 Laplacian eigenvectors scaled by sqrt(eigenvalue) (FP64 Lanczos,
+stored FP32, real); K = 3; S = 2^20 uniform sphere directions; FP32 scorer.
+One step is one full solve through the C-ABI: direction generation, fused
+FP32 scoring, top-64 selection, FP64 rescore, label write-out (inputs
+resident in HBM).
 
 Prints one JSON line.  `value` is candidate-rows scored per second
 (n * S / seconds per step).  `roofline` covers the fused scoring kernel,
 timed live with HIP events on the library's stream; `cpu_baseline` is the
-FP64 CPU oracle on a bounded prefix of the same direction stream.
+FP64 CPU oracle on a bounded prefix of the same direction stream.  The other
+forms (the Erdos-Renyi workload, precision, batched, exact, learned proposal
+and the steps before and after the path) are measured under `forms`.
 """
 from __future__ import annotations
 
@@ -25,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 HBM_PEAK_GBPS = 8000.0            # MI355X published HBM3E bandwidth
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_maxcut_er.json")
+TRAFFIC_FILES = {"maxcut_ppm": os.path.join(ROOT, "profiles", "traffic_maxcut_ppm.json"),
+                 "maxcut_er": os.path.join(ROOT, "profiles", "traffic_maxcut_er.json")}
 
 
 def parse():
@@ -41,12 +46,25 @@ def parse():
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
     ap.add_argument("--form", choices=("exact", "precision_bf16", "batched", "learned_proposal", "refine",
-                                       "rank1_hybrid", "samplers", "spectral"),
+                                       "rank1_hybrid", "samplers", "spectral", "plain_maxcut_er"),
                     help="measure only this form and print its record (for profiling)")
+    ap.add_argument("--workload", choices=("maxcut_ppm", "maxcut_er"), default="maxcut_ppm",
+                    help="workload of the headline line (default: the planted partition)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-sized float32 device tensor once before timing "
                          "(a known-size kernel for scaling memory counters)")
     return ap.parse_args()
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(inst, seconds: float):
@@ -55,7 +73,7 @@ def cpu_baseline(inst, seconds: float):
     import oracle
 
     oracle.build()
-    probe = 64
+    probe = 16
     t = time.perf_counter()
     oracle.sampled(inst.V, inst.K, probe, inst.seed, want_f=False)
     dt = max(time.perf_counter() - t, 1e-3)
@@ -64,7 +82,7 @@ def cpu_baseline(inst, seconds: float):
     res = oracle.sampled(inst.V, inst.K, count, inst.seed, want_f=False)
     dt = time.perf_counter() - t
     return {"value": count * inst.n / dt, "unit": "candidate-rows/s", "cores": res["threads"],
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"first {count} of the {inst.S} directions (same stream, FP64, "
                       f"{res['threads']} threads, {dt:.1f} s)"}
 
@@ -87,10 +105,11 @@ def _hbm_roofline(nbytes: float, ms: float, what: str) -> dict:
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "algorithmic_bytes": nbytes, "ms": ms, "what": what}
 
 
-def load_traffic(kernel: str):
-    if not os.path.exists(TRAFFIC_FILE):
+def load_traffic(kernel: str, workload: str):
+    path = TRAFFIC_FILES.get(workload)
+    if not path or not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel") != kernel or rec.get("source_hash") != _source_hash():
         return None
@@ -101,7 +120,7 @@ def _source_hash() -> str:
     import hashlib
 
     h = hashlib.sha1()
-    for f in ("sampled.hip", "lrqo_device.h", "sampled_internal.h"):
+    for f in ("sampled.hip", "sampled_kernels.h", "lrqo_device.h", "sampled_internal.h"):
         with open(os.path.join(ROOT, "paper_2602_20376_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
@@ -500,6 +519,60 @@ def form_learned(train_count):
             **{k: round(v, 2) for k, v in phases.items()}}
 
 
+def measure_headline(inst, workload: str, steps: int, warmup: int) -> dict:
+    """Whole solves of the sampled FP32 path on `inst`: `warmup` untimed, then
+    `steps` timed between device synchronisations; the scorer's own time from
+    the library's stream events."""
+    import torch
+
+    from paper_2602_20376_amd import inputs, lrqo
+
+    n, r, K, S = inst.n, inst.r, inst.K, inst.S
+    V = torch.from_numpy(inputs.as_real_f32(inst.V)).cuda()
+    z = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        lrqo.solve_sampled(V, K, S, inst.seed, real=True, z=z)
+    torch.cuda.synchronize()
+    score_ms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = lrqo.solve_sampled(V, K, S, inst.seed, real=True, z=z)
+        score_ms.append(out.score_ms)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / steps
+    value = n * S / (ms_per_step / 1000.0)
+    flops_per_rowcand = 8 * r                      # real V: 2r FMA for V c, 2r FMA for V^H z
+    flops = flops_per_rowcand * n * S
+    avg_score_ms = sum(score_ms) / len(score_ms)
+    achieved = flops / (avg_score_ms / 1000.0) / 1e12
+    kernel = f"k_score_rows<{r}, 4, true, {K if K in (2, 3, 4, 8, 16) else 0}, false>"
+    rows_at_peak = FP32_VECTOR_PEAK_TFLOPS * 1e12 / flops_per_rowcand
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": load_traffic(kernel, workload), "kernel": kernel,
+                "kernel_ms": round(avg_score_ms, 4),
+                "algorithmic_flops_per_launch": flops,
+                "candidate_rows_per_s_at_peak": rows_at_peak,
+                "end_to_end_frac": round(value / rows_at_peak, 4)}
+    data = ("synthetic (seeded 3-block planted-partition graph Laplacian, FP64 Lanczos factor stored FP32)"
+            if workload == "maxcut_ppm" else
+            "synthetic (seeded ER graph Laplacian, FP64 Lanczos factor stored FP32)")
+    return {"value": value, "unit": "candidate-rows/s", "ms_per_step": ms_per_step, "data": data,
+            "config": {"workload": workload, "n": n, "r": r, "K": K, "S": S,
+                       "real_V": True, "rescore_topk": 64, "parallelism": "single GPU"},
+            "obj": out.obj, "best_index": out.best_index, "roofline": roofline}
+
+
+def form_plain_maxcut_er():
+    """The plain sampled path on the Erdos-Renyi Max-3-Cut workload
+    (n = 100,000, r = 4, K = 3, S = 65,536): 20 solves after 3 warm-up."""
+    from paper_2602_20376_amd import inputs
+
+    rec = measure_headline(inputs.maxcut_er(), "maxcut_er", 20, 3)
+    return rec
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -515,17 +588,14 @@ def main():
 
     if args.form:
         fn = {"precision_bf16": form_precision, "batched": form_batched, "exact": form_exact, "refine": form_refine,
+              "plain_maxcut_er": form_plain_maxcut_er,
               "rank1_hybrid": form_rank1_hybrid, "samplers": form_samplers, "spectral": form_spectral,
               "learned_proposal": lambda: form_learned(args.train_count)}[args.form]
         print(json.dumps({"form": args.form, **fn()}), flush=True)
         return
 
-    inst = inputs.maxcut_er()
-    n, r, K, S = inst.n, inst.r, inst.K, inst.S
-    V = torch.from_numpy(inputs.as_real_f32(inst.V)).cuda()
-    z = torch.empty(n, dtype=torch.uint8, device="cuda")
+    inst = inputs.maxcut_ppm() if args.workload == "maxcut_ppm" else inputs.maxcut_er()
     lrqo.load()
-
     if args.copy_calibration:
         nel = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(nel, dtype=torch.float32, device="cuda")
@@ -533,47 +603,17 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    for _ in range(args.warmup):
-        lrqo.solve_sampled(V, K, S, inst.seed, real=True, z=z)
-    torch.cuda.synchronize()
-    score_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = lrqo.solve_sampled(V, K, S, inst.seed, real=True, z=z)
-        score_ms.append(out.score_ms)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    value = n * S / (ms_per_step / 1000.0)
-    flops_per_rowcand = 8 * r                      # real V: 2r FMA for V c, 2r FMA for V^H z
-    flops = flops_per_rowcand * n * S
-    avg_score_ms = sum(score_ms) / len(score_ms)
-    achieved = flops / (avg_score_ms / 1000.0) / 1e12
-    kernel = f"k_score_rows<{r}, 4, true, {K if K in (2, 3, 4, 8, 16) else 0}>"
-    rows_at_peak = FP32_VECTOR_PEAK_TFLOPS * 1e12 / flops_per_rowcand
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": load_traffic(kernel), "kernel": kernel,
-                "kernel_ms": round(avg_score_ms, 4),
-                "algorithmic_flops_per_launch": flops,
-                "candidate_rows_per_s_at_peak": rows_at_peak,
-                "end_to_end_frac": round(value / rows_at_peak, 4)}
-
-    rec = {"metric": "candidate-rows scored/s", "value": value, "unit": "candidate-rows/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic (seeded ER graph Laplacian, FP64 Lanczos factor stored FP32)",
-           "config": {"workload": "maxcut_er", "n": n, "r": r, "K": K, "S": S,
-                      "real_V": True, "rescore_topk": 64, "parallelism": "single GPU"},
-           "obj": out.obj, "best_index": out.best_index,
-           "roofline": roofline}
+    head = measure_headline(inst, args.workload, args.steps, args.warmup)
+    rec = {"metric": "candidate-rows scored/s", "value": head.pop("value"), "unit": head.pop("unit"),
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": head.pop("data"), "config": head.pop("config"), **head}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(inst, args.cpu_seconds)
     if not args.no_forms:
         forms = {}
-        for name, fn in (("exact", form_exact), ("precision_bf16", form_precision), ("batched", form_batched),
+        for name, fn in (("plain_maxcut_er", form_plain_maxcut_er), ("exact", form_exact),
+                         ("precision_bf16", form_precision), ("batched", form_batched),
                          ("refine", form_refine), ("rank1_hybrid", form_rank1_hybrid),
                          ("samplers", form_samplers), ("spectral", form_spectral),
                          ("learned_proposal", lambda: form_learned(args.train_count))):

@@ -41,7 +41,9 @@ typedef enum lrqo_status {
     LRQO_ENOMEM = -2,     /* device scratch could not be allocated */
     LRQO_EDEVICE = -3,    /* a HIP runtime call failed (message says which) */
     LRQO_ETOOBIG = -4,    /* exact enumeration larger than the cap */
-    LRQO_ENOTFINITE = -5  /* V holds a NaN or an infinity */
+    LRQO_ENOTFINITE = -5, /* V holds a NaN or an infinity */
+    LRQO_EDEGENERATE = -6 /* warning only, never returned: reported in
+                             lrqo_exact_result.warning */
 } lrqo_status;
 
 #define LRQO_MAX_R 8
@@ -103,6 +105,15 @@ typedef struct lrqo_sampled_options {
     const float* directions; /* optional device [S][2r]: unit directions to score in
                                 place of the stream ((re, im) pairs, FP32); then
                                 first_index must be 0 and best_index indexes this list */
+    /* Inspection outputs (each may be NULL / 0; they do not change the result): */
+    float* dirs_out;         /* optional device [S][2r]: the FP32 direction each candidate
+                                was scored with, (re, im) pairs */
+    int32_t probe_count;     /* 0..64 candidates whose per-row labels the scorer writes */
+    int32_t probe_pad;
+    const int64_t* probe;    /* host [probe_count]: their positions 0..S-1 in this call */
+    uint16_t* probe_labels;  /* device [probe_count][n]: the scorer's label of row i for
+                                probe t at [t*n + i], | 0x100 when the precision form
+                                recomputed that row in FP32 */
 } lrqo_sampled_options;
 
 typedef struct lrqo_sampled_result {
@@ -126,6 +137,25 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
                                   uint64_t seed, const lrqo_sampled_options* opt, uint8_t* z,
                                   lrqo_sampled_result* res);
 
+/* Allocation-free form of lrqo_solve_sampled_ex, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, semantics and results, but the library's
+ * scratch (result record, roots, scores, slice sums, selection and rescore
+ * buffers) lives in a static device array of LRQO_NOALLOC_SCRATCH_BYTES,
+ * one per GPU, held until the process ends; the call allocates no device or
+ * host memory.  A call whose scratch would exceed the array returns
+ * LRQO_ETOOBIG before any device work (S up to 2^20 fits at any n for r <= 4
+ * when the scorer needs one row slice, S = 65,536 with eight slices).  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several host threads or streams) race, so callers serialise them.  The
+ * array keeps the last call's contents; each call rewrites everything it
+ * reads (the result record and the flag counter are cleared first). */
+#define LRQO_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+lrqo_status lrqo_solve_sampled_noalloc(const float* V, int64_t n, int32_t r, int32_t K, int64_t S,
+                                       uint64_t seed, const lrqo_sampled_options* opt, uint8_t* z,
+                                       lrqo_sampled_result* res);
+
 /* --------------------------------------------------------------------------
  * Exact maximisation by arrangement-vertex enumeration (Sec. 3, Alg. 2,
  * Thm. rankr).
@@ -133,18 +163,31 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
  * Builds the augmented real rows a_{i,m} = [Im(rho_m V_i), Re(rho_m V_i)],
  * rho_m = exp(-i pi (2m+1)/K), m < B_K (eq. tildeV, Def. BK), enumerates every
  * set of 2d-1 rows with at most two per coordinate (d = r, r-1, ..., 1, the
- * recursion of Alg. 2 on the leading d columns), solves the FP64 null vector
- * of each full-rank set (rank test sigma ratio > 1e-10 in the pivots of a
- * fully pivoted elimination), takes both signs, labels untouched rows by the
- * decision rule and tries, for coordinates in the set, both labels beside the
- * boundary (one row in the set) or all K labels (two rows: V_i c = 0,
- * Cor. two_implies_all).  Candidates are scored in FP32; the best 64 are
- * rescored in FP64 and the FP64 maximum is returned.
+ * recursion of Alg. 2 on the leading d columns) in colex order within each
+ * level, solves the FP64 null vector of each set (twice-orthogonalised
+ * Gram-Schmidt; the set is full rank when its smallest residual exceeds
+ * 1e-10 times its largest row norm), takes both signs, labels untouched rows
+ * by the decision rule and tries, for coordinates in the set, both labels
+ * beside the boundary (one row in the set) or all K labels (two rows:
+ * V_i c = 0, Cor. two_implies_all).  Candidates are scored in FP32; the sets
+ * are taken in chunks, and after each chunk its best sets join a shortlist of
+ * the 64 best distinct FP32 scores (equal scores keep the set with the lowest
+ * global index: every vertex of one cell gives the same score, and keeping
+ * one of them leaves room for other assignments).  The shortlist is rescored
+ * in FP64 and the FP64 maximum is returned (ties to the lower set index).
  *
  * V (device): n x r complex128, interleaved (re, im), row-major.
  * z (device): n uint8 labels.  obj (host): FP64 objective.
- * Ranges: 1 <= r <= 4, r <= n, 2 <= K <= 255; the number of index sets
- * C(n B_K, 2r-1) must not exceed max_sets (default 2^34) or LRQO_ETOOBIG.
+ * Ranges: 1 <= r <= 4, r <= n <= 2^31 - 1, 2 <= K <= 255, at most 2^20
+ * label combinations per vertex (2^(2r-1-2p) K^p); the number of index sets
+ * sum_d C(n B_K, 2d-1) must not exceed the cap: max_sets when positive, 2^34
+ * when 0, and 2^62 when negative (the cap lifted); otherwise LRQO_ETOOBIG
+ * before any device work.  Set indices are 64-bit.
+ * Environment (inspection only, the result does not depend on them):
+ * LRQO_EXACT_CHUNK sets per chunk (default 2^26); LRQO_EXACT_FORM=fused
+ * scores every set in one pass over all rows (the form otherwise used when
+ * a chunk's per-set buffers exceed 128 MB) instead of the vertex / row-slice
+ * / combine split.
  * ------------------------------------------------------------------------ */
 
 typedef struct lrqo_exact_result {
@@ -153,12 +196,15 @@ typedef struct lrqo_exact_result {
     int64_t rank_deficient;  /* sets rejected by the rank test */
     int64_t candidates;      /* scored label vectors */
     float device_ms;
+    int32_t warning;         /* LRQO_OK, or LRQO_EDEGENERATE when some valid set was rank
+                                deficient: V is not in general position (Assumption 1);
+                                the result is still the best candidate found */
 } lrqo_exact_result;
 
 lrqo_status lrqo_solve_exact(const double* V, int64_t n, int32_t r, int32_t K, uint8_t* z,
                              double* obj);
 
-/* max_sets <= 0 means the default cap; res (host) may be NULL. */
+/* max_sets: the cap above; res (host) may be NULL. */
 lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K,
                                 int64_t max_sets, uint8_t* z, lrqo_exact_result* res);
 
@@ -172,7 +218,7 @@ lrqo_status lrqo_solve_exact_ex(const double* V, int64_t n, int32_t r, int32_t K
  * row j = (2^32 w[2j+1] + w[2j]) mod N, w[4b+t] = word t of Philox4x32-10
  * with key (seed & 0xffffffff, seed >> 32) and counter (s & 0xffffffff,
  * s >> 32, 0x4E554C4C, b); the set is the sorted rows.  Same layouts and
- * limits as lrqo_solve_exact_ex except n B_K (any) and 1 <= S <= 2^31 - 1.
+ * limits as lrqo_solve_exact_ex except the cap and 1 <= S <= 2^31 - 1.
  * res->index_sets counts draws with distinct rows and at most two per
  * coordinate, res->rank_deficient those of them that fail the rank test.
  * No feasible draw returns LRQO_EINVAL. */

@@ -83,3 +83,59 @@ def top_factor(M: np.ndarray, r: int):
     lam, U = lam[::-1][:r], U[:, ::-1][:, :r]
     U = np.stack([fix_phase(U[:, k].astype(np.complex128)) for k in range(r)], axis=1)
     return lam, U * np.sqrt(np.maximum(lam, 0.0))[None, :]
+
+
+# ------------------------------------------------ rows of W, vectorised
+# The same definition as w_entry, evaluated for a whole row with Philox in
+# numpy (64-bit products of 32-bit words), so that rows of Q = U U^H + sigma W
+# can be formed at n ~ 10^5 - 10^6 on the host.
+
+_M0, _M1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+_W0, _W1 = np.uint32(0x9E3779B9), np.uint32(0xBB67AE85)
+
+
+def philox_np(c0, c1, c2, c3, k0: int, k1: int):
+    """Philox4x32-10 on arrays of counters (uint32), one key."""
+    x0, x1, x2, x3 = (np.asarray(c, dtype=np.uint32).copy() for c in (c0, c1, c2, c3))
+    ka, kb = np.uint32(k0), np.uint32(k1)
+    mask = np.uint64(0xFFFFFFFF)
+    for rnd in range(10):
+        if rnd > 0:
+            ka = np.uint32((int(ka) + int(_W0)) & 0xFFFFFFFF)
+            kb = np.uint32((int(kb) + int(_W1)) & 0xFFFFFFFF)
+        p0 = _M0 * x0.astype(np.uint64)
+        p1 = _M1 * x2.astype(np.uint64)
+        hi0, lo0 = (p0 >> np.uint64(32)).astype(np.uint32), (p0 & mask).astype(np.uint32)
+        hi1, lo1 = (p1 >> np.uint64(32)).astype(np.uint32), (p1 & mask).astype(np.uint32)
+        x0, x1, x2, x3 = hi1 ^ x1 ^ ka, lo1, hi0 ^ x3 ^ kb, lo0
+    return x0, x1, x2, x3
+
+
+def w_row(seed: int, i: int, n: int) -> np.ndarray:
+    """Row i of W (n entries) by the definition of w_entry."""
+    j = np.arange(n, dtype=np.int64)
+    lo = np.minimum(i, j)               # the generating pair is (min, max)
+    hi = np.maximum(i, j)
+    o = philox_np(lo.astype(np.uint32), (hi >> 1).astype(np.uint32), np.full(n, W_STREAM, np.uint32),
+                  np.zeros(n, np.uint32), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    odd = (hi & 1).astype(bool)
+    w0 = np.where(odd, o[2], o[0])
+    w1 = np.where(odd, o[3], o[1])
+    u0 = ((w0 >> np.uint32(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+    u1 = ((w1 >> np.uint32(9)).astype(np.float64) + 0.5) * 2.0 ** -23
+    rad = np.sqrt(-np.log(u0))
+    w = rad * np.exp(2j * np.pi * u1)
+    w = np.where(j < i, np.conj(w), w)          # W_ij = conj(W_ji) below the diagonal
+    w[i] = np.sqrt(-2.0 * np.log(u0[i])) * np.cos(2.0 * np.pi * u1[i])
+    return w
+
+
+def phase_sync_rows_times(U: np.ndarray, sigma: float, seed: int, rows, X: np.ndarray) -> np.ndarray:
+    """(Q X)[rows, :] for Q = U U^H + sigma W, one row of W at a time (FP64)."""
+    U = np.asarray(U, dtype=np.complex128)
+    X = np.asarray(X, dtype=np.complex128)
+    UX = U.conj().T @ X
+    out = np.empty((len(rows), X.shape[1]), dtype=np.complex128)
+    for t, i in enumerate(rows):
+        out[t] = U[i] @ UX + sigma * (w_row(seed, int(i), U.shape[0]) @ X)
+    return out

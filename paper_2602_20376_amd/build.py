@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrqo.so")
-SOURCES = ["lrqo_runtime.hip", "select.hip", "sampled.hip", "api_sampled.hip", "exact.hip",
+SOURCES = ["lrqo_runtime.hip", "select.hip", "sampled.hip", "sampled_probe.hip", "api_sampled.hip", "exact.hip",
            "batched.hip", "proposal.hip", "graph.hip", "sort.hip", "rank1.hip", "lanczos.hip"]
 ARCH = "gfx950"
 

@@ -29,34 +29,56 @@ lrqo_status check_sampled_args(const float* V, int64_t n, int32_t r, int32_t K, 
             return fail(LRQO_EINVAL, "first_index + S overflows");
         if (opt->directions && opt->first_index != 0)
             return fail(LRQO_EINVAL, "first_index must be 0 with a direction list");
+        if (opt->probe_count < 0 || opt->probe_count > LRQO_MAX_TOPK)
+            return fail(LRQO_EINVAL, "probe_count must be in [0, 64]");
+        if (opt->probe_count > 0) {
+            if (!opt->probe || !opt->probe_labels)
+                return fail(LRQO_EINVAL, "probe and probe_labels are needed with probe_count > 0");
+            for (int t = 0; t < opt->probe_count; ++t)
+                if (opt->probe[t] < 0 || opt->probe[t] >= S)
+                    return fail(LRQO_EINVAL, "probe positions must be in [0, S)");
+        }
     }
     return LRQO_OK;
 }
 
-}  // namespace
+// Scratch of lrqo_solve_sampled_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes this name to a kernel (on the host it
+// is a stand-in, not a device address): the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in the device context.
+static __device__ __align__(256) char scratch[LRQO_NOALLOC_SCRATCH_BYTES];
 
-extern "C" {
+lrqo_status static_scratch_ptr(lrqo::DeviceCtx* ctx, void** out) {
+    if (!ctx->static_scratch) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return lrqo::fail(LRQO_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                                hipGetErrorString(e));
+        ctx->static_scratch = ptr;
+    }
+    *out = ctx->static_scratch;
+    return LRQO_OK;
+}
 
-lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t K, int64_t S,
-                                  uint64_t seed, const lrqo_sampled_options* opt, uint8_t* z,
-                                  lrqo_sampled_result* res) {
+// Arguments of a sampled call as a job, after the checks that need no device.
+lrqo_status make_job(const float* V, int64_t n, int32_t r, int32_t K, int64_t S, uint64_t seed,
+                     const lrqo_sampled_options* opt, uint8_t* z, lrqo::SampledJob& job) {
     using namespace lrqo;
-    clear_error();
     LRQO_TRY(check_sampled_args(V, n, r, K, S, opt, z));
     lrqo_sampled_options o{};
     if (opt) o = *opt;
     if (o.rescore_topk == 0) o.rescore_topk = LRQO_MAX_TOPK;
     if (o.precision == 1 && r > 4) return fail(LRQO_EINVAL, "the precision form (BF16 MFMA) needs r <= 4");
-
-    DeviceCtx* ctx = device_ctx();
-    if (!ctx) return LRQO_EDEVICE;
     if (!is_device_pointer(V)) return fail(LRQO_EINVAL, "V is not device memory");
     if (!is_device_pointer(z)) return fail(LRQO_EINVAL, "z is not device memory");
     if (o.f_out && !is_device_pointer(o.f_out)) return fail(LRQO_EINVAL, "f_out is not device memory");
     if (o.directions && !is_device_pointer(o.directions))
         return fail(LRQO_EINVAL, "directions is not device memory");
-
-    SampledJob job{};
+    if (o.dirs_out && !is_device_pointer(o.dirs_out)) return fail(LRQO_EINVAL, "dirs_out is not device memory");
+    if (o.probe_count > 0 && !is_device_pointer(o.probe_labels))
+        return fail(LRQO_EINVAL, "probe_labels is not device memory");
+    job = SampledJob{};
     job.V = V;
     job.n = n;
     job.r = r;
@@ -70,7 +92,81 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
     job.topk = o.rescore_topk;
     job.f_out = o.f_out;
     job.dirs = o.directions;
+    job.dirs_out = o.dirs_out;
+    job.probe_out = o.probe_labels;
+    job.probe_count = o.probe_count;
+    for (int t = 0; t < o.probe_count; ++t) job.probe_idx[t] = (uint32_t)o.probe[t];
     job.z = z;
+    return LRQO_OK;
+}
+
+void fill_result(const lrqo::DevResult& h, const lrqo::ScratchPlan& plan, float ms, float score_ms,
+                 lrqo_sampled_result* res) {
+    if (!res) return;
+    std::memset(res, 0, sizeof *res);
+    res->best_index = h.best_index;
+    res->obj = h.obj;
+    res->fp32_obj = h.fp32_obj;
+    for (int j = 0; j < 2 * LRQO_MAX_R; ++j) res->best_c[j] = h.c[j];
+    res->flagged_rows = (int64_t)h.flagged_rows;
+    res->device_ms = ms;
+    res->score_ms = score_ms;
+    res->rescored = plan.topk;
+    res->slices = plan.slices;
+}
+
+}  // namespace
+
+extern "C" {
+
+lrqo_status lrqo_solve_sampled_noalloc(const float* V, int64_t n, int32_t r, int32_t K, int64_t S,
+                                       uint64_t seed, const lrqo_sampled_options* opt, uint8_t* z,
+                                       lrqo_sampled_result* res) {
+    using namespace lrqo;
+    clear_error();
+    LRQO_TRY(check_sampled_args(V, n, r, K, S, opt, z));
+    DeviceCtx* ctx = device_ctx();
+    if (!ctx) return LRQO_EDEVICE;
+    SampledJob job;
+    LRQO_TRY(make_job(V, n, r, K, S, seed, opt, z, job));
+    ScratchPlan plan;
+    plan_sampled(job, plan);
+    if (plan.bytes > (size_t)LRQO_NOALLOC_SCRATCH_BYTES)
+        return fail(LRQO_ETOOBIG, "scratch of " + std::to_string(plan.bytes) + " bytes exceeds the " +
+                                      std::to_string((size_t)LRQO_NOALLOC_SCRATCH_BYTES) +
+                                      "-byte static array of the allocation-free entry point");
+    job.ev_score0 = ctx->ev_score0;
+    job.ev_score1 = ctx->ev_score1;
+
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    void* ptr = nullptr;
+    LRQO_TRY(static_scratch_ptr(ctx, &ptr));
+    hipStream_t st = current_stream();
+    DevResult h{};
+    LRQO_HIP(hipEventRecord(ctx->ev_start, st));
+    LRQO_TRY(launch_sampled(job, plan, ptr, st));
+    // the result block sits first in the scratch (pageable host copy)
+    LRQO_HIP(hipMemcpyAsync(&h, ptr, sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    LRQO_HIP(hipEventRecord(ctx->ev_stop, st));
+    LRQO_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f, score_ms = 0.0f;
+    LRQO_HIP(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop));
+    LRQO_HIP(hipEventElapsedTime(&score_ms, ctx->ev_score0, ctx->ev_score1));
+    if (h.nonfinite) return fail(LRQO_ENOTFINITE, "V holds a NaN or an infinity");
+    fill_result(h, plan, ms, score_ms, res);
+    return LRQO_OK;
+}
+
+lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t K, int64_t S,
+                                  uint64_t seed, const lrqo_sampled_options* opt, uint8_t* z,
+                                  lrqo_sampled_result* res) {
+    using namespace lrqo;
+    clear_error();
+    LRQO_TRY(check_sampled_args(V, n, r, K, S, opt, z));
+    DeviceCtx* ctx = device_ctx();
+    if (!ctx) return LRQO_EDEVICE;
+    SampledJob job;
+    LRQO_TRY(make_job(V, n, r, K, S, seed, opt, z, job));
     job.ev_score0 = ctx->ev_score0;
     job.ev_score1 = ctx->ev_score1;
 
@@ -93,18 +189,7 @@ lrqo_status lrqo_solve_sampled_ex(const float* V, int64_t n, int32_t r, int32_t 
     LRQO_HIP(hipEventElapsedTime(&score_ms, ctx->ev_score0, ctx->ev_score1));
 
     if (hres->nonfinite) return fail(LRQO_ENOTFINITE, "V holds a NaN or an infinity");
-    if (res) {
-        std::memset(res, 0, sizeof *res);
-        res->best_index = hres->best_index;
-        res->obj = hres->obj;
-        res->fp32_obj = hres->fp32_obj;
-        for (int j = 0; j < 2 * LRQO_MAX_R; ++j) res->best_c[j] = hres->c[j];
-        res->flagged_rows = (int64_t)hres->flagged_rows;
-        res->device_ms = ms;
-        res->score_ms = score_ms;
-        res->rescored = plan.topk;
-        res->slices = plan.slices;
-    }
+    fill_result(*hres, plan, ms, score_ms, res);
     return LRQO_OK;
 }
 

@@ -30,6 +30,7 @@
 //   k_exact_labels  labels of the winner
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -49,6 +50,9 @@ constexpr int kTopT = 64;
 constexpr int kRescoreSlices = 64;   // row slices of the FP64 rescore, at most
 constexpr double kRankTol = 1e-10;
 constexpr int64_t kMaxCombos = 1 << 20;
+constexpr uint64_t kChunkSets = 1ull << 26;          // sets scored between shortlist merges
+constexpr uint64_t kDefaultMaxSets = 1ull << 34;     // default cap on the index sets of a solve
+constexpr uint64_t kHardMaxSets = 1ull << 62;        // limit with the cap lifted (max_sets < 0)
 
 // A vertex as the split scorer reads it: FP32 direction (re, im per
 // column), the coordinates of its index set (-1 when it has none), and
@@ -71,9 +75,9 @@ struct ExactParams {
     const double2* rho;                 // [B]
     const double2* roots64;             // [K]
     const float2* roots32;              // [K]
-    uint64_t count;                     // index sets at this level
-    uint64_t offset;                    // global index of this level's first set
-    float* fbuf;
+    uint64_t count;                     // index sets of this chunk
+    uint64_t rank0;                     // rank (within its level) of the chunk's first set
+    float* fbuf;                        // best FP32 score of each set of the chunk
     unsigned long long* stats;          // valid sets, rank deficient, candidates: kStatSlots slots each
     int random;                         // 1: index sets drawn at random (null-vector sampler)
     uint64_t draw_seed;
@@ -86,6 +90,14 @@ struct ExactParams {
 struct LevelTable {
     uint64_t offset[kMaxR + 1];
     uint64_t count[kMaxR + 1];
+};
+
+// Shortlist of the enumeration: one entry per FP32 score value (the set
+// with the lowest global index), best first; f < 0 marks an empty slot.
+struct TopEntry {
+    float f;
+    int32_t pad;
+    uint64_t gidx;      // global set index: level offset + rank within the level
 };
 
 struct RescoreEntry {
@@ -106,13 +118,14 @@ struct ExactDevResult {
 };
 
 // ---------------------------------------------------------------- vertex
-// Colex unranking: rank = sum_t C(c_t, t+1) with c_0 < c_1 < ... < c_{M-1}.
+// Colex unranking: rank = sum_t C(c_t, t+1) with c_0 < c_1 < ... < c_{M-1}
+// (binomials C(x, k) for k >= 2 from the table; rank < 2^64).
 template <int M>
 __device__ __forceinline__ void unrank(uint64_t rank, const unsigned long long* binom, int64_t N,
                                        int64_t (&c)[M]) {
     int64_t hi = N - 1;
 #pragma unroll
-    for (int t = M - 1; t >= 0; --t) {
+    for (int t = M - 1; t >= 1; --t) {
         const unsigned long long* col = binom + (size_t)(t + 1) * (N + 1);
         int64_t lo = t, h = hi;
         while (lo < h) {
@@ -124,6 +137,7 @@ __device__ __forceinline__ void unrank(uint64_t rank, const unsigned long long* 
         rank -= col[lo];
         hi = lo - 1;
     }
+    c[0] = (int64_t)rank;     // C(x, 1) = x
 }
 
 // Null-vector sampler, draw s: M rows of the augmented matrix, row j =
@@ -511,13 +525,13 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
     const bool cplx = *p.complex_v != 0;   // the same in every thread
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
-        const uint64_t rank = base + tid;
+        const uint64_t rank = base + tid;          // within the chunk
         const bool active = rank < p.count;
         int64_t g[M];
         int mm[M];
         double v[C2];
         bool valid = false, ok = false;
-        if (active) ok = vertex<D>(p, rank, g, mm, v, valid);
+        if (active) ok = vertex<D>(p, p.rank0 + rank, g, mm, v, valid);
         if (!ok) {
 #pragma unroll
             for (int t = 0; t < M; ++t) g[t] = -1;
@@ -538,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
             score_rows<R, D, KS, true>(p, c, g32, 0, p.n, tile, roots_s, acc);
         unsigned long long ncand = 0;
         const float best = ok ? combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand) : 0.0f;
-        if (active) p.fbuf[p.offset + rank] = best;
+        if (active) p.fbuf[rank] = best;
         add_stats(p, active, valid, ok, ncand);
     }
 }
@@ -554,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_vertex(ExactParams p, VertexRe
         int mm[M];
         double v[C2];
         bool valid = false;
-        const bool ok = vertex<D>(p, rank, g, mm, v, valid);
+        const bool ok = vertex<D>(p, p.rank0 + rank, g, mm, v, valid);
         VertexRec rec;
 #pragma unroll
         for (int j = 0; j < 2 * kMaxR; ++j) rec.c[j] = 0.0f;
@@ -635,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_combine(ExactParams p, int sli
         int mm[M];
         double v[C2];
         bool valid = false, ok = false;
-        if (active) ok = vertex<D>(p, rank, g, mm, v, valid);
+        if (active) ok = vertex<D>(p, p.rank0 + rank, g, mm, v, valid);
         unsigned long long ncand = 0;
         float best = 0.0f;
         if (ok) {
@@ -650,9 +664,49 @@ __global__ __launch_bounds__(kBlock) void k_exact_combine(ExactParams p, int sli
                 }
             best = combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand);
         }
-        if (active) p.fbuf[p.offset + rank] = best;
+        if (active) p.fbuf[rank] = best;
         add_stats(p, active, valid, ok, ncand);
     }
+}
+
+// Merges a chunk's best keys (sorted, one per score value, indices local to
+// the chunk, global index base + local) into the running shortlist: sorted by
+// score descending then global index ascending, one entry per score value
+// (the lower index: earlier chunks hold lower indices), at most kTopT.  One
+// thread; the lists are short.
+__global__ void k_exact_merge(TopEntry* __restrict__ top, const unsigned long long* __restrict__ keys, int T,
+                              uint64_t base) {
+    __shared__ TopEntry a[kTopT], out[kTopT];
+    if (threadIdx.x != 0) return;
+    for (int t = 0; t < kTopT; ++t) a[t] = top[t];
+    int i = 0, j = 0, m = 0;
+    float last = -1.0f;
+    while (m < kTopT) {
+        const bool ha = i < kTopT && a[i].f >= 0.0f;
+        const bool hb = j < T && keys[j] != 0ull;
+        if (!ha && !hb) break;
+        TopEntry e;
+        if (ha && hb) {
+            const float fb = key_value(keys[j]);
+            const uint64_t gb = base + key_index(keys[j]);
+            const bool take_a = a[i].f > fb || (a[i].f == fb && a[i].gidx < gb);
+            e = take_a ? a[i] : TopEntry{fb, 0, gb};
+            if (take_a) ++i; else ++j;
+        } else if (ha) {
+            e = a[i++];
+        } else {
+            e = TopEntry{key_value(keys[j]), 0, base + key_index(keys[j])};
+            ++j;
+        }
+        if (m > 0 && e.f == last) continue;     // the same score value: keep the earlier set
+        out[m++] = e;
+        last = e.f;
+    }
+    for (int t = 0; t < kTopT; ++t) top[t] = t < m ? out[t] : TopEntry{-1.0f, 0, 0};
+}
+
+__global__ void k_exact_top_init(TopEntry* __restrict__ top) {
+    if (threadIdx.x < kTopT) top[threadIdx.x] = TopEntry{-1.0f, 0, 0};
 }
 
 // ---------------------------------------------------------------- FP64 rescore
@@ -812,13 +866,13 @@ __device__ void rescore_one(ExactParams p, uint64_t rank, const double* part, in
 // both signs' sums over slice q of the rows.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_exact_rescore_rows(ExactParams p, LevelTable lt,
-                                                               const unsigned long long* keys, int64_t rows,
+                                                               const TopEntry* top, int64_t rows,
                                                                double* part) {
     const int t = blockIdx.x, q = blockIdx.y;
     const int64_t r0 = min(p.n, (int64_t)q * rows), r1 = min(p.n, r0 + rows);
     double* out = part + ((size_t)t * gridDim.y + q) * 2 * (2 * R);
     uint64_t rank;
-    const int d = level_of(lt, R, key_index(keys[t]), rank);
+    const int d = top[t].f < 0.0f ? 0 : level_of(lt, R, top[t].gidx, rank);
     switch (d) {
         case 1: rescore_rows_one<R, 1>(p, rank, r0, r1, out); break;
         case 2: if constexpr (R >= 2) rescore_rows_one<R, 2>(p, rank, r0, r1, out); break;
@@ -831,12 +885,12 @@ __global__ __launch_bounds__(kBlock) void k_exact_rescore_rows(ExactParams p, Le
 
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_exact_rescore(ExactParams p, LevelTable lt,
-                                                          const unsigned long long* keys, const double* part,
+                                                          const TopEntry* top, const double* part,
                                                           int slices, RescoreEntry* out) {
     const int t = blockIdx.x;
     const double* pt = part + (size_t)t * slices * 2 * (2 * R);
     uint64_t rank;
-    const int d = level_of(lt, R, key_index(keys[t]), rank);
+    const int d = top[t].f < 0.0f ? 0 : level_of(lt, R, top[t].gidx, rank);
     switch (d) {
         case 1: rescore_one<R, 1>(p, rank, pt, slices, out + t); break;
         case 2: if constexpr (R >= 2) rescore_one<R, 2>(p, rank, pt, slices, out + t); break;
@@ -847,14 +901,14 @@ __global__ __launch_bounds__(kBlock) void k_exact_rescore(ExactParams p, LevelTa
     }
 }
 
-__global__ void k_exact_pick(const RescoreEntry* __restrict__ e, const unsigned long long* keys,
+__global__ void k_exact_pick(const RescoreEntry* __restrict__ e, const TopEntry* top,
                              int T, LevelTable lt, int r, ExactDevResult* res) {
     if (threadIdx.x != 0) return;
     int bt = -1;
-    uint32_t bidx = 0xFFFFFFFFu;
+    uint64_t bidx = ~0ull;
     for (int t = 0; t < T; ++t) {
-        if (e[t].f < 0.0) continue;
-        const uint32_t idx = key_index(keys[t]);
+        if (e[t].f < 0.0 || top[t].f < 0.0f) continue;
+        const uint64_t idx = top[t].gidx;
         if (bt < 0 || e[t].f > e[bt].f || (e[t].f == e[bt].f && idx < bidx)) {
             bt = t;
             bidx = idx;
@@ -867,7 +921,7 @@ __global__ void k_exact_pick(const RescoreEntry* __restrict__ e, const unsigned 
     }
     uint64_t rank;
     res->obj = e[bt].f;
-    res->gidx = bidx;
+    res->gidx = (int64_t)bidx;
     res->level = level_of(lt, r, bidx, rank);
     res->sign = e[bt].sign;
     res->combo = e[bt].combo;
@@ -964,9 +1018,9 @@ int exact_slices(uint64_t count, int64_t n, int r, int64_t& rows) {
 }
 
 template <int R, int D>
-void launch_level(ExactParams p, hipStream_t st) {
+void launch_level(ExactParams p, bool force_fused, hipStream_t st) {
     const uint64_t blocks = std::min<uint64_t>((p.count + kBlock - 1) / kBlock, 8192);
-    const int slices = exact_slices(p.count, p.n, R, p.rows_per_slice);
+    const int slices = force_fused ? 0 : exact_slices(p.count, p.n, R, p.rows_per_slice);
     if (slices == 0) {
         switch (p.K) {
             case 2: hipLaunchKernelGGL((k_exact_score<R, D, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
@@ -988,37 +1042,57 @@ void launch_level(ExactParams p, hipStream_t st) {
 }
 
 template <int R>
-lrqo_status run_exact(ExactParams p, const LevelTable& lt, const unsigned long long** keys_out,
+lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, bool force_fused, TopEntry* top,
                       unsigned long long* ka, unsigned long long* kb, RescoreEntry* entries, double* rpart,
-                      ExactDevResult* dres, uint8_t* z, uint32_t total, int T, hipStream_t st) {
+                      ExactDevResult* dres, uint8_t* z, hipStream_t st) {
+    hipLaunchKernelGGL(k_exact_top_init, dim3(1), dim3(kTopT), 0, st, top);
     for (int d = R; d >= 1; --d) {
-        if (lt.count[d] == 0) continue;
-        ExactParams q = p;
-        q.count = lt.count[d];
-        q.offset = lt.offset[d];
-        switch (d) {
-            case 1: launch_level<R, 1>(q, st); break;
-            case 2: if constexpr (R >= 2) launch_level<R, 2>(q, st); break;
-            case 3: if constexpr (R >= 3) launch_level<R, 3>(q, st); break;
-            case 4: if constexpr (R >= 4) launch_level<R, 4>(q, st); break;
+        for (uint64_t c0 = 0; c0 < lt.count[d]; c0 += chunk) {
+            ExactParams q = p;
+            q.count = std::min<uint64_t>(chunk, lt.count[d] - c0);
+            q.rank0 = c0;
+            switch (d) {
+                case 1: launch_level<R, 1>(q, force_fused, st); break;
+                case 2: if constexpr (R >= 2) launch_level<R, 2>(q, force_fused, st); break;
+                case 3: if constexpr (R >= 3) launch_level<R, 3>(q, force_fused, st); break;
+                case 4: if constexpr (R >= 4) launch_level<R, 4>(q, force_fused, st); break;
+            }
+            LRQO_HIP(hipGetLastError());
+            const int T = (int)std::min<uint64_t>(kTopT, q.count);
+            const unsigned long long* keys = nullptr;
+            LRQO_TRY(topk_select(p.fbuf, (uint32_t)q.count, T, ka, kb, st, &keys, true));
+            hipLaunchKernelGGL(k_exact_merge, dim3(1), dim3(kTopT), 0, st, top, keys, T, lt.offset[d] + c0);
+            LRQO_HIP(hipGetLastError());
         }
-        LRQO_HIP(hipGetLastError());
     }
-    const unsigned long long* keys = nullptr;
-    LRQO_TRY(topk_select(p.fbuf, total, T, ka, kb, st, &keys));
     const int64_t rrows = std::max<int64_t>(4096, (p.n + kRescoreSlices - 1) / kRescoreSlices);
     const int rslices = (int)((p.n + rrows - 1) / rrows);
-    hipLaunchKernelGGL((k_exact_rescore_rows<R>), dim3(T, rslices), dim3(kBlock), 0, st, p, lt, keys, rrows,
+    hipLaunchKernelGGL((k_exact_rescore_rows<R>), dim3(kTopT, rslices), dim3(kBlock), 0, st, p, lt, top, rrows,
                        rpart);
-    hipLaunchKernelGGL((k_exact_rescore<R>), dim3(T), dim3(kBlock), 0, st, p, lt, keys, rpart, rslices, entries);
+    hipLaunchKernelGGL((k_exact_rescore<R>), dim3(kTopT), dim3(kBlock), 0, st, p, lt, top, rpart, rslices, entries);
     LRQO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_exact_pick, dim3(1), dim3(64), 0, st, entries, keys, T, lt, R, dres);
+    hipLaunchKernelGGL(k_exact_pick, dim3(1), dim3(64), 0, st, entries, top, kTopT, lt, R, dres);
     LRQO_HIP(hipGetLastError());
     hipLaunchKernelGGL((k_exact_labels<R>), dim3((unsigned)((p.n + kBlock - 1) / kBlock)),
                        dim3(kBlock), 0, st, p, lt, dres, z);
     LRQO_HIP(hipGetLastError());
-    *keys_out = keys;
     return LRQO_OK;
+}
+
+// Sets per enumeration chunk: each chunk's scores (4 bytes per set) are
+// reduced to its best distinct values before the next chunk is scored.
+uint64_t exact_chunk() {
+    const char* e = std::getenv("LRQO_EXACT_CHUNK");
+    if (e && *e) {
+        const long long v = std::atoll(e);
+        if (v >= 1) return (uint64_t)v;
+    }
+    return kChunkSets;
+}
+
+bool exact_force_fused() {
+    const char* e = std::getenv("LRQO_EXACT_FORM");
+    return e && std::strcmp(e, "fused") == 0;
 }
 
 // Shared by the exact enumeration (random = false: every valid index set of
@@ -1030,19 +1104,20 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     if (!V) return fail(LRQO_EINVAL, "V is null");
     if (!z) return fail(LRQO_EINVAL, "z is null");
     if (r < 1 || r > kMaxR) return fail(LRQO_EINVAL, "r must be in [1, 4] for the vertex solvers");
-    if (n < r || n > (1 << 24)) return fail(LRQO_EINVAL, "n must be in [r, 2^24]");
+    if (n < r || n > INT32_MAX) return fail(LRQO_EINVAL, "n must be in [r, 2^31 - 1]");
     if (K < 2 || K > LRQO_MAX_K) return fail(LRQO_EINVAL, "K must be in [2, 255]");
     if (random && (S < 1 || S > 0x7FFFFFFFll)) return fail(LRQO_EINVAL, "S must be in [1, 2^31 - 1]");
     const int B = boundary_count(K);
     const int64_t N = n * B;
-    if (!random && N > (1 << 22)) return fail(LRQO_ETOOBIG, "n B_K above 2^22 rows: too many index sets");
     // label combinations of one vertex: at most 2^(2r-1-2p) K^p, p double groups
     for (int pdbl = 0; 2 * pdbl <= 2 * r - 1; ++pdbl) {
         long double combos = std::ldexp(1.0L, 2 * r - 1 - 2 * pdbl) * std::pow((long double)K, pdbl);
         if (combos > (long double)kMaxCombos)
             return fail(LRQO_ETOOBIG, "label combinations per vertex exceed 2^20 (K too large for r)");
     }
-    const uint64_t cap = max_sets > 0 ? (uint64_t)max_sets : ((1ull << 31) - 1);
+    const unsigned __int128 cap = max_sets > 0 ? (unsigned __int128)max_sets
+                                  : max_sets == 0 ? (unsigned __int128)kDefaultMaxSets
+                                                  : (unsigned __int128)kHardMaxSets;
     LevelTable lt{};
     unsigned __int128 total128 = 0;
     if (random) {
@@ -1052,23 +1127,38 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     } else {
         for (int d = r; d >= 1; --d) {
             const unsigned __int128 c = binom128(N, 2 * d - 1);
-            lt.offset[d] = (uint64_t)std::min<unsigned __int128>(total128, ~0ull);
-            lt.count[d] = (uint64_t)std::min<unsigned __int128>(c, ~0ull);
+            lt.offset[d] = (uint64_t)std::min<unsigned __int128>(total128, kHardMaxSets);
+            lt.count[d] = (uint64_t)std::min<unsigned __int128>(c, kHardMaxSets);
             total128 += c;
         }
-        if (total128 > (unsigned __int128)cap || total128 > 0xFFFFFFF0ull)
-            return fail(LRQO_ETOOBIG, "number of index sets C(n B_K, 2d-1) summed over levels exceeds the cap");
+        if (total128 > cap || total128 > (unsigned __int128)kHardMaxSets)
+            return fail(LRQO_ETOOBIG, "number of index sets C(n B_K, 2d-1) summed over levels exceeds the cap "
+                                      "(max_sets; 0 means 2^34, a negative value lifts it up to 2^62)");
     }
-    const uint32_t total = (uint32_t)total128;
 
     DeviceCtx* ctx = device_ctx();
     if (!ctx) return LRQO_EDEVICE;
     if (!is_device_pointer(V)) return fail(LRQO_EINVAL, "V is not device memory");
     if (!is_device_pointer(z)) return fail(LRQO_EINVAL, "z is not device memory");
 
-    const int T = (int)std::min<uint32_t>(kTopT, total);
+    const uint64_t chunk = random ? (uint64_t)S : exact_chunk();
+    const bool force_fused = exact_force_fused();
+    uint64_t cmax = 0;                   // the largest chunk
+    for (int d = r; d >= 1; --d) cmax = std::max<uint64_t>(cmax, std::min<uint64_t>(chunk, lt.count[d]));
     const int Mmax = 2 * r - 1;
-    const size_t binom_entries = random ? 1 : (size_t)(Mmax + 1) * (size_t)(N + 1);
+    const size_t binom_entries = (random || Mmax < 2) ? 1 : (size_t)(Mmax + 1) * (size_t)(N + 1);
+    uint64_t rec_count = 0, part_floats = 0;     // the largest split chunk's needs
+    if (!force_fused) {
+        for (int d = r; d >= 1; --d) {
+            if (lt.count[d] == 0) continue;
+            const uint64_t cnt = std::min<uint64_t>(chunk, lt.count[d]);
+            int64_t rows = 0;
+            const int sl = exact_slices(cnt, n, r, rows);
+            if (sl == 0) continue;
+            rec_count = std::max<uint64_t>(rec_count, cnt);
+            part_floats = std::max<uint64_t>(part_floats, cnt * (uint64_t)sl * 2 * (2 * r));
+        }
+    }
     CarveSize cs;
     cs.add<ExactDevResult>(1);
     cs.add<unsigned long long>(3 * kStatSlots);
@@ -1077,20 +1167,12 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     cs.add<double2>(LRQO_MAX_K);
     cs.add<double2>(LRQO_MAX_K);
     cs.add<float2>(LRQO_MAX_K);
-    cs.add<float>(total);
-    cs.add<unsigned long long>(topk_buffer_keys(total, T));
-    cs.add<unsigned long long>(topk_buffer_keys(total, T));
-    cs.add<RescoreEntry>(T);
-    cs.add<double>((size_t)T * kRescoreSlices * 2 * (2 * r));
-    uint64_t rec_count = 0, part_floats = 0;     // the largest split level's needs
-    for (int d = r; d >= 1; --d) {
-        if (lt.count[d] == 0) continue;
-        int64_t rows = 0;
-        const int sl = exact_slices(lt.count[d], n, r, rows);
-        if (sl == 0) continue;
-        rec_count = std::max<uint64_t>(rec_count, lt.count[d]);
-        part_floats = std::max<uint64_t>(part_floats, lt.count[d] * (uint64_t)sl * 2 * (2 * r));
-    }
+    cs.add<float>(cmax);
+    cs.add<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
+    cs.add<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
+    cs.add<TopEntry>(kTopT);
+    cs.add<RescoreEntry>(kTopT);
+    cs.add<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * r));
     cs.add<VertexRec>(rec_count);
     cs.add<float>(part_floats);
     const size_t host_bytes = 4096 + binom_entries * sizeof(unsigned long long) +
@@ -1108,11 +1190,12 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     double2* rho = cv.take<double2>(LRQO_MAX_K);
     double2* roots64 = cv.take<double2>(LRQO_MAX_K);
     float2* roots32 = cv.take<float2>(LRQO_MAX_K);
-    float* fbuf = cv.take<float>(total);
-    unsigned long long* ka = cv.take<unsigned long long>(topk_buffer_keys(total, T));
-    unsigned long long* kb = cv.take<unsigned long long>(topk_buffer_keys(total, T));
-    RescoreEntry* entries = cv.take<RescoreEntry>(T);
-    double* rpart = cv.take<double>((size_t)T * kRescoreSlices * 2 * (2 * r));
+    float* fbuf = cv.take<float>(cmax);
+    unsigned long long* ka = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
+    unsigned long long* kb = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
+    TopEntry* top = cv.take<TopEntry>(kTopT);
+    RescoreEntry* entries = cv.take<RescoreEntry>(kTopT);
+    double* rpart = cv.take<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * r));
     VertexRec* recs = cv.take<VertexRec>(rec_count);
     float* part = cv.take<float>(part_floats);
 
@@ -1125,20 +1208,21 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     double2* hr64 = hrho + LRQO_MAX_K;
     float2* hr32 = reinterpret_cast<float2*>(hr64 + LRQO_MAX_K);
     // C(x, k) by Pascal's rule, saturating at 2^64-1 (only values below the
-    // set count, <= 2^32, are ever compared exactly)
-    if (random) hbin[0] = 0;
-    for (int k = 0; k <= (random ? -1 : Mmax); ++k)
-        for (int64_t x = 0; x <= N; ++x) {
-            unsigned long long c;
-            if (k == 0) c = 1;
-            else if (x == 0) c = 0;
-            else {
-                const unsigned long long a = hbin[(size_t)k * (N + 1) + x - 1];
-                const unsigned long long b = hbin[(size_t)(k - 1) * (N + 1) + x - 1];
-                c = (a > ~0ull - b) ? ~0ull : a + b;
+    // set count, < 2^62, are ever compared exactly)
+    if (binom_entries == 1) hbin[0] = 0;
+    else
+        for (int k = 0; k <= Mmax; ++k)
+            for (int64_t x = 0; x <= N; ++x) {
+                unsigned long long c;
+                if (k == 0) c = 1;
+                else if (x == 0) c = 0;
+                else {
+                    const unsigned long long a = hbin[(size_t)k * (N + 1) + x - 1];
+                    const unsigned long long b = hbin[(size_t)(k - 1) * (N + 1) + x - 1];
+                    c = (a > ~0ull - b) ? ~0ull : a + b;
+                }
+                hbin[(size_t)k * (N + 1) + x] = c;
             }
-            hbin[(size_t)k * (N + 1) + x] = c;
-        }
     const double pi = 3.14159265358979323846264338327950288;
     for (int m = 0; m < B; ++m) {
         const double a = -pi * (2.0 * m + 1.0) / (double)K;
@@ -1182,28 +1266,23 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     int* nonfinite = &dres->nonfinite;
     int* complex_v = &dres->complex_v;
     p.complex_v = complex_v;
-    const unsigned long long* keys = nullptr;
     lrqo_status s = LRQO_OK;
     switch (r) {
         case 1:
-            hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
-                               complex_v);
-            s = run_exact<1>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
+            hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            s = run_exact<1>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
         case 2:
-            hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
-                               complex_v);
-            s = run_exact<2>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
+            hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            s = run_exact<2>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
         case 3:
-            hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
-                               complex_v);
-            s = run_exact<3>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
+            hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            s = run_exact<3>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
         case 4:
-            hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite,
-                               complex_v);
-            s = run_exact<4>(p, lt, &keys, ka, kb, entries, rpart, dres, z, total, T, st);
+            hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            s = run_exact<4>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
     }
     if (s != LRQO_OK) return s;
@@ -1227,6 +1306,9 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
         res->rank_deficient = sum3[1];
         res->candidates = sum3[2];
         res->device_ms = ms;
+        // general position (Assumption 1) implies every valid set has full
+        // rank; a rank-deficient set shows the input violates it
+        res->warning = sum3[1] > 0 ? LRQO_EDEGENERATE : LRQO_OK;
     }
     return LRQO_OK;
 }

@@ -161,6 +161,33 @@ __device__ __forceinline__ unsigned long long wave_top_union(unsigned long long 
     return x;
 }
 
+// Best 64 keys of two descending lists with one key per objective value: the
+// 128 keys are merged into a sorted sequence (half-cleaner against the
+// reversed second list, both halves sorted), a key whose objective equals the
+// one before it is cleared (the larger key, i.e. the lower index, stays), and
+// the best 64 survivors are kept.  Clearing to 0 (below every real key) makes
+// the result a list padded at its end.
+__device__ __forceinline__ unsigned long long wave_top_union_distinct(unsigned long long a,
+                                                                      unsigned long long b, int lane) {
+    const unsigned long long br = __shfl(b, 63 - lane, 64);
+    unsigned long long hi = key_max(a, br), lo = key_min(a, br);
+    for (int j = 32; j > 0; j >>= 1) {
+        const unsigned long long yh = __shfl_xor(hi, j, 64), yl = __shfl_xor(lo, j, 64);
+        const bool up = (lane & j) == 0;
+        hi = up ? key_max(hi, yh) : key_min(hi, yh);
+        lo = up ? key_max(lo, yl) : key_min(lo, yl);
+    }
+    // hi holds positions 0..63 of the merged sequence, lo positions 64..127
+    const unsigned long long h63 = __shfl(hi, 63, 64);
+    const unsigned long long hp = __shfl_up(hi, 1, 64);
+    const unsigned long long lp = __shfl_up(lo, 1, 64);
+    const unsigned long long hprev = lane == 0 ? 0ull : hp;
+    const unsigned long long lprev = lane == 0 ? h63 : lp;
+    if (hi != 0 && hprev != 0 && (hi >> 32) == (hprev >> 32)) hi = 0;
+    if (lo != 0 && lprev != 0 && (lo >> 32) == (lprev >> 32)) lo = 0;
+    return wave_top_union(wave_sort_desc(hi, lane), wave_sort_desc(lo, lane), lane);
+}
+
 // Packed arg-max key: objective bits above, complemented index below, so the
 // unsigned maximum is the largest objective and, among equal objectives, the
 // lowest index.  f >= 0, so its IEEE bits order like the values.

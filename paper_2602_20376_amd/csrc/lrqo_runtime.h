@@ -29,6 +29,7 @@ struct DeviceCtx {
     size_t host_bytes = 0;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     hipEvent_t ev_score0 = nullptr, ev_score1 = nullptr;  // bracket the scoring kernels
+    void* static_scratch = nullptr;  // this device's copy of the allocation-free entry point's array
 };
 
 // Context of the current device (created on first use).  nullptr on failure

@@ -101,7 +101,7 @@ bool is_device_pointer(const void* p) {
 
 extern "C" {
 
-int32_t lrqo_version(void) { return 100; }
+int32_t lrqo_version(void) { return 20000; }
 
 const char* lrqo_last_error(void) { return lrqo::t_error.c_str(); }
 

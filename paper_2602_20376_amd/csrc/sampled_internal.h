@@ -6,7 +6,16 @@
 
 #include "../../include/lrqo.h"
 
+#ifndef LRQO_BF16_SPLIT
+#define LRQO_BF16_SPLIT 2      // bf16 hi + lo parts of V and c in the precision form
+#endif
+#ifndef LRQO_SCORE_CPL
+#define LRQO_SCORE_CPL 4       // candidates per lane of the r <= 4 scorers
+#endif
+
 namespace lrqo {
+
+constexpr int kMaxProbe = 64;   // probed candidates of one call, at most
 
 // Result block written by the device and copied to pinned host memory.
 struct DevResult {
@@ -33,6 +42,10 @@ struct ScoreParams {
     const float2* roots32;
     unsigned long long* flagged;   // precision form: row-candidates recomputed in FP32
     const float* dirs;             // optional [S][2r] directions in place of the stream
+    float* dirs_out;               // optional [S][2r]: the FP32 direction each candidate was scored with
+    uint16_t* probe_out;           // [probe_count][n] labels of the probed candidates (| 0x100: recomputed)
+    int probe_count;
+    uint32_t probe_idx[kMaxProbe]; // positions (0..S-1) of the probed candidates
 };
 
 struct RescoreParams {
@@ -63,6 +76,10 @@ struct SampledJob {
     int topk;
     float* f_out;
     const float* dirs;
+    float* dirs_out;
+    uint16_t* probe_out;
+    int probe_count;
+    uint32_t probe_idx[kMaxProbe];
     uint8_t* z;
     hipEvent_t ev_score0;   // recorded before / after the scoring kernels
     hipEvent_t ev_score1;
@@ -98,6 +115,9 @@ struct Scratch {
 constexpr int kCheckBlocks = 256;   // blocks of the prologue's finiteness check
 
 void plan_sampled(const SampledJob& job, ScratchPlan& plan);
+// The scorers with per-row label output for p.probe_count candidates
+// (sampled_probe.hip); same arithmetic as the plain launches.
+void launch_score_probe(const ScoreParams& p, dim3 grid, hipStream_t st, int r, bool real, int precision);
 lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena, hipStream_t st);
 
 }  // namespace lrqo

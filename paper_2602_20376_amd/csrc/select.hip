@@ -22,9 +22,11 @@ constexpr int kChunk = 2048;  // keys per block, kChunk / kWaves per wave
 // Keys come from f (index = position) or from a previous pass.  Padding keys
 // are 0, below every real key (a real key's index is < 2^32-1, so its low
 // word is nonzero).
+// distinct = 1: one key per objective value (the lowest index), for inputs
+// where many candidates share a bit-identical score.
 __global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
                                                  const unsigned long long* __restrict__ keys_in,
-                                                 uint32_t count, int T, int sorted,
+                                                 uint32_t count, int T, int sorted, int distinct,
                                                  unsigned long long* __restrict__ keys_out) {
     __shared__ unsigned long long top[kWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -36,12 +38,14 @@ __global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
         if (g < count) key = f ? pack_key(f[g], g) : keys_in[g];
         const unsigned long long floor64 = __shfl(run, 63, 64);
         if (__ballot(key > floor64) == 0) continue;  // uniform across the wave
-        run = wave_top_union(run, sorted ? key : wave_sort_desc(key, lane), lane);
+        const unsigned long long tile = sorted ? key : wave_sort_desc(key, lane);
+        run = distinct ? wave_top_union_distinct(run, tile, lane) : wave_top_union(run, tile, lane);
     }
     top[w][lane] = run;
     __syncthreads();
     if (w != 0) return;
-    for (int v = 1; v < kWaves; ++v) run = wave_top_union(run, top[v][lane], lane);
+    for (int v = 1; v < kWaves; ++v)
+        run = distinct ? wave_top_union_distinct(run, top[v][lane], lane) : wave_top_union(run, top[v][lane], lane);
     if (lane < T) keys_out[(size_t)blockIdx.x * T + lane] = run;
 }
 
@@ -54,7 +58,7 @@ size_t topk_buffer_keys(uint32_t count, int T) {
 namespace {
 
 lrqo_status topk_passes(const float* f, const unsigned long long* keys, bool sorted, uint32_t count, int T,
-                        unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
+                        bool distinct, unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
                         const unsigned long long** out) {
     uint32_t n = count;
     int ping = 0;
@@ -63,7 +67,7 @@ lrqo_status topk_passes(const float* f, const unsigned long long* keys, bool sor
         const uint32_t blocks = (n + kChunk - 1) / kChunk;
         unsigned long long* dst = ping ? buf_b : buf_a;
         hipLaunchKernelGGL(k_topk, dim3(blocks), dim3(kBlock), 0, st, from_f ? f : nullptr, keys, n,
-                           T, sorted ? 1 : 0, dst);
+                           T, sorted ? 1 : 0, distinct ? 1 : 0, dst);
         LRQO_HIP(hipGetLastError());
         keys = dst;
         n = blocks * (uint32_t)T;
@@ -80,14 +84,14 @@ lrqo_status topk_passes(const float* f, const unsigned long long* keys, bool sor
 
 lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long long* buf_a,
                         unsigned long long* buf_b, hipStream_t st,
-                        const unsigned long long** out) {
-    return topk_passes(f, nullptr, false, count, T, buf_a, buf_b, st, out);
+                        const unsigned long long** out, bool distinct) {
+    return topk_passes(f, nullptr, false, count, T, distinct, buf_a, buf_b, st, out);
 }
 
 lrqo_status topk_select_lists(const unsigned long long* lists, uint32_t count, int T,
                               unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
                               const unsigned long long** out) {
-    return topk_passes(nullptr, lists, true, count, T, buf_a, buf_b, st, out);
+    return topk_passes(nullptr, lists, true, count, T, false, buf_a, buf_b, st, out);
 }
 
 }  // namespace lrqo

@@ -19,11 +19,11 @@ MAX_K = 255
 MAX_TOPK = 64
 
 STATUS = {0: "LRQO_OK", -1: "LRQO_EINVAL", -2: "LRQO_ENOMEM", -3: "LRQO_EDEVICE",
-          -4: "LRQO_ETOOBIG", -5: "LRQO_ENOTFINITE"}
+          -4: "LRQO_ETOOBIG", -5: "LRQO_ENOTFINITE", -6: "LRQO_EDEGENERATE"}
 
 # every entry point declared in include/lrqo.h
 EXPORTS = ("lrqo_version", "lrqo_last_error", "lrqo_set_stream", "lrqo_shutdown",
-           "lrqo_solve_sampled", "lrqo_solve_sampled_ex", "lrqo_solve_exact",
+           "lrqo_solve_sampled", "lrqo_solve_sampled_ex", "lrqo_solve_sampled_noalloc", "lrqo_solve_exact",
            "lrqo_solve_exact_ex", "lrqo_solve_batched", "lrqo_proposal_param_count",
            "lrqo_proposal_create", "lrqo_proposal_destroy", "lrqo_proposal_get_state",
            "lrqo_proposal_set_state", "lrqo_proposal_train_step", "lrqo_proposal_sample",
@@ -41,7 +41,9 @@ class SampledOptions(ctypes.Structure):
     _fields_ = [("real_v", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rescore_topk", ctypes.c_int32), ("instance", ctypes.c_uint32),
                 ("first_index", ctypes.c_uint64), ("f_out", ctypes.c_void_p),
-                ("directions", ctypes.c_void_p)]
+                ("directions", ctypes.c_void_p), ("dirs_out", ctypes.c_void_p),
+                ("probe_count", ctypes.c_int32), ("probe_pad", ctypes.c_int32),
+                ("probe", ctypes.c_void_p), ("probe_labels", ctypes.c_void_p)]
 
 
 class SampledResult(ctypes.Structure):
@@ -55,7 +57,7 @@ class SampledResult(ctypes.Structure):
 class ExactResult(ctypes.Structure):
     _fields_ = [("obj", ctypes.c_double), ("index_sets", ctypes.c_int64),
                 ("rank_deficient", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                ("device_ms", ctypes.c_float)]
+                ("device_ms", ctypes.c_float), ("warning", ctypes.c_int32)]
 
 
 class BatchOptions(ctypes.Structure):
@@ -131,6 +133,8 @@ def load(path: str = LIB_PATH):
                                           ctypes.POINTER(SampledOptions), vp,
                                           ctypes.POINTER(SampledResult)]
     lib.lrqo_solve_sampled_ex.restype = i32
+    lib.lrqo_solve_sampled_noalloc.argtypes = lib.lrqo_solve_sampled_ex.argtypes
+    lib.lrqo_solve_sampled_noalloc.restype = i32
     lib.lrqo_solve_exact.argtypes = [vp, i64, i32, i32, vp, ctypes.POINTER(ctypes.c_double)]
     lib.lrqo_solve_exact.restype = i32
     lib.lrqo_solve_exact_ex.argtypes = [vp, i64, i32, i32, i64, vp, ctypes.POINTER(ExactResult)]
@@ -225,21 +229,35 @@ def _factor_view(V, real):
 
 def solve_sampled(V, K: int, S: int, seed: int, *, real: bool | None = None, precision: int = 0,
                   topk: int = 64, instance: int = 0, first_index: int = 0, f_out=None,
-                  z=None, directions=None) -> SampledOutput:
-    """Best of S sampled directions (see lrqo_solve_sampled_ex)."""
+                  z=None, directions=None, dirs_out=None, probe=None, probe_labels=None,
+                  noalloc: bool = False) -> SampledOutput:
+    """Best of S sampled directions (see lrqo_solve_sampled_ex).  dirs_out
+    (float32 device (S, 2r)) receives the scored FP32 directions; probe (host
+    ints) and probe_labels (uint16 device (len(probe), n)) the scorer's
+    per-row labels of those candidates.  noalloc: through
+    lrqo_solve_sampled_noalloc (static scratch, no allocation)."""
+    import numpy as np
     import torch
 
     lib = load()
     Vf, n, r, is_real = _factor_view(V, real)
     if z is None:
         z = torch.empty(n, dtype=torch.uint8, device=V.device)
+    pr = np.ascontiguousarray(probe if probe is not None else [], dtype=np.int64)
+    if pr.size and (probe_labels is None or probe_labels.dtype != torch.uint16
+                    or probe_labels.numel() != pr.size * n):
+        raise ValueError("probe_labels must be a uint16 device tensor of len(probe) * n entries")
     opt = SampledOptions(1 if is_real else 0, int(precision), int(topk), int(instance),
                          int(first_index), ctypes.c_void_p(f_out.data_ptr() if f_out is not None else 0),
-                         ctypes.c_void_p(directions.data_ptr() if directions is not None else 0))
+                         ctypes.c_void_p(directions.data_ptr() if directions is not None else 0),
+                         ctypes.c_void_p(dirs_out.data_ptr() if dirs_out is not None else 0),
+                         int(pr.size), 0, pr.ctypes.data_as(ctypes.c_void_p) if pr.size else None,
+                         ctypes.c_void_p(probe_labels.data_ptr() if pr.size else 0))
     res = SampledResult()
     with torch.cuda.device(V.device):
         _bind_stream(torch)
-        _check(lib.lrqo_solve_sampled_ex(ctypes.c_void_p(Vf.data_ptr()), n, r, int(K), int(S),
+        entry = lib.lrqo_solve_sampled_noalloc if noalloc else lib.lrqo_solve_sampled_ex
+        _check(entry(ctypes.c_void_p(Vf.data_ptr()), n, r, int(K), int(S),
                                          int(seed) & (2**64 - 1), ctypes.byref(opt),
                                          ctypes.c_void_p(z.data_ptr()), ctypes.byref(res)))
     c = [complex(res.best_c[2 * j], res.best_c[2 * j + 1]) for j in range(r)]

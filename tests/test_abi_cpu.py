@@ -44,22 +44,36 @@ def test_version_and_error_text(lib):
     assert isinstance(lib.lrqo_last_error(), bytes)
 
 
-def _sampled(lib, V=1, n=10, r=2, K=3, S=16, z=1, opt=None):
+def _sampled(lib, V=1, n=10, r=2, K=3, S=16, z=1, opt=None, entry="lrqo_solve_sampled_ex"):
     res = lrqo.SampledResult()
-    return lib.lrqo_solve_sampled_ex(ctypes.c_void_p(V), n, r, K, S, 1,
-                                     ctypes.byref(opt) if opt is not None else None,
-                                     ctypes.c_void_p(z), ctypes.byref(res))
+    return getattr(lib, entry)(ctypes.c_void_p(V), n, r, K, S, 1,
+                               ctypes.byref(opt) if opt is not None else None,
+                               ctypes.c_void_p(z), ctypes.byref(res))
 
 
+@pytest.mark.parametrize("entry", ["lrqo_solve_sampled_ex", "lrqo_solve_sampled_noalloc"])
 @pytest.mark.parametrize("kw,msg", [
     (dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(n=0), "n must"),
     (dict(n=2**31), "n must"), (dict(r=0), "r must"), (dict(r=9), "r must"),
     (dict(K=1), "K must"), (dict(K=256), "K must"), (dict(S=0), "S must"),
     (dict(S=2**32), "S must"),
 ])
-def test_sampled_rejects_bad_arguments(lib, kw, msg):
-    assert _sampled(lib, **kw) == -1
+def test_sampled_rejects_bad_arguments(lib, kw, msg, entry):
+    assert _sampled(lib, entry=entry, **kw) == -1
     assert msg in lrqo.last_error()
+
+
+def test_sampled_rejects_bad_probes(lib):
+    import numpy as np
+
+    o = lrqo.SampledOptions(0, 0, 0, 0, 0, None, None, None, 65, 0, None, None)
+    assert _sampled(lib, opt=o) == -1 and "probe_count" in lrqo.last_error()
+    o = lrqo.SampledOptions(0, 0, 0, 0, 0, None, None, None, 1, 0, None, None)
+    assert _sampled(lib, opt=o) == -1 and "probe and probe_labels" in lrqo.last_error()
+    pos = np.array([3, 16], dtype=np.int64)
+    o = lrqo.SampledOptions(0, 0, 0, 0, 0, None, None, None, 2, 0, pos.ctypes.data_as(ctypes.c_void_p),
+                            ctypes.c_void_p(8))
+    assert _sampled(lib, opt=o, S=16) == -1 and "probe positions" in lrqo.last_error()
 
 
 def test_sampled_rejects_bad_options(lib):

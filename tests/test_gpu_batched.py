@@ -154,8 +154,9 @@ def test_autotuner_cache(lrqo_mod, tmp_path, monkeypatch):
 
 def test_psk_batch_workload(lrqo_mod, tmp_path, monkeypatch):
     """Workload: 4,096 PSK-shaped instances, n ~ U{16..256}, r ~ U{2,3,4},
-    K = 8, S = 4,096 each, one persistent launch; 24 instances checked
-    against the oracle in full, every objective checked to be finite."""
+    K = 8, S = 4,096 each, one persistent launch; every instance checked
+    against the oracle in full (labels at the winner, FP64 objective there,
+    best of its 4,096 directions within 1e-5)."""
     monkeypatch.setenv("LRQO_TUNE_CACHE", str(tmp_path / "tune.json"))
     b = inputs.psk_batch()
     cat, offs = b.device_layout()
@@ -164,7 +165,7 @@ def test_psk_batch_workload(lrqo_mod, tmp_path, monkeypatch):
     assert out.row_candidates == int(b.n.sum()) * b.S
     z = out.z.cpu().numpy()
     zo = np.concatenate([[0], np.cumsum(b.n)])
-    for t in np.random.default_rng(0).choice(b.count, 24, replace=False):
+    for t in range(b.count):
         V = b.factor(int(t)).astype(np.complex64).astype(np.complex128)
         _check_instance(lrqo_mod, V, b.K, b.S, b.seed, int(t), out.obj[t], out.best_index[t],
                         z[zo[t]:zo[t + 1]])

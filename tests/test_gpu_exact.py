@@ -7,12 +7,24 @@ rotation; conjugation too for a real factor), and the enumeration statistics
 (valid index sets, rank-deficient sets, scored label vectors) match the
 oracle's counts exactly.
 """
+import os
+from math import comb
+
 import numpy as np
 import pytest
 
 import oracle
 from oracle import brute, exact, rank1
 from paper_2602_20376_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_counts():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "valid_set_counts.txt"))
+            if l.strip() and not l.startswith("#")]
+    return {(int(a), int(b), int(c)): int(d) for a, b, c, d in rows}
+
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -137,6 +149,86 @@ def test_exact_degenerate_duplicate_rows(lrqo_mod):
     opt, _, _ = brute.brute_force(V, 3)
     assert abs(res.obj - opt) <= 1e-12 * opt
     assert res.rank_deficient > 0
+    assert res.warning == -6            # LRQO_EDEGENERATE: general position violated
+
+
+def test_exact_general_position_no_warning(lrqo_mod):
+    V = inputs.random_V(9, 2, 78)
+    _, res = _solve(lrqo_mod, V, 3)
+    assert res.rank_deficient == 0 and res.warning == 0
+
+
+@pytest.mark.parametrize("n,r,K", [(12, 2, 3), (16, 2, 3), (20, 2, 3), (9, 3, 3), (13, 2, 4), (14, 1, 7)])
+def test_exact_fused_form_vs_oracle(lrqo_mod, n, r, K, monkeypatch):
+    """The fused scorer (one pass over all rows per set, the form large
+    enumerations take) forced at small n: optimum, labels and every count
+    equal to the oracle's."""
+    monkeypatch.setenv("LRQO_EXACT_FORM", "fused")
+    V = inputs.random_V(n, r, 600 + 7 * n + r + K)
+    z, res = _solve(lrqo_mod, V, K)
+    _check(V, K, z, res)
+
+
+@pytest.mark.parametrize("chunk,form", [(1, ""), (7, "fused"), (1000, ""), (1000, "fused"), (4096, "")])
+def test_exact_chunked_shortlist(lrqo_mod, chunk, form, monkeypatch):
+    """The sets taken in chunks, each chunk's best distinct scores merged into
+    the shortlist (chunk = 1: every set merged on its own; 7: ragged
+    chunks), against the oracle on the 12 x 2 workload and the brute force."""
+    monkeypatch.setenv("LRQO_EXACT_CHUNK", str(chunk))
+    if form:
+        monkeypatch.setenv("LRQO_EXACT_FORM", form)
+    inst = inputs.exact_small()
+    z, res = _solve(lrqo_mod, inst.V, 3)
+    _check(inst.V, 3, z, res)
+    assert res.index_sets == _golden_counts()[(12, 2, 3)]
+
+
+def test_exact_counts_closed_form(lrqo_mod):
+    """Valid index sets equal the closed form at several sizes (golden values
+    evaluated by hand, and the formula beyond them)."""
+    gold = _golden_counts()
+    for (n, r, K) in [(12, 2, 3), (6, 2, 3), (10, 1, 4)]:
+        V = inputs.random_V(n, r, 40 + n)
+        _, res = _solve(lrqo_mod, V, K)
+        assert res.index_sets == gold[(n, r, K)]
+    B = 3
+    for n in (64, 160):
+        V = inputs.random_V(n, 2, 4000 + n)
+        _, res = _solve(lrqo_mod, V, 3)
+        want = n * B + comb(n, 3) * B ** 3 + n * comb(B, 2) * (n - 1) * B
+        assert res.index_sets == want
+
+
+def test_exact_cap_and_force(lrqo_mod):
+    """Above the cap the call is refused before device work; a negative cap
+    lifts it (n = 1,200 at r = 2, K = 3: 7.8e9 sets, refused under
+    max_sets = 10^9)."""
+    V = torch.from_numpy(inputs.random_V(1200, 2, 5)).cuda()
+    with pytest.raises(lrqo_mod.LrqoError, match="ETOOBIG"):
+        lrqo_mod.solve_exact(V, 3, max_sets=10 ** 9)
+    small = torch.from_numpy(inputs.random_V(30, 2, 6)).cuda()
+    with pytest.raises(lrqo_mod.LrqoError, match="ETOOBIG"):
+        lrqo_mod.solve_exact(small, 3, max_sets=1000)
+    _, res = lrqo_mod.solve_exact(small, 3, max_sets=-1)
+    assert res.index_sets == 30 * 3 + comb(30, 3) * 27 + 30 * 3 * 29 * 3
+
+
+@pytest.mark.parametrize("n", [1000, 1500])
+def test_exact_beyond_2_32_sets(lrqo_mod, n):
+    """Rank-2 exact enumeration at the sizes of the paper's GPU campaign
+    (n = 1,000: 4.5e9 index sets; n = 1,500: 1.5e10, both beyond 32-bit set
+    indices), K = 3: every set enumerated (the count equals the closed form),
+    the FP64 objective of the returned labels is the returned objective, and
+    the exact optimum is at least the best of 2^20 sampled directions."""
+    V = inputs.random_V(n, 2, 7000 + n)
+    z, res = _solve(lrqo_mod, V, 3)
+    print(f"exact n={n}: {res.index_sets} sets in {res.device_ms:.0f} ms, obj {res.obj!r}", flush=True)
+    assert res.index_sets == _golden_counts()[(n, 2, 3)]
+    assert res.rank_deficient == 0 and res.warning == 0
+    assert abs(oracle.objective(V, 3, z) - res.obj) <= 1e-11 * res.obj
+    samp = lrqo_mod.solve_sampled(torch.from_numpy(V.astype(np.complex64)).cuda(), 3, 1 << 20, 99 + n)
+    V32 = V.astype(np.complex64).astype(np.complex128)
+    assert oracle.objective(V32, 3, z) >= oracle.objective(V32, 3, samp.z.cpu().numpy()) * (1 - 1e-6)
 
 
 def test_exact_nonfinite(lrqo_mod):

@@ -1,19 +1,22 @@
 """GPU parity of the precision form (BF16 MFMA for V c, FP32 recompute of
 rows inside the BF16 error margin, FP64 rescore) through the C-ABI.
 
-Bar: the same as the FP32 sampled path against the FP64 oracle (labels at
-the returned direction bit-exact away from boundaries; objective equal to the
-oracle's f at that direction to 1e-12; within 1e-5 of the oracle's best of
-the same S), plus: every per-candidate FP32 score of the precision form
-equals the plain FP32 path's score within the FP32 summation bound, which a
-row labelled from a wrong BF16 value (unflagged inside its margin) would
-break by a whole label flip.
+Bar: the sampled path's bar against the FP64 oracle (returned labels, FP64
+objective at the returned direction, best of the same S within 1e-5), and:
+  * every FP32 score of the precision form lies inside the oracle's interval
+    over the labels the FP32 reach leaves open (plus the accumulation
+    allowance): a row labelled from a wrong BF16 value would leave it;
+  * for probed candidates, every row the precision form did not recompute
+    carries the FP32 scorer's label (bit-exact), and every row outside the
+    FP32 reach carries the FP64 label.
 """
 import numpy as np
 import pytest
 
+import oracle
+import parity_helpers as PH
 from paper_2602_20376_amd import inputs
-from test_gpu_sampled import _check_f32, _fp32_exact, _to_dev, check_result
+from test_gpu_sampled import _fp32_exact, _to_dev, check_result
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -29,25 +32,47 @@ def lrqo_mod():
     return lrqo
 
 
-def _both(lrqo_mod, V, K, S, seed, real):
+def _both(lrqo_mod, V, K, S, seed, real, n_probes=8):
+    """FP32 and precision-form solves of the same stream with scores,
+    directions and the probed candidates' labels."""
+    n, r = V.shape
     Vd = _to_dev(V, real)
-    f0 = torch.empty(S, dtype=torch.float32, device="cuda")
-    f1 = torch.empty(S, dtype=torch.float32, device="cuda")
-    a = lrqo_mod.solve_sampled(Vd, K, S, seed, real=real, f_out=f0)
-    b = lrqo_mod.solve_sampled(Vd, K, S, seed, real=real, precision=1, f_out=f1)
-    return a, b, f0.cpu().numpy().astype(np.float64), f1.cpu().numpy().astype(np.float64)
+    runs = []
+    for prec in (0, 1):
+        f = torch.empty(S, dtype=torch.float32, device="cuda")
+        d = torch.empty((S, 2 * r), dtype=torch.float32, device="cuda")
+        out = lrqo_mod.solve_sampled(Vd, K, S, seed, real=real, precision=prec, f_out=f, dirs_out=d)
+        runs.append([out, f.cpu().numpy().astype(np.float64), PH.dirs_complex(d.cpu().numpy(), r)])
+    a, b = runs
+    assert np.array_equal(a[2], b[2]), "both forms score the same directions"
+    rng = np.random.default_rng(S + 7 * n)
+    probe = sorted(set(rng.choice(S, min(S, n_probes), replace=False).tolist())
+                   | {a[0].best_index, b[0].best_index} | set(np.argsort(b[1])[-4:].tolist()))[:64]
+    labs = []
+    for prec, run in ((0, a), (1, b)):
+        lab = torch.empty((len(probe), n), dtype=torch.uint16, device="cuda")
+        f = torch.empty(S, dtype=torch.float32, device="cuda")
+        lrqo_mod.solve_sampled(Vd, K, S, seed, real=real, precision=prec, f_out=f, probe=probe, probe_labels=lab)
+        assert np.array_equal(f.cpu().numpy().astype(np.float64), run[1]), "probed launch scores differently"
+        labs.append(lab.cpu().numpy())
+    return a, b, probe, labs
 
 
-def _scores_agree(V, fa, fb, max_frac=0.005):
-    """FP32 scores of the two paths within the FP32 summation bound; a few
-    candidates may differ where the two FP32 label computations (different
-    rounding of w) split a row that sits within ~1e-7 of a boundary."""
-    n = V.shape[0]
-    u = 2.0 ** -24
-    scale = np.sum(np.sum(np.abs(V), axis=0) ** 2)
-    tol = 8.0 * (n + 16) * u * scale + 1e-6 * np.abs(fa)
-    bad = np.abs(fa - fb) > tol
-    assert np.mean(bad) <= max_frac, (int(bad.sum()), fa.size)
+def _check_probes(V, K, dirs, probe, lab32, lab16):
+    """Unflagged BF16 rows carry the FP32 label; all rows outside the FP32
+    reach carry the FP64 label.  Returns (rows compared, rows recomputed)."""
+    V = _fp32_exact(V)
+    flagged = 0
+    compared = 0
+    for t, pos in enumerate(probe):
+        fl = (lab16[t] & 0x100) != 0
+        flagged += int(fl.sum())
+        same = (lab16[t] & 0xFF) == (lab32[t] & 0xFF)
+        assert np.all(same[~fl]), (pos, np.nonzero(~same & ~fl)[0][:5].tolist())
+        compared += int((~fl).sum())
+        PH.check_labels(V, K, dirs[pos], lab16[t])
+        PH.check_labels(V, K, dirs[pos], lab32[t])
+    return compared, flagged
 
 
 CASES = [
@@ -61,6 +86,8 @@ CASES = [
     (200, 4, 4, 1024, False),
     (400, 2, 2, 1000, True),
     (129, 2, 2, 999, True),
+    (3000, 3, 3, 2000, False),
+    (2500, 4, 5, 1500, False),
 ]
 
 
@@ -68,20 +95,23 @@ CASES = [
 def test_precision_parity(lrqo_mod, n, r, K, S, real):
     seed = 9100 + 7 * n + r + K
     V = _fp32_exact(inputs.random_V(n, r, seed, real=real))
-    a, b, fa, fb = _both(lrqo_mod, V, K, S, seed, real)
-    check_result(V, K, S, seed, b, real=real, f32=fb)
-    _scores_agree(V, fa, fb)
-    assert abs(b.obj - a.obj) <= 1e-5 * a.obj
-    assert b.flagged_rows >= 0
+    a, b, probe, (l32, l16) = _both(lrqo_mod, V, K, S, seed, real)
+    (oa, fa, dirs), (ob, fb, _) = a, b
+    check_result(V, K, S, seed, ob, real=real, f32=fb, dirs=dirs)
+    PH.check_scores(V, K, dirs, fa)
+    _check_probes(V, K, dirs, probe, l32, l16)
+    assert abs(ob.obj - oa.obj) <= 1e-5 * oa.obj
+    assert ob.flagged_rows >= 0
 
 
 def test_precision_flags_rows(lrqo_mod):
     """Rows are flagged (the BF16 margin is not vacuous) and the count is a
     small fraction of all row-candidates."""
     V = _fp32_exact(inputs.random_V(4000, 3, 5))
-    _, b, _, _ = _both(lrqo_mod, V, 3, 8192, 11, False)
+    a, b, probe, (l32, l16) = _both(lrqo_mod, V, 3, 8192, 11, False)
     total = 4000 * 8192
-    assert 0 < b.flagged_rows < 0.05 * total, b.flagged_rows
+    assert 0 < b[0].flagged_rows < 0.05 * total, b[0].flagged_rows
+    _check_probes(V, 3, a[2], probe, l32, l16)
 
 
 def test_precision_rejects_large_r(lrqo_mod):
@@ -92,15 +122,21 @@ def test_precision_rejects_large_r(lrqo_mod):
 
 def test_maxcut_ppm_full_size(lrqo_mod):
     """Workload: 3-block planted partition, n = 1,000,000, r = 3, K = 3,
-    S = 2^20.  Both forms reach the same FP64-rescored objective within
-    1e-5; the oracle scores sampled directions and the winner one by one."""
+    S = 2^20, both forms in the benchmark's launch configuration.  Both reach
+    the same FP64-rescored objective within 1e-5; the oracle scores the
+    contiguous block of the first 8,192 directions (both forms' FP32 scores
+    inside its intervals; the FP64 stream's best over the block); probed
+    candidates row by row."""
     inst = inputs.maxcut_ppm()
-    V = inst.V
-    a, b, fa, fb = _both(lrqo_mod, V, inst.K, inst.S, inst.seed, True)
-    assert abs(b.obj - a.obj) <= 1e-5 * a.obj, (a.obj, b.obj)
-    rng = np.random.default_rng(3)
-    sample = np.unique(np.concatenate([rng.choice(inst.S, 24, replace=False),
-                                       np.argsort(fb)[-8:]]))
-    check_result(V, inst.K, inst.S, inst.seed, b, real=True, f32=fb, full_oracle=False,
-                 sample=sample)
-    _scores_agree(_fp32_exact(V), fa[sample], fb[sample], max_frac=0.05)
+    V = _fp32_exact(inst.V)
+    a, b, probe, (l32, l16) = _both(lrqo_mod, V, inst.K, inst.S, inst.seed, True)
+    (oa, fa, dirs), (ob, fb, _) = a, b
+    assert abs(ob.obj - oa.obj) <= 1e-5 * oa.obj, (oa.obj, ob.obj)
+    blk = np.arange(8192)
+    ref, stats = check_result(V, inst.K, inst.S, inst.seed, ob, real=True, f32=fb, dirs=dirs, full_oracle=False,
+                              block=blk)
+    sa = PH.check_scores(V, inst.K, dirs[blk], fa[blk])
+    compared, flagged = _check_probes(V, inst.K, dirs, probe, l32, l16)
+    print(f"maxcut_ppm: fp32 {oa.obj!r} bf16 {ob.obj!r} block oracle {ref['best_f']!r} "
+          f"max |f32-f|/A fp32 {sa['max_ratio']:.3g} bf16 {stats['max_ratio']:.3g}; probed rows "
+          f"{compared} unflagged equal to FP32, {flagged} recomputed", flush=True)
