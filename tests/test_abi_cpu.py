@@ -94,7 +94,7 @@ def test_simple_entry_rejects_null_obj(lib):
 @pytest.mark.parametrize("kw,msg", [
     (dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=5), "r must"),
     (dict(n=1, r=2), "n must"), (dict(K=1), "K must"), (dict(K=300), "K must"),
-    (dict(n=2**25, r=1), "n must"),
+    (dict(n=2**31, r=1), "n must"),
 ])
 def test_exact_rejects_bad_arguments(lib, kw, msg):
     args = dict(V=1, n=12, r=2, K=3, z=1)
@@ -107,11 +107,20 @@ def test_exact_rejects_bad_arguments(lib, kw, msg):
 
 
 def test_exact_size_cap(lib):
-    """C(n B_K, 2r-1) above the cap is refused before any device work."""
+    """C(n B_K, 2r-1) above the cap is refused before any device work: the
+    default cap 2^34, a positive max_sets, and 2^62 when the cap is lifted."""
     res = lrqo.ExactResult()
     st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(1), 10**6, 4, 3, 0, ctypes.c_void_p(1),
                                  ctypes.byref(res))
     assert st == -4 and "index sets" in lrqo.last_error()
+    # n = 1,700, r = 2, K = 3: sum C(5100, 3) + 5100 = 2.2e10 > 2^34 by default
+    st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(1), 1700, 2, 3, 0, ctypes.c_void_p(1), ctypes.byref(res))
+    assert st == -4
+    st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(1), 30, 2, 3, 1000, ctypes.c_void_p(1), ctypes.byref(res))
+    assert st == -4
+    # lifted: 2^62 still bounds it (C(3 * 10^6, 7) > 2^62 at r = 4)
+    st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(1), 10**6, 4, 3, -1, ctypes.c_void_p(1), ctypes.byref(res))
+    assert st == -4
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
