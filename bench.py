@@ -468,53 +468,95 @@ def form_spectral():
     return out
 
 
-def form_learned(train_count):
+def form_learned(train_count, held_out: int = 11):
     """Learned proposal against uniform sampling on phase synchronisation
-    (n = 262,144, r = 3, K = 16): samples needed to reach 99.9% of the best
-    objective found by either (uniform budget 2^20, learned budget 2^16)."""
+    (n = 262,144, r = 3, K = 16) on the top-3 factors of U U^H + sigma W (the
+    library's matrix-free Lanczos) of `held_out` instances the network never
+    saw.  Per instance: the reference is the best objective either sampler
+    finds at its maximum budget (uniform 2^20, learned 2^16); each sampler's
+    knee is the number of directions its running best needs to reach 99.9% of
+    the reference; then each is timed end to end at its own knee budget (the
+    learned side with its inference: gauge frame, network, sampling) and must
+    reach 99.9% of the reference there.  Medians over the instances."""
     import numpy as np
     import torch
 
-    from paper_2602_20376_amd import inputs, lrqo
+    from paper_2602_20376_amd import lrqo, phase_sync
     from paper_2602_20376_amd import proposal as drv
 
     prop, hist, phases = drv.train_default(count=train_count)
-    inst = inputs.phase_sync()
-    Vd = torch.from_numpy(inst.V.astype(np.complex64)).cuda()
-    SU, SL = inst.S, 1 << 16
-    fu = torch.empty(SU, device="cuda")
-    fl = torch.empty(SL, device="cuda")
-    ou = lrqo.solve_sampled(Vd, inst.K, SU, inst.seed, f_out=fu)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    dirs = prop.sample(Vd, SL, inst.seed, uniform_fraction=1.0 / 16)
-    torch.cuda.synchronize()
-    t_infer = (time.perf_counter() - t) * 1000.0
-    ol = lrqo.solve_sampled(Vd, inst.K, SL, inst.seed, directions=dirs, f_out=fl)
-    ref = max(ou.obj, ol.obj)
+    n, K, SU, SL = 262_144, 16, 1 << 20, 1 << 16
+    frac_uniform = 1.0 / 16
+
+    def timed(fn, S, reps=5):
+        ts, out = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn(S)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1000.0)
+        return float(np.median(ts)), out
+
+    per = []
+    factor_ms = []
+    infer_ms = []
+    for t in range(held_out):
+        t0 = time.perf_counter()
+        V = phase_sync.fp32_factor(n, 6000 + t)
+        factor_ms.append((time.perf_counter() - t0) * 1000.0)
+        Vd = torch.from_numpy(V.astype(np.complex64)).cuda()
+        dseed = 2005 + t
+        fu = torch.empty(SU, device="cuda")
+        fl = torch.empty(SL, device="cuda")
+        ou = lrqo.solve_sampled(Vd, K, SU, dseed, f_out=fu)
+        torch.cuda.synchronize()
+        ti = time.perf_counter()
+        dirs = prop.sample(Vd, SL, dseed, uniform_fraction=frac_uniform)
+        torch.cuda.synchronize()
+        infer_ms.append((time.perf_counter() - ti) * 1000.0)
+        ol = lrqo.solve_sampled(Vd, K, SL, dseed, directions=dirs, f_out=fl)
+        ref = max(ou.obj, ol.obj)
+        ku = drv.knee(fu.cpu().numpy(), ref)
+        kl = drv.knee(fl.cpu().numpy(), ref)
+
+        def run_u(S):
+            return lrqo.solve_sampled(Vd, K, S, dseed)
+
+        def run_l(S):
+            d = prop.sample(Vd, S, dseed, uniform_fraction=frac_uniform)
+            return lrqo.solve_sampled(Vd, K, S, dseed, directions=d)
+
+        tu, o_u = timed(run_u, ku or SU)
+        tl, o_l = timed(run_l, kl or SL)
+        per.append({"instance": 6000 + t, "ref_obj": ref, "uniform_best": ou.obj, "learned_best": ol.obj,
+                    "knee_uniform": ku, "knee_learned": kl, "ms_uniform": tu, "ms_learned": tl,
+                    "uniform_reached": bool(o_u.obj >= 0.999 * ref), "learned_reached": bool(o_l.obj >= 0.999 * ref),
+                    "speedup": tu / tl})
     from oracle import proposal as OP
 
     theta = prop.get_state()["theta"].astype(np.float64)
+    V0 = phase_sync.fp32_factor(n, 6000)
 
     def oracle_infer():
-        G, s_ = OP.canonical_frame(inst.V, inst.K)
-        return OP.forward(theta, OP.features(inst.V, G, s_))
+        G, s_ = OP.canonical_frame(V0, K)
+        return OP.forward(theta, OP.features(V0, G, s_))
 
     oms, _ = _timed(oracle_infer)
-    ku = drv.knee(fu.cpu().numpy(), ref)
-    kl = drv.knee(fl.cpu().numpy(), ref)
-    row_rate = inst.n * SU / (ou.score_ms / 1000.0)
-    return {"workload": "phase_sync", "n": inst.n, "r": inst.r, "K": inst.K,
-            "uniform_S": SU, "learned_S": SL, "uniform_obj": ou.obj, "learned_obj": ol.obj,
-            "samples_to_99.9pct_uniform": ku, "samples_to_99.9pct_learned": kl,
-            "sample_ratio_uniform_over_learned": (ku / kl) if (ku and kl) else None,
-            "learned_inference_ms": t_infer, "uniform_candidate_rows_per_s": row_rate,
-            # time to 99.9% of the best: the knee's samples at the measured
-            # scoring rate on this factor, plus inference for the learned side
-            "time_to_99.9pct_uniform_ms": (ku * inst.n / row_rate * 1000.0) if ku else None,
-            "time_to_99.9pct_learned_ms": (t_infer + kl * inst.n / row_rate * 1000.0) if kl else None,
+    med = lambda key: float(np.median([p[key] for p in per if p[key] is not None]))
+    return {"workload": "phase_sync (top-3 factor of U U^H + sigma W by the GPU Lanczos)", "n": n, "r": 3,
+            "K": K, "uniform_S": SU, "learned_S": SL, "held_out_instances": held_out,
+            "median_knee_uniform": med("knee_uniform"), "median_knee_learned": med("knee_learned"),
+            "median_ms_uniform": med("ms_uniform"), "median_ms_learned": med("ms_learned"),
+            "median_speedup": med("speedup"),
+            "learned_reached_all": all(p["learned_reached"] for p in per),
+            "uniform_reached_all": all(p["uniform_reached"] for p in per),
+            "learned_at_least_uniform_best": int(sum(p["learned_best"] >= p["uniform_best"] * (1 - 1e-9) for p in per)),
+            "median_inference_ms": float(np.median(infer_ms)),
+            "median_factor_ms": float(np.median(factor_ms)),
+            "per_instance": per,
             "oracle": {"kind": "oracle", "inference_ms": oms,
-                       "sample": "gauge frame, features and network forward on the same factor (FP64)"},
+                       "sample": "gauge frame, features and network forward on one held-out factor (FP64)"},
             "train_instances": train_count, "train_final_loss": hist[-1], "train_first_loss": hist[0],
             **{k: round(v, 2) for k, v in phases.items()}}
 
@@ -625,12 +667,14 @@ def main():
         rec["forms"] = forms
         lp = forms.get("learned_proposal", {})
         rec["secondary_metric"] = {
-            "metric": "samples to 99.9% of best obj, learned vs uniform",
-            "uniform": lp.get("samples_to_99.9pct_uniform"),
-            "learned": lp.get("samples_to_99.9pct_learned"),
-            "time_ms_uniform": lp.get("time_to_99.9pct_uniform_ms"),
-            "time_ms_learned_with_inference": lp.get("time_to_99.9pct_learned_ms"),
-            "workload": "phase_sync n=262144 r=3 K=16"}
+            "metric": "samples to 99.9% of best obj, learned vs uniform (median over held-out instances)",
+            "uniform": lp.get("median_knee_uniform"),
+            "learned": lp.get("median_knee_learned"),
+            "time_ms_uniform": lp.get("median_ms_uniform"),
+            "time_ms_learned_with_inference": lp.get("median_ms_learned"),
+            "median_speedup": lp.get("median_speedup"),
+            "instances": lp.get("held_out_instances"),
+            "workload": "phase_sync n=262144 r=3 K=16 (true top-3 factors)"}
     print(json.dumps(rec), flush=True)
 
 

@@ -15,7 +15,10 @@
  * current HIP device; host arguments are ordinary host memory.  The caller
  * owns all of them; the library never frees or keeps caller memory.  The
  * library's own scratch (per device, grown on demand) is released by
- * lrqo_shutdown().
+ * lrqo_shutdown().  The environment variable LRQO_ARENA_LIMIT (bytes), read
+ * at every call, caps the scratch one call may need: a call needing more
+ * returns LRQO_ENOMEM before any device work (as it does when the device
+ * allocation itself fails).
  *
  * Ordering: work is enqueued on the stream set by lrqo_set_stream (the null
  * stream by default) and every solve call synchronises that stream before it

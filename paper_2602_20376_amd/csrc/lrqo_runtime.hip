@@ -1,6 +1,7 @@
 // Host runtime of liblrqo: error text, stream, per-device scratch.
 #include "lrqo_runtime.h"
 
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 
@@ -46,7 +47,20 @@ DeviceCtx* device_ctx() {
     return g_ctx[dev];
 }
 
+// Upper bound on one call's device scratch, from LRQO_ARENA_LIMIT (bytes; a
+// positive integer, read at every call); 0 means none.
+size_t arena_limit() {
+    const char* e = std::getenv("LRQO_ARENA_LIMIT");
+    if (!e || !*e) return 0;
+    const long long v = std::atoll(e);
+    return v > 0 ? (size_t)v : 0;
+}
+
 lrqo_status reserve_arena(DeviceCtx* ctx, size_t bytes) {
+    const size_t limit = arena_limit();
+    if (limit && bytes > limit)
+        return fail(LRQO_ENOMEM, "device scratch of " + std::to_string(bytes) + " bytes exceeds LRQO_ARENA_LIMIT (" +
+                                     std::to_string(limit) + " bytes)");
     if (bytes <= ctx->arena_bytes) return LRQO_OK;
     if (ctx->arena) {
         LRQO_HIP(hipDeviceSynchronize());

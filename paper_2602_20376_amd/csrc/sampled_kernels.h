@@ -47,23 +47,34 @@ __device__ __forceinline__ int root_index(float zr, float zi, int K) {
 template <int R, int CPL, bool PROBE>
 __device__ __forceinline__ void lane_directions(const ScoreParams& p, uint32_t base, uint32_t stride, bool writer,
                                                 float (&c)[CPL][2 * R], int (&slot)[CPL]) {
+    // generation alone in its loop, so that it unrolls and c stays in registers
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
         const uint32_t idx = base + q * stride;
-        slot[q] = -1;
         if (idx < p.S) {
             direction_any<R>(p.dirs, p.seed, p.first + idx, p.instance, c[q]);
-            if (p.dirs_out && writer) {
-#pragma unroll
-                for (int j = 0; j < 2 * R; ++j) p.dirs_out[(size_t)idx * (2 * R) + j] = c[q][j];
-            }
-            if constexpr (PROBE) {
-                for (int t = 0; t < p.probe_count; ++t)
-                    if (p.probe_idx[t] == idx) slot[q] = t;
-            }
         } else {
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) c[q][j] = 0.0f;
+        }
+    }
+    if (p.dirs_out && writer) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+            const uint32_t idx = base + q * stride;
+            if (idx < p.S) {
+#pragma unroll
+                for (int j = 0; j < 2 * R; ++j) p.dirs_out[(size_t)idx * (2 * R) + j] = c[q][j];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+        slot[q] = -1;
+        if constexpr (PROBE) {
+            const uint32_t idx = base + q * stride;
+            for (int t = 0; t < p.probe_count; ++t)
+                if (idx < p.S && p.probe_idx[t] == idx) slot[q] = t;
         }
     }
 }

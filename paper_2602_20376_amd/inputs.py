@@ -18,11 +18,14 @@ Workload shapes (instance seed = 1000 + workload number, direction seed =
 4. ``psk_batch``     4,096 PSK-detection-shaped instances: n ~ U{16..256},
    r ~ U{2,3,4}; Q = H^H H + 0.05 (G + G^H)/sqrt(2), H r x n and G n x n with
    N_C(0,1) entries; top-r eigenpairs of Q; V = U diag(sqrt(max(lambda,0))).
-5. ``phase_sync``    phase synchronisation, n = 262,144, r = 3: the top-3
-   eigenvectors of Q = U U^H + sigma W (U unit-modulus random phases,
-   sigma = 0.5 sqrt(n)) are drawn from their spiked-model law (overlap
-   1 - 1/theta^2 with the planted directions, theta = 2), because the dense
-   n x n eigenproblem is out of reach on a host.
+5. phase synchronisation, n = 262,144, r = 3, K = 16: the top-3 factor of
+   Q = U U^H + sigma W (U unit-modulus random phases, sigma = 0.5 sqrt(n)).
+   The workload factor itself is computed by the library's matrix-free
+   Lanczos (paper_2602_20376_amd/phase_sync.py); this module only draws the
+   surrogate ``phase_sync_factor`` from the spiked-model law of those
+   eigenvectors (overlap 1 - 1/theta^2 with the planted directions,
+   theta = 2), used for the proposal network's training set and for unit
+   tests of the network.
 """
 from __future__ import annotations
 
@@ -32,7 +35,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-WORKLOADS = ("exact_small", "maxcut_er", "maxcut_ppm", "psk_batch", "phase_sync")
+WORKLOADS = ("exact_small", "maxcut_er", "maxcut_ppm", "psk_batch")
 
 
 def instance_seed(workload_no: int) -> int:
@@ -360,12 +363,6 @@ def phase_sync_factor(n: int, r: int, seed: int, theta: float = 2.0) -> np.ndarr
     lam = sigma * np.sqrt(n) * (theta + 1.0 / theta) * (1.0 + 0.01 * rng.standard_normal(r))
     lam = np.sort(lam)[::-1]
     return (E * np.sqrt(lam)[None, :]).astype(np.complex64).astype(np.complex128)
-
-
-def phase_sync(n: int = 262_144, r: int = 3, K: int = 16, S: int = 1 << 20, seed=None) -> Instance:
-    s = instance_seed(5) if seed is None else seed
-    V = _cached(f"phase_sync:{n}:{r}:{s}:v1", lambda: phase_sync_factor(n, r, s))
-    return Instance(V, K, S, direction_seed(5), False, f"phase_sync(n={n},r={r},K={K},S={S})")
 
 
 def as_interleaved_f32(V: np.ndarray) -> np.ndarray:

@@ -305,3 +305,16 @@ def test_phase_sync_full_size(lrqo_mod):
                               block=np.arange(8192), probe=probe, labels=lab)
     print(f"phase_sync: best {out.obj!r} block oracle {ref['best_f']!r} max |f32-f|/A {stats['max_ratio']:.3g}",
           flush=True)
+
+
+def test_arena_limit_gives_enomem(lrqo_mod, monkeypatch):
+    """A call whose scratch exceeds LRQO_ARENA_LIMIT returns LRQO_ENOMEM
+    before any device work; without the limit the same call succeeds."""
+    V = inputs.random_V(20_000, 4, 3)
+    Vd = _to_dev(V, False)
+    monkeypatch.setenv("LRQO_ARENA_LIMIT", str(1 << 20))
+    with pytest.raises(lrqo_mod.LrqoError, match="ENOMEM"):
+        lrqo_mod.solve_sampled(Vd, 3, 1 << 18, 1)
+    monkeypatch.delenv("LRQO_ARENA_LIMIT")
+    out = lrqo_mod.solve_sampled(Vd, 3, 1 << 18, 1)
+    assert out.obj > 0
