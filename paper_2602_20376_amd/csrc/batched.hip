@@ -76,7 +76,7 @@ __global__ void k_bfill(unsigned int* cursor) {
 template <int R, int CPL, int KS>
 __device__ void score_item(const BatchDevParams& p, int t, int tile, const float* Vs, int n,
                            const float2* roots) {
-    float c[CPL][2 * R], acc[CPL][2 * R];
+    float c[CPL][2 * R], c3[CPL][2 * R], acc[CPL][2 * R];
     const int base = tile * p.tile + threadIdx.x;
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
@@ -87,7 +87,10 @@ __device__ void score_item(const BatchDevParams& p, int t, int tile, const float
             for (int j = 0; j < 2 * R; ++j) c[q][j] = 0.0f;
         }
 #pragma unroll
-        for (int j = 0; j < 2 * R; ++j) acc[q][j] = 0.0f;
+        for (int j = 0; j < 2 * R; ++j) {
+            acc[q][j] = 0.0f;
+            c3[q][j] = re_prescale(KS) * c[q][j];   // K = 3 and 8: Re w pre-scaled
+        }
     }
     for (int i = 0; i < n; ++i) {
         float v[2 * R];
@@ -99,11 +102,19 @@ __device__ void score_item(const BatchDevParams& p, int t, int tile, const float
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const float vr = v[2 * j], vi = v[2 * j + 1];
-                wr = fmaf(vr, c[q][2 * j], fmaf(-vi, c[q][2 * j + 1], wr));
+                wr = fmaf(vr, c3[q][2 * j], fmaf(-vi, c3[q][2 * j + 1], wr));
                 wi = fmaf(vr, c[q][2 * j + 1], fmaf(vi, c[q][2 * j], wi));
             }
             float zr, zi;
-            nearest_root<KS>(wr, wi, p.K, roots, zr, zi);
+            if constexpr (KS == 3) {
+                const bool k0 = fabsf(wi) <= wr;            // |Im w| <= sqrt(3) Re w
+                zr = k0 ? 1.0f : -0.5f;
+                zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
+            } else if constexpr (KS == 8) {
+                nearest_root_k8t(wr, wi, zr, zi);
+            } else {
+                nearest_root<KS>(wr, wi, p.K, roots, zr, zi);
+            }
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const float vr = v[2 * j], vi = v[2 * j + 1];

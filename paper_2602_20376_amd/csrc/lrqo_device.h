@@ -251,6 +251,25 @@ __device__ __forceinline__ void nearest_root(float wr, float wi, int K, const fl
     }
 }
 
+// K = 8 with the real part of w pre-scaled by t = tan(pi/8) (the caller forms
+// Re w from t c): in the quadrant of w, the x axis (labels 0 or 4) when
+// |Im w| <= t |Re w|, the y axis (2 or 6) when |Re w| <= t |Im w|, the
+// diagonal otherwise; the signs of Re w and Im w pick the quadrant.  One
+// multiply fewer than the unscaled form.
+__device__ __forceinline__ void nearest_root_k8t(float wrt, float wi, float& zr, float& zi) {
+    const float axt = fabsf(wrt), ay = fabsf(wi);
+    const bool h = ay <= axt;
+    const bool v = axt <= 0.17157287525380990f * ay;   // t^2 = 3 - 2 sqrt(2)
+    const float d = 0.70710678118654752f;
+    zr = copysignf(h ? 1.0f : (v ? 0.0f : d), wrt);
+    zi = copysignf(h ? 0.0f : (v ? 1.0f : d), wi);
+}
+
+// Factor on c for the real part of w, matching the pre-scaled quantisers.
+__host__ __device__ constexpr float re_prescale(int KS) {
+    return KS == 3 ? 1.7320508075688772f : (KS == 8 ? 0.41421356237309505f : 1.0f);
+}
+
 // The same closed forms in FP64 for the rescore (any K through label_f64
 // and an FP64 root table).  Away from decision boundaries they agree with
 // label_f64; on a boundary (measure zero) either neighbour may be taken.
