@@ -120,7 +120,7 @@ def _source_hash() -> str:
     import hashlib
 
     h = hashlib.sha1()
-    for f in ("sampled.hip", "sampled_kernels.h", "lrqo_device.h", "sampled_internal.h"):
+    for f in ("sampled_kernels.h", "lrqo_device.h", "sampled_internal.h"):
         with open(os.path.join(ROOT, "paper_2602_20376_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]

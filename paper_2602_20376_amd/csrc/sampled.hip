@@ -25,6 +25,7 @@
 #include "lrqo_runtime.h"
 #include "sampled_internal.h"
 #include "sampled_kernels.h"
+#include "sampled_bf16.h"
 #include "select.h"
 
 #ifndef LRQO_SCORE_BLOCKS
@@ -271,6 +272,10 @@ __global__ __launch_bounds__(kBlock) void k_labels(const float* __restrict__ V, 
 // set of 64*CPL candidates; the vector-ALU scorer's 256 lanes hold distinct ones).
 int cands_per_lane(int R) { return R <= 4 ? LRQO_SCORE_CPL : 1; }
 int cands_per_block(int R) { return R <= 4 ? kWave * cands_per_lane(R) : kBlock * cands_per_lane(R); }
+int cands_per_block(const SampledJob& job) {
+    const bool mfma = job.precision == 1 && job.r <= 4 && (job.K == 2 || job.K == 3 || job.K == 4) && bf16_form() == 0;
+    return mfma ? kBf16xCands : cands_per_block(job.r);
+}
 
 template <int R, bool REAL, int KS>
 void launch_score(const ScoreParams& p, dim3 grid, hipStream_t st) {
@@ -285,9 +290,14 @@ void launch_score(const ScoreParams& p, dim3 grid, hipStream_t st) {
 template <int R, bool REAL, int KS>
 void launch_score_bf16(const ScoreParams& p, dim3 grid, hipStream_t st) {
     if constexpr (R <= 4) {
-        constexpr int CPL = LRQO_SCORE_CPL;
-        hipLaunchKernelGGL((k_score_bf16<R, CPL, REAL, KS, LRQO_BF16_SPLIT, false>), grid, dim3(kBlock), 0, st,
-                           p);
+        if constexpr (KS == 2 || KS == 3 || KS == 4) {
+            if (bf16_form() == 0) {
+                hipLaunchKernelGGL((k_score_bf16x<R, REAL, KS, kBf16xQ, false>), grid, dim3(kBlock), 0, st, p);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_score_bf16<R, LRQO_SCORE_CPL, REAL, KS, LRQO_BF16_SPLIT, false>), grid, dim3(kBlock), 0,
+                           st, p);
     }
 }
 
@@ -319,7 +329,7 @@ void launch_score_k(const ScoreParams& p, dim3 grid, hipStream_t st, int precisi
 template <int R, bool REAL>
 lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     const uint32_t S = (uint32_t)job.S;
-    const int64_t cand_blocks = ((int64_t)S + cands_per_block(R) - 1) / cands_per_block(R);
+    const int64_t cand_blocks = ((int64_t)S + cands_per_block(job) - 1) / cands_per_block(job);
 
     // ---- fused scorer
     ScoreParams p{};
@@ -409,7 +419,7 @@ lrqo_status dispatch_r(const SampledJob& job, Scratch& sc, hipStream_t st) {
 // Plans the launch shapes and the scratch layout of one sampled solve.
 void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     const int R = job.r;
-    const int64_t cand_blocks = (job.S + cands_per_block(R) - 1) / cands_per_block(R);
+    const int64_t cand_blocks = (job.S + cands_per_block(job) - 1) / cands_per_block(job);
     // enough blocks to fill 256 CUs several times over, slices of >= 1024 rows
     int64_t slices = std::max<int64_t>(1, (LRQO_SCORE_BLOCKS + cand_blocks - 1) / cand_blocks);
     slices = std::min<int64_t>(slices, std::max<int64_t>(1, job.n / 1024));

@@ -118,6 +118,12 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan);
 // The scorers with per-row label output for p.probe_count candidates
 // (sampled_probe.hip); same arithmetic as the plain launches.
 void launch_score_probe(const ScoreParams& p, dim3 grid, hipStream_t st, int r, bool real, int precision);
+
+// Layout of the precision form's scorer: 0 = both products on MFMA
+// (k_score_bf16x; K = 2, 3, 4, other K take 1), 1 = V c on 4x4x4 MFMA tiles
+// with V^H z on the vector ALU (k_score_bf16).  LRQO_BF16_FORM = "w4" selects
+// 1 (read once per process).
+int bf16_form();
 lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void* arena, hipStream_t st);
 
 }  // namespace lrqo

@@ -2,9 +2,13 @@
 // (inspection of the decision rule as the scorer applies it).  The kernels
 // are those of sampled_kernels.h with PROBE = true: the same arithmetic, plus
 // a store of each probed candidate's label for every row.
+#include <cstdlib>
+#include <cstring>
+
 #include "lrqo_device.h"
 #include "sampled_internal.h"
 #include "sampled_kernels.h"
+#include "sampled_bf16.h"
 
 namespace lrqo {
 
@@ -23,6 +27,12 @@ void probe_fp32(const ScoreParams& p, dim3 grid, hipStream_t st) {
 template <int R, bool REAL, int KS>
 void probe_bf16(const ScoreParams& p, dim3 grid, hipStream_t st) {
     if constexpr (R <= 4) {
+        if constexpr (KS == 2 || KS == 3 || KS == 4) {
+            if (bf16_form() == 0) {
+                hipLaunchKernelGGL((k_score_bf16x<R, REAL, KS, kBf16xQ, true>), grid, dim3(kBlock), 0, st, p);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_score_bf16<R, LRQO_SCORE_CPL, REAL, KS, LRQO_BF16_SPLIT, true>), grid, dim3(kBlock), 0,
                            st, p);
     }
@@ -65,6 +75,14 @@ void probe_r(const ScoreParams& p, dim3 grid, hipStream_t st, int r, int precisi
 }
 
 }  // namespace
+
+int bf16_form() {
+    static const int form = [] {
+        const char* e = std::getenv("LRQO_BF16_FORM");
+        return e && std::strcmp(e, "w4") == 0 ? 1 : 0;
+    }();
+    return form;
+}
 
 void launch_score_probe(const ScoreParams& p, dim3 grid, hipStream_t st, int r, bool real, int precision) {
     if (real) probe_r<true>(p, grid, st, r, precision);

@@ -88,6 +88,9 @@ CASES = [
     (129, 2, 2, 999, True),
     (3000, 3, 3, 2000, False),
     (2500, 4, 5, 1500, False),
+    (600, 3, 4, 1100, True),
+    (2100, 4, 2, 700, False),
+    (5000, 1, 3, 300, True),
 ]
 
 
@@ -112,6 +115,20 @@ def test_precision_flags_rows(lrqo_mod):
     total = 4000 * 8192
     assert 0 < b[0].flagged_rows < 0.05 * total, b[0].flagged_rows
     _check_probes(V, 3, a[2], probe, l32, l16)
+
+
+@pytest.mark.parametrize("K,real", [(3, True), (3, False), (4, True), (2, False)])
+def test_precision_zero_and_repeated_rows(lrqo_mod, K, real):
+    """Exactly zero rows (never flagged: they add nothing to s whatever their
+    label) and repeated rows, in both forms."""
+    V = _fp32_exact(inputs.random_V(700, 2, 41 + K, real=real))
+    V[::7] = 0
+    V[1::7] = V[2::7]
+    a, b, probe, (l32, l16) = _both(lrqo_mod, V, K, 1500, 43, real)
+    (oa, fa, dirs), (ob, fb, _) = a, b
+    check_result(V, K, 1500, 43, ob, real=real, f32=fb, dirs=dirs)
+    PH.check_scores(V, K, dirs, fb)
+    _check_probes(V, K, dirs, probe, l32, l16)
 
 
 def test_precision_rejects_large_r(lrqo_mod):
