@@ -354,41 +354,49 @@ namespace lrqo {
 namespace {
 
 // ------------------------------------------------------------ precision form, both products on MFMA
-// For K = 2, 3, 4 and r <= 4.  Every K-th root then has coordinates in
-// {0, +-1, -1/2} once Im z is divided by sqrt(3)/2 for K = 3, so the labels
-// are exact in BF16 and s = V^H z runs on the matrix core as well as w = V c.
+// For K = 2, 3, 4 and r <= 4.  V and c enter as three BF16 parts each (hi,
+// mid, lo: an FP32 value is their sum to within 2^-24 of itself), and w is
+// formed from the six products of order up to 2^-16,
+//   hi.hi + mid.hi + hi.mid + lo.hi + hi.lo + mid.mid,
+// so w carries FP32-grade error (the dropped products are of order 2^-24):
+// at most 43 * 2^-24 * sum_j |V_ij| |c_j| with the accumulation charged one
+// FP32 ulp per addition.  The labels are taken from w directly, with no
+// recomputation: away from a decision boundary (beyond the FP32 reach, as for
+// the FP32 scorer) they are the FP64 rule's.  Every K-th root has coordinates
+// in {0, +-1, -1/2} once Im z is divided by sqrt(3)/2 for K = 3, so the labels
+// are exact in BF16 and s = V^H z runs on the matrix core too.
 //
-// w: one v_mfma_f32_32x32x16_bf16 per part (Re w, Im w) and chunk of 16
-// k-slots gives 32 rows x 32 candidates.  The three products of the hi/lo
-// split, V_hi c_hi + V_lo c_hi + V_hi c_lo, lie along k: with C values per row
-// (C = r for a real V; 2r for a complex one, Re V then Im V), slot
-// kappa = tau C + x holds term tau of component x, so one MFMA forms the whole
-// split product when 3C <= 16.  Operand layout (gfx950): lane l supplies row
-// (A) / column (B) l % 32 and k-slots 8 (l / 32) .. 8 (l / 32) + 7; register g
-// of the result is row 8 (g / 4) + 4 (l / 32) + g % 4, column l % 32.
+// w: v_mfma_f32_32x32x16_bf16 gives 32 rows x 32 candidates per part
+// (Re w, Im w) and chunk of 16 k-slots; slot kappa = tau C + x holds product
+// tau of component x (C = r for a real V; 2r for a complex one, Re V then
+// Im V).  Operand layout (gfx950): lane l supplies row (A) / column (B) l % 32
+// and k-slots 8 (l / 32) .. 8 (l / 32) + 7; register g of the result is row
+// 8 (g / 4) + 4 (l / 32) + g % 4, column l % 32.
 //
 // s: with the tile's labels Z, D_r += A2 Z_r and D_i += A2 Z_i on
-// v_mfma_f32_16x16x32_bf16 (16 A2 rows x 16 candidates x 32 rows of V).  Row
-// m = p C + x of A2 holds part p of component x of every row of V in three
-// BF16 parts (hi, mid, lo: |v - hi - mid - lo| <= 2^-24 |v|, the
-// representation error of one FP32 rounding).  The labels come out of the
-// first product as two per dword in the lanes of their candidate; one
-// v_permlane16_swap per pair of dwords moves them into the second product's
-// B layout (lane l: candidate l % 16, k-slots 8 (l / 16) .. + 7), so k-slot
-// (G, t) of the second product is row 8 (g / 4) + 4 (G / 2) + g % 4 with
-// g = 8 (G % 2) + t; A2 is laid out in LDS in that order.  D stays in registers
-// for the whole slice; each candidate's parts are added once at the end.
+// v_mfma_f32_16x16x32_bf16 (16 A2 rows x 16 candidates x 32 rows of V); row
+// m = p C + x of A2 holds part p of component x of every row of V.  The
+// labels come out of the first product two per dword in the lanes of their
+// candidate; one v_permlane16_swap per pair of dwords moves them into the
+// second product's B layout (lane l: candidate l % 16, k-slots 8 (l / 16) ..
+// + 7), so k-slot (G, t) of the second product is row 8 (g / 4) + 4 (G / 2) +
+// g % 4 with g = 8 (G % 2) + t; A2 is laid out in LDS in that order.  D stays
+// in registers for the whole slice; each candidate's parts are added once at
+// the end.
 typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 template <int R, bool REAL>
 struct Split32 {
-    static constexpr int C = REAL ? R : 2 * R;   // values per row
-    static constexpr int N = 3 * C;              // k-slots of the split product
-    static constexpr int NCH = (N + 15) / 16;    // chunks of 16 slots
+    static constexpr int C = REAL ? R : 2 * R;      // values per row
+    static constexpr int N = 6 * C;                 // k-slots of the split product
+    static constexpr int NCH = (N + 15) / 16;       // chunks of 16 slots
     static constexpr int NMB = (3 * C + 15) / 16;   // 16-row blocks of A2
 };
+// The parts (0 hi, 1 mid, 2 lo) of V and of c in product tau.
+__host__ __device__ constexpr int part_v(int tau) { return tau == 1 || tau == 5 ? 1 : (tau == 3 ? 2 : 0); }
+__host__ __device__ constexpr int part_c(int tau) { return tau == 2 || tau == 5 ? 1 : (tau == 4 ? 2 : 0); }
 
 __device__ __forceinline__ v8bf as_bf(v8s x) { return __builtin_bit_cast(v8bf, x); }
 
@@ -406,6 +414,15 @@ __device__ __forceinline__ uint32_t sign_pair(float lo, float hi) {
     return __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x0B0B0909u);
 }
 
+// Three BF16 parts of x: hi = rn(x), mid = rn(x - hi), lo = rn(x - hi - mid)
+// (both differences exact in FP32).
+__device__ __forceinline__ void bf16_split3(float x, unsigned short (&pt)[3]) {
+    pt[0] = bf16_rne(x);
+    const float r1 = x - bf16_to_f32(pt[0]);
+    pt[1] = bf16_rne(r1);
+    pt[2] = bf16_rne(r1 - bf16_to_f32(pt[1]));
+}
+
 template <int R, bool REAL, int KS, int Q, bool PROBE>
 __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
     static_assert(R <= 4, "precision form covers r <= 4");
@@ -415,22 +432,15 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
     constexpr int RF = Row<R, REAL>::F;
     constexpr int C = SP::C, NCH = SP::NCH, NMB = SP::NMB;
     constexpr bool IM = KS != 2;    // K = 2: neither Im w nor Im z is needed
-    constexpr float kappa = bf16_kappa<2>() * 1.0001f;
+    // The quantiser's test value u: K = 3 u = sqrt(3) Re w - |Im w| (label 0
+    // iff u >= 0, else the sign of Im w), with Re w taken from sqrt(3) c;
+    // K = 4 u = |Re w| - |Im w| (a horizontal root iff u >= 0, its sign from
+    // Re w, else from Im w); K = 2 u = Re w.
     constexpr float s3 = re_prescale(KS);
-    // The quantiser's test value u and its error bound tb * kappa ||V_i||:
-    // K = 3: u = sqrt(3) Re w - |Im w| (label 0 iff u >= 0, else the sign of
-    //        Im w), error at most 2 b for a real V and (1 + sqrt(3)) b for a
-    //        complex one (bf16_root); the Im w column is scaled by that same
-    //        factor, so that both tests read min(|u|, |Im w'|) <= tb b;
-    // K = 4: u = |Re w| - |Im w| (a horizontal root iff u >= 0), error 2 b;
-    // K = 2: u = Re w, error b.
-    constexpr float tb = KS == 3 ? (REAL ? 2.0f : 2.7320508075688772f) : (KS == 4 ? 2.0f : 1.0f);
-    constexpr float si = KS == 3 ? tb : 1.0f;
     constexpr float zs = KS == 3 ? 0.8660254037844386f : 1.0f;   // Im z = zs * (packed Im label)
     __shared__ __align__(16) float tile[kTile * RF];
     __shared__ __align__(16) v8s apk[NCH][kTile][2];
     __shared__ __align__(16) unsigned short a2s[kTile / 32][16 * NMB][4][8];
-    __shared__ __align__(16) float bnt[kTile];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
@@ -456,24 +466,19 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
                 dr[q][mb][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
                 di[q][mb][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
             }
-        float br[C], bi[C];
+        unsigned short brp[C][3], bip[C][3];
 #pragma unroll
         for (int x = 0; x < C; ++x) {
+            float br, bi;
             if (REAL || x < R) {
-                br[x] = s3 * c[q][2 * (x % R)];
-                bi[x] = si * c[q][2 * (x % R) + 1];
+                br = s3 * c[q][2 * (x % R)];
+                bi = c[q][2 * (x % R) + 1];
             } else {
-                br[x] = -s3 * c[q][2 * (x - R) + 1];
-                bi[x] = si * c[q][2 * (x - R)];
+                br = -s3 * c[q][2 * (x - R) + 1];
+                bi = c[q][2 * (x - R)];
             }
-        }
-        unsigned short brh[C], brl[C], bih[C], bil[C];
-#pragma unroll
-        for (int x = 0; x < C; ++x) {
-            brh[x] = bf16_rne(br[x]);
-            brl[x] = bf16_rne(br[x] - bf16_to_f32(brh[x]));
-            bih[x] = bf16_rne(bi[x]);
-            bil[x] = bf16_rne(bi[x] - bf16_to_f32(bih[x]));
+            bf16_split3(br, brp[x]);
+            bf16_split3(bi, bip[x]);
         }
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
@@ -485,8 +490,8 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
                     const int kap = 16 * ch + 8 * hh + t;
                     if (hh == h && kap < SP::N) {
                         const int tau = kap / C, x = kap % C;
-                        vr = (short)(tau == 2 ? brl[x] : brh[x]);
-                        vi = (short)(tau == 2 ? bil[x] : bih[x]);
+                        vr = (short)brp[x][part_c(tau)];
+                        vi = (short)bip[x][part_c(tau)];
                     }
                 }
                 bre[q][ch][t] = vr;
@@ -495,7 +500,6 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
         }
     }
 
-    unsigned flagged = 0;
     const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
     const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
     for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
@@ -504,23 +508,14 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
         const float* __restrict__ src = p.V + t0 * RF;
         for (int e = tid; e < kTile * RF; e += kBlock) tile[e] = e < cnt * RF ? src[e] : 0.0f;
         __syncthreads();
-        {   // row tid: A of the first product, its k-slot in A2, its bound
+        {   // row tid: A of the first product and its k-slot in A2
             const int i = tid;
-            float a[C];
+            unsigned short ap[C][3];
 #pragma unroll
             for (int x = 0; x < C; ++x) {
-                if constexpr (REAL) a[x] = tile[i * RF + x];
-                else a[x] = x < R ? tile[i * RF + 2 * x] : tile[i * RF + 2 * (x - R) + 1];
-            }
-            unsigned short ah[C], am[C], al[C];
-            float nrm2 = 0.0f;
-#pragma unroll
-            for (int x = 0; x < C; ++x) {
-                ah[x] = bf16_rne(a[x]);
-                const float rest = a[x] - bf16_to_f32(ah[x]);    // exact
-                am[x] = bf16_rne(rest);
-                al[x] = bf16_rne(rest - bf16_to_f32(am[x]));     // exact difference, rounded once
-                nrm2 = fmaf(a[x], a[x], nrm2);
+                const float a = REAL ? tile[i * RF + x]
+                                     : (x < R ? tile[i * RF + 2 * x] : tile[i * RF + 2 * (x - R) + 1]);
+                bf16_split3(a, ap[x]);
             }
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
@@ -530,24 +525,16 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
                         const int kap = 16 * ch + 8 * hh + t;
-                        short val = 0;
-                        if (kap < SP::N) {
-                            const int tau = kap / C, x = kap % C;
-                            val = (short)(tau == 1 ? am[x] : ah[x]);
-                        }
-                        e[t] = val;
+                        e[t] = kap < SP::N ? (short)ap[kap % C][part_v(kap / C)] : (short)0;
                     }
                     apk[ch][i][hh] = e;
                 }
             const int rho = i & 31;
             const int g = 4 * (rho >> 3) + (rho & 3), G = 2 * ((rho >> 2) & 1) + (g >> 3), t = g & 7;
 #pragma unroll
-            for (int x = 0; x < C; ++x) {
-                a2s[i >> 5][x][G][t] = ah[x];
-                a2s[i >> 5][C + x][G][t] = am[x];
-                a2s[i >> 5][2 * C + x][G][t] = al[x];
-            }
-            bnt[i] = (i < cnt && nrm2 > 0.0f) ? tb * kappa * sqrtf(nrm2) : -1.0f;
+            for (int x = 0; x < C; ++x)
+#pragma unroll
+                for (int pp = 0; pp < 3; ++pp) a2s[i >> 5][pp * C + x][G][t] = ap[x][pp];
         }
         __syncthreads();
         for (int sub = 0; sub * 32 < cnt; ++sub) {
@@ -557,13 +544,6 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb)
                 a2[mb] = *reinterpret_cast<const v8s*>(&a2s[sub][16 * mb + (lane & 15)][lane >> 4][0]);
-            float bt[16];
-#pragma unroll
-            for (int gg = 0; gg < 4; ++gg) {
-                const v4f y = *reinterpret_cast<const v4f*>(&bnt[sub * 32 + 8 * gg + 4 * h]);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) bt[4 * gg + e] = y[e];
-            }
             v16f wre[Q], wim[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -578,48 +558,12 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
             }
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                float u[16], wr[16], wi[16];
-                bool any = false;
+                float u[16];
 #pragma unroll
                 for (int g = 0; g < 16; ++g) {
-                    wr[g] = wre[q][g];
-                    wi[g] = wim[q][g];
-                    if constexpr (KS == 3) {
-                        u[g] = fmaf(-1.0f / si, fabsf(wi[g]), wr[g]);
-                        any |= (fabsf(u[g]) <= bt[g]) | (fabsf(wi[g]) <= bt[g]);
-                    } else if constexpr (KS == 4) {
-                        u[g] = fabsf(wr[g]) - fabsf(wi[g]);
-                        any |= fabsf(u[g]) <= bt[g];
-                    } else {
-                        u[g] = wr[g];
-                        any |= fabsf(u[g]) <= bt[g];
-                    }
-                }
-                if (__ballot(any)) {   // rare: rows within their bound take the FP32 label
-#pragma unroll
-                    for (int g = 0; g < 16; ++g) {
-                        const bool f = (fabsf(u[g]) <= bt[g]) | (KS == 3 && fabsf(wi[g]) <= bt[g]);
-                        if (f) {
-                            ++flagged;
-                            const int row = sub * 32 + 8 * (g >> 2) + 4 * h + (g & 3);
-                            float v[RF], fr, fi, nr, ni;
-#pragma unroll
-                            for (int e = 0; e < RF; ++e) v[e] = tile[row * RF + e];
-                            w_f32<R, REAL>(v, c[q], fr, fi);
-                            nearest_root<KS>(fr, fi, KS, nullptr, nr, ni);
-                            // test values that give the FP32 label below
-                            if constexpr (KS == 3) {
-                                u[g] = nr > 0.0f ? 1.0f : -1.0f;
-                                wi[g] = ni;
-                            } else if constexpr (KS == 4) {
-                                u[g] = nr != 0.0f ? 1.0f : -1.0f;
-                                wr[g] = nr;
-                                wi[g] = ni;
-                            } else {
-                                u[g] = nr;
-                            }
-                        }
-                    }
+                    if constexpr (KS == 3) u[g] = wre[q][g] - fabsf(wim[q][g]);
+                    else if constexpr (KS == 4) u[g] = fabsf(wre[q][g]) - fabsf(wim[q][g]);
+                    else u[g] = wre[q][g];
                 }
                 if constexpr (PROBE) {
                     if (slot[q] >= 0) {
@@ -627,18 +571,13 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
                         for (int g = 0; g < 16; ++g) {
                             const int row = sub * 32 + 8 * (g >> 2) + 4 * h + (g & 3);
                             if (row >= cnt) continue;
-                            const float owr = wre[q][g], owi = wim[q][g];
-                            bool f;
-                            if constexpr (KS == 3) f = (fabsf(fmaf(-1.0f / si, fabsf(owi), owr)) <= bt[g]) | (fabsf(owi) <= bt[g]);
-                            else if constexpr (KS == 4) f = fabsf(fabsf(owr) - fabsf(owi)) <= bt[g];
-                            else f = fabsf(owr) <= bt[g];
                             const bool neg = __float_as_uint(u[g]) >> 31;   // the sign bits, as packed below
-                            const bool wneg = __float_as_uint(wi[g]) >> 31, rneg = __float_as_uint(wr[g]) >> 31;
+                            const bool wneg = __float_as_uint(wim[q][g]) >> 31, rneg = __float_as_uint(wre[q][g]) >> 31;
                             int k;
                             if constexpr (KS == 3) k = neg ? (wneg ? 2 : 1) : 0;
                             else if constexpr (KS == 4) k = neg ? (wneg ? 3 : 1) : (rneg ? 2 : 0);
                             else k = neg ? 1 : 0;
-                            p.probe_out[(size_t)slot[q] * p.n + t0 + row] = (uint16_t)(k | (f ? 0x100 : 0));
+                            p.probe_out[(size_t)slot[q] * p.n + t0 + row] = (uint16_t)k;
                         }
                     }
                 }
@@ -649,12 +588,12 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const uint32_t m = sign_pair(u[2 * e], u[2 * e + 1]);
-                    const uint32_t isg = (hi_pair(wi[2 * e], wi[2 * e + 1]) & 0x80008000u) | 0x3F803F80u;
+                    const uint32_t isg = (hi_pair(wim[q][2 * e], wim[q][2 * e + 1]) & 0x80008000u) | 0x3F803F80u;
                     if constexpr (KS == 3) {
                         ur[e] = (m & 0xBF00BF00u) | (~m & 0x3F803F80u);   // -1/2 : 1
                         ui[e] = isg & m;                                     // +-1 : 0
                     } else if constexpr (KS == 4) {
-                        ur[e] = ((hi_pair(wr[2 * e], wr[2 * e + 1]) & 0x80008000u) | 0x3F803F80u) & ~m;
+                        ur[e] = ((hi_pair(wre[q][2 * e], wre[q][2 * e + 1]) & 0x80008000u) | 0x3F803F80u) & ~m;
                         ui[e] = isg & m;
                     } else {
                         ur[e] = (m & 0x80008000u) | 0x3F803F80u;           // +-1 from the sign of Re w
@@ -689,9 +628,6 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
             }
         }
     }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) flagged += __shfl_xor(flagged, off, kWave);
-    if (lane == 0 && flagged) atomicAdd(p.flagged, (unsigned long long)flagged);
 
     // register g of lane l in block (mb, n) is A2 row 16 mb + 4 (l / 16) + g,
     // i.e. part m / C of component m % C, of candidate 16 n + l % 16: gather

@@ -40,6 +40,18 @@ import oracle
 U32 = 2.0 ** -24
 REACH = 64.0 * U32
 
+# Precision form (K = 2, 3, 4): w from six BF16 products of three-part
+# splits of V and c.  The split drops products of order 2^-24 (about 4 u per
+# term); the MFMA's sum of at most 6C = 48 products is charged one FP32 ulp
+# (2u) per addition; so |w - w(FP64)| <= (2 * 48 + 5) u sum_j |V_ij||c_j|.  A
+# quantiser test is a linear form in (Re w, Im w) whose zero set is a
+# boundary line; its error over the distance to that line is at most
+# (1 + sqrt(3))/2 (K = 3, Re w pre-scaled) or sqrt(2) (K = 4), so the
+# Euclidean distance within which a label can differ from the FP64 one is
+# below 1.42 * 101 u < 256 u.  The generic-K precision form recomputes such
+# rows in FP32 and stays within REACH.
+REACH_PRECISION = 256.0 * U32
+
 
 def fp32_exact(V):
     """The FP64 values of the FP32-stored factor (what the GPU reads)."""

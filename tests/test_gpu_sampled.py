@@ -68,7 +68,7 @@ def solve_checked(lrqo_mod, V, K, S, seed, real=False, probe=(), n_random_probes
 
 
 def check_result(V, K, S, seed, out, real=False, f32=None, dirs=None, full_oracle=True, block=None,
-                 instance=0, first=0, probe=(), labels=None):
+                 instance=0, first=0, probe=(), labels=None, reach=PH.REACH):
     """The bar of the module docstring.  `block` (indices into this call's
     candidates) restricts the per-candidate and best-of checks to a subset
     when the whole stream is too long for the oracle."""
@@ -98,20 +98,20 @@ def check_result(V, K, S, seed, out, real=False, f32=None, dirs=None, full_oracl
     assert abs(oracle.objective(V, K, z_gpu) - out.obj) <= tol64
     stats = {}
     for t, pos in enumerate(probe):
-        stats.setdefault("probe_rows", []).append(PH.check_labels(V, K, dirs[pos], labels[t]))
+        stats.setdefault("probe_rows", []).append(PH.check_labels(V, K, dirs[pos], labels[t], reach=reach))
     if full_oracle:
         ref = oracle.sampled(V, K, S, seed, instance=instance, s0=first)
         assert out.obj >= ref["best_f"] * (1 - 1e-5), (out.obj, ref["best_f"])
         assert out.obj <= ref["best_f"] * (1 + 1e-5), (out.obj, ref["best_f"])
         if f32 is not None:
-            sc = PH.check_scores(V, K, dirs, f32)
+            sc = PH.check_scores(V, K, dirs, f32, reach=reach)
             stats["max_ratio"] = sc["max_ratio"]
             stats["top_diff"] = PH.top_sets_agree(f32, sc["f"], sc["allowance"], T=min(64, S))
             assert out.obj >= sc["f"].max() * (1 - 1e-12) - tol64
         return ref, stats
     if block is not None:
         block = np.asarray(block)
-        sc = PH.check_scores(V, K, dirs[block], f32[block])
+        sc = PH.check_scores(V, K, dirs[block], f32[block], reach=reach)
         stats["max_ratio"] = sc["max_ratio"]
         # the FP64 stream over the same contiguous range (best of its part)
         lo_b, hi_b = int(block.min()), int(block.max()) + 1
