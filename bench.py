@@ -99,6 +99,15 @@ def _alu_roofline(flops: float, ms: float, what: str) -> dict:
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "algorithmic_flops": flops, "ms": ms, "what": what}
 
 
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def _mfma_roofline(flops: float, ms: float, what: str) -> dict:
+    achieved = flops / (ms / 1000.0) / 1e12
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "flops": flops, "ms": ms, "what": what}
+
+
 def _hbm_roofline(nbytes: float, ms: float, what: str) -> dict:
     achieved = nbytes / (ms / 1000.0) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -157,9 +166,18 @@ def form_precision():
     cnt = 64
     oms, ores = _timed(lambda: oracle.sampled(inst.V, inst.K, cnt, inst.seed, want_f=False))
     flops = 8 * inst.r * inst.n * inst.S
+    # the K = 3 precision scorer per 32 rows x 32 candidates: 8 (V c, six split
+    # products in one 32-slot chunk) + 4 (V^H z) v_mfma_f32_16x16x32_bf16,
+    # 16,384 flops each as issued; of these, 6 products x 4r flops for V c and
+    # 3 parts x 4r flops for V^H z are the split arithmetic itself
+    issued = 12 * 16384 / 1024 * inst.n * inst.S
+    split = (6 * 4 * inst.r + 3 * 4 * inst.r) * inst.n * inst.S
     return {"workload": "maxcut_ppm", "n": inst.n, "r": inst.r, "K": inst.K, "S": inst.S,
             "roofline_fp32": _alu_roofline(flops, o32.score_ms, "k_score_rows, 8r flops per row-candidate"),
-            "roofline_bf16": _alu_roofline(flops, o16.score_ms, "k_score_bf16, same algorithmic flops"),
+            "roofline_bf16": _alu_roofline(flops, o16.score_ms, "k_score_bf16x, the same 8r algorithmic flops"),
+            "roofline_bf16_mfma": _mfma_roofline(issued, o16.score_ms,
+                                                 "k_score_bf16x, MFMA flops as issued (K-slot and row padding included)"),
+            "bf16_split_flops_per_launch": split,
             "oracle": {"kind": "oracle", "ms": oms, "candidate_rows_per_s": cnt * inst.n / (oms / 1000.0),
                        "cores": ores["threads"],
                        "sample": f"first {cnt} of the {inst.S} directions (FP64, {ores['threads']} threads)"},

@@ -292,7 +292,7 @@ void launch_score_bf16(const ScoreParams& p, dim3 grid, hipStream_t st) {
     if constexpr (R <= 4) {
         if constexpr (KS == 2 || KS == 3 || KS == 4) {
             if (bf16_form() == 0) {
-                hipLaunchKernelGGL((k_score_bf16x<R, REAL, KS, kBf16xQ, false>), grid, dim3(kBlock), 0, st, p);
+                hipLaunchKernelGGL((k_score_bf16x<R, REAL, KS, false>), grid, dim3(kBlock), 0, st, p);
                 return;
             }
         }

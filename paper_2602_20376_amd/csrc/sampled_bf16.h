@@ -358,40 +358,35 @@ namespace {
 // mid, lo: an FP32 value is their sum to within 2^-24 of itself), and w is
 // formed from the six products of order up to 2^-16,
 //   hi.hi + mid.hi + hi.mid + lo.hi + hi.lo + mid.mid,
-// so w carries FP32-grade error (the dropped products are of order 2^-24):
-// at most 43 * 2^-24 * sum_j |V_ij| |c_j| with the accumulation charged one
-// FP32 ulp per addition.  The labels are taken from w directly, with no
-// recomputation: away from a decision boundary (beyond the FP32 reach, as for
-// the FP32 scorer) they are the FP64 rule's.  Every K-th root has coordinates
-// in {0, +-1, -1/2} once Im z is divided by sqrt(3)/2 for K = 3, so the labels
-// are exact in BF16 and s = V^H z runs on the matrix core too.
+// so w carries FP32-grade error (the dropped products are of order 2^-24).
+// The labels are taken from w directly, with no recomputation: away from a
+// decision boundary they are the FP64 rule's.  Every K-th root has
+// coordinates in {0, +-1, -1/2} once Im z is divided by sqrt(3)/2 for K = 3,
+// so the labels are exact in BF16 and s = V^H z runs on the matrix core too.
 //
-// w: v_mfma_f32_32x32x16_bf16 gives 32 rows x 32 candidates per part
-// (Re w, Im w) and chunk of 16 k-slots; slot kappa = tau C + x holds product
-// tau of component x (C = r for a real V; 2r for a complex one, Re V then
-// Im V).  Operand layout (gfx950): lane l supplies row (A) / column (B) l % 32
-// and k-slots 8 (l / 32) .. 8 (l / 32) + 7; register g of the result is row
-// 8 (g / 4) + 4 (l / 32) + g % 4, column l % 32.
-//
-// s: with the tile's labels Z, D_r += A2 Z_r and D_i += A2 Z_i on
-// v_mfma_f32_16x16x32_bf16 (16 A2 rows x 16 candidates x 32 rows of V); row
-// m = p C + x of A2 holds part p of component x of every row of V.  The
-// labels come out of the first product two per dword in the lanes of their
-// candidate; one v_permlane16_swap per pair of dwords moves them into the
-// second product's B layout (lane l: candidate l % 16, k-slots 8 (l / 16) ..
-// + 7), so k-slot (G, t) of the second product is row 8 (g / 4) + 4 (G / 2) +
-// g % 4 with g = 8 (G % 2) + t; A2 is laid out in LDS in that order.  D stays
-// in registers for the whole slice; each candidate's parts are added once at
-// the end.
+// Both products are v_mfma_f32_16x16x32_bf16 (gfx950 layout: lane l supplies
+// row (A) / column (B) l % 16 and k-slots 8 (l / 16) .. + 7; register g of the
+// result is row 4 (l / 16) + g, column l % 16).  A wave holds 32 candidates
+// (two column halves n) and takes the rows of a tile 32 at a time (two
+// 16-row blocks b).
+//   w: for each (n, b) and part (Re w, Im w), the 16 rows x 16 candidates with
+//      the C components (C = r for a real V; 2r for a complex one, Re V then
+//      Im V) times the six products on k: slot kappa = tau C + x holds
+//      product tau of component x (one instruction when 6C <= 32).
+//   s: D_r += A2 Z_r and D_i += A2 Z_i: A2 row m = p C + x holds part p of
+//      component x of the rows; k-slot (G, t) is row 16 (t / 4) + 4 G + t % 4
+//      of the 32, which is where lane l (G = l / 16) holds the labels it
+//      computed (block t / 4, register t % 4), so they go into the second
+//      product without leaving their lanes.  D stays in registers for the
+//      whole slice; each candidate's parts are added once at the end.
 typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
 
 template <int R, bool REAL>
-struct Split32 {
+struct Split16 {
     static constexpr int C = REAL ? R : 2 * R;      // values per row
     static constexpr int N = 6 * C;                 // k-slots of the split product
-    static constexpr int NCH = (N + 15) / 16;       // chunks of 16 slots
+    static constexpr int NCH = (N + 31) / 32;       // chunks of 32 slots
     static constexpr int NMB = (3 * C + 15) / 16;   // 16-row blocks of A2
 };
 // The parts (0 hi, 1 mid, 2 lo) of V and of c in product tau.
@@ -400,9 +395,8 @@ __host__ __device__ constexpr int part_c(int tau) { return tau == 2 || tau == 5 
 
 __device__ __forceinline__ v8bf as_bf(v8s x) { return __builtin_bit_cast(v8bf, x); }
 
-// Groups of 32 candidates per wave, and candidates per block.
-constexpr int kBf16xQ = 1;
-constexpr int kBf16xCands = (kBlock / kWave) * 32 * kBf16xQ;
+// Candidates per block (four waves of 32).
+constexpr int kBf16xCands = (kBlock / kWave) * 32;
 
 // Upper halves of two FP32 values in one dword (first in the low half), and
 // their sign bits spread over the halves (v_perm_b32 selectors 9 and 11
@@ -423,12 +417,12 @@ __device__ __forceinline__ void bf16_split3(float x, unsigned short (&pt)[3]) {
     pt[2] = bf16_rne(r1 - bf16_to_f32(pt[1]));
 }
 
-template <int R, bool REAL, int KS, int Q, bool PROBE>
+template <int R, bool REAL, int KS, bool PROBE>
 __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
     static_assert(R <= 4, "precision form covers r <= 4");
     static_assert(KS == 2 || KS == 3 || KS == 4, "labels exact in BF16 for K = 2, 3, 4");
     static_assert(kBlock == kTile, "one thread prepares one row of the tile");
-    using SP = Split32<R, REAL>;
+    using SP = Split16<R, REAL>;
     constexpr int RF = Row<R, REAL>::F;
     constexpr int C = SP::C, NCH = SP::NCH, NMB = SP::NMB;
     constexpr bool IM = KS != 2;    // K = 2: neither Im w nor Im z is needed
@@ -438,44 +432,41 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
     // Re w, else from Im w); K = 2 u = Re w.
     constexpr float s3 = re_prescale(KS);
     constexpr float zs = KS == 3 ? 0.8660254037844386f : 1.0f;   // Im z = zs * (packed Im label)
-    __shared__ __align__(16) float tile[kTile * RF];
-    __shared__ __align__(16) v8s apk[NCH][kTile][2];
+    __shared__ __align__(16) v8s apk[NCH][kTile / 16][16][4];
     __shared__ __align__(16) unsigned short a2s[kTile / 32][16 * NMB][4][8];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
-    const int h = lane >> 5, col = lane & 31;
+    const int G = lane >> 4, col = lane & 15;
     {   // A2 rows 3C.. stay zero
         unsigned short* z = &a2s[0][0][0][0];
         for (int e = tid; e < (kTile / 32) * 16 * NMB * 32; e += kBlock) z[e] = 0;
     }
 
-    // candidates: wave w, group q, column j -> base + 32 Q w + 32 q + j
-    const uint32_t wbase = blockIdx.x * (uint32_t)(kBlock / kWave * 32 * Q) + (uint32_t)wave * (32 * Q);
-    float c[Q][2 * R];
-    int slot[Q];
-    lane_directions<R, Q, PROBE>(p, wbase + col, 32, blockIdx.y == 0 && h == 0, c, slot);
-    v8s bre[Q][NCH], bim[Q][NCH];
-    v4f dr[Q][NMB][2], di[Q][NMB][2];
+    // candidates: wave w, half n, column j -> base + 32 w + 16 n + j
+    const uint32_t wbase = blockIdx.x * (uint32_t)kBf16xCands + (uint32_t)wave * 32;
+    float c[2][2 * R];
+    int slot[2];
+    lane_directions<R, 2, PROBE>(p, wbase + col, 16, blockIdx.y == 0 && G == 0, c, slot);
+    v8s bre[2][NCH], bim[2][NCH];
+    v4f dr[2][NMB], di[2][NMB];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+    for (int n = 0; n < 2; ++n) {
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-            for (int n = 0; n < 2; ++n) {
-                dr[q][mb][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-                di[q][mb][n] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-            }
+        for (int mb = 0; mb < NMB; ++mb) {
+            dr[n][mb] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            di[n][mb] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        }
         unsigned short brp[C][3], bip[C][3];
 #pragma unroll
         for (int x = 0; x < C; ++x) {
             float br, bi;
             if (REAL || x < R) {
-                br = s3 * c[q][2 * (x % R)];
-                bi = c[q][2 * (x % R) + 1];
+                br = s3 * c[n][2 * (x % R)];
+                bi = c[n][2 * (x % R) + 1];
             } else {
-                br = -s3 * c[q][2 * (x - R) + 1];
-                bi = c[q][2 * (x - R)];
+                br = -s3 * c[n][2 * (x - R) + 1];
+                bi = c[n][2 * (x - R)];
             }
             bf16_split3(br, brp[x]);
             bf16_split3(bi, bip[x]);
@@ -486,200 +477,195 @@ __global__ __launch_bounds__(kBlock) void k_score_bf16x(ScoreParams p) {
             for (int t = 0; t < 8; ++t) {
                 short vr = 0, vi = 0;
 #pragma unroll
-                for (int hh = 0; hh < 2; ++hh) {   // the slot index at compile time
-                    const int kap = 16 * ch + 8 * hh + t;
-                    if (hh == h && kap < SP::N) {
+                for (int gg = 0; gg < 4; ++gg) {   // the slot index at compile time
+                    const int kap = 32 * ch + 8 * gg + t;
+                    if (gg == G && kap < SP::N) {
                         const int tau = kap / C, x = kap % C;
                         vr = (short)brp[x][part_c(tau)];
                         vi = (short)bip[x][part_c(tau)];
                     }
                 }
-                bre[q][ch][t] = vr;
-                bim[q][ch][t] = vi;
+                bre[n][ch][t] = vr;
+                bim[n][ch][t] = vi;
             }
         }
     }
 
     const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
     const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
+    // row tid of each tile straight from HBM (each thread needs exactly its
+    // own row), the next tile's loads in flight while the current one is scored
+    float v[RF];
+#pragma unroll
+    for (int e = 0; e < RF; ++e) v[e] = r0 + tid < r1 ? p.V[(r0 + tid) * RF + e] : 0.0f;
     for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
         const int cnt = (int)min((int64_t)kTile, r1 - t0);
-        __syncthreads();
-        const float* __restrict__ src = p.V + t0 * RF;
-        for (int e = tid; e < kTile * RF; e += kBlock) tile[e] = e < cnt * RF ? src[e] : 0.0f;
-        __syncthreads();
+        __syncthreads();   // the previous tile's operands are consumed
         {   // row tid: A of the first product and its k-slot in A2
             const int i = tid;
             unsigned short ap[C][3];
 #pragma unroll
             for (int x = 0; x < C; ++x) {
-                const float a = REAL ? tile[i * RF + x]
-                                     : (x < R ? tile[i * RF + 2 * x] : tile[i * RF + 2 * (x - R) + 1]);
+                const float a = REAL ? v[x] : (x < R ? v[2 * x] : v[2 * (x - R) + 1]);
                 bf16_split3(a, ap[x]);
             }
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-                for (int hh = 0; hh < 2; ++hh) {
+                for (int gg = 0; gg < 4; ++gg) {
                     v8s e;
 #pragma unroll
                     for (int t = 0; t < 8; ++t) {
-                        const int kap = 16 * ch + 8 * hh + t;
+                        const int kap = 32 * ch + 8 * gg + t;
                         e[t] = kap < SP::N ? (short)ap[kap % C][part_v(kap / C)] : (short)0;
                     }
-                    apk[ch][i][hh] = e;
+                    apk[ch][i >> 4][i & 15][gg] = e;
                 }
             const int rho = i & 31;
-            const int g = 4 * (rho >> 3) + (rho & 3), G = 2 * ((rho >> 2) & 1) + (g >> 3), t = g & 7;
+            const int tt = 4 * (rho >> 4) + (rho & 3), gi = (rho >> 2) & 3;
 #pragma unroll
             for (int x = 0; x < C; ++x)
 #pragma unroll
-                for (int pp = 0; pp < 3; ++pp) a2s[i >> 5][pp * C + x][G][t] = ap[x][pp];
+                for (int pp = 0; pp < 3; ++pp) a2s[i >> 5][pp * C + x][gi][tt] = ap[x][pp];
         }
         __syncthreads();
-        for (int sub = 0; sub * 32 < cnt; ++sub) {
-            v8s a[NCH], a2[NMB];
+        {
+            const int64_t nx = t0 + kTile + tid;
 #pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) a[ch] = apk[ch][sub * 32 + col][h];
+            for (int e = 0; e < RF; ++e) v[e] = nx < r1 ? p.V[nx * RF + e] : 0.0f;
+        }
+        for (int sub = 0; sub * 32 < cnt; ++sub) {
+            v8s a[2][NCH], a2[NMB];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) a[b][ch] = apk[ch][2 * sub + b][col][G];
 #pragma unroll
             for (int mb = 0; mb < NMB; ++mb)
-                a2[mb] = *reinterpret_cast<const v8s*>(&a2s[sub][16 * mb + (lane & 15)][lane >> 4][0]);
-            v16f wre[Q], wim[Q];
+                a2[mb] = *reinterpret_cast<const v8s*>(&a2s[sub][16 * mb + col][G][0]);
+            // w for both halves and both row blocks: independent instructions
+            v4f wre[2][2], wim[2][2];
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                wre[q] = v16f{};
-                wim[q] = v16f{};
+            for (int n = 0; n < 2; ++n)
 #pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) {
-                    wre[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a[ch]), as_bf(bre[q][ch]), wre[q], 0, 0, 0);
-                    if constexpr (IM)
-                        wim[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf(a[ch]), as_bf(bim[q][ch]), wim[q], 0, 0, 0);
+                for (int b = 0; b < 2; ++b) {
+                    wre[n][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+                    wim[n][b] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        wre[n][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a[b][ch]), as_bf(bre[n][ch]), wre[n][b], 0, 0, 0);
+                        if constexpr (IM)
+                            wim[n][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a[b][ch]), as_bf(bim[n][ch]), wim[n][b], 0, 0, 0);
+                    }
                 }
-            }
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                float u[16];
+            for (int n = 0; n < 2; ++n) {
+                // values t = 4 b + g: row 16 b + 4 G + g
+                float u[8], wr[8], wi[8];
 #pragma unroll
-                for (int g = 0; g < 16; ++g) {
-                    if constexpr (KS == 3) u[g] = wre[q][g] - fabsf(wim[q][g]);
-                    else if constexpr (KS == 4) u[g] = fabsf(wre[q][g]) - fabsf(wim[q][g]);
-                    else u[g] = wre[q][g];
+                for (int t = 0; t < 8; ++t) {
+                    wr[t] = wre[n][t >> 2][t & 3];
+                    wi[t] = wim[n][t >> 2][t & 3];
+                    if constexpr (KS == 3) u[t] = wr[t] - fabsf(wi[t]);
+                    else if constexpr (KS == 4) u[t] = fabsf(wr[t]) - fabsf(wi[t]);
+                    else u[t] = wr[t];
                 }
                 if constexpr (PROBE) {
-                    if (slot[q] >= 0) {
+                    if (slot[n] >= 0) {
 #pragma unroll
-                        for (int g = 0; g < 16; ++g) {
-                            const int row = sub * 32 + 8 * (g >> 2) + 4 * h + (g & 3);
+                        for (int t = 0; t < 8; ++t) {
+                            const int row = sub * 32 + 16 * (t >> 2) + 4 * G + (t & 3);
                             if (row >= cnt) continue;
-                            const bool neg = __float_as_uint(u[g]) >> 31;   // the sign bits, as packed below
-                            const bool wneg = __float_as_uint(wim[q][g]) >> 31, rneg = __float_as_uint(wre[q][g]) >> 31;
+                            const bool neg = __float_as_uint(u[t]) >> 31;   // the sign bits, as packed below
+                            const bool wneg = __float_as_uint(wi[t]) >> 31, rneg = __float_as_uint(wr[t]) >> 31;
                             int k;
                             if constexpr (KS == 3) k = neg ? (wneg ? 2 : 1) : 0;
                             else if constexpr (KS == 4) k = neg ? (wneg ? 3 : 1) : (rneg ? 2 : 0);
                             else k = neg ? 1 : 0;
-                            p.probe_out[(size_t)slot[q] * p.n + t0 + row] = (uint16_t)k;
+                            p.probe_out[(size_t)slot[n] * p.n + t0 + row] = (uint16_t)k;
                         }
                     }
                 }
                 // labels to BF16, two rows per dword, from sign bits
-                // (m = 0xFFFF in each half whose u is negative), then into
-                // the second product's layout
-                uint32_t ur[8], ui[8];
+                // (m = 0xFFFF in each half whose u is negative)
+                uint32_t ur[4], ui[4];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
+                for (int e = 0; e < 4; ++e) {
                     const uint32_t m = sign_pair(u[2 * e], u[2 * e + 1]);
-                    const uint32_t isg = (hi_pair(wim[q][2 * e], wim[q][2 * e + 1]) & 0x80008000u) | 0x3F803F80u;
+                    const uint32_t isg = (hi_pair(wi[2 * e], wi[2 * e + 1]) & 0x80008000u) | 0x3F803F80u;
                     if constexpr (KS == 3) {
                         ur[e] = (m & 0xBF00BF00u) | (~m & 0x3F803F80u);   // -1/2 : 1
                         ui[e] = isg & m;                                     // +-1 : 0
                     } else if constexpr (KS == 4) {
-                        ur[e] = ((hi_pair(wre[q][2 * e], wre[q][2 * e + 1]) & 0x80008000u) | 0x3F803F80u) & ~m;
+                        ur[e] = ((hi_pair(wr[2 * e], wr[2 * e + 1]) & 0x80008000u) | 0x3F803F80u) & ~m;
                         ui[e] = isg & m;
                     } else {
                         ur[e] = (m & 0x80008000u) | 0x3F803F80u;           // +-1 from the sign of Re w
                         ui[e] = 0;
                     }
                 }
-                uint32_t zr2[2][4], zi2[2][4];
+                const v8s zr = __builtin_bit_cast(v8s, ur);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const auto sr = __builtin_amdgcn_permlane16_swap(ur[e], ur[e + 4], false, false);
-                    zr2[0][e] = sr[0];
-                    zr2[1][e] = sr[1];
-                    if constexpr (IM) {
-                        const auto sx = __builtin_amdgcn_permlane16_swap(ui[e], ui[e + 4], false, false);
-                        zi2[0][e] = sx[0];
-                        zi2[1][e] = sx[1];
-                    }
-                }
-#pragma unroll
-                for (int n = 0; n < 2; ++n) {
-                    const v8s br2 = __builtin_bit_cast(v8s, zr2[n]);
+                for (int mb = 0; mb < NMB; ++mb)
+                    dr[n][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a2[mb]), as_bf(zr), dr[n][mb], 0, 0, 0);
+                if constexpr (IM) {
+                    const v8s zi = __builtin_bit_cast(v8s, ui);
 #pragma unroll
                     for (int mb = 0; mb < NMB; ++mb)
-                        dr[q][mb][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a2[mb]), as_bf(br2), dr[q][mb][n], 0, 0, 0);
-                    if constexpr (IM) {
-                        const v8s bi2 = __builtin_bit_cast(v8s, zi2[n]);
-#pragma unroll
-                        for (int mb = 0; mb < NMB; ++mb)
-                            di[q][mb][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a2[mb]), as_bf(bi2), di[q][mb][n], 0, 0, 0);
-                    }
+                        di[n][mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a2[mb]), as_bf(zi), di[n][mb], 0, 0, 0);
                 }
             }
         }
     }
 
-    // register g of lane l in block (mb, n) is A2 row 16 mb + 4 (l / 16) + g,
-    // i.e. part m / C of component m % C, of candidate 16 n + l % 16: gather
-    // the four lane groups, add the parts; lanes 0..31 write candidate l
+    // register g of lane l in (n, mb) is A2 row 16 mb + 4 (l / 16) + g, i.e.
+    // part m / C of component m % C, of candidate 16 n + l % 16: gather the
+    // four lane groups, add the parts; lanes 0..31 write candidate l
+    float pr[2][C], pi[2][C];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        float pr[2][C], pi[2][C];
+    for (int n = 0; n < 2; ++n)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
+        for (int x = 0; x < C; ++x) pr[n][x] = pi[n][x] = 0.0f;
 #pragma unroll
-            for (int x = 0; x < C; ++x) pr[n][x] = pi[n][x] = 0.0f;
+    for (int n = 0; n < 2; ++n)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
+        for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-            for (int mb = 0; mb < NMB; ++mb)
+            for (int gg = 0; gg < 4; ++gg)
 #pragma unroll
-                for (int G = 0; G < 4; ++G)
+                for (int g = 0; g < 4; ++g) {
+                    const int m = 16 * mb + 4 * gg + g;
+                    if (m >= 3 * C) continue;
+                    const int srcl = col + 16 * gg;
+                    pr[n][m % C] += __shfl(dr[n][mb][g], srcl, kWave);
+                    if constexpr (IM) pi[n][m % C] += __shfl(di[n][mb][g], srcl, kWave);
+                }
+    const uint32_t idx = wbase + lane;
+    if (lane >= 32 || idx >= p.S) return;
+    const int n = lane >> 4;
+    float s[2 * R];
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const int m = 16 * mb + 4 * G + g;
-                        if (m >= 3 * C) continue;
-                        const int srcl = (lane & 15) + 16 * G;
-                        pr[n][m % C] += __shfl(dr[q][mb][n][g], srcl, kWave);
-                        if constexpr (IM) pi[n][m % C] += __shfl(di[q][mb][n][g], srcl, kWave);
-                    }
-        const int n = lane >> 4;
-        const uint32_t idx = wbase + 32 * q + lane;
-        if (lane >= 32 || idx >= p.S) continue;
-        float s[2 * R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const float prj = n ? pr[1][j] : pr[0][j];
-            const float pij = n ? pi[1][j] : pi[0][j];
-            if constexpr (REAL) {
-                s[2 * j] = prj;
-                s[2 * j + 1] = IM ? zs * pij : 0.0f;
-            } else {
-                const float prR = n ? pr[1][R + j] : pr[0][R + j];
-                const float piR = n ? pi[1][R + j] : pi[0][R + j];
-                s[2 * j] = IM ? prj + zs * piR : prj;
-                s[2 * j + 1] = IM ? zs * pij - prR : -prR;
-            }
-        }
-        if (gridDim.y == 1) {
-            float f = 0.0f;
-#pragma unroll
-            for (int j = 0; j < 2 * R; ++j) f = fmaf(s[j], s[j], f);
-            p.f_out[idx] = f;
+    for (int j = 0; j < R; ++j) {
+        const float prj = n ? pr[1][j] : pr[0][j];
+        const float pij = n ? pi[1][j] : pi[0][j];
+        if constexpr (REAL) {
+            s[2 * j] = prj;
+            s[2 * j + 1] = IM ? zs * pij : 0.0f;
         } else {
-#pragma unroll
-            for (int j = 0; j < 2 * R; ++j) p.partial[((size_t)blockIdx.y * (2 * R) + j) * p.S + idx] = s[j];
+            const float prR = n ? pr[1][R + j] : pr[0][R + j];
+            const float piR = n ? pi[1][R + j] : pi[0][R + j];
+            s[2 * j] = IM ? prj + zs * piR : prj;
+            s[2 * j + 1] = IM ? zs * pij - prR : -prR;
         }
+    }
+    if (gridDim.y == 1) {
+        float f = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) f = fmaf(s[j], s[j], f);
+        p.f_out[idx] = f;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) p.partial[((size_t)blockIdx.y * (2 * R) + j) * p.S + idx] = s[j];
     }
 }
 

@@ -29,7 +29,7 @@ void probe_bf16(const ScoreParams& p, dim3 grid, hipStream_t st) {
     if constexpr (R <= 4) {
         if constexpr (KS == 2 || KS == 3 || KS == 4) {
             if (bf16_form() == 0) {
-                hipLaunchKernelGGL((k_score_bf16x<R, REAL, KS, kBf16xQ, true>), grid, dim3(kBlock), 0, st, p);
+                hipLaunchKernelGGL((k_score_bf16x<R, REAL, KS, true>), grid, dim3(kBlock), 0, st, p);
                 return;
             }
         }
