@@ -27,25 +27,34 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lrqo_oracle.c")
 _SO = os.path.join(_HERE, "liblrqo_oracle.so")
+# a sanitized copy (AddressSanitizer + UndefinedBehaviorSanitizer) for the
+# sanitizer tests; LRQO_ORACLE_LIBRARY selects it in their child process
+_SO_SAN = os.path.join(os.path.dirname(_HERE), "_build_san", "liblrqo_oracle.so")
 _lib = None
 
 
-def build(force: bool = False) -> str:
+def build(force: bool = False, sanitize: bool = False) -> str:
     """Compile the C oracle with gcc (-O2, OpenMP, no fast-math)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + f".tmp{os.getpid()}"
+    out = _SO_SAN if sanitize else _SO
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(out), exist_ok=True)
+        tmp = out + f".tmp{os.getpid()}"
+        san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+               "-fno-omit-frame-pointer", "-g"] if sanitize else []
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _SO)
-    return _SO
+                               "-fno-fast-math", "-Wall", *san, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    build()
-    lib = ctypes.CDLL(_SO)
+    path = os.environ.get("LRQO_ORACLE_LIBRARY")
+    if not path:
+        path = build()
+    lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     d, i32, i64, u32, u64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
     vp = ctypes.c_void_p
