@@ -98,9 +98,15 @@ lrqo_status lrqo_shutdown(void);
 
 typedef struct lrqo_sampled_options {
     int32_t real_v;          /* 0: complex64 V; 1: real FP32 V */
-    int32_t precision;       /* 0: FP32 scorer; 1: BF16 MFMA for V c with
-                                FP32 recompute of rows inside the BF16 error
-                                margin (results as for 0) */
+    int32_t precision;       /* 0: FP32 scorer; 1: precision form (r <= 4,
+                                else LRQO_EINVAL).  K = 2, 3, 4: V c and V^H z
+                                on BF16 MFMA from three-part BF16 splits of V
+                                and c (FP32-grade w; a label can differ from
+                                the FP64 rule only within 256 u sum_j
+                                |V_ij||c_j| of a decision boundary, u = 2^-24);
+                                other K: V c on BF16 MFMA with hi + lo parts,
+                                rows inside the BF16 error margin recomputed in
+                                FP32.  The FP64 rescore is the same in both */
     int32_t rescore_topk;    /* 1..64; 0 means 64 */
     uint32_t instance;       /* counter word 2 of the direction stream */
     uint64_t first_index;    /* index of the first direction (range splitting) */
@@ -124,7 +130,8 @@ typedef struct lrqo_sampled_result {
     double obj;              /* FP64 ||V^H z||^2 of the returned labels */
     double fp32_obj;         /* the FP32 scorer's value for the same direction */
     double best_c[2 * LRQO_MAX_R]; /* winner's direction, FP64 copy of the FP32 values, (re, im) pairs */
-    int64_t flagged_rows;    /* precision 1: row-candidates recomputed in FP32 */
+    int64_t flagged_rows;    /* precision 1: row-candidates recomputed in FP32
+                                (always 0 for K = 2, 3, 4, which recompute none) */
     float device_ms;         /* device time of the call, from stream events */
     float score_ms;          /* device time of the fused scoring kernel alone */
     int32_t rescored;        /* candidates that went through the FP64 rescore */
