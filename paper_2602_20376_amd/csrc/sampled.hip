@@ -10,6 +10,7 @@
 //                   stream through LDS; per row-candidate w = V_i c, the
 //                   nearest K-th root of arg(w), s += conj(V_i) z_i.  With
 //                   several row slices (gridDim.y > 1) partial sums instead.
+//                   The precision form's scorers are in sampled_bf16.h.
 //   k_finalize      sums the slice partials in a fixed order -> f = ||s||^2,
 //                   and sorts each wave's 64 keys for the selection
 //   topk_select     best T packed (f, index) keys (select.hip)

@@ -1,7 +1,9 @@
-// The precision form's fused scorer (BF16 MFMA for w = V c, rows inside the
-// BF16 error margin recomputed in FP32, V^H z accumulated in FP32 on the
-// vector ALU).  Internal header, included after sampled_kernels.h by
-// sampled.hip and sampled_probe.hip.
+// The precision form's fused scorers.  K = 2, 3, 4: k_score_bf16x, both
+// w = V c and s = V^H z on BF16 MFMA from three-part splits (FP32-grade w,
+// no recompute).  Other K: k_score_bf16, w = V c on BF16 MFMA from hi + lo
+// parts, rows inside the BF16 error margin recomputed in FP32, V^H z
+// accumulated in FP32 on the vector ALU.  Internal header, included after
+// sampled_kernels.h by sampled.hip and sampled_probe.hip.
 #pragma once
 
 #include "sampled_kernels.h"
