@@ -218,6 +218,24 @@ __device__ __forceinline__ void score_vals(const float (&v)[Row<R, REAL>::F],
                 wi = fmaf(vr, c[q][2 * j + 1], fmaf(vi, c[q][2 * j], wi));
             }
         }
+        if constexpr (REAL && KS == 3) {
+            // real V, K = 3: z = 1 - 3/2 q + i (sqrt(3)/2) q sigma with
+            // q = [label != 0] and sigma = sign(Im w); dr accumulates
+            // sum_i V_i q_i and di sum_i V_i q_i sigma_i, and the caller
+            // forms s = sum_i V_i - 3/2 dr + i (sqrt(3)/2) di
+            const bool k0 = fabsf(wi) <= wr;
+            const float qf = k0 ? 0.0f : 1.0f;
+            const float qs = copysignf(qf, wi);
+            if constexpr (PROBE) {
+                if (slot[q] >= 0) probe_row[(size_t)slot[q] * n] = (uint16_t)(k0 ? 0 : ((__float_as_uint(wi) >> 31) ? 2 : 1));
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                dr[q][j] = fmaf(v[j], qf, dr[q][j]);
+                di[q][j] = fmaf(v[j], qs, di[q][j]);
+            }
+            continue;
+        }
         float zr, zi;
         if constexpr (KS == 3) nearest_root_k3s(wr, wi, zr, zi);
         else if constexpr (KS == 8) nearest_root_k8t(wr, wi, zr, zi);
@@ -265,9 +283,10 @@ __device__ __forceinline__ void score_row(const float* __restrict__ row, const f
 
 // Sums of the four waves of a block added in wave order; wave 0 writes f
 // (one slice) or the slice's partial sums.
-template <int R, int CPL>
+template <int R, int CPL, bool Q3 = false>
 __device__ __forceinline__ void block_sums_out(const ScoreParams& p, float (&acc)[CPL][2 * R], uint32_t base,
-                                               float (*red)[CPL * 2 * R][kWave], int wave, int lane) {
+                                               float (*red)[CPL * 2 * R][kWave], int wave, int lane,
+                                               const float* tsum = nullptr) {
     constexpr int NW = kBlock / kWave;
     if (wave > 0) {
 #pragma unroll
@@ -283,6 +302,23 @@ __device__ __forceinline__ void block_sums_out(const ScoreParams& p, float (&acc
         for (int q = 0; q < CPL; ++q)
 #pragma unroll
             for (int j = 0; j < 2 * R; ++j) acc[q][j] += red[w][q * 2 * R + j][lane];
+    if constexpr (Q3) {   // (sum_i V_i q_i, sum_i V_i q_i sigma_i) -> s (score_vals, real V, K = 3);
+                          // tsum[w * R + j]: wave w's share of sum_i V_ij over the slice
+        float t[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            t[j] = tsum[j];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) t[j] += tsum[w * R + j];
+        }
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                acc[q][2 * j] = fmaf(-1.5f, acc[q][2 * j], t[j]);
+                acc[q][2 * j + 1] *= 0.8660254037844386f;
+            }
+    }
 
     if (gridDim.y == 1) {
 #pragma unroll
@@ -317,6 +353,8 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
     __shared__ __align__(16) float tile[kTile * RF];
     __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
     __shared__ float red[NW - 1][CPL * 2 * R][kWave];
+    constexpr bool Q3 = REAL && KS == 3;   // score_vals' real K = 3 form needs sum_i V_i
+    __shared__ float tsum[Q3 ? NW * R : 1];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
@@ -324,6 +362,9 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
         for (int k = tid; k < p.K; k += kBlock) roots_s[k] = p.roots32[k];
         __syncthreads();
     }
+    float tp[R];   // Q3: this thread's rows (row tid of every tile) summed
+#pragma unroll
+    for (int j = 0; j < R; ++j) tp[j] = 0.0f;
 
     float c[CPL][2 * R], c3[CPL][2 * R];
     int slot[CPL];
@@ -348,6 +389,12 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
         const float* __restrict__ src = p.V + t0 * RF;
         for (int e = tid; e < cnt * RF; e += kBlock) tile[e] = src[e];
         __syncthreads();
+        if constexpr (Q3) {
+            if (tid < cnt) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) tp[j] += tile[tid * RF + j];
+            }
+        }
         if (cnt == kTile) {
 #pragma unroll 4
             for (int ii = 0; ii < kTile / NW; ++ii) {
@@ -378,7 +425,16 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
             }
         }
     }
-    block_sums_out<R, CPL>(p, acc, base, red, wave, lane);
+    if constexpr (Q3) {   // wave sums of tp, in a fixed order
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            float t = tp[j];
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, kWave);
+            if (lane == 0) tsum[wave * R + j] = t;
+        }
+    }
+    block_sums_out<R, CPL, Q3>(p, acc, base, red, wave, lane, tsum);
 }
 
 }  // namespace
