@@ -383,12 +383,27 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
     const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
     const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
     uint16_t* probe_base = PROBE ? p.probe_out : nullptr;
+    // each thread stages RF values of a tile (kTile == kBlock); the next
+    // tile's values are loaded into registers while the current one is scored
+    static_assert(kTile == kBlock, "one row's worth of values per thread");
+    float pre[RF];
+    auto fetch = [&](int64_t t0n) {
+        const int64_t lim = (min((int64_t)kTile, r1 - t0n)) * RF;
+        const float* __restrict__ src = p.V + t0n * RF;
+#pragma unroll
+        for (int k = 0; k < RF; ++k) {
+            const int e = tid + k * kBlock;
+            pre[k] = e < lim ? src[e] : 0.0f;
+        }
+    };
+    fetch(r0);
     for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
         const int cnt = (int)min((int64_t)kTile, r1 - t0);
         __syncthreads();
-        const float* __restrict__ src = p.V + t0 * RF;
-        for (int e = tid; e < cnt * RF; e += kBlock) tile[e] = src[e];
+#pragma unroll
+        for (int k = 0; k < RF; ++k) tile[tid + k * kBlock] = pre[k];
         __syncthreads();
+        if (t0 + kTile < r1) fetch(t0 + kTile);
         if constexpr (Q3) {
             if (tid < cnt) {
 #pragma unroll
