@@ -106,7 +106,9 @@ typedef struct lrqo_sampled_options {
                                 |V_ij||c_j| of a decision boundary, u = 2^-24);
                                 other K: V c on BF16 MFMA with hi + lo parts,
                                 rows inside the BF16 error margin recomputed in
-                                FP32.  The FP64 rescore is the same in both */
+                                FP32.  The FP64 rescore is the same in both.
+                                LRQO_BF16_FORM=w4 (read once per process)
+                                selects the second form for every K */
     int32_t rescore_topk;    /* 1..64; 0 means 64 */
     uint32_t instance;       /* counter word 2 of the direction stream */
     uint64_t first_index;    /* index of the first direction (range splitting) */

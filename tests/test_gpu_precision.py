@@ -152,6 +152,28 @@ def test_precision_zero_and_repeated_rows(lrqo_mod, K, real):
     _check_probes(V, K, dirs, probe, l32, l16)
 
 
+@pytest.mark.parametrize("K", [3, 4, 5])
+def test_precision_ranges_directions_and_determinism(lrqo_mod, K):
+    """The precision form over disjoint index ranges merges to the whole
+    range; an explicit direction list (the stream's own directions) scores
+    bit-identically to the stream; repeated calls are bit-identical."""
+    V = _fp32_exact(inputs.random_V(700, 3, 71 + K))
+    Vd = _to_dev(V, False)
+    f_whole = torch.empty(4000, dtype=torch.float32, device="cuda")
+    d_whole = torch.empty((4000, 6), dtype=torch.float32, device="cuda")
+    whole = lrqo_mod.solve_sampled(Vd, K, 4000, 9, precision=1, f_out=f_whole, dirs_out=d_whole)
+    parts = [lrqo_mod.solve_sampled(Vd, K, 1000, 9, precision=1, first_index=1000 * q) for q in range(4)]
+    best = max(parts, key=lambda o: (o.obj, -o.best_index))
+    assert best.best_index == whole.best_index and best.obj == whole.obj
+    check_result(V, K, 1000, 9, parts[1], first=1000, reach=reach_of(K))
+    f_list = torch.empty(4000, dtype=torch.float32, device="cuda")
+    listed = lrqo_mod.solve_sampled(Vd, K, 4000, 9, precision=1, f_out=f_list, directions=d_whole)
+    assert torch.equal(f_list, f_whole) and listed.best_index == whole.best_index and listed.obj == whole.obj
+    again = torch.empty(4000, dtype=torch.float32, device="cuda")
+    rep = lrqo_mod.solve_sampled(Vd, K, 4000, 9, precision=1, f_out=again)
+    assert torch.equal(again, f_whole) and torch.equal(rep.z, whole.z)
+
+
 def test_precision_rejects_large_r(lrqo_mod):
     V = torch.zeros((10, 5), dtype=torch.complex64, device="cuda")
     with pytest.raises(lrqo_mod.LrqoError, match="r <= 4"):
