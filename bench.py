@@ -100,6 +100,14 @@ def _alu_roofline(flops: float, ms: float, what: str) -> dict:
 
 
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def _fp64_roofline(flops: float, ms: float, what: str) -> dict:
+    achieved = flops / (ms / 1000.0) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4), "algorithmic_flops": flops, "ms": ms,
+            "what": what}
 
 
 def _mfma_roofline(flops: float, ms: float, what: str) -> dict:
@@ -482,7 +490,13 @@ def form_spectral():
                          "iterations": res.iterations, "eigenvalues_over_n": [x / n for x in res.eigenvalues[:3]],
                          "W_entries_generated_per_s":
                              res.iterations * float(n) * (n + 1) / 2 / (res.device_ms / 1000.0),
-                         "ms_per_product": res.device_ms / res.iterations}
+                         "ms_per_product": res.device_ms / res.iterations,
+                         # k_w_tiles dominates: per upper-triangle entry, W_ij x_j and
+                         # conj(W_ij) x_i in FP64 (8 multiply-adds); the Philox draw and the
+                         # four transcendentals that form W_ij are not counted
+                         "roofline": _fp64_roofline(16.0 * res.iterations * float(n) * (n + 1) / 2, res.device_ms,
+                                                    "matrix-free (U U^H + sigma W) x: 8 FP64 FMAs per generated "
+                                                    "upper-triangle entry of W, all products of the solve")}
     return out
 
 
