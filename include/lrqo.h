@@ -177,7 +177,8 @@ lrqo_status lrqo_solve_sampled_noalloc(const float* V, int64_t n, int32_t r, int
  * set of 2d-1 rows with at most two per coordinate (d = r, r-1, ..., 1, the
  * recursion of Alg. 2 on the leading d columns) in colex order within each
  * level, solves the FP64 null vector of each set (twice-orthogonalised
- * Gram-Schmidt; the set is full rank when its smallest residual exceeds
+ * Gram-Schmidt, by one thread per set up to d = 4 and by sixteen lanes per
+ * set above; the set is full rank when its smallest residual exceeds
  * 1e-10 times its largest row norm), takes both signs, labels untouched rows
  * by the decision rule and tries, for coordinates in the set, both labels
  * beside the boundary (one row in the set) or all K labels (two rows:
@@ -190,11 +191,15 @@ lrqo_status lrqo_solve_sampled_noalloc(const float* V, int64_t n, int32_t r, int
  *
  * V (device): n x r complex128, interleaved (re, im), row-major.
  * z (device): n uint8 labels.  obj (host): FP64 objective.
- * Ranges: 1 <= r <= 4, r <= n <= 2^31 - 1, 2 <= K <= 255, at most 2^20
+ * Ranges: 1 <= r <= 8, r <= n <= 2^31 - 1, 2 <= K <= 255, at most 2^20
  * label combinations per vertex (2^(2r-1-2p) K^p); the number of index sets
  * sum_d C(n B_K, 2d-1) must not exceed the cap: max_sets when positive, 2^34
  * when 0, and 2^62 when negative (the cap lifted); otherwise LRQO_ETOOBIG
  * before any device work.  Set indices are 64-bit.
+ * A factor that violates general position (Assumption 1; for instance a real
+ * V with K = 2, whose augmented rows only constrain Re c) makes valid sets
+ * rank deficient: res->warning is LRQO_EDEGENERATE and the result is the best
+ * candidate found, with no claim of optimality.
  * Environment (inspection only, the result does not depend on them):
  * LRQO_EXACT_CHUNK sets per chunk (default 2^26); LRQO_EXACT_FORM=fused
  * scores every set in one pass over all rows (the form otherwise used when

@@ -15,7 +15,9 @@
 //                   arithmetic, half the FMAs, when none is)
 //   k_exact_score   one thread per index set (grid-stride) and row slice:
 //                   colex unranking (or a random draw), FP64 null vector by
-//                   twice-orthogonalised Gram-Schmidt, both signs scored in
+//                   twice-orthogonalised Gram-Schmidt (in the thread for
+//                   d <= 4, by sixteen lanes per set for larger d), both signs
+//                   scored in
 //                   FP32 over the slice's rows (row tiles in LDS);
 //                   coordinates in the set tried with every label the vertex
 //                   leaves open; best FP32 score per set -> fbuf
@@ -45,7 +47,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTile = 256;
-constexpr int kMaxR = 4;
+constexpr int kMaxR = 8;
+constexpr int kThreadMaxD = 4;    // levels whose vertex one thread solves alone
 constexpr int kTopT = 64;
 constexpr int kRescoreSlices = 64;   // row slices of the FP64 rescore, at most
 constexpr double kRankTol = 1e-10;
@@ -56,12 +59,19 @@ constexpr uint64_t kHardMaxSets = 1ull << 62;        // limit with the cap lifte
 
 // A vertex as the split scorer reads it: FP32 direction (re, im per
 // column), the coordinates of its index set (-1 when it has none), and
-// whether the set gave a full-rank vertex.
-struct VertexRec {
-    float c[2 * 4];
-    int32_t g[2 * 4 - 1];
+// whether the set gave a full-rank vertex.  64 bytes up to d = 4, 128 above.
+template <int DP>
+struct VertexRecT {
+    float c[2 * DP];
+    int32_t g[2 * DP - 1];
     int32_t ok;
 };
+template <int D>
+using VertexRec = VertexRecT<(D <= kThreadMaxD ? kThreadMaxD : kMaxR)>;
+
+size_t vertex_rec_bytes(int r) {
+    return r <= kThreadMaxD ? sizeof(VertexRecT<kThreadMaxD>) : sizeof(VertexRecT<kMaxR>);
+}
 
 struct ExactParams {
     const double* V64;   // n x r complex128, interleaved
@@ -71,7 +81,7 @@ struct ExactParams {
     int K;
     int B;
     int64_t N;                          // n * B rows of the augmented matrix
-    const unsigned long long* binom;    // C(x, k) at [k * (N + 1) + x], k = 0 .. 7
+    const unsigned long long* binom;    // C(x, k) at [k * (N + 1) + x], k = 0 .. 2r - 1
     const double2* rho;                 // [B]
     const double2* roots64;             // [K]
     const float2* roots32;              // [K]
@@ -83,7 +93,7 @@ struct ExactParams {
     uint64_t draw_seed;
     int64_t rows_per_slice;             // rows of one slice of the split scorer's grid
     float* part;                        // split form: slice sums
-    VertexRec* recs;                    // split form: one record per set
+    void* recs;                         // split form: one VertexRec<d> per set
     const int32_t* complex_v;           // nonzero: V has an imaginary part (else real arithmetic)
 };
 
@@ -162,7 +172,7 @@ __device__ __forceinline__ void draw_rows(uint64_t seed, uint64_t s, int64_t N, 
 #pragma unroll
     for (int j = 0; j < M; ++j)
         c[j] = (int64_t)((((uint64_t)w[2 * j + 1] << 32) | (uint64_t)w[2 * j]) % (uint64_t)N);
-    for (int t = 1; t < M; ++t) {       // insertion sort, M <= 7
+    for (int t = 1; t < M; ++t) {       // insertion sort, M <= 15
         const int64_t x = c[t];
         int u = t - 1;
         while (u >= 0 && c[u] > x) {
@@ -176,13 +186,11 @@ __device__ __forceinline__ void draw_rows(uint64_t seed, uint64_t s, int64_t N, 
     for (int t = 0; t + 1 < M; ++t) distinct &= c[t] < c[t + 1];
 }
 
-// The vertex of one index set: groups g[t], boundary ids mm[t], unit null
-// vector v in R^{2D}.  Returns false for a set with three rows of one group
-// (invalid) or below the rank tolerance (rank_deficient set accordingly).
+// The rows of one index set: groups g[t] and boundary ids mm[t]; false for
+// a set with a repeated row (random draws) or three rows of one group.
 template <int D>
-__device__ bool vertex(const ExactParams& p, uint64_t rank, int64_t (&g)[2 * D - 1],
-                       int (&mm)[2 * D - 1], double (&v)[2 * D], bool& valid) {
-    constexpr int M = 2 * D - 1, C2 = 2 * D;
+__device__ bool set_rows(const ExactParams& p, uint64_t rank, int64_t (&g)[2 * D - 1], int (&mm)[2 * D - 1]) {
+    constexpr int M = 2 * D - 1;
     int64_t c[M];
     bool distinct = true;
     if (p.random) draw_rows<M>(p.draw_seed, rank, p.N, c, distinct);
@@ -192,9 +200,21 @@ __device__ bool vertex(const ExactParams& p, uint64_t rank, int64_t (&g)[2 * D -
         g[t] = c[t] / p.B;
         mm[t] = (int)(c[t] - g[t] * p.B);
     }
-    valid = distinct;
+    bool valid = distinct;
 #pragma unroll
     for (int t = 0; t + 2 < M; ++t) valid &= g[t] != g[t + 2];
+    return valid;
+}
+
+// The vertex of one index set, solved by one thread (d <= 4): groups g[t],
+// boundary ids mm[t], unit null vector v in R^{2D}.  Returns false for an
+// invalid set or one below the rank tolerance (rank_deficient set
+// accordingly).
+template <int D>
+__device__ bool vertex(const ExactParams& p, uint64_t rank, int64_t (&g)[2 * D - 1],
+                       int (&mm)[2 * D - 1], double (&v)[2 * D], bool& valid) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    valid = set_rows<D>(p, rank, g, mm);
     if (!valid) return false;
 
     double a[M][C2];
@@ -283,6 +303,133 @@ __device__ bool vertex(const ExactParams& p, uint64_t rank, int64_t (&g)[2 * D -
     return amax > 0.0 && rmin > kRankTol * amax;
 }
 
+// Levels d > 4: the (2d-1) x 2d block of a set no longer fits one thread's
+// registers.  Sixteen lanes share a set instead, lane k holding column k of
+// its rows (zero for k >= 2d), and every dot product over the 2d columns is a
+// butterfly sum over the sixteen lanes, which leaves the same value in each of
+// them.  The steps are those of vertex(): row scales, two Gram-Schmidt passes,
+// the complement direction e_kb of largest residual, its projection and
+// normalisation.
+constexpr int kCoopLanes = 16;
+static_assert(2 * kMaxR <= kCoopLanes, "a lane per column");
+
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+    for (int off = kCoopLanes / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+template <int D>
+__device__ double solve_columns(const ExactParams& p, const int64_t (&g)[2 * D - 1], const int (&mm)[2 * D - 1],
+                                int k, bool& ok) {
+    constexpr int M = 2 * D - 1, C2 = 2 * D;
+    const int j = k < D ? k : k - D;          // column of V behind column k
+    double a[M];
+    double amax = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+        const double2 rh = p.rho[mm[t]];
+        double x = 0.0;
+        if (k < C2) {
+            const double vr = p.V64[(g[t] * p.r + j) * 2], vi = p.V64[(g[t] * p.r + j) * 2 + 1];
+            x = k < D ? rh.x * vi + rh.y * vr      // Im(rho V_ij)
+                      : rh.x * vr - rh.y * vi;     // Re(rho V_ij)
+        }
+        a[t] = x;
+        amax = fmax(amax, sqrt(group_sum(x * x)));
+    }
+    double rmin = INFINITY;
+#pragma unroll
+    for (int t = 0; t < M; ++t) {
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+            for (int u = 0; u < t; ++u) a[t] -= group_sum(a[u] * a[t]) * a[u];
+        }
+        const double nrm = sqrt(group_sum(a[t] * a[t]));
+        rmin = fmin(rmin, nrm);
+        a[t] *= nrm > 0.0 ? 1.0 / nrm : 0.0;
+    }
+    // the unit vector with the largest residual, the lowest k on ties
+    double wres = -INFINITY;
+    if (k < C2) {
+        wres = 1.0;
+#pragma unroll
+        for (int t = 0; t < M; ++t) wres -= a[t] * a[t];
+    }
+    int kb = k;
+#pragma unroll
+    for (int off = kCoopLanes / 2; off > 0; off >>= 1) {
+        const double wo = __shfl_xor(wres, off, kWave);
+        const int ko = __shfl_xor(kb, off, kWave);
+        if (wo > wres || (wo == wres && ko < kb)) {
+            wres = wo;
+            kb = ko;
+        }
+    }
+    const int base = (int)(threadIdx.x % kWave) & ~(kCoopLanes - 1);
+    double vk = k == kb ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) vk -= __shfl(a[t], base + kb, kWave) * a[t];
+    if (k >= C2) vk = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t) vk -= group_sum(a[t] * vk) * a[t];
+    vk *= 1.0 / sqrt(group_sum(vk * vk));
+    ok = amax > 0.0 && rmin > kRankTol * amax;
+    return vk;
+}
+
+struct CoopLds {
+    uint64_t rank[kBlock];
+    double v[kBlock][2 * kMaxR];
+    int32_t state[kBlock];       // 1: a valid set to solve; then 2 if full rank
+};
+
+__device__ __forceinline__ CoopLds& coop_lds() {
+    __shared__ CoopLds s;
+    return s;
+}
+
+// The vertex of each thread's set for every level: alone for d <= 4; for
+// d > 4 every thread of the block must call it (it has barriers), sixteen
+// lanes per set, each thread getting back its own set's vertex (uniform:
+// every thread passes the same rank, solved once).
+template <int D>
+__device__ bool vertex_blk(const ExactParams& p, uint64_t rank, bool active, bool uniform,
+                           int64_t (&g)[2 * D - 1], int (&mm)[2 * D - 1], double (&v)[2 * D], bool& valid) {
+    if constexpr (D <= kThreadMaxD) {
+        valid = false;
+        return active && vertex<D>(p, rank, g, mm, v, valid);
+    } else {
+        constexpr int M = 2 * D - 1, C2 = 2 * D;
+        CoopLds& sh = coop_lds();
+        const int tid = threadIdx.x;
+        valid = active && set_rows<D>(p, rank, g, mm);
+        sh.rank[tid] = rank;
+        sh.state[tid] = valid ? 1 : 0;
+        __syncthreads();
+        const int lane = tid % kCoopLanes;
+        const int nsets = uniform ? 1 : kBlock;
+        for (int q = tid / kCoopLanes; q < nsets; q += kBlock / kCoopLanes) {
+            if (sh.state[q] == 0) continue;          // the same for the sixteen lanes
+            int64_t gq[M];
+            int mq[M];
+            set_rows<D>(p, sh.rank[q], gq, mq);
+            bool okq = false;
+            const double vk = solve_columns<D>(p, gq, mq, lane, okq);
+            if (lane < C2) sh.v[q][lane] = vk;
+            if (lane == 0 && okq) sh.state[q] = 2;
+        }
+        __syncthreads();
+        const int src = uniform ? 0 : tid;
+        const bool ok = valid && sh.state[src] == 2;
+#pragma unroll
+        for (int c = 0; c < C2; ++c) v[c] = ok ? sh.v[src][c] : 0.0;
+        __syncthreads();                             // before the next call rewrites the block's slots
+        return ok;
+    }
+}
+
 // Options left open at a vertex for the coordinates of the set (both rows
 // of a double group share one entry; the second gets count 1): first label
 // o[t] and count cnt[t] of consecutive labels mod K.
@@ -333,6 +480,20 @@ __global__ void k_to_f32(const double* __restrict__ V64, float* __restrict__ V32
         if (!isfinite(x)) *nonfinite = 1;
         if ((e & 1) && x != 0.0) *complex_v = 1;   // every writer stores the same value
         V32[e] = (float)x;
+    }
+}
+
+// r > 4: the factor in kMaxR columns, zeros beyond its r (the kernels for
+// those ranks are built for kMaxR columns only; a zero column adds exact
+// zeros to every sum and product, so the results are those of r columns).
+__global__ void k_pad_columns(const double* __restrict__ V, double* __restrict__ Vp, int64_t n, int r) {
+    const int64_t count = n * kMaxR;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / kMaxR;
+        const int j = (int)(e - i * kMaxR);
+        Vp[2 * e] = j < r ? V[2 * (i * r + j)] : 0.0;
+        Vp[2 * e + 1] = j < r ? V[2 * (i * r + j) + 1] : 0.0;
     }
 }
 
@@ -419,12 +580,16 @@ __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1]
                              const double (&v)[2 * D], const float (&acc)[2][2 * R],
                              const float2* roots_s, unsigned long long& ncand) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
-    // the set's rows in registers once (every combination reads them)
-    float vt[M][2 * R];
+    // the set's rows in registers once (every combination reads them) when
+    // they fit; above that they are read from the FP32 copy (cached)
+    constexpr bool kHold = M * 2 * R <= 64;
+    float vt[kHold ? M : 1][kHold ? 2 * R : 1];
+    if constexpr (kHold) {
 #pragma unroll
-    for (int t = 0; t < M; ++t)
+        for (int t = 0; t < M; ++t)
 #pragma unroll
-        for (int j = 0; j < 2 * R; ++j) vt[t][j] = g[t] >= 0 ? p.V32[g[t] * 2 * R + j] : 0.0f;
+            for (int j = 0; j < 2 * R; ++j) vt[t][j] = g[t] >= 0 ? p.V32[g[t] * 2 * R + j] : 0.0f;
+    }
     float best = 0.0f;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -454,7 +619,14 @@ __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1]
                 const float2 z = roots_s[k];
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
-                    const float vr = vt[t][2 * j], vi = vt[t][2 * j + 1];
+                    float vr, vi;
+                    if constexpr (kHold) {
+                        vr = vt[t][2 * j];
+                        vi = vt[t][2 * j + 1];
+                    } else {
+                        vr = p.V32[g[t] * 2 * R + 2 * j];
+                        vi = p.V32[g[t] * 2 * R + 2 * j + 1];
+                    }
                     sr[2 * j] = fmaf(vr, z.x, fmaf(vi, z.y, sr[2 * j]));
                     sr[2 * j + 1] = fmaf(vr, z.y, fmaf(-vi, z.x, sr[2 * j + 1]));
                 }
@@ -530,8 +702,8 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
         int64_t g[M];
         int mm[M];
         double v[C2];
-        bool valid = false, ok = false;
-        if (active) ok = vertex<D>(p, p.rank0 + rank, g, mm, v, valid);
+        bool valid = false;
+        const bool ok = vertex_blk<D>(p, p.rank0 + rank, active, false, g, mm, v, valid);
         if (!ok) {
 #pragma unroll
             for (int t = 0; t < M; ++t) g[t] = -1;
@@ -546,7 +718,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
 #pragma unroll
         for (int t = 0; t < M; ++t) g32[t] = (int32_t)g[t];
         float acc[2][2 * R];
-        if (cplx)
+        if (cplx || R > kThreadMaxD)
             score_rows<R, D, KS, false>(p, c, g32, 0, p.n, tile, roots_s, acc);
         else
             score_rows<R, D, KS, true>(p, c, g32, 0, p.n, tile, roots_s, acc);
@@ -560,20 +732,25 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
 // Split form, stage 1: the vertex of each set in FP64, kept as its FP32
 // direction and its touched rows (-1 where the set has no full-rank vertex).
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_exact_vertex(ExactParams p, VertexRec* __restrict__ recs) {
+__global__ __launch_bounds__(kBlock) void k_exact_vertex(ExactParams p, VertexRec<D>* __restrict__ recs) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
+    using Rec = VertexRec<D>;
+    constexpr int DP = (int)(sizeof(Rec::c) / sizeof(float)) / 2;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t rank = (uint64_t)blockIdx.x * kBlock + threadIdx.x; rank < p.count; rank += stride) {
+    for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {   // block-uniform
+        const uint64_t rank = base + threadIdx.x;
+        const bool active = rank < p.count;
         int64_t g[M];
         int mm[M];
         double v[C2];
         bool valid = false;
-        const bool ok = vertex<D>(p, p.rank0 + rank, g, mm, v, valid);
-        VertexRec rec;
+        const bool ok = vertex_blk<D>(p, p.rank0 + rank, active, false, g, mm, v, valid);
+        if (!active) continue;
+        Rec rec;
 #pragma unroll
-        for (int j = 0; j < 2 * kMaxR; ++j) rec.c[j] = 0.0f;
+        for (int j = 0; j < 2 * DP; ++j) rec.c[j] = 0.0f;
 #pragma unroll
-        for (int t = 0; t < 2 * kMaxR - 1; ++t) rec.g[t] = -1;
+        for (int t = 0; t < 2 * DP - 1; ++t) rec.g[t] = -1;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             rec.c[2 * j] = ok ? (float)v[j] : 0.0f;
@@ -590,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_vertex(ExactParams p, VertexRe
 // set's two signs over the slice's rows from the stored record (no FP64
 // state, so many waves fit on a SIMD) and writes the slice sums to p.part.
 template <int R, int D, int KS>
-__global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const VertexRec* __restrict__ recs) {
+__global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const VertexRec<D>* __restrict__ recs) {
     constexpr int M = 2 * D - 1;
     __shared__ __align__(16) float tile[kTile * 2 * R];
     __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
@@ -607,7 +784,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const Vert
         float c[2 * D];
         int32_t g[M];
         if (active) {
-            const VertexRec rec = recs[rank];
+            const VertexRec<D> rec = recs[rank];
 #pragma unroll
             for (int j = 0; j < 2 * D; ++j) c[j] = rec.c[j];
 #pragma unroll
@@ -619,7 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const Vert
             for (int t = 0; t < M; ++t) g[t] = -1;
         }
         float acc[2][2 * R];
-        if (cplx)
+        if (cplx || R > kThreadMaxD)
             score_rows<R, D, KS, false>(p, c, g, r0, r1, tile, roots_s, acc);
         else
             score_rows<R, D, KS, true>(p, c, g, r0, r1, tile, roots_s, acc);
@@ -648,8 +825,8 @@ __global__ __launch_bounds__(kBlock) void k_exact_combine(ExactParams p, int sli
         int64_t g[M];
         int mm[M];
         double v[C2];
-        bool valid = false, ok = false;
-        if (active) ok = vertex<D>(p, p.rank0 + rank, g, mm, v, valid);
+        bool valid = false;
+        const bool ok = vertex_blk<D>(p, p.rank0 + rank, active, false, g, mm, v, valid);
         unsigned long long ncand = 0;
         float best = 0.0f;
         if (ok) {
@@ -734,7 +911,7 @@ __device__ void rescore_rows_one(const ExactParams& p, uint64_t rank, int64_t r0
     int mm[M];
     double v[C2];
     bool valid;
-    const bool ok = vertex<D>(p, rank, g, mm, v, valid);
+    const bool ok = vertex_blk<D>(p, rank, true, true, g, mm, v, valid);
     if (!ok) {
         if (threadIdx.x < 4 * R) out[threadIdx.x] = 0.0;
         return;
@@ -792,7 +969,7 @@ __device__ void rescore_one(ExactParams p, uint64_t rank, const double* part, in
     int mm[M];
     double v[C2];
     bool valid;
-    const bool ok = vertex<D>(p, rank, g, mm, v, valid);
+    const bool ok = vertex_blk<D>(p, rank, true, true, g, mm, v, valid);
     RescoreEntry best{-1.0, 0, 0, 0};
     if (!ok) {
         if (threadIdx.x == 0) *out = best;
@@ -878,6 +1055,10 @@ __global__ __launch_bounds__(kBlock) void k_exact_rescore_rows(ExactParams p, Le
         case 2: if constexpr (R >= 2) rescore_rows_one<R, 2>(p, rank, r0, r1, out); break;
         case 3: if constexpr (R >= 3) rescore_rows_one<R, 3>(p, rank, r0, r1, out); break;
         case 4: if constexpr (R >= 4) rescore_rows_one<R, 4>(p, rank, r0, r1, out); break;
+        case 5: if constexpr (R >= 5) rescore_rows_one<R, 5>(p, rank, r0, r1, out); break;
+        case 6: if constexpr (R >= 6) rescore_rows_one<R, 6>(p, rank, r0, r1, out); break;
+        case 7: if constexpr (R >= 7) rescore_rows_one<R, 7>(p, rank, r0, r1, out); break;
+        case 8: if constexpr (R >= 8) rescore_rows_one<R, 8>(p, rank, r0, r1, out); break;
         default:
             if (threadIdx.x < 4 * R) out[threadIdx.x] = 0.0;
     }
@@ -896,6 +1077,10 @@ __global__ __launch_bounds__(kBlock) void k_exact_rescore(ExactParams p, LevelTa
         case 2: if constexpr (R >= 2) rescore_one<R, 2>(p, rank, pt, slices, out + t); break;
         case 3: if constexpr (R >= 3) rescore_one<R, 3>(p, rank, pt, slices, out + t); break;
         case 4: if constexpr (R >= 4) rescore_one<R, 4>(p, rank, pt, slices, out + t); break;
+        case 5: if constexpr (R >= 5) rescore_one<R, 5>(p, rank, pt, slices, out + t); break;
+        case 6: if constexpr (R >= 6) rescore_one<R, 6>(p, rank, pt, slices, out + t); break;
+        case 7: if constexpr (R >= 7) rescore_one<R, 7>(p, rank, pt, slices, out + t); break;
+        case 8: if constexpr (R >= 8) rescore_one<R, 8>(p, rank, pt, slices, out + t); break;
         default:
             if (threadIdx.x == 0) out[t] = RescoreEntry{-1.0, 0, 0, 0};
     }
@@ -935,7 +1120,8 @@ __device__ void labels_one(const ExactParams& p, uint64_t rank, const ExactDevRe
     int mm[M];
     double v[C2];
     bool valid;
-    vertex<D>(p, rank, g, mm, v, valid);
+    vertex_blk<D>(p, rank, true, true, g, mm, v, valid);
+    if (i >= p.n) return;
     double cs[C2];
 #pragma unroll
     for (int k = 0; k < C2; ++k) cs[k] = res.sign ? -v[k] : v[k];
@@ -969,8 +1155,8 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void k_exact_labels(ExactParams p, LevelTable lt,
                                                          const ExactDevResult* __restrict__ res,
                                                          uint8_t* __restrict__ z) {
-    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (i >= p.n || res->level == 0) return;
+    const int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x;   // rows past n only join the barriers
+    if (res->level == 0) return;
     uint64_t rank;
     const int d = level_of(lt, R, (uint64_t)res->gidx, rank);
     switch (d) {
@@ -978,6 +1164,10 @@ __global__ __launch_bounds__(kBlock) void k_exact_labels(ExactParams p, LevelTab
         case 2: if constexpr (R >= 2) labels_one<R, 2>(p, rank, *res, i, z); break;
         case 3: if constexpr (R >= 3) labels_one<R, 3>(p, rank, *res, i, z); break;
         case 4: if constexpr (R >= 4) labels_one<R, 4>(p, rank, *res, i, z); break;
+        case 5: if constexpr (R >= 5) labels_one<R, 5>(p, rank, *res, i, z); break;
+        case 6: if constexpr (R >= 6) labels_one<R, 6>(p, rank, *res, i, z); break;
+        case 7: if constexpr (R >= 7) labels_one<R, 7>(p, rank, *res, i, z); break;
+        case 8: if constexpr (R >= 8) labels_one<R, 8>(p, rank, *res, i, z); break;
         default: break;
     }
 }
@@ -986,7 +1176,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_labels(ExactParams p, LevelTab
 // Bytes of the split form's buffers: one record per set, and the slice sums
 // (two signs, 2r components) per set and slice.
 uint64_t split_bytes(uint64_t count, int slices, int r) {
-    return count * (sizeof(VertexRec) + (uint64_t)slices * 2 * (2 * r) * sizeof(float));
+    return count * (vertex_rec_bytes(r) + (uint64_t)slices * 2 * (2 * r) * sizeof(float));
 }
 
 unsigned __int128 binom128(int64_t x, int k) {
@@ -1017,26 +1207,31 @@ int exact_slices(uint64_t count, int64_t n, int r, int64_t& rows) {
     return (int)slices;
 }
 
+// r > 4 takes the generic quantiser (atan2 and the root table) only: at the
+// sizes such enumerations reach (n of a few tens) the row pass is not what
+// costs, the vertex solves and the label combinations are.
 template <int R, int D>
 void launch_level(ExactParams p, bool force_fused, hipStream_t st) {
     const uint64_t blocks = std::min<uint64_t>((p.count + kBlock - 1) / kBlock, 8192);
     const int slices = force_fused ? 0 : exact_slices(p.count, p.n, R, p.rows_per_slice);
+    const int ks = R > kThreadMaxD ? 0 : p.K;
     if (slices == 0) {
-        switch (p.K) {
-            case 2: hipLaunchKernelGGL((k_exact_score<R, D, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
-            case 3: hipLaunchKernelGGL((k_exact_score<R, D, 3>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
-            case 4: hipLaunchKernelGGL((k_exact_score<R, D, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+        switch (ks) {
+            case 2: if constexpr (R <= kThreadMaxD) hipLaunchKernelGGL((k_exact_score<R, D, 2>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+            case 3: if constexpr (R <= kThreadMaxD) hipLaunchKernelGGL((k_exact_score<R, D, 3>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
+            case 4: if constexpr (R <= kThreadMaxD) hipLaunchKernelGGL((k_exact_score<R, D, 4>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
             default: hipLaunchKernelGGL((k_exact_score<R, D, 0>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p); break;
         }
         return;
     }
-    hipLaunchKernelGGL((k_exact_vertex<D>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p, p.recs);
+    VertexRec<D>* recs = static_cast<VertexRec<D>*>(p.recs);
+    hipLaunchKernelGGL((k_exact_vertex<D>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p, recs);
     const dim3 grid((unsigned)blocks, (unsigned)slices);
-    switch (p.K) {
-        case 2: hipLaunchKernelGGL((k_exact_rows<R, D, 2>), grid, dim3(kBlock), 0, st, p, p.recs); break;
-        case 3: hipLaunchKernelGGL((k_exact_rows<R, D, 3>), grid, dim3(kBlock), 0, st, p, p.recs); break;
-        case 4: hipLaunchKernelGGL((k_exact_rows<R, D, 4>), grid, dim3(kBlock), 0, st, p, p.recs); break;
-        default: hipLaunchKernelGGL((k_exact_rows<R, D, 0>), grid, dim3(kBlock), 0, st, p, p.recs); break;
+    switch (ks) {
+        case 2: if constexpr (R <= kThreadMaxD) hipLaunchKernelGGL((k_exact_rows<R, D, 2>), grid, dim3(kBlock), 0, st, p, recs); break;
+        case 3: if constexpr (R <= kThreadMaxD) hipLaunchKernelGGL((k_exact_rows<R, D, 3>), grid, dim3(kBlock), 0, st, p, recs); break;
+        case 4: if constexpr (R <= kThreadMaxD) hipLaunchKernelGGL((k_exact_rows<R, D, 4>), grid, dim3(kBlock), 0, st, p, recs); break;
+        default: hipLaunchKernelGGL((k_exact_rows<R, D, 0>), grid, dim3(kBlock), 0, st, p, recs); break;
     }
     hipLaunchKernelGGL((k_exact_combine<R, D>), dim3((unsigned)blocks), dim3(kBlock), 0, st, p, slices);
 }
@@ -1056,6 +1251,10 @@ lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, bool 
                 case 2: if constexpr (R >= 2) launch_level<R, 2>(q, force_fused, st); break;
                 case 3: if constexpr (R >= 3) launch_level<R, 3>(q, force_fused, st); break;
                 case 4: if constexpr (R >= 4) launch_level<R, 4>(q, force_fused, st); break;
+                case 5: if constexpr (R >= 5) launch_level<R, 5>(q, force_fused, st); break;
+                case 6: if constexpr (R >= 6) launch_level<R, 6>(q, force_fused, st); break;
+                case 7: if constexpr (R >= 7) launch_level<R, 7>(q, force_fused, st); break;
+                case 8: if constexpr (R >= 8) launch_level<R, 8>(q, force_fused, st); break;
             }
             LRQO_HIP(hipGetLastError());
             const int T = (int)std::min<uint64_t>(kTopT, q.count);
@@ -1103,7 +1302,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     clear_error();
     if (!V) return fail(LRQO_EINVAL, "V is null");
     if (!z) return fail(LRQO_EINVAL, "z is null");
-    if (r < 1 || r > kMaxR) return fail(LRQO_EINVAL, "r must be in [1, 4] for the vertex solvers");
+    if (r < 1 || r > kMaxR) return fail(LRQO_EINVAL, "r must be in [1, 8] for the vertex solvers");
     if (n < r || n > INT32_MAX) return fail(LRQO_EINVAL, "n must be in [r, 2^31 - 1]");
     if (K < 2 || K > LRQO_MAX_K) return fail(LRQO_EINVAL, "K must be in [2, 255]");
     if (random && (S < 1 || S > 0x7FFFFFFFll)) return fail(LRQO_EINVAL, "S must be in [1, 2^31 - 1]");
@@ -1143,6 +1342,8 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
 
     const uint64_t chunk = random ? (uint64_t)S : exact_chunk();
     const bool force_fused = exact_force_fused();
+    const int rk = r <= kThreadMaxD ? r : kMaxR;     // columns the kernels see
+    const bool pad = rk != r;                        // 4 < r < kMaxR: a zero-padded copy of V
     uint64_t cmax = 0;                   // the largest chunk
     for (int d = r; d >= 1; --d) cmax = std::max<uint64_t>(cmax, std::min<uint64_t>(chunk, lt.count[d]));
     const int Mmax = 2 * r - 1;
@@ -1153,16 +1354,17 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
             if (lt.count[d] == 0) continue;
             const uint64_t cnt = std::min<uint64_t>(chunk, lt.count[d]);
             int64_t rows = 0;
-            const int sl = exact_slices(cnt, n, r, rows);
+            const int sl = exact_slices(cnt, n, rk, rows);
             if (sl == 0) continue;
             rec_count = std::max<uint64_t>(rec_count, cnt);
-            part_floats = std::max<uint64_t>(part_floats, cnt * (uint64_t)sl * 2 * (2 * r));
+            part_floats = std::max<uint64_t>(part_floats, cnt * (uint64_t)sl * 2 * (2 * rk));
         }
     }
     CarveSize cs;
     cs.add<ExactDevResult>(1);
     cs.add<unsigned long long>(3 * kStatSlots);
-    cs.add<float>((size_t)n * r * 2);
+    cs.add<float>((size_t)n * rk * 2);
+    cs.add<double>(pad ? (size_t)n * rk * 2 : 0);
     cs.add<unsigned long long>(binom_entries);
     cs.add<double2>(LRQO_MAX_K);
     cs.add<double2>(LRQO_MAX_K);
@@ -1172,8 +1374,8 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     cs.add<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
     cs.add<TopEntry>(kTopT);
     cs.add<RescoreEntry>(kTopT);
-    cs.add<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * r));
-    cs.add<VertexRec>(rec_count);
+    cs.add<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * rk));
+    cs.add<char>(rec_count * vertex_rec_bytes(rk));
     cs.add<float>(part_floats);
     const size_t host_bytes = 4096 + binom_entries * sizeof(unsigned long long) +
                               LRQO_MAX_K * (2 * sizeof(double2) + sizeof(float2));
@@ -1185,7 +1387,8 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     Carve cv(ctx->arena);
     ExactDevResult* dres = cv.take<ExactDevResult>(1);
     unsigned long long* stats = cv.take<unsigned long long>(3 * kStatSlots);
-    float* V32 = cv.take<float>((size_t)n * r * 2);
+    float* V32 = cv.take<float>((size_t)n * rk * 2);
+    double* Vpad = pad ? cv.take<double>((size_t)n * rk * 2) : nullptr;
     unsigned long long* binom = cv.take<unsigned long long>(binom_entries);
     double2* rho = cv.take<double2>(LRQO_MAX_K);
     double2* roots64 = cv.take<double2>(LRQO_MAX_K);
@@ -1195,8 +1398,8 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     unsigned long long* kb = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
     TopEntry* top = cv.take<TopEntry>(kTopT);
     RescoreEntry* entries = cv.take<RescoreEntry>(kTopT);
-    double* rpart = cv.take<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * r));
-    VertexRec* recs = cv.take<VertexRec>(rec_count);
+    double* rpart = cv.take<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * rk));
+    void* recs = cv.take<char>(rec_count * vertex_rec_bytes(rk));
     float* part = cv.take<float>(part_floats);
 
     // host tables (pinned staging): result block, binomials, rho, roots
@@ -1244,10 +1447,10 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     LRQO_HIP(hipMemsetAsync(stats, 0, 3 * kStatSlots * sizeof(unsigned long long), st));
 
     ExactParams p{};
-    p.V64 = V;
+    p.V64 = pad ? Vpad : V;
     p.V32 = V32;
     p.n = n;
-    p.r = r;
+    p.r = rk;
     p.K = K;
     p.B = B;
     p.N = N;
@@ -1262,7 +1465,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     p.part = part;
     p.recs = recs;
 
-    const int64_t vcount = n * r * 2;
+    const int64_t vcount = n * rk * 2;
     int* nonfinite = &dres->nonfinite;
     int* complex_v = &dres->complex_v;
     p.complex_v = complex_v;
@@ -1283,6 +1486,12 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
         case 4:
             hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
             s = run_exact<4>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
+            break;
+        default:
+            if (pad) hipLaunchKernelGGL(k_pad_columns, dim3(256), dim3(256), 0, st, V, Vpad, n, r);
+            hipLaunchKernelGGL((k_to_f32<kMaxR>), dim3(256), dim3(256), 0, st, p.V64, V32, vcount, nonfinite,
+                               complex_v);
+            s = run_exact<kMaxR>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
     }
     if (s != LRQO_OK) return s;

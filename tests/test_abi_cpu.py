@@ -92,8 +92,8 @@ def test_simple_entry_rejects_null_obj(lib):
 
 
 @pytest.mark.parametrize("kw,msg", [
-    (dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=5), "r must"),
-    (dict(n=1, r=2), "n must"), (dict(K=1), "K must"), (dict(K=300), "K must"),
+    (dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=9), "r must"), (dict(r=0), "r must"),
+    (dict(n=7, r=8), "n must"), (dict(n=1, r=2), "n must"), (dict(K=1), "K must"), (dict(K=300), "K must"),
     (dict(n=2**31, r=1), "n must"),
 ])
 def test_exact_rejects_bad_arguments(lib, kw, msg):
@@ -104,6 +104,18 @@ def test_exact_rejects_bad_arguments(lib, kw, msg):
                                  ctypes.c_void_p(args["z"]), ctypes.byref(res))
     assert st == -1
     assert msg in lrqo.last_error()
+
+
+def test_exact_high_rank_limits(lib):
+    """r = 8 is accepted up to the per-vertex label combinations: at K = 16 a
+    vertex with seven zero coordinates leaves 2 * 16^7 > 2^20 combinations
+    (refused before any device work); at K = 2 the 2^15 of a level-8 vertex
+    pass, and the set count is the next check."""
+    res = lrqo.ExactResult()
+    st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(1), 20, 8, 16, 0, ctypes.c_void_p(1), ctypes.byref(res))
+    assert st == -4 and "label combinations" in lrqo.last_error()
+    st = lib.lrqo_solve_exact_ex(ctypes.c_void_p(1), 200, 8, 2, 0, ctypes.c_void_p(1), ctypes.byref(res))
+    assert st == -4 and "index sets" in lrqo.last_error()
 
 
 def test_exact_size_cap(lib):
@@ -169,7 +181,7 @@ def test_nullvec_rejects_bad_arguments(lib):
     res = lrqo.ExactResult()
     call = lambda V=1, n=10, r=2, K=3, S=16, z=1: lib.lrqo_solve_nullvec(
         ctypes.c_void_p(V), n, r, K, S, 1, ctypes.c_void_p(z), ctypes.byref(res))
-    for kw, msg in [(dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=5), "r must"),
+    for kw, msg in [(dict(V=0), "V is null"), (dict(z=0), "z is null"), (dict(r=9), "r must"),
                     (dict(n=1), "n must"), (dict(K=1), "K must"), (dict(S=0), "S must"),
                     (dict(S=2**31), "S must")]:
         assert call(**kw) == -1, kw

@@ -77,6 +77,77 @@ def test_exact_vs_brute(lrqo_mod, n, r, K):
     assert abs(res.obj - opt) <= 1e-12 * opt
 
 
+HIGH_RANK = [(10, 5, 2), (6, 5, 3), (7, 6, 4), (12, 6, 2), (14, 7, 2), (15, 8, 2), (8, 8, 4)]
+
+
+@pytest.mark.parametrize("n,r,K", HIGH_RANK)
+def test_exact_high_rank_vs_brute(lrqo_mod, n, r, K):
+    """r = 5 .. 8 (sets of 9 to 15 rows; their levels solve each vertex with
+    sixteen lanes, the lower levels one thread per set): optimum, labels and
+    every count equal to the oracle's, and the optimum is the brute force."""
+    V = inputs.random_V(n, r, 100 * n + 10 * r + K)
+    z, res = _solve(lrqo_mod, V, K)
+    _check(V, K, z, res)
+    opt, _, _ = brute.brute_force(V, K)
+    assert abs(res.obj - opt) <= 1e-12 * opt
+
+
+@pytest.mark.parametrize("n,r,K,chunk,form", [(10, 5, 2, 7, "fused"), (7, 6, 4, 100, ""), (12, 6, 2, 5, "fused"),
+                                              (14, 7, 2, 1000, "fused"), (15, 8, 2, 4096, "")])
+def test_exact_high_rank_forms(lrqo_mod, n, r, K, chunk, form, monkeypatch):
+    """The fused scorer and ragged chunks at r = 5 .. 8 against the oracle."""
+    monkeypatch.setenv("LRQO_EXACT_CHUNK", str(chunk))
+    if form:
+        monkeypatch.setenv("LRQO_EXACT_FORM", form)
+    V = inputs.random_V(n, r, 100 * n + 10 * r + K)
+    z, res = _solve(lrqo_mod, V, K)
+    _check(V, K, z, res)
+
+
+def test_exact_high_rank_real_factor(lrqo_mod):
+    """A real factor at r = 5, K = 4 (not in general position: a quarter of
+    the sets are rank deficient): optimum and labels up to rotation and
+    conjugation against the oracle and the brute force."""
+    V = inputs.random_V(7, 5, 515, real=True)
+    z, res = _solve(lrqo_mod, V, 4)
+    _check(V, 4, z, res, real=True, stats=False)
+    opt, _, _ = brute.brute_force(V, 4)
+    assert abs(res.obj - opt) <= 1e-12 * opt
+    assert res.warning == -6
+
+
+@pytest.mark.parametrize("r", [2, 6])
+def test_exact_real_factor_k2_is_flagged(lrqo_mod, r):
+    """A real factor with K = 2 is far from general position: every augmented
+    row is [-V_i, 0], so the rows only constrain Re c and every set of more
+    than one row is rank deficient.  Assumption 1 fails, the call says so
+    (LRQO_EDEGENERATE) and returns the best candidate it found, whose FP64
+    objective is the returned one; optimality is not claimed (the oracle,
+    which branches every row lying on a boundary line, reaches the brute-force
+    optimum here by enumerating every labelling)."""
+    V = inputs.random_V(12, r, 515, real=True)
+    z, res = _solve(lrqo_mod, V, 2)
+    assert res.warning == -6 and res.rank_deficient > 0
+    assert abs(oracle.objective(V, 2, z) - res.obj) <= 1e-12 * res.obj
+
+
+def test_exact_high_rank_at_scale(lrqo_mod):
+    """n = 30, r = 5, K = 2: 1.7e7 index sets (beyond the oracle's reach; the
+    fused scorer runs).  Held to what holds at any size: the count equals
+    sum_d C(30, 2d-1), the FP64 objective of the returned labels is the
+    returned objective, and the exact optimum is at least the best of 2^20
+    sampled directions."""
+    V = inputs.random_V(30, 5, 3050)
+    z, res = _solve(lrqo_mod, V, 2)
+    print(f"exact n=30 r=5: {res.index_sets} sets in {res.device_ms:.0f} ms", flush=True)
+    assert res.index_sets == sum(comb(30, 2 * d - 1) for d in range(1, 6))
+    assert res.rank_deficient == 0 and res.warning == 0
+    assert abs(oracle.objective(V, 2, z) - res.obj) <= 1e-12 * res.obj
+    samp = lrqo_mod.solve_sampled(torch.from_numpy(V.astype(np.complex64)).cuda(), 2, 1 << 20, 3)
+    V32 = V.astype(np.complex64).astype(np.complex128)
+    assert oracle.objective(V32, 2, z) >= oracle.objective(V32, 2, samp.z.cpu().numpy()) * (1 - 1e-6)
+
+
 def test_exact_larger_n(lrqo_mod):
     """n = 20 (34,220 index sets at r = 2): several tiles of 256 threads and a
     ragged last block; no brute force, the oracle's Alg. 2 decides."""

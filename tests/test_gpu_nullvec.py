@@ -29,7 +29,9 @@ def lrqo_mod():
 
 
 CASES = [(12, 2, 3, 3000, 5), (30, 2, 4, 2000, 6), (20, 3, 3, 1200, 7), (40, 1, 5, 600, 8),
-         (10, 4, 3, 400, 9), (25, 2, 8, 1000, 10)]
+         (10, 4, 3, 400, 9), (25, 2, 8, 1000, 10),
+         # r = 5 .. 8: draws of 9 to 15 rows, vertices solved by sixteen lanes
+         (20, 5, 3, 300, 11), (12, 6, 4, 300, 12), (60, 7, 2, 200, 13), (50, 8, 2, 150, 14)]
 
 
 @pytest.mark.parametrize("n,r,K,S,seed", CASES)

@@ -153,7 +153,9 @@ def test_pointwise_rounding_bound(oracle_lib, K):
 # ------------------------------------------------------------ exact solvers
 
 EXACT_CASES = [(12, 2, 3), (9, 2, 4), (8, 2, 5), (7, 3, 3), (10, 1, 3), (9, 2, 2),
-               (6, 3, 4), (7, 1, 8), (6, 2, 8)]
+               (6, 3, 4), (7, 1, 8), (6, 2, 8),
+               # r = 5 .. 8: levels whose sets have 9 to 15 rows
+               (10, 5, 2), (12, 6, 2), (7, 6, 4), (14, 7, 2)]
 
 
 @pytest.mark.parametrize("n,r,K", EXACT_CASES)

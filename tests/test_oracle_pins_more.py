@@ -81,7 +81,8 @@ def test_valid_set_count_golden():
         assert valid_set_count(int(n), int(r), int(K)) == int(val)
 
 
-@pytest.mark.parametrize("n,r,K", [(12, 2, 3), (7, 3, 3), (9, 2, 4), (8, 2, 5), (10, 1, 3), (6, 2, 8), (6, 3, 4)])
+@pytest.mark.parametrize("n,r,K", [(12, 2, 3), (7, 3, 3), (9, 2, 4), (8, 2, 5), (10, 1, 3), (6, 2, 8), (6, 3, 4),
+                                   (10, 5, 2), (7, 6, 4)])
 def test_enumeration_counts_closed_form(oracle_lib, n, r, K):
     """The oracle's index-set count equals the closed form (and, for a complex
     factor in general position, no valid set is rank deficient)."""
