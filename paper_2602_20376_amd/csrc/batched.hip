@@ -89,7 +89,17 @@ __device__ void score_item(const BatchDevParams& p, int t, int tile, const float
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) {
             acc[q][j] = 0.0f;
-            c3[q][j] = re_prescale(KS) * c[q][j];   // K = 3 and 8: Re w pre-scaled
+            c3[q][j] = re_prescale(KS) * c[q][j];   // K = 3: Re w pre-scaled
+        }
+        if constexpr (KS == 8) {                    // K = 8: the direction turned by e^{-i pi/8}
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float cr = c[q][2 * j], ci = c[q][2 * j + 1];
+                c[q][2 * j] = fmaf(cr, kCos8, ci * kSin8);
+                c[q][2 * j + 1] = fmaf(ci, kCos8, -(cr * kSin8));
+                c3[q][2 * j] = c[q][2 * j];
+                c3[q][2 * j + 1] = c[q][2 * j + 1];
+            }
         }
     }
     for (int i = 0; i < n; ++i) {
@@ -111,7 +121,7 @@ __device__ void score_item(const BatchDevParams& p, int t, int tile, const float
                 zr = k0 ? 1.0f : -0.5f;
                 zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
             } else if constexpr (KS == 8) {
-                nearest_root_k8t(wr, wi, zr, zi);
+                bisector_k8(wr, wi, zr, zi);        // turned root; ||s||^2 is unchanged
             } else {
                 nearest_root<KS>(wr, wi, p.K, roots, zr, zi);
             }

@@ -251,23 +251,26 @@ __device__ __forceinline__ void nearest_root(float wr, float wi, int K, const fl
     }
 }
 
-// K = 8 with the real part of w pre-scaled by t = tan(pi/8) (the caller forms
-// Re w from t c): in the quadrant of w, the x axis (labels 0 or 4) when
-// |Im w| <= t |Re w|, the y axis (2 or 6) when |Re w| <= t |Im w|, the
-// diagonal otherwise; the signs of Re w and Im w pick the quadrant.  One
-// multiply fewer than the unscaled form.
-__device__ __forceinline__ void nearest_root_k8t(float wrt, float wi, float& zr, float& zi) {
-    const float axt = fabsf(wrt), ay = fabsf(wi);
-    const bool h = ay <= axt;
-    const bool v = axt <= 0.17157287525380990f * ay;   // t^2 = 3 - 2 sqrt(2)
-    const float d = 0.70710678118654752f;
-    zr = copysignf(h ? 1.0f : (v ? 0.0f : d), wrt);
-    zi = copysignf(h ? 0.0f : (v ? 1.0f : d), wi);
+// K = 8 in the frame of w' = w e^{-i pi/8} (the caller scores the turned
+// direction c e^{-i pi/8}).  The set of w nearest root k, arg w within pi/8
+// of k pi/4, becomes the wedge of w' between the lines at (k-1) pi/4 and
+// k pi/4: the signs of Re w', Im w' and which of |Re w'|, |Im w'| is larger
+// fix it.  The root turned by the same angle, e^{i (k pi/4 - pi/8)}, is the
+// wedge's bisector: (cos pi/8, sin pi/8) or (sin pi/8, cos pi/8), with the
+// signs of w'.  Sums of V^H times turned roots are the sums of V^H z turned
+// by e^{-i pi/8}, a unit factor that leaves ||s||^2 unchanged.
+constexpr float kCos8 = 0.92387953251128674f;   // cos(pi/8)
+constexpr float kSin8 = 0.38268343236508977f;   // sin(pi/8)
+
+__device__ __forceinline__ void bisector_k8(float a, float b, float& yr, float& yi) {
+    const bool big = fabsf(a) >= fabsf(b);
+    yr = copysignf(big ? kCos8 : kSin8, a);
+    yi = copysignf(big ? kSin8 : kCos8, b);
 }
 
-// Factor on c for the real part of w, matching the pre-scaled quantisers.
+// Factor on c for the real part of w, matching the pre-scaled K = 3 quantiser.
 __host__ __device__ constexpr float re_prescale(int KS) {
-    return KS == 3 ? 1.7320508075688772f : (KS == 8 ? 0.41421356237309505f : 1.0f);
+    return KS == 3 ? 1.7320508075688772f : 1.0f;
 }
 
 // The same closed forms in FP64 for the rescore (any K through label_f64

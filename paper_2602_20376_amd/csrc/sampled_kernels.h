@@ -238,10 +238,17 @@ __device__ __forceinline__ void score_vals(const float (&v)[Row<R, REAL>::F],
         }
         float zr, zi;
         if constexpr (KS == 3) nearest_root_k3s(wr, wi, zr, zi);
-        else if constexpr (KS == 8) nearest_root_k8t(wr, wi, zr, zi);
+        else if constexpr (KS == 8) bisector_k8(wr, wi, zr, zi);   // root turned by e^{-i pi/8}
         else nearest_root<KS>(wr, wi, K, roots, zr, zi);
         if constexpr (PROBE) {
-            if (slot[q] >= 0) probe_row[(size_t)slot[q] * n] = (uint16_t)root_index(zr, zi, K);
+            if (slot[q] >= 0) {
+                float lr = zr, li = zi;
+                if constexpr (KS == 8) {          // the label of the root itself
+                    lr = zr * kCos8 - zi * kSin8;
+                    li = zr * kSin8 + zi * kCos8;
+                }
+                probe_row[(size_t)slot[q] * n] = (uint16_t)root_index(lr, li, K);
+            }
         }
         if constexpr (REAL) {
 #pragma unroll
@@ -373,9 +380,21 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
     lane_directions<R, CPL, PROBE>(p, base, kWave, blockIdx.y == 0 && wave == 0, c, slot);
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
-        // K = 3 and 8: the real part of w is formed with a pre-scaled c
+        // K = 3: the real part of w is formed with a pre-scaled c; K = 8: w
+        // is formed with c turned by e^{-i pi/8} (the stored directions are
+        // the unturned ones)
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) c3[q][j] = re_prescale(KS) * c[q][j];
+        if constexpr (KS == 8) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const float cr = c[q][2 * j], ci = c[q][2 * j + 1];
+                c[q][2 * j] = fmaf(cr, kCos8, ci * kSin8);
+                c[q][2 * j + 1] = fmaf(ci, kCos8, -(cr * kSin8));
+                c3[q][2 * j] = c[q][2 * j];
+                c3[q][2 * j + 1] = c[q][2 * j + 1];
+            }
+        }
         dr[q] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
         di[q] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
     }
