@@ -41,11 +41,14 @@ namespace {
 // Block 0: roots of unity omega^k = (cos, sin)(2 pi k / K) in FP64 and their
 // FP32 roundings, and the zeroed result record.  Every block: whether its
 // share of V holds a NaN or an infinity, into bad[blockIdx.x] (so that no
-// block writes the record while block 0 clears it; k_pick gathers them).
+// block writes the record while block 0 clears it; k_pick gathers them), and
+// the largest finite |V| entry of the share, into vmax[blockIdx.x] (the real
+// K = 3 scorer sizes its quantiser scale from it).
 __global__ __launch_bounds__(kBlock) void k_prologue(int K, double2* __restrict__ roots64,
                                                      float2* __restrict__ roots32, DevResult* __restrict__ res,
                                                      const float* __restrict__ V, int64_t count,
-                                                     int* __restrict__ bad) {
+                                                     int* __restrict__ bad, float* __restrict__ vmax) {
+    __shared__ float wmax[kBlock / kWave];
     if (blockIdx.x == 0) {
         for (int k = threadIdx.x; k < K; k += blockDim.x) {
             double sn, cs;
@@ -56,11 +59,24 @@ __global__ __launch_bounds__(kBlock) void k_prologue(int K, double2* __restrict_
         if (threadIdx.x == 0) *res = DevResult{};
     }
     bool b = false;
+    float m = 0.0f;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
-         e += (int64_t)gridDim.x * blockDim.x)
-        b |= !isfinite(V[e]);
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const float x = V[e];
+        const bool fin = isfinite(x);
+        b |= !fin;
+        m = fin ? fmaxf(m, fabsf(x)) : m;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = m;
     const int any = __syncthreads_or(b);
-    if (threadIdx.x == 0) bad[blockIdx.x] = any;
+    if (threadIdx.x == 0) {
+        bad[blockIdx.x] = any;
+        float mm = 0.0f;
+        for (int w = 0; w < kBlock / kWave; ++w) mm = fmaxf(mm, wmax[w]);
+        vmax[blockIdx.x] = mm;
+    }
 }
 
 // Slice sums: f of each candidate from the scorer's per-slice partial sums
@@ -352,6 +368,8 @@ lrqo_status run_sampled(const SampledJob& job, Scratch& sc, hipStream_t st) {
     p.probe_out = job.probe_out;
     p.probe_count = job.probe_count;
     for (int t = 0; t < job.probe_count; ++t) p.probe_idx[t] = job.probe_idx[t];
+    p.vmax = sc.vmax;
+    p.vmax_count = kCheckBlocks;
     launch_score_k<R, REAL>(p, dim3((unsigned)cand_blocks, (unsigned)sc.slices), st, job.precision);
     LRQO_HIP(hipGetLastError());
     LRQO_HIP(hipEventRecord(job.ev_score1, st));
@@ -444,6 +462,7 @@ void plan_sampled(const SampledJob& job, ScratchPlan& plan) {
     cs.add<unsigned long long>(slices > 1 ? (size_t)(job.S + kBlock - 1) / kBlock * kBlock : 0);
     cs.add<double>((size_t)plan.topk * plan.rescore_slices * 2 * R);
     cs.add<int>(kCheckBlocks);
+    cs.add<float>(kCheckBlocks);
     plan.bytes = cs.bytes;
 }
 
@@ -467,10 +486,11 @@ lrqo_status launch_sampled(const SampledJob& job, const ScratchPlan& plan, void*
     sc.rescore = cv.take<double>((size_t)plan.topk * plan.rescore_slices * 2 * job.r);
 
     sc.bad_blocks = cv.take<int>(kCheckBlocks);
+    sc.vmax = cv.take<float>(kCheckBlocks);
 
     const int64_t vcount = job.n * job.r * (job.real ? 1 : 2);
     hipLaunchKernelGGL(k_prologue, dim3(kCheckBlocks), dim3(kBlock), 0, st, job.K, sc.roots64, sc.roots32,
-                       sc.result, job.V, vcount, sc.bad_blocks);
+                       sc.result, job.V, vcount, sc.bad_blocks, sc.vmax);
     LRQO_HIP(hipGetLastError());
     return job.real ? dispatch_r<true>(job, sc, st) : dispatch_r<false>(job, sc, st);
 }

@@ -46,6 +46,8 @@ struct ScoreParams {
     uint16_t* probe_out;           // [probe_count][n] labels of the probed candidates (| 0x100: recomputed)
     int probe_count;
     uint32_t probe_idx[kMaxProbe]; // positions (0..S-1) of the probed candidates
+    const float* vmax;             // [vmax_count] largest |V| entry of each prologue block's share
+    int vmax_count;
 };
 
 struct RescoreParams {
@@ -110,6 +112,7 @@ struct Scratch {
     int rescore_slices;
     int64_t rescore_rows;
     int* bad_blocks;            // [kCheckBlocks] finiteness flags of the prologue's blocks
+    float* vmax;                // [kCheckBlocks] largest finite |V| entry of each prologue block's share
 };
 
 constexpr int kCheckBlocks = 256;   // blocks of the prologue's finiteness check

@@ -191,6 +191,23 @@ __device__ __forceinline__ void nearest_root_k3s(float wr3, float wi, float& zr,
     zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
 }
 
+// Scale B = 2^e of the real K = 3 quantiser, from the largest |V| entry M
+// (the prologue's per-block maxima, reduced by each wave): e = 118 -
+// floor(log2 M) keeps B |w| below 2^122 for r <= 4 and unit directions, so
+// B (|Im w| - sqrt(3) Re w) cannot overflow; it reaches [0, 1) without being
+// 0 only for rows whose |w| is below about 2^-95 M (where it stands for a
+// tie), and is at least 1 otherwise.  Any B when M is 0 or not finite (the
+// call then fails on the finiteness check).
+__device__ __forceinline__ float q3_scale(const float* vmax, int count) {
+    float m = 0.0f;
+    for (int k = (int)(threadIdx.x & (kWave - 1)); k < count; k += kWave) m = fmaxf(m, vmax[k]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if (!(m > 0.0f) || !isfinite(m)) return 1.0f;
+    const int e = min(126, max(-126, 118 - ilogbf(m)));
+    return ldexpf(1.0f, e);
+}
+
 // One row (values v) against the lane's candidates; dr[q][j] / di[q][j]
 // accumulate the real / imaginary part of s_j (for complex r <= 2 the packed
 // form keeps Re V and Im V products apart).  PROBE: probed candidates write
@@ -222,12 +239,16 @@ __device__ __forceinline__ void score_vals(const float (&v)[Row<R, REAL>::F],
             // real V, K = 3: z = 1 - 3/2 q + i (sqrt(3)/2) q sigma with
             // q = [label != 0] and sigma = sign(Im w); dr accumulates
             // sum_i V_i q_i and di sum_i V_i q_i sigma_i, and the caller
-            // forms s = sum_i V_i - 3/2 dr + i (sqrt(3)/2) di
-            const bool k0 = fabsf(wi) <= wr;
-            const float qf = k0 ? 0.0f : 1.0f;
+            // forms s = sum_i V_i - 3/2 dr + i (sqrt(3)/2) di.  Here
+            // wi = B Im w and wr = -B sqrt(3) Re w (B a power of two, see
+            // q3_scale), so |wi| + wr = B (|Im w| - sqrt(3) Re w) has the
+            // sign of the label test exactly, and clamped to [0, 1] it is q
+            // (one add with the clamp modifier); q sigma takes the sign of wi
+            const float qf = __builtin_amdgcn_fmed3f(fabsf(wi) + wr, 0.0f, 1.0f);
             const float qs = copysignf(qf, wi);
             if constexpr (PROBE) {
-                if (slot[q] >= 0) probe_row[(size_t)slot[q] * n] = (uint16_t)(k0 ? 0 : ((__float_as_uint(wi) >> 31) ? 2 : 1));
+                if (slot[q] >= 0)
+                    probe_row[(size_t)slot[q] * n] = (uint16_t)(qf == 0.0f ? 0 : ((__float_as_uint(wi) >> 31) ? 2 : 1));
             }
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -376,15 +397,25 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
     float c[CPL][2 * R], c3[CPL][2 * R];
     int slot[CPL];
     v4f dr[CPL], di[CPL];
+    float qscale = 1.0f;
+    if constexpr (Q3) qscale = q3_scale(p.vmax, p.vmax_count);
     const uint32_t base = blockIdx.x * (uint32_t)(kWave * CPL) + lane;
     lane_directions<R, CPL, PROBE>(p, base, kWave, blockIdx.y == 0 && wave == 0, c, slot);
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
-        // K = 3: the real part of w is formed with a pre-scaled c; K = 8: w
-        // is formed with c turned by e^{-i pi/8} (the stored directions are
-        // the unturned ones)
+        // K = 3: the real part of w is formed with a pre-scaled c (real V:
+        // -B sqrt(3) c, and B c for the imaginary part); K = 8: w is formed
+        // with c turned by e^{-i pi/8} (the stored directions are the
+        // unturned ones)
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) c3[q][j] = re_prescale(KS) * c[q][j];
+        if constexpr (Q3) {
+#pragma unroll
+            for (int j = 0; j < 2 * R; ++j) {
+                c3[q][j] *= -qscale;
+                c[q][j] *= qscale;
+            }
+        }
         if constexpr (KS == 8) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
