@@ -91,12 +91,10 @@ __device__ void score_item(const BatchDevParams& p, int t, int tile, const float
             acc[q][j] = 0.0f;
             c3[q][j] = re_prescale(KS) * c[q][j];   // K = 3: Re w pre-scaled
         }
-        if constexpr (KS == 8) {                    // K = 8: the direction turned by e^{-i pi/8}
+        if constexpr (KS == 8 || KS == 16) {        // the direction turned by e^{-i pi/K}
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const float cr = c[q][2 * j], ci = c[q][2 * j + 1];
-                c[q][2 * j] = fmaf(cr, kCos8, ci * kSin8);
-                c[q][2 * j + 1] = fmaf(ci, kCos8, -(cr * kSin8));
+                turn_direction<KS>(c[q][2 * j], c[q][2 * j + 1]);
                 c3[q][2 * j] = c[q][2 * j];
                 c3[q][2 * j + 1] = c[q][2 * j + 1];
             }
@@ -122,6 +120,8 @@ __device__ void score_item(const BatchDevParams& p, int t, int tile, const float
                 zi = k0 ? 0.0f : copysignf(0.8660254037844386f, wi);
             } else if constexpr (KS == 8) {
                 bisector_k8(wr, wi, zr, zi);        // turned root; ||s||^2 is unchanged
+            } else if constexpr (KS == 16) {
+                bisector_k16(wr, wi, zr, zi);
             } else {
                 nearest_root<KS>(wr, wi, p.K, roots, zr, zi);
             }

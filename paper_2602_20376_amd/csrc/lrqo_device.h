@@ -268,6 +268,35 @@ __device__ __forceinline__ void bisector_k8(float a, float b, float& yr, float& 
     yi = copysignf(big ? kSin8 : kCos8, b);
 }
 
+// K = 16 likewise, in the frame of w' = w e^{-i pi/16}: the sectors become
+// the wedges between consecutive multiples of pi/8.  In the quadrant of w'
+// they are told apart by which part is larger and by whether the smaller
+// exceeds tan(pi/8) times the larger; the turned roots are their bisectors,
+// at pi/16, 3 pi/16, 5 pi/16 and 7 pi/16 from the real axis.
+constexpr float kCos16 = 0.98078528040323043f;    // cos(pi/16)
+constexpr float kSin16 = 0.19509032201612826f;    // sin(pi/16)
+constexpr float kCos316 = 0.83146961230254524f;   // cos(3 pi/16)
+constexpr float kSin316 = 0.55557023301960218f;   // sin(3 pi/16)
+
+__device__ __forceinline__ void bisector_k16(float a, float b, float& yr, float& yi) {
+    const float ax = fabsf(a), ay = fabsf(b);
+    const bool big = ax >= ay;
+    const float lo = big ? ay : ax, hi = big ? ax : ay;
+    const bool inner = lo > 0.41421356237309505f * hi;   // tan(pi/8)
+    const float p = inner ? kCos316 : kCos16, q = inner ? kSin316 : kSin16;
+    yr = copysignf(big ? p : q, a);
+    yi = copysignf(big ? q : p, b);
+}
+
+// Turn of the direction for the K = 8 and 16 forms: c e^{-i pi/K}.
+template <int KS>
+__device__ __forceinline__ void turn_direction(float& cr, float& ci) {
+    constexpr float co = KS == 8 ? kCos8 : kCos16, si = KS == 8 ? kSin8 : kSin16;
+    const float r = cr, i = ci;
+    cr = fmaf(r, co, i * si);
+    ci = fmaf(i, co, -(r * si));
+}
+
 // Factor on c for the real part of w, matching the pre-scaled K = 3 quantiser.
 __host__ __device__ constexpr float re_prescale(int KS) {
     return KS == 3 ? 1.7320508075688772f : 1.0f;

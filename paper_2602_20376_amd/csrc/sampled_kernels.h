@@ -259,14 +259,16 @@ __device__ __forceinline__ void score_vals(const float (&v)[Row<R, REAL>::F],
         }
         float zr, zi;
         if constexpr (KS == 3) nearest_root_k3s(wr, wi, zr, zi);
-        else if constexpr (KS == 8) bisector_k8(wr, wi, zr, zi);   // root turned by e^{-i pi/8}
+        else if constexpr (KS == 8) bisector_k8(wr, wi, zr, zi);     // root turned by e^{-i pi/8}
+        else if constexpr (KS == 16) bisector_k16(wr, wi, zr, zi);   // root turned by e^{-i pi/16}
         else nearest_root<KS>(wr, wi, K, roots, zr, zi);
         if constexpr (PROBE) {
             if (slot[q] >= 0) {
                 float lr = zr, li = zi;
-                if constexpr (KS == 8) {          // the label of the root itself
-                    lr = zr * kCos8 - zi * kSin8;
-                    li = zr * kSin8 + zi * kCos8;
+                if constexpr (KS == 8 || KS == 16) {   // the label of the root itself
+                    constexpr float co = KS == 8 ? kCos8 : kCos16, si = KS == 8 ? kSin8 : kSin16;
+                    lr = zr * co - zi * si;
+                    li = zr * si + zi * co;
                 }
                 probe_row[(size_t)slot[q] * n] = (uint16_t)root_index(lr, li, K);
             }
@@ -404,9 +406,9 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
 #pragma unroll
     for (int q = 0; q < CPL; ++q) {
         // K = 3: the real part of w is formed with a pre-scaled c (real V:
-        // -B sqrt(3) c, and B c for the imaginary part); K = 8: w is formed
-        // with c turned by e^{-i pi/8} (the stored directions are the
-        // unturned ones)
+        // -B sqrt(3) c, and B c for the imaginary part); K = 8 and 16: w is
+        // formed with c turned by e^{-i pi/K} (the stored directions are
+        // the unturned ones)
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) c3[q][j] = re_prescale(KS) * c[q][j];
         if constexpr (Q3) {
@@ -416,12 +418,10 @@ __global__ __launch_bounds__(kBlock) void k_score_rows(ScoreParams p) {
                 c[q][j] *= qscale;
             }
         }
-        if constexpr (KS == 8) {
+        if constexpr (KS == 8 || KS == 16) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const float cr = c[q][2 * j], ci = c[q][2 * j + 1];
-                c[q][2 * j] = fmaf(cr, kCos8, ci * kSin8);
-                c[q][2 * j + 1] = fmaf(ci, kCos8, -(cr * kSin8));
+                turn_direction<KS>(c[q][2 * j], c[q][2 * j + 1]);
                 c3[q][2 * j] = c[q][2 * j];
                 c3[q][2 * j + 1] = c[q][2 * j + 1];
             }
