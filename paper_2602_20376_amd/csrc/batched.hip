@@ -202,6 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_score(BatchDevParams p) {
 //   labels   FP64 decision rule of the winner for every row
 constexpr int kStage = 512;          // keys the threshold pass may keep
 
+template <int KS>
 struct SelectShared {
     float Vs[kMaxRows * 8];         // V_t as stored (real: n x r, complex: n x 2r floats)
     unsigned long long top[kBlock / 64][64];
@@ -209,12 +210,13 @@ struct SelectShared {
     unsigned long long tau;
     unsigned int cnt;
     double part[kBlock / 64][kTopT][8];
-    double2 roots[LRQO_MAX_K];
+    double2 roots[KS == 0 ? LRQO_MAX_K : 1];   // the generic quantiser's table only (31 KB in all otherwise:
+                                               // five blocks per CU)
     double cbest[8];
 };
 
 template <int R, int KS>
-__device__ void select_rescore(const BatchDevParams& p, int t, SelectShared& sh) {
+__device__ void select_rescore(const BatchDevParams& p, int t, SelectShared<KS>& sh) {
     constexpr int NW = kBlock / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int S = p.S, T = p.T, n = p.n[t];
@@ -355,9 +357,11 @@ __device__ void select_rescore(const BatchDevParams& p, int t, SelectShared& sh)
 
 template <int KS>
 __global__ __launch_bounds__(kBlock) void k_batch_select(BatchDevParams p) {
-    __shared__ SelectShared sh;
+    __shared__ SelectShared<KS> sh;
     const int t = blockIdx.x;
-    for (int k = threadIdx.x; k < p.K; k += kBlock) sh.roots[k] = p.roots64[k];
+    if constexpr (KS == 0) {
+        for (int k = threadIdx.x; k < p.K; k += kBlock) sh.roots[k] = p.roots64[k];
+    }
     const int nf = p.n[t] * p.r[t] * (p.real ? 1 : 2);
     const float* src = p.V + p.voff[t];
     for (int e = threadIdx.x; e < nf; e += kBlock) sh.Vs[e] = src[e];

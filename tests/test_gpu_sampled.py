@@ -230,6 +230,35 @@ def test_degenerate_rows(lrqo_mod):
     check_result(V, 4, 2000, 8, out)
 
 
+@pytest.mark.parametrize("e", [40, -40])
+def test_real_k3_scale_invariance(lrqo_mod, e):
+    """The real K = 3 scorer takes its label test on a power-of-two scale
+    sized from the largest |V| entry.  Scaling V by 2^e scales every FP32
+    product and sum exactly, so the FP32 scores scale by 4^e bit for bit:
+    the same winner and labels, and an FP64 objective scaled by exactly 4^e."""
+    V = inputs.random_V(3000, 3, 31, real=True)
+    f1 = torch.empty(4096, device="cuda")
+    f2 = torch.empty(4096, device="cuda")
+    a = lrqo_mod.solve_sampled(_to_dev(V, True), 3, 4096, 9, real=True, f_out=f1)
+    b = lrqo_mod.solve_sampled(_to_dev(V * 2.0 ** e, True), 3, 4096, 9, real=True, f_out=f2)
+    assert a.best_index == b.best_index
+    assert torch.equal(a.z, b.z)
+    assert torch.equal(f1 * 2.0 ** (2 * e), f2)
+    assert b.obj == a.obj * 2.0 ** (2 * e)
+    check_result(V, 3, 4096, 9, a, real=True)
+
+
+def test_real_k3_rows_of_mixed_magnitude(lrqo_mod):
+    """Rows 2^-60 and 2^20 times the others in one real factor (the scale of
+    the K = 3 label test follows the largest entry): the best of S equals
+    the FP64 oracle's, labels at the winner bit-exact away from boundaries."""
+    V = inputs.random_V(2000, 3, 32, real=True)
+    V[::7] *= 2.0 ** -60
+    V[5] *= 2.0 ** 20
+    out = lrqo_mod.solve_sampled(_to_dev(V, True), 3, 3000, 4, real=True)
+    check_result(V, 3, 3000, 4, out, real=True)
+
+
 def test_nonfinite_is_rejected(lrqo_mod):
     V = inputs.random_V(50, 2, 6).astype(np.complex64)
     V[7, 1] = np.nan
