@@ -45,7 +45,7 @@ def parse():
                     help="skip the precision / batched / learned-proposal measurements")
     ap.add_argument("--train-count", type=int, default=10_000,
                     help="training instances of the learned proposal")
-    ap.add_argument("--form", choices=("exact", "precision_bf16", "batched", "learned_proposal", "refine",
+    ap.add_argument("--form", choices=("exact", "exact_campaign", "precision_bf16", "batched", "learned_proposal", "refine",
                                        "rank1_hybrid", "samplers", "spectral", "plain_maxcut_er"),
                     help="measure only this form and print its record (for profiling)")
     ap.add_argument("--workload", choices=("maxcut_ppm", "maxcut_er"), default="maxcut_ppm",
@@ -237,6 +237,32 @@ def form_exact():
                         "roofline": _alu_roofline(flops, res.device_ms,
                                                   "per index set and row, V c once and V^H z for each sign "
                                                   "(24r flops, complex V) over the whole solve")}
+    return out
+
+
+def form_exact_campaign():
+    """Rank-2 exact enumeration (K = 3) at the sizes of the paper's GPU
+    campaign on 5-regular graphs (App. "GPU-Parallel Rank-2 Campaign", Table
+    gpu_regular: n = 250 ... 1,500 on 15 P100s): one solve per size on this
+    GPU, on the rank-2 Laplacian factor of a random 5-regular graph.  The
+    enumeration's size depends only on (n, r, K); the paper's wall times are
+    quoted beside as context."""
+    import numpy as np
+    import torch
+
+    from paper_2602_20376_amd import inputs, lrqo
+
+    paper_s = {250: 30, 500: 213, 750: 330, 1000: 851, 1250: 2053, 1500: 7126}
+    out = {"workload": "5-regular graphs, rank-2 Laplacian factor, K = 3", "sizes": {}}
+    for n, ps in paper_s.items():
+        V = inputs.regular_factor(n, 5, 2).astype(np.complex128)
+        _, res = lrqo.solve_exact(torch.from_numpy(V).cuda(), 3, max_sets=-1)
+        out["sizes"][str(n)] = {"index_sets": res.index_sets, "candidates": res.candidates,
+                                "device_s": res.device_ms / 1000.0, "obj": res.obj,
+                                "sets_per_s": res.index_sets / (res.device_ms / 1000.0),
+                                "paper_wall_s_15xP100": ps}
+        print(f"exact campaign n={n}: {res.index_sets} sets in {res.device_ms / 1000.0:.2f} s", file=sys.stderr,
+              flush=True)
     return out
 
 
@@ -661,7 +687,8 @@ def main():
     from paper_2602_20376_amd import inputs, lrqo
 
     if args.form:
-        fn = {"precision_bf16": form_precision, "batched": form_batched, "exact": form_exact, "refine": form_refine,
+        fn = {"precision_bf16": form_precision, "batched": form_batched, "exact": form_exact,
+              "exact_campaign": form_exact_campaign, "refine": form_refine,
               "plain_maxcut_er": form_plain_maxcut_er,
               "rank1_hybrid": form_rank1_hybrid, "samplers": form_samplers, "spectral": form_spectral,
               "learned_proposal": lambda: form_learned(args.train_count)}[args.form]

@@ -170,6 +170,28 @@ def random_edges(n: int, m: int, seed: int):
     return _unique_pairs(rng, n, m, draw)
 
 
+def regular_edges(n: int, d: int, seed: int):
+    """A random d-regular simple graph on n vertices (n d even): the union of
+    d random perfect matchings (d odd, n even), each matching drawn again
+    until it shares no edge with the earlier ones."""
+    if n % 2 or d < 1:
+        raise ValueError("n must be even and d positive")
+    rng = np.random.default_rng(seed)
+    seen = set()
+    ii, jj = [], []
+    for _ in range(d):
+        while True:
+            p = rng.permutation(n)
+            a, b = np.minimum(p[0::2], p[1::2]), np.maximum(p[0::2], p[1::2])
+            keys = set((a.astype(np.int64) * n + b).tolist())
+            if not keys & seen:
+                break
+        seen |= keys
+        ii.append(a)
+        jj.append(b)
+    return np.concatenate(ii), np.concatenate(jj)
+
+
 def top_factor_sparse(L, r: int, seed: int) -> np.ndarray:
     """V = U diag(sqrt(lambda)) from the r largest eigenpairs of a PSD sparse
     matrix (FP64 Lanczos via ARPACK), columns in descending eigenvalue order."""
@@ -250,6 +272,13 @@ def maxcut_er(n: int = 100_000, mean_degree: float = 10.0, r: int = 4, K: int = 
     V32 = _cached(f"maxcut_er:{n}:{mean_degree}:{r}:{seed}:v1", build)
     return Instance(V32.astype(np.float64).astype(np.complex128), K, S, direction_seed(2), True,
                     f"maxcut_er(n={n},deg={mean_degree:g},r={r},K={K},S={S})")
+
+
+def regular_factor(n: int, d: int = 5, r: int = 2, seed: int = 0) -> np.ndarray:
+    """Max-3-Cut factor of a random d-regular graph: the top r eigenvectors
+    of its Laplacian scaled by sqrt(eigenvalue), FP64."""
+    i, j = regular_edges(n, d, instance_seed(10) + seed)
+    return top_factor_sparse(laplacian(n, i, j), r, instance_seed(10) + seed)
 
 
 def maxcut_er_graph(n: int = 100_000, mean_degree: float = 10.0):
