@@ -95,6 +95,7 @@ struct ExactParams {
     float* part;                        // split form: slice sums
     void* recs;                         // split form: one VertexRec<d> per set
     const int32_t* complex_v;           // nonzero: V has an imaginary part (else real arithmetic)
+    const uint32_t* vmax_bits;          // bits of the largest |V| entry (FP32, non-negative)
 };
 
 struct LevelTable {
@@ -125,6 +126,7 @@ struct ExactDevResult {
     int64_t combo;
     int32_t nonfinite;
     int32_t complex_v;   // some imaginary part of V is not zero
+    uint32_t vmax_bits;  // FP32 bits of the largest finite |V| entry (ordered as integers)
 };
 
 // ---------------------------------------------------------------- vertex
@@ -473,13 +475,26 @@ __device__ void open_labels(const ExactParams& p, const int64_t (&g)[2 * D - 1],
 // ---------------------------------------------------------------- FP32 scoring
 template <int R>
 __global__ void k_to_f32(const double* __restrict__ V64, float* __restrict__ V32, int64_t count,
-                         int* nonfinite, int* complex_v) {
+                         int* nonfinite, int* complex_v, uint32_t* vmax_bits) {
+    __shared__ uint32_t wmax[kBlock / kWave];
+    float m = 0.0f;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
          e += (int64_t)gridDim.x * blockDim.x) {
         const double x = V64[e];
         if (!isfinite(x)) *nonfinite = 1;
         if ((e & 1) && x != 0.0) *complex_v = 1;   // every writer stores the same value
-        V32[e] = (float)x;
+        const float xf = (float)x;
+        V32[e] = xf;
+        m = isfinite(xf) ? fmaxf(m, fabsf(xf)) : m;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = __float_as_uint(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) b = max(b, wmax[w]);
+        if (b) atomicMax(vmax_bits, b);              // non-negative floats order as their bits
     }
 }
 
@@ -504,16 +519,46 @@ __global__ void k_pad_columns(const double* __restrict__ V, double* __restrict__
 // REAL: V has no imaginary part; the tiles hold the real parts only and
 // the terms with Im V are left out (they are exact zeros, so the sums are
 // the same numbers).
+// REAL and K = 3: the set's rows are zeroed in V instead of in the labels,
+// and each sign accumulates in the basis q = [label != 0]: sum_i V_i q_i and
+// sum_i V_i q_i sign(Im w_i), with sum_i V_i beside, so that
+// s = sum V - 3/2 sum V q + i (sqrt(3)/2) sum V q sign(Im w) after the loop.
+// w is formed from B Im c and -B sqrt(3) Re c (B a power of two sized from
+// the largest |V| entry, as in the sampled scorer): |Im w'| + Re w' is
+// B (|Im w| - sqrt(3) Re w), the label test for +c, |Im w'| - Re w' the one
+// for -c (-c gives -w), each clamped to [0, 1] by the add's output modifier.
+__device__ __forceinline__ float exact_q3_scale(uint32_t vmax_bits) {
+    const float m = __uint_as_float(vmax_bits);
+    if (!(m > 0.0f) || !isfinite(m)) return 1.0f;
+    return ldexpf(1.0f, min(126, max(-126, 118 - ilogbf(m))));
+}
+
 template <int R, int D, int KS, bool REAL>
 __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c)[2 * D],
                                            const int32_t (&g)[2 * D - 1], int64_t r0, int64_t r1,
                                            float* tile, const float2* roots_s, float (&acc)[2][2 * R]) {
     constexpr int M = 2 * D - 1;
     constexpr int RW = REAL ? R : 2 * R;   // floats per staged row
+    constexpr bool Q3 = REAL && KS == 3;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) acc[s][j] = 0.0f;
+    float cw[Q3 ? 2 * D : 1];              // Q3: -B sqrt(3) Re c, B Im c
+    float tq[2][Q3 ? R : 1], ts[2][Q3 ? R : 1], tv[Q3 ? R : 1];
+    if constexpr (Q3) {
+        const float B = exact_q3_scale(*p.vmax_bits);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            cw[2 * j] = -B * (1.7320508075688772f * c[2 * j]);
+            cw[2 * j + 1] = B * c[2 * j + 1];
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            tq[0][j] = tq[1][j] = ts[0][j] = ts[1][j] = 0.0f;
+            tv[j] = 0.0f;
+        }
+    }
     int64_t next = INT64_MAX;                  // next touched row at or after r0
 #pragma unroll
     for (int t = 0; t < M; ++t)
@@ -536,6 +581,30 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
                 for (int t = 0; t < M; ++t)
                     if (g[t] > row && g[t] < nn) nn = g[t];
                 next = nn;
+            }
+            if constexpr (Q3) {
+                float vz[R];
+#pragma unroll
+                for (int e = 0; e < R; ++e) vz[e] = touched ? 0.0f : vv[e];
+                float wr = 0.0f, wi = 0.0f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    wr = fmaf(vz[j], cw[2 * j], wr);
+                    wi = fmaf(vz[j], cw[2 * j + 1], wi);
+                }
+                const float qp = __builtin_amdgcn_fmed3f(fabsf(wi) + wr, 0.0f, 1.0f);   // +c
+                const float qm = __builtin_amdgcn_fmed3f(fabsf(wi) - wr, 0.0f, 1.0f);   // -c
+                const float sp = copysignf(qp, wi);    // q sign(Im w) for +c
+                const float sm = copysignf(qm, wi);    // minus q sign(Im w) for -c
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    tq[0][j] = fmaf(vz[j], qp, tq[0][j]);
+                    ts[0][j] = fmaf(vz[j], sp, ts[0][j]);
+                    tq[1][j] = fmaf(vz[j], qm, tq[1][j]);
+                    ts[1][j] = fmaf(-vz[j], sm, ts[1][j]);
+                    tv[j] += vz[j];
+                }
+                continue;
             }
             // V_i c once: for -c it is exactly -(V_i c)
             float wr = 0.0f, wi = 0.0f;
@@ -569,6 +638,15 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
                 }
             }
         }
+    }
+    if constexpr (Q3) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                acc[s][2 * j] = fmaf(-1.5f, tq[s][j], tv[j]);
+                acc[s][2 * j + 1] = 0.8660254037844386f * ts[s][j];
+            }
     }
 }
 
@@ -1469,28 +1547,34 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     int* nonfinite = &dres->nonfinite;
     int* complex_v = &dres->complex_v;
     p.complex_v = complex_v;
+    uint32_t* vmax_bits = &dres->vmax_bits;
+    p.vmax_bits = vmax_bits;
     lrqo_status s = LRQO_OK;
     switch (r) {
         case 1:
-            hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
+                               vmax_bits);
             s = run_exact<1>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
         case 2:
-            hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
+                               vmax_bits);
             s = run_exact<2>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
         case 3:
-            hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
+                               vmax_bits);
             s = run_exact<3>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
         case 4:
-            hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v);
+            hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
+                               vmax_bits);
             s = run_exact<4>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
         default:
             if (pad) hipLaunchKernelGGL(k_pad_columns, dim3(256), dim3(256), 0, st, V, Vpad, n, r);
             hipLaunchKernelGGL((k_to_f32<kMaxR>), dim3(256), dim3(256), 0, st, p.V64, V32, vcount, nonfinite,
-                               complex_v);
+                               complex_v, vmax_bits);
             s = run_exact<kMaxR>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
             break;
     }
