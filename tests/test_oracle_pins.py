@@ -225,6 +225,20 @@ def test_candidate_count_bounded_by_card(oracle_lib):
     assert len(classes) <= exact.card_formula(6, 2, 3)
 
 
+@pytest.mark.parametrize("n,r,K", [(8, 2, 3), (7, 3, 3), (6, 2, 4), (9, 2, 2), (10, 5, 2)])
+def test_candidate_set_holds_brute_force_maximiser(oracle_lib, n, r, K):
+    """Thm. rankr: the labellings that Alg. 2 enumerates include the maximiser
+    over all K^n assignments (up to a global rotation), and the best of them
+    is the brute-force optimum."""
+    V = inputs.random_V(n, r, 7000 + 10 * n + r + K)
+    ex = exact.solve_exact(V, K, collect_distinct=True)
+    opt, zb, _ = brute.brute_force(V, K)
+    classes = {bytes(oracle.canonical(np.frombuffer(b, np.uint8), K)) for b in ex["distinct_set"]}
+    assert bytes(oracle.canonical(zb, K)) in classes
+    Z = np.array([np.frombuffer(b, np.uint8) for b in ex["distinct_set"]], dtype=np.int64)
+    assert abs(exact.objective_many(V, K, Z).max() - opt) <= 1e-12 * opt
+
+
 def test_two_implies_all_and_triples(oracle_lib):
     """Cor. two_implies_all: two rows of one group force V_i c = 0;
     Lemma rank_deficiency: three rows of one group are rank deficient."""
