@@ -264,24 +264,24 @@ __global__ __launch_bounds__(kBlock) void k_frame_m(const float* __restrict__ V,
     }
 }
 
-// Thread e < count of a block sums entry e of instance t over the splits
-// (in split order, eight loads in flight) into tot[e].
-__device__ __forceinline__ void sum_splits(const double* __restrict__ work, int t, int splits, int width,
-                                           double* tot) {
-    const int e = threadIdx.x;
-    if (e < width) {
-        const double* src = work + (size_t)t * splits * width + e;
-        double a = 0.0;
-        int q = 0;
-        for (; q + 8 <= splits; q += 8) {
-            double v[8];
+// One wave sums each entry e < W of instance t over the splits into tot[e]:
+// lane l adds splits l, l + 64, ... in order (all W entries' loads in flight
+// together), then the 64 lane sums are added by a butterfly (a fixed order).
+template <int W>
+__device__ __forceinline__ void sum_splits(const double* __restrict__ work, int t, int splits, double* tot) {
+    const int l = threadIdx.x;              // blockDim.x == kWave
+    const double* src = work + (size_t)t * splits * W;
+    double a[W];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(q + u) * width];
+    for (int e = 0; e < W; ++e) a[e] = 0.0;
+    for (int q = l; q < splits; q += kWave) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a += v[u];
-        }
-        for (; q < splits; ++q) a += src[(size_t)q * width];
-        tot[e] = a;
+        for (int e = 0; e < W; ++e) a[e] += src[(size_t)q * W + e];
+    }
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+        const double x = wave_sum_f64(a[e]);
+        if (l == 0) tot[e] = x;
     }
     __syncthreads();
 }
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kWave) void k_frame_eig(const double* __restrict__ 
                             Frame* __restrict__ frames) {
     __shared__ double tot[kFrameM];
     const int t = blockIdx.x;
-    sum_splits(work, t, splits, kFrameM, tot);
+    sum_splits<kFrameM>(work, t, splits, tot);
     if (threadIdx.x != 0) return;
     double Mr[3][3], Mi[3][3], Ur[3][3], Ui[3][3];
     for (int a = 0; a < 3; ++a)
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_frame_p(const float* __restrict__ V,
 __global__ __launch_bounds__(kWave) void k_frame_fin(const double* __restrict__ work, int splits, int K, Frame* __restrict__ frames) {
     __shared__ double tot[kFrameP];
     const int t = blockIdx.x;
-    sum_splits(work, t, splits, kFrameP, tot);
+    sum_splits<kFrameP>(work, t, splits, tot);
     if (threadIdx.x != 0) return;
     double PK[6], P1[6];
     for (int e = 0; e < 6; ++e) {
@@ -501,25 +501,37 @@ __global__ __launch_bounds__(kBlock) void k_mlp_fwd(const float* __restrict__ V,
 }
 
 // Mean embedding per instance from its items' partial sums (items of one
-// instance are consecutive).
-__global__ void k_pool(const float* __restrict__ partial, const int32_t* first_item,
-                       const int64_t* nrows, int count, float* __restrict__ mvec) {
+// instance are consecutive).  kPoolGroups groups of H threads each add a
+// contiguous run of the items (in item order, sixteen loads in flight); the
+// group sums are then added in group order.
+constexpr int kPoolGroups = 16;
+
+__global__ __launch_bounds__(H * kPoolGroups) void k_pool(const float* __restrict__ partial, const int32_t* first_item,
+                                                          const int64_t* nrows, int count, float* __restrict__ mvec) {
+    __shared__ float gsum[kPoolGroups][H];
     const int t = blockIdx.x;
-    const int o = threadIdx.x;
-    if (t >= count || o >= H) return;
+    const int o = threadIdx.x % H, grp = threadIdx.x / H;
+    if (t >= count) return;                  // the same in every thread of the block
+    const int first = first_item[t], end = first_item[t + 1];
+    const int per = (end - first + kPoolGroups - 1) / kPoolGroups;
+    int it = min(end, first + grp * per);
+    const int stop = min(end, it + per);
     float v = 0.0f;
-    int it = first_item[t];
-    const int end = first_item[t + 1];
-    // sixteen loads in flight; the additions keep item order
-    for (; it + 16 <= end; it += 16) {
+    for (; it + 16 <= stop; it += 16) {
         float p[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) p[u] = partial[(size_t)(it + u) * H + o];
 #pragma unroll
         for (int u = 0; u < 16; ++u) v += p[u];
     }
-    for (; it < end; ++it) v += partial[(size_t)it * H + o];
-    mvec[(size_t)t * H + o] = v / (float)nrows[t];
+    for (; it < stop; ++it) v += partial[(size_t)it * H + o];
+    gsum[grp][o] = v;
+    __syncthreads();
+    if (grp == 0) {
+        float sum = 0.0f;
+        for (int g = 0; g < kPoolGroups; ++g) sum += gsum[g][o];
+        mvec[(size_t)t * H + o] = sum / (float)nrows[t];
+    }
 }
 
 // Head: mixture parameters of one instance.
@@ -1041,7 +1053,7 @@ lrqo_status run_embed(lrqo_proposal* P, const float* V, int count, const RowPlan
     hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)rp.inst.size()), dim3(kBlock), 0, st, V, b.voff, b.n,
                        b.frames, P->theta, items, b.partial);
     LRQO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_pool, dim3(count), dim3(H), 0, st, b.partial, b.first, b.n, count, b.mvec);
+    hipLaunchKernelGGL(k_pool, dim3(count), dim3(H * kPoolGroups), 0, st, b.partial, b.first, b.n, count, b.mvec);
     LRQO_HIP(hipGetLastError());
     return LRQO_OK;
 }
