@@ -116,6 +116,18 @@ def test_exact_high_rank_real_factor(lrqo_mod):
     assert res.warning == -6
 
 
+@pytest.mark.parametrize("n,r", [(10, 1), (8, 3), (6, 4)])
+def test_exact_real_factor_k3_ranks(lrqo_mod, n, r):
+    """Real factors with K = 3 at r = 1, 3, 4 (the row pass in the q basis
+    with the clamped label tests): optimum and labels up to rotation and
+    conjugation against the oracle and the brute force."""
+    V = inputs.random_V(n, r, 300 + n + r, real=True)
+    z, res = _solve(lrqo_mod, V, 3)
+    _check(V, 3, z, res, real=True, stats=False)
+    opt, _, _ = brute.brute_force(V, 3)
+    assert abs(res.obj - opt) <= 1e-12 * opt
+
+
 @pytest.mark.parametrize("r", [2, 6])
 def test_exact_real_factor_k2_is_flagged(lrqo_mod, r):
     """A real factor with K = 2 is far from general position: every augmented

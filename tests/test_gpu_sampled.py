@@ -127,6 +127,7 @@ CASES = [
     (12, 2, 3, 4096, False),
     (1, 1, 3, 100, False),
     (7, 1, 2, 333, True),
+    (300, 1, 3, 2000, True),
     (200, 3, 5, 5000, False),
     (257, 4, 3, 4097, True),
     (1000, 8, 16, 2000, False),
