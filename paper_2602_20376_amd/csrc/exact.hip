@@ -47,6 +47,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTile = 256;
+constexpr int kSub = 32;         // rows per wave-uniform touched test in the row pass
 constexpr int kMaxR = 8;
 constexpr int kThreadMaxD = 4;    // levels whose vertex one thread solves alone
 constexpr int kTopT = 64;
@@ -521,8 +522,10 @@ __global__ void k_pad_columns(const double* __restrict__ V, double* __restrict__
 // the same numbers).
 // REAL and K = 3: the set's rows are zeroed in V instead of in the labels,
 // and each sign accumulates in the basis q = [label != 0]: sum_i V_i q_i and
-// sum_i V_i q_i sign(Im w_i), with sum_i V_i beside, so that
-// s = sum V - 3/2 sum V q + i (sqrt(3)/2) sum V q sign(Im w) after the loop.
+// sum_i V_i q_i sign(Im w_i), so that s = sum V - 3/2 sum V q +
+// i (sqrt(3)/2) sum V q sign(Im w) after the loop; sum V over the untouched
+// rows, the same for every direction, is the slice's column sums (one pass
+// per block) less the set's rows.
 // w is formed from B Im c and -B sqrt(3) Re c (B a power of two sized from
 // the largest |V| entry, as in the sampled scorer): |Im w'| + Re w' is
 // B (|Im w| - sqrt(3) Re w), the label test for +c, |Im w'| - Re w' the one
@@ -533,10 +536,39 @@ __device__ __forceinline__ float exact_q3_scale(uint32_t vmax_bits) {
     return ldexpf(1.0f, min(126, max(-126, 118 - ilogbf(m))));
 }
 
+// Column sums of Re V over rows [r0, r1) of the FP32 copy, added in FP64 in
+// a fixed order and rounded once, so every block of a slice holds the same
+// numbers.  Called by every thread of the block.
+template <int R>
+__device__ void slice_col_sums(const ExactParams& p, int64_t r0, int64_t r1, float* colsum) {
+    __shared__ double red[kBlock / kWave][R];
+    double part[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) part[j] = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock)
+#pragma unroll
+        for (int j = 0; j < R; ++j) part[j] += (double)p.V32[(i * R + j) * 2];
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) part[j] += __shfl_xor(part[j], off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int j = 0; j < R; ++j) red[threadIdx.x / kWave][j] = part[j];
+    __syncthreads();
+    if (threadIdx.x < R) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += red[w][threadIdx.x];
+        colsum[threadIdx.x] = (float)t;
+    }
+    __syncthreads();
+}
+
 template <int R, int D, int KS, bool REAL>
 __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c)[2 * D],
                                            const int32_t (&g)[2 * D - 1], int64_t r0, int64_t r1,
-                                           float* tile, const float2* roots_s, float (&acc)[2][2 * R]) {
+                                           float* tile, const float2* roots_s, const float* colsum,
+                                           float (&acc)[2][2 * R]) {
     constexpr int M = 2 * D - 1;
     constexpr int RW = REAL ? R : 2 * R;   // floats per staged row
     constexpr bool Q3 = REAL && KS == 3;
@@ -554,58 +586,43 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
             cw[2 * j + 1] = B * c[2 * j + 1];
         }
 #pragma unroll
-        for (int j = 0; j < R; ++j) {
-            tq[0][j] = tq[1][j] = ts[0][j] = ts[1][j] = 0.0f;
-            tv[j] = 0.0f;
-        }
+        for (int j = 0; j < R; ++j) tq[0][j] = tq[1][j] = ts[0][j] = ts[1][j] = 0.0f;
     }
-    int64_t next = INT64_MAX;                  // next touched row at or after r0
+    int64_t next = INT64_MAX;                  // r > 4: next touched row at or after r0
 #pragma unroll
     for (int t = 0; t < M; ++t)
         if (g[t] >= r0 && g[t] < next) next = g[t];
-    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
-        const int cnt = (int)min((int64_t)kTile, r1 - t0);
-        __syncthreads();
-        const float* __restrict__ src = p.V32 + t0 * 2 * R;
-        for (int e = threadIdx.x; e < cnt * RW; e += kBlock) tile[e] = REAL ? src[2 * e] : src[e];
-        __syncthreads();
-        for (int i = 0; i < cnt; ++i) {
-            const int64_t row = t0 + i;
-            float vv[RW];
+    uint32_t nx = UINT32_MAX;                  // r <= 4: the same as 32 bits (none: UINT32_MAX)
 #pragma unroll
-            for (int e = 0; e < RW; ++e) vv[e] = tile[i * RW + e];
-            const bool touched = row == next;
-            if (touched) {          // rare: advance the cursor
-                int64_t nn = INT64_MAX;
+    for (int t = 0; t < M; ++t)
+        if (g[t] >= r0) nx = min(nx, (uint32_t)g[t]);
+    // One row of the tile; a touched row counts as zeros.
+    auto row = [&](int i, bool touched) {
+        float vv[RW];
 #pragma unroll
-                for (int t = 0; t < M; ++t)
-                    if (g[t] > row && g[t] < nn) nn = g[t];
-                next = nn;
+        for (int e = 0; e < RW; ++e) vv[e] = tile[i * RW + e];
+        if constexpr (Q3) {
+            float vz[R];
+#pragma unroll
+            for (int e = 0; e < R; ++e) vz[e] = touched ? 0.0f : vv[e];
+            float wr = 0.0f, wi = 0.0f;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                wr = fmaf(vz[j], cw[2 * j], wr);
+                wi = fmaf(vz[j], cw[2 * j + 1], wi);
             }
-            if constexpr (Q3) {
-                float vz[R];
+            const float qp = __builtin_amdgcn_fmed3f(fabsf(wi) + wr, 0.0f, 1.0f);   // +c
+            const float qm = __builtin_amdgcn_fmed3f(fabsf(wi) - wr, 0.0f, 1.0f);   // -c
+            const float sp = copysignf(qp, wi);    // q sign(Im w) for +c
+            const float sm = copysignf(qm, wi);    // minus q sign(Im w) for -c
 #pragma unroll
-                for (int e = 0; e < R; ++e) vz[e] = touched ? 0.0f : vv[e];
-                float wr = 0.0f, wi = 0.0f;
-#pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    wr = fmaf(vz[j], cw[2 * j], wr);
-                    wi = fmaf(vz[j], cw[2 * j + 1], wi);
-                }
-                const float qp = __builtin_amdgcn_fmed3f(fabsf(wi) + wr, 0.0f, 1.0f);   // +c
-                const float qm = __builtin_amdgcn_fmed3f(fabsf(wi) - wr, 0.0f, 1.0f);   // -c
-                const float sp = copysignf(qp, wi);    // q sign(Im w) for +c
-                const float sm = copysignf(qm, wi);    // minus q sign(Im w) for -c
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    tq[0][j] = fmaf(vz[j], qp, tq[0][j]);
-                    ts[0][j] = fmaf(vz[j], sp, ts[0][j]);
-                    tq[1][j] = fmaf(vz[j], qm, tq[1][j]);
-                    ts[1][j] = fmaf(-vz[j], sm, ts[1][j]);
-                    tv[j] += vz[j];
-                }
-                continue;
+            for (int j = 0; j < R; ++j) {
+                tq[0][j] = fmaf(vz[j], qp, tq[0][j]);
+                ts[0][j] = fmaf(vz[j], sp, ts[0][j]);
+                tq[1][j] = fmaf(vz[j], qm, tq[1][j]);
+                ts[1][j] = fmaf(-vz[j], sm, ts[1][j]);
             }
+        } else {
             // V_i c once: for -c it is exactly -(V_i c)
             float wr = 0.0f, wi = 0.0f;
 #pragma unroll
@@ -638,8 +655,89 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
                 }
             }
         }
+    };
+    // r > 4: one row with the touched test against a cursor over the set's
+    // sorted rows, which moves on past a touched row.
+    auto row_checked = [&](int i, int64_t rw) {
+        const bool touched = rw == next;
+        if (touched) {          // rare: advance the cursor
+            int64_t nn = INT64_MAX;
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                if (g[t] > rw && g[t] < nn) nn = g[t];
+            next = nn;
+        }
+        row(i, touched);
+    };
+    for (int64_t t0 = r0; t0 < r1; t0 += kTile) {
+        const int cnt = (int)min((int64_t)kTile, r1 - t0);
+        __syncthreads();
+        const float* __restrict__ src = p.V32 + t0 * 2 * R;
+        for (int e = threadIdx.x; e < cnt * RW; e += kBlock) tile[e] = REAL ? src[2 * e] : src[e];
+        __syncthreads();
+        if constexpr (R <= kThreadMaxD) {
+            // Runs of kSub rows: a run that no set of the wave touches
+            // (every lane's cursor lies beyond it; a wave-uniform test, all
+            // lanes take part) is scored with no per-row test at all, the
+            // others with the set's rows in the run as a bit mask, both
+            // unrolled.
+            for (int i = 0; i < cnt; i += kSub) {
+                const uint32_t a = (uint32_t)(t0 + i);       // rows < 2^31
+                if (!__any(nx < a + kSub)) {
+                    if (cnt - i >= kSub) {
+                        if constexpr (KS != 0) {
+#pragma unroll
+                            for (int k = 0; k < kSub; ++k) row(i + k, false);
+                        } else {
+#pragma unroll 4
+                            for (int k = 0; k < kSub; ++k) row(i + k, false);
+                        }
+                    } else {
+                        for (int k = 0; k < cnt - i; ++k) row(i + k, false);
+                    }
+                    continue;
+                }
+                // the set's rows among rows [a, a + kSub) as one bit each
+                // (a row below a, or -1, wraps to a large offset); the
+                // cursor moves past the run
+                uint32_t mask = 0;
+                uint32_t nn = UINT32_MAX;
+#pragma unroll
+                for (int t = 0; t < M; ++t) {
+                    const uint32_t gt = (uint32_t)g[t];
+                    const uint32_t d = gt - a;
+                    mask |= d < (uint32_t)kSub ? 1u << d : 0u;
+                    nn = min(nn, d >= (uint32_t)kSub && gt >= a ? gt : UINT32_MAX);
+                }
+                nx = nn;
+                if (cnt - i >= kSub) {
+                    if constexpr (KS != 0) {
+#pragma unroll
+                        for (int k = 0; k < kSub; ++k) row(i + k, (mask >> k) & 1u);
+                    } else {
+#pragma unroll 4
+                        for (int k = 0; k < kSub; ++k) row(i + k, (mask >> k) & 1u);
+                    }
+                } else {
+                    for (int k = 0; k < cnt - i; ++k) row(i + k, (mask >> k) & 1u);
+                }
+            }
+        } else {
+            for (int i = 0; i < cnt; ++i) row_checked(i, t0 + i);
+        }
     }
     if constexpr (Q3) {
+        // sum of V over the untouched rows: the slice's column sums less the
+        // set's distinct rows in the slice, in row order
+#pragma unroll
+        for (int j = 0; j < R; ++j) tv[j] = colsum[j];
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            if (g[t] >= r0 && g[t] < r1 && (t == 0 || g[t] != g[t - 1])) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) tv[j] -= p.V32[((int64_t)g[t] * R + j) * 2];
+            }
+        }
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
@@ -773,6 +871,10 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
     }
     for (int k = tid; k < p.K; k += kBlock) roots_all[k] = p.roots32[k];   // read after the tile barriers
     const bool cplx = *p.complex_v != 0;   // the same in every thread
+    __shared__ float colsum[R];
+    if constexpr (KS == 3 && R <= kThreadMaxD) {
+        if (!cplx) slice_col_sums<R>(p, 0, p.n, colsum);
+    }
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
         const uint64_t rank = base + tid;          // within the chunk
@@ -797,9 +899,9 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
         for (int t = 0; t < M; ++t) g32[t] = (int32_t)g[t];
         float acc[2][2 * R];
         if (cplx || R > kThreadMaxD)
-            score_rows<R, D, KS, false>(p, c, g32, 0, p.n, tile, roots_s, acc);
+            score_rows<R, D, KS, false>(p, c, g32, 0, p.n, tile, roots_s, colsum, acc);
         else
-            score_rows<R, D, KS, true>(p, c, g32, 0, p.n, tile, roots_s, acc);
+            score_rows<R, D, KS, true>(p, c, g32, 0, p.n, tile, roots_s, colsum, acc);
         unsigned long long ncand = 0;
         const float best = ok ? combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand) : 0.0f;
         if (active) p.fbuf[rank] = best;
@@ -855,6 +957,10 @@ __global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const Vert
     const int64_t r0 = (int64_t)blockIdx.y * p.rows_per_slice;
     const int64_t r1 = min(p.n, r0 + p.rows_per_slice);
     const bool cplx = *p.complex_v != 0;   // the same in every thread
+    __shared__ float colsum[R];
+    if constexpr (KS == 3 && R <= kThreadMaxD) {
+        if (!cplx) slice_col_sums<R>(p, r0, r1, colsum);
+    }
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < p.count; base += stride) {
         const uint64_t rank = base + threadIdx.x;
@@ -875,9 +981,9 @@ __global__ __launch_bounds__(kBlock) void k_exact_rows(ExactParams p, const Vert
         }
         float acc[2][2 * R];
         if (cplx || R > kThreadMaxD)
-            score_rows<R, D, KS, false>(p, c, g, r0, r1, tile, roots_s, acc);
+            score_rows<R, D, KS, false>(p, c, g, r0, r1, tile, roots_s, colsum, acc);
         else
-            score_rows<R, D, KS, true>(p, c, g, r0, r1, tile, roots_s, acc);
+            score_rows<R, D, KS, true>(p, c, g, r0, r1, tile, roots_s, colsum, acc);
         if (active) {
 #pragma unroll
             for (int s = 0; s < 2; ++s)
