@@ -31,6 +31,7 @@
 //   k_exact_pick    FP64 arg-max (ties -> lowest set index)
 //   k_exact_labels  labels of the winner
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -111,6 +112,7 @@ struct TopEntry {
     int32_t pad;
     uint64_t gidx;      // global set index: level offset + rank within the level
 };
+static_assert(offsetof(TopEntry, f) == 0, "the selection reads the last entry's score through a float pointer");
 
 struct RescoreEntry {
     double f;
@@ -1443,7 +1445,10 @@ lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, bool 
             LRQO_HIP(hipGetLastError());
             const int T = (int)std::min<uint64_t>(kTopT, q.count);
             const unsigned long long* keys = nullptr;
-            LRQO_TRY(topk_select(p.fbuf, (uint32_t)q.count, T, ka, kb, st, &keys, true));
+            // a score below the shortlist's last (once it holds kTopT values)
+            // cannot enter it: the selection drops those on the device
+            LRQO_TRY(topk_select(p.fbuf, (uint32_t)q.count, T, ka, kb, st, &keys, true,
+                                 reinterpret_cast<const float*>(top + (kTopT - 1))));
             hipLaunchKernelGGL(k_exact_merge, dim3(1), dim3(kTopT), 0, st, top, keys, T, lt.offset[d] + c0);
             LRQO_HIP(hipGetLastError());
         }

@@ -16,9 +16,13 @@ size_t topk_buffer_keys(uint32_t count, int T);
 // descending, at *out (one of buf_a / buf_b).  Requires 1 <= T <= 64 and
 // T <= count; f must be finite and >= 0.  distinct: one key per value of f
 // (its lowest index); then fewer than T values leave padding keys 0 at the end.
+// floor_f (device pointer, may be null; read when the selection runs): values
+// of f strictly below *floor_f are left out when *floor_f >= 0 (their places
+// become padding keys 0 at the end).
 lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long long* buf_a,
                         unsigned long long* buf_b, hipStream_t st,
-                        const unsigned long long** out, bool distinct = false);
+                        const unsigned long long** out, bool distinct = false,
+                        const float* floor_f = nullptr);
 
 // The same from keys already sorted in lists of 64 (lists[64 q + l] the
 // l-th largest of list q, padding keys 0); count a multiple of 64.

@@ -24,18 +24,29 @@ constexpr int kChunk = 2048;  // keys per block, kChunk / kWaves per wave
 // word is nonzero).
 // distinct = 1: one key per objective value (the lowest index), for inputs
 // where many candidates share a bit-identical score.
+// floor_f (may be null; read on the device): scores strictly below *floor_f
+// are dropped (their keys count as padding) when *floor_f >= 0.
 __global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
                                                  const unsigned long long* __restrict__ keys_in,
                                                  uint32_t count, int T, int sorted, int distinct,
+                                                 const float* __restrict__ floor_f,
                                                  unsigned long long* __restrict__ keys_out) {
     __shared__ unsigned long long top[kWaves][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t base = blockIdx.x * (uint32_t)kChunk + (uint32_t)w * (kChunk / kWaves);
+    // non-negative floats order as their bits; a key with score x is at
+    // least bits(x) << 32
+    unsigned long long lo = 0;
+    if (floor_f) {
+        const float fl = *floor_f;
+        if (fl >= 0.0f) lo = (unsigned long long)__float_as_uint(fl) << 32;
+    }
     unsigned long long run = 0;
     for (int t = 0; t < kChunk / kWaves; t += 64) {
         const uint32_t g = base + (uint32_t)(t + lane);
         unsigned long long key = 0;
         if (g < count) key = f ? pack_key(f[g], g) : keys_in[g];
+        key = key < lo ? 0ull : key;
         const unsigned long long floor64 = __shfl(run, 63, 64);
         if (__ballot(key > floor64) == 0) continue;  // uniform across the wave
         const unsigned long long tile = sorted ? key : wave_sort_desc(key, lane);
@@ -58,8 +69,8 @@ size_t topk_buffer_keys(uint32_t count, int T) {
 namespace {
 
 lrqo_status topk_passes(const float* f, const unsigned long long* keys, bool sorted, uint32_t count, int T,
-                        bool distinct, unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
-                        const unsigned long long** out) {
+                        bool distinct, const float* floor_f, unsigned long long* buf_a, unsigned long long* buf_b,
+                        hipStream_t st, const unsigned long long** out) {
     uint32_t n = count;
     int ping = 0;
     bool from_f = f != nullptr;
@@ -67,7 +78,7 @@ lrqo_status topk_passes(const float* f, const unsigned long long* keys, bool sor
         const uint32_t blocks = (n + kChunk - 1) / kChunk;
         unsigned long long* dst = ping ? buf_b : buf_a;
         hipLaunchKernelGGL(k_topk, dim3(blocks), dim3(kBlock), 0, st, from_f ? f : nullptr, keys, n,
-                           T, sorted ? 1 : 0, distinct ? 1 : 0, dst);
+                           T, sorted ? 1 : 0, distinct ? 1 : 0, from_f ? floor_f : nullptr, dst);
         LRQO_HIP(hipGetLastError());
         keys = dst;
         n = blocks * (uint32_t)T;
@@ -84,14 +95,14 @@ lrqo_status topk_passes(const float* f, const unsigned long long* keys, bool sor
 
 lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long long* buf_a,
                         unsigned long long* buf_b, hipStream_t st,
-                        const unsigned long long** out, bool distinct) {
-    return topk_passes(f, nullptr, false, count, T, distinct, buf_a, buf_b, st, out);
+                        const unsigned long long** out, bool distinct, const float* floor_f) {
+    return topk_passes(f, nullptr, false, count, T, distinct, floor_f, buf_a, buf_b, st, out);
 }
 
 lrqo_status topk_select_lists(const unsigned long long* lists, uint32_t count, int T,
                               unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
                               const unsigned long long** out) {
-    return topk_passes(nullptr, lists, true, count, T, false, buf_a, buf_b, st, out);
+    return topk_passes(nullptr, lists, true, count, T, false, nullptr, buf_a, buf_b, st, out);
 }
 
 }  // namespace lrqo
