@@ -467,7 +467,9 @@ __device__ void open_labels(const ExactParams& p, const int64_t (&g)[2 * D - 1],
             o[t] = mm[t];                          // on ray pi(2m+1)/K: labels m, m+1
             cnt[t] = 2;
         } else if (p.K & 1) {
-            o[t] = label_f64(wr, wi, p.K);         // opposite ray is a root direction
+            // the opposite ray, at angle pi (2m + 1 + K) / K, points at root
+            // m + (K + 1) / 2: the decision rule's label there
+            o[t] = (mm[t] + (p.K + 1) / 2) % p.K;
         } else {
             o[t] = (mm[t] + p.K / 2) % p.K;        // opposite ray is boundary m + K/2
             cnt[t] = 2;
@@ -752,8 +754,14 @@ __device__ __forceinline__ void score_rows(const ExactParams& p, const float (&c
 
 // Best FP32 score over both signs and every open-label combination of the
 // set's coordinates, from the sums acc[s] of the untouched rows; also the
-// number of combinations tried.
-template <int R, int D>
+// number of combinations tried.  Both signs run in one loop (the mixed-radix
+// counter is back at zero after the last combination of +v, where the loop
+// turns to -v), so a wave runs the longest lane's total of the two rather
+// than the sum of each sign's longest.  The second row of a coordinate with
+// two rows adds nothing (its labels are the first row's); it enters as a
+// zero row.  KS = 3 takes the roots in closed form (the same FP32 values as
+// the table), other K from the table roots_s.
+template <int R, int D, int KS>
 __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1], const int (&mm)[2 * D - 1],
                              const double (&v)[2 * D], const float (&acc)[2][2 * R],
                              const float2* roots_s, unsigned long long& ncand) {
@@ -761,67 +769,80 @@ __device__ float combos_best(const ExactParams& p, const int64_t (&g)[2 * D - 1]
     // the set's rows in registers once (every combination reads them) when
     // they fit; above that they are read from the FP32 copy (cached)
     constexpr bool kHold = M * 2 * R <= 64;
+    bool first[M];
+#pragma unroll
+    for (int t = 0; t < M; ++t) first[t] = g[t] >= 0 && ((t == 0) || (g[t] != g[t - 1]));
     float vt[kHold ? M : 1][kHold ? 2 * R : 1];
     if constexpr (kHold) {
 #pragma unroll
         for (int t = 0; t < M; ++t)
 #pragma unroll
-            for (int j = 0; j < 2 * R; ++j) vt[t][j] = g[t] >= 0 ? p.V32[g[t] * 2 * R + j] : 0.0f;
+            for (int j = 0; j < 2 * R; ++j) vt[t][j] = first[t] ? p.V32[g[t] * 2 * R + j] : 0.0f;
     }
-    float best = 0.0f;
+    int o[2][M], cn[2][M];
+    int64_t tot[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         double cs[C2];
 #pragma unroll
         for (int k = 0; k < C2; ++k) cs[k] = s ? -v[k] : v[k];
-        int o[M], cn[M];
-        open_labels<D>(p, g, mm, cs, o, cn);
-        int64_t total = 1;
+        open_labels<D>(p, g, mm, cs, o[s], cn[s]);
+        tot[s] = 1;
 #pragma unroll
-        for (int t = 0; t < M; ++t) total *= cn[t];
-        ncand += (unsigned long long)total;
-        // the combinations in mixed radix cn[0], cn[1], ... (digit t least
-        // significant first), stepped by a counter instead of divisions
-        int dig[M];
+        for (int t = 0; t < M; ++t) tot[s] *= cn[s][t];
+    }
+    ncand += (unsigned long long)(tot[0] + tot[1]);
+    // the combinations in mixed radix cn[s][0], cn[s][1], ... (digit t least
+    // significant first), stepped by a counter instead of divisions
+    int dig[M];
 #pragma unroll
-        for (int t = 0; t < M; ++t) dig[t] = 0;
-        for (int64_t combo = 0; combo < total; ++combo) {
-            float sr[2 * R];
+    for (int t = 0; t < M; ++t) dig[t] = 0;
+    bool neg = false;                 // false: +v, true: -v
+    float best = 0.0f;
+    for (int64_t it = 0; it < tot[0] + tot[1]; ++it) {
+        float sr[2 * R];
 #pragma unroll
-            for (int j = 0; j < 2 * R; ++j) sr[j] = acc[s][j];
+        for (int j = 0; j < 2 * R; ++j) sr[j] = neg ? acc[1][j] : acc[0][j];
 #pragma unroll
-            for (int t = 0; t < M; ++t) {
-                if (cn[t] == 1 && !((t == 0) || (g[t] != g[t - 1]))) continue;
-                int k = o[t] + dig[t];
-                k = k >= p.K ? k - p.K : k;
+        for (int t = 0; t < M; ++t) {
+            int k = (neg ? o[1][t] : o[0][t]) + dig[t];
+            k = k >= p.K ? k - p.K : k;
+            float zx, zy;
+            if constexpr (KS == 3) {
+                zx = k == 0 ? 1.0f : -0.5f;
+                zy = k == 0 ? 0.0f : (k == 1 ? 0.8660254037844386f : -0.8660254037844386f);
+            } else {
                 const float2 z = roots_s[k];
-#pragma unroll
-                for (int j = 0; j < R; ++j) {
-                    float vr, vi;
-                    if constexpr (kHold) {
-                        vr = vt[t][2 * j];
-                        vi = vt[t][2 * j + 1];
-                    } else {
-                        vr = p.V32[g[t] * 2 * R + 2 * j];
-                        vi = p.V32[g[t] * 2 * R + 2 * j + 1];
-                    }
-                    sr[2 * j] = fmaf(vr, z.x, fmaf(vi, z.y, sr[2 * j]));
-                    sr[2 * j + 1] = fmaf(vr, z.y, fmaf(-vi, z.x, sr[2 * j + 1]));
-                }
+                zx = z.x;
+                zy = z.y;
             }
-            float f = 0.0f;
 #pragma unroll
-            for (int j = 0; j < 2 * R; ++j) f = fmaf(sr[j], sr[j], f);
-            best = fmaxf(best, f);
-            bool carry = true;
-#pragma unroll
-            for (int t = 0; t < M; ++t) {
-                if (carry) {
-                    carry = ++dig[t] == cn[t];
-                    if (carry) dig[t] = 0;
+            for (int j = 0; j < R; ++j) {
+                float vr, vi;
+                if constexpr (kHold) {
+                    vr = vt[t][2 * j];
+                    vi = vt[t][2 * j + 1];
+                } else {
+                    vr = first[t] ? p.V32[g[t] * 2 * R + 2 * j] : 0.0f;
+                    vi = first[t] ? p.V32[g[t] * 2 * R + 2 * j + 1] : 0.0f;
                 }
+                sr[2 * j] = fmaf(vr, zx, fmaf(vi, zy, sr[2 * j]));
+                sr[2 * j + 1] = fmaf(vr, zy, fmaf(-vi, zx, sr[2 * j + 1]));
             }
         }
+        float f = 0.0f;
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) f = fmaf(sr[j], sr[j], f);
+        best = fmaxf(best, f);
+        bool carry = true;
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            if (carry) {
+                carry = ++dig[t] == (neg ? cn[1][t] : cn[0][t]);
+                if (carry) dig[t] = 0;
+            }
+        }
+        neg = neg || carry;           // every digit wrapped: +v is done
     }
     return best;
 }
@@ -905,7 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
         else
             score_rows<R, D, KS, true>(p, c, g32, 0, p.n, tile, roots_s, colsum, acc);
         unsigned long long ncand = 0;
-        const float best = ok ? combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand) : 0.0f;
+        const float best = ok ? combos_best<R, D, KS>(p, g, mm, v, acc, roots_all, ncand) : 0.0f;
         if (active) p.fbuf[rank] = best;
         add_stats(p, active, valid, ok, ncand);
     }
@@ -1025,7 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_exact_combine(ExactParams p, int sli
                     for (int q = 0; q < slices; ++q) a += p.part[(((uint64_t)q * 2 + s) * (2 * R) + j) * p.count + rank];
                     acc[s][j] = a;
                 }
-            best = combos_best<R, D>(p, g, mm, v, acc, roots_all, ncand);
+            best = combos_best<R, D, 0>(p, g, mm, v, acc, roots_all, ncand);
         }
         if (active) p.fbuf[rank] = best;
         add_stats(p, active, valid, ok, ncand);
