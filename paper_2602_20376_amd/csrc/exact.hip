@@ -49,6 +49,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kTile = 256;
 constexpr int kSub = 32;         // rows per wave-uniform touched test in the row pass
+constexpr int kFloorGroup = 2048;  // scores per group of the selection's first pass (select.hip)
 constexpr int kMaxR = 8;
 constexpr int kThreadMaxD = 4;    // levels whose vertex one thread solves alone
 constexpr int kTopT = 64;
@@ -1445,9 +1446,10 @@ void launch_level(ExactParams p, bool force_fused, hipStream_t st) {
 
 template <int R>
 lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, bool force_fused, TopEntry* top,
-                      unsigned long long* ka, unsigned long long* kb, RescoreEntry* entries, double* rpart,
-                      ExactDevResult* dres, uint8_t* z, hipStream_t st) {
+                      unsigned long long* ka, unsigned long long* kb, float* floor_buf, RescoreEntry* entries,
+                      double* rpart, ExactDevResult* dres, uint8_t* z, hipStream_t st) {
     hipLaunchKernelGGL(k_exact_top_init, dim3(1), dim3(kTopT), 0, st, top);
+    bool first = true;
     for (int d = R; d >= 1; --d) {
         for (uint64_t c0 = 0; c0 < lt.count[d]; c0 += chunk) {
             ExactParams q = p;
@@ -1467,9 +1469,16 @@ lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, bool 
             const int T = (int)std::min<uint64_t>(kTopT, q.count);
             const unsigned long long* keys = nullptr;
             // a score below the shortlist's last (once it holds kTopT values)
-            // cannot enter it: the selection drops those on the device
-            LRQO_TRY(topk_select(p.fbuf, (uint32_t)q.count, T, ka, kb, st, &keys, true,
-                                 reinterpret_cast<const float*>(top + (kTopT - 1))));
+            // cannot enter it: the selection drops those on the device.  The
+            // first chunk, with the shortlist still empty, takes its floor
+            // from the maxima of its groups of scores instead.
+            const float* floor_f = reinterpret_cast<const float*>(top + (kTopT - 1));
+            if (first && T == kTopT && q.count >= (uint64_t)kFloorGroup * kTopT) {
+                LRQO_TRY(topk_block_floor(p.fbuf, (uint32_t)q.count, T, floor_f, floor_buf, ka, kb, st));
+                floor_f = floor_buf;
+            }
+            first = false;
+            LRQO_TRY(topk_select(p.fbuf, (uint32_t)q.count, T, ka, kb, st, &keys, true, floor_f));
             hipLaunchKernelGGL(k_exact_merge, dim3(1), dim3(kTopT), 0, st, top, keys, T, lt.offset[d] + c0);
             LRQO_HIP(hipGetLastError());
         }
@@ -1583,6 +1592,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     cs.add<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
     cs.add<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
     cs.add<TopEntry>(kTopT);
+    cs.add<float>(1);
     cs.add<RescoreEntry>(kTopT);
     cs.add<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * rk));
     cs.add<char>(rec_count * vertex_rec_bytes(rk));
@@ -1607,6 +1617,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     unsigned long long* ka = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
     unsigned long long* kb = cv.take<unsigned long long>(topk_buffer_keys((uint32_t)cmax, kTopT));
     TopEntry* top = cv.take<TopEntry>(kTopT);
+    float* floor_buf = cv.take<float>(1);
     RescoreEntry* entries = cv.take<RescoreEntry>(kTopT);
     double* rpart = cv.take<double>((size_t)kTopT * kRescoreSlices * 2 * (2 * rk));
     void* recs = cv.take<char>(rec_count * vertex_rec_bytes(rk));
@@ -1686,28 +1697,28 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
         case 1:
             hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<1>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
+            s = run_exact<1>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         case 2:
             hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<2>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
+            s = run_exact<2>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         case 3:
             hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<3>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
+            s = run_exact<3>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         case 4:
             hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<4>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
+            s = run_exact<4>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         default:
             if (pad) hipLaunchKernelGGL(k_pad_columns, dim3(256), dim3(256), 0, st, V, Vpad, n, r);
             hipLaunchKernelGGL((k_to_f32<kMaxR>), dim3(256), dim3(256), 0, st, p.V64, V32, vcount, nonfinite,
                                complex_v, vmax_bits);
-            s = run_exact<kMaxR>(p, lt, chunk, force_fused, top, ka, kb, entries, rpart, dres, z, st);
+            s = run_exact<kMaxR>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
     }
     if (s != LRQO_OK) return s;

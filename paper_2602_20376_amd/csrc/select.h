@@ -24,6 +24,16 @@ lrqo_status topk_select(const float* f, uint32_t count, int T, unsigned long lon
                         const unsigned long long** out, bool distinct = false,
                         const float* floor_f = nullptr);
 
+// A floor for a distinct top-T selection of f[0..count) that drops nothing
+// the selection keeps: the T-th largest distinct value among the maxima of
+// the groups of scores (2,048 each) that the selection's first pass takes,
+// since at least T distinct scores reach it; -1 when the maxima hold fewer
+// than T distinct values.  *floor_out (device) receives the larger of it and
+// *floor_in (device, may be null).  Needs count >= 2,048 T; uses buf_a and
+// buf_b as topk_select does.
+lrqo_status topk_block_floor(const float* f, uint32_t count, int T, const float* floor_in, float* floor_out,
+                             unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st);
+
 // The same from keys already sorted in lists of 64 (lists[64 q + l] the
 // l-th largest of list q, padding keys 0); count a multiple of 64.
 lrqo_status topk_select_lists(const unsigned long long* lists, uint32_t count, int T,

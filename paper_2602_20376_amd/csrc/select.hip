@@ -60,6 +60,37 @@ __global__ __launch_bounds__(kBlock) void k_topk(const float* __restrict__ f,
     if (lane < T) keys_out[(size_t)blockIdx.x * T + lane] = run;
 }
 
+// Per group of kChunk scores (k_topk's grouping): the key of its largest
+// score.
+__global__ __launch_bounds__(kBlock) void k_block_max(const float* __restrict__ f, uint32_t count,
+                                                      unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long wm[kWaves];
+    const uint32_t base = blockIdx.x * (uint32_t)kChunk;
+    unsigned long long m = 0;
+    for (int e = threadIdx.x; e < kChunk; e += kBlock) {
+        const uint32_t g = base + (uint32_t)e;
+        if (g < count) m = key_max(m, pack_key(f[g], g));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = key_max(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) m = key_max(m, wm[w]);
+        out[blockIdx.x] = m;
+    }
+}
+
+// *floor_out = the larger of *floor_in (when given) and the value of the
+// T-th key of a distinct top-T list (-1 when the list holds fewer than T).
+__global__ void k_floor_from(const unsigned long long* __restrict__ top, int T, const float* __restrict__ floor_in,
+                             float* __restrict__ floor_out) {
+    if (threadIdx.x != 0) return;
+    float v = top[T - 1] != 0ull ? key_value(top[T - 1]) : -1.0f;
+    if (floor_in) v = fmaxf(v, *floor_in);
+    *floor_out = v;
+}
+
 }  // namespace
 
 size_t topk_buffer_keys(uint32_t count, int T) {
@@ -103,6 +134,19 @@ lrqo_status topk_select_lists(const unsigned long long* lists, uint32_t count, i
                               unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st,
                               const unsigned long long** out) {
     return topk_passes(nullptr, lists, true, count, T, false, nullptr, buf_a, buf_b, st, out);
+}
+
+lrqo_status topk_block_floor(const float* f, uint32_t count, int T, const float* floor_in, float* floor_out,
+                             unsigned long long* buf_a, unsigned long long* buf_b, hipStream_t st) {
+    const uint32_t groups = (count + kChunk - 1) / kChunk;
+    if (T < 1 || T > 64 || groups < (uint32_t)T) return LRQO_EINVAL;
+    hipLaunchKernelGGL(k_block_max, dim3(groups), dim3(kBlock), 0, st, f, count, buf_b);
+    LRQO_HIP(hipGetLastError());
+    const unsigned long long* top = nullptr;
+    LRQO_TRY(topk_passes(nullptr, buf_b, false, groups, T, true, nullptr, buf_a, buf_b, st, &top));
+    hipLaunchKernelGGL(k_floor_from, dim3(1), dim3(64), 0, st, top, T, floor_in, floor_out);
+    LRQO_HIP(hipGetLastError());
+    return LRQO_OK;
 }
 
 }  // namespace lrqo

@@ -187,6 +187,24 @@ def test_exact_fused_form_at_scale(lrqo_mod):
     assert f_exact_on_32 >= f_samp * (1 - 1e-6)
 
 
+def test_exact_first_chunk_floor_drops_nothing(lrqo_mod, monkeypatch):
+    """The first chunk's selection floor (the 64th largest distinct maximum of
+    its groups of 2,048 scores) may only drop scores that cannot enter the
+    best 64.  A one-chunk solve (n = 80, r = 2, K = 3: 2.3 million sets, the
+    floor on) returns the same objective, labels and counts as the same solve
+    in chunks of 100,000 sets, which never take that floor (later chunks take
+    the shortlist's).  Both run the fused scorer, so every set's FP32 score is
+    the same number in both."""
+    V = inputs.random_V(80, 2, 8081)
+    monkeypatch.setenv("LRQO_EXACT_FORM", "fused")
+    z1, r1 = _solve(lrqo_mod, V, 3)
+    monkeypatch.setenv("LRQO_EXACT_CHUNK", "100000")
+    z2, r2 = _solve(lrqo_mod, V, 3)
+    assert r1.index_sets > 20 * 100_000
+    assert r1.obj == r2.obj and np.array_equal(z1, z2)
+    assert (r1.index_sets, r1.candidates, r1.rank_deficient) == (r2.index_sets, r2.candidates, r2.rank_deficient)
+
+
 def test_exact_real_factor(lrqo_mod):
     """A real factor violates general position (Assumption 1): at vertices
     c ~ exp(i pi(2m+1)/K) x, x real, every row lies on boundary line m.  The
