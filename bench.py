@@ -200,8 +200,9 @@ def form_exact():
     """Exact vertex enumeration (Alg. 2 with its recursion over leading
     columns): the parity configuration exact_small (n = 12, r = 2, K = 3)
     beside the FP64 oracle (Alg. 2 in numpy) and brute force over the 3^12
-    assignments, and two larger enumerations of the same kind (n = 64: the
-    split scorer; n = 160: C(480, 3) index sets, the fused scorer)."""
+    assignments, and two larger enumerations of the same kind (n = 64 and
+    n = 160: C(480, 3) index sets; both one pass per set, the fused
+    scorer, at these sizes)."""
     import torch
 
     import oracle

@@ -202,9 +202,10 @@ lrqo_status lrqo_solve_sampled_noalloc(const float* V, int64_t n, int32_t r, int
  * candidate found, with no claim of optimality.
  * Environment (inspection only, the result does not depend on them):
  * LRQO_EXACT_CHUNK sets per chunk (default 2^26); LRQO_EXACT_FORM=fused
- * scores every set in one pass over all rows (the form otherwise used when
- * a chunk's per-set buffers exceed 128 MB) instead of the vertex / row-slice
- * / combine split.
+ * scores every set in one pass over all rows, =split runs the vertex /
+ * row-slice / combine kernels; unset, the split form is taken only where it
+ * slices the rows (n of 2,048 and more with few sets) and a chunk's per-set
+ * buffers fit in 128 MB.
  * ------------------------------------------------------------------------ */
 
 typedef struct lrqo_exact_result {

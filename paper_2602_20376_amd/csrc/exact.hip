@@ -1404,7 +1404,13 @@ int boundary_count(int K) { return (K % 2 == 0) ? K / 2 : K; }
 // over, slices of at least 1024 rows.  Returns the slice count (0: fused).
 constexpr uint64_t kSplitBytes = 128ull << 20;
 
-int exact_slices(uint64_t count, int64_t n, int r, int64_t& rows) {
+// Form of a level's launch: kFormAuto takes the split form only where it
+// slices the rows (one slice would solve each vertex twice for nothing);
+// the other two force a form (the split one still needs its buffers).
+constexpr int kFormAuto = 0, kFormFused = 1, kFormSplit = 2;
+
+int exact_slices(uint64_t count, int64_t n, int r, int64_t& rows, int form) {
+    if (form == kFormFused) return 0;
     const uint64_t blocks = std::min<uint64_t>((count + kBlock - 1) / kBlock, 8192);
     int64_t slices = std::max<int64_t>(1, (int64_t)((2048 + blocks - 1) / blocks));
     slices = std::min<int64_t>(slices, std::max<int64_t>(1, n / 1024));
@@ -1412,6 +1418,7 @@ int exact_slices(uint64_t count, int64_t n, int r, int64_t& rows) {
     rows = ((rows + 63) / 64) * 64;
     slices = (n + rows - 1) / rows;
     if (split_bytes(count, (int)slices, r) > kSplitBytes) return 0;
+    if (slices == 1 && form != kFormSplit) return 0;
     return (int)slices;
 }
 
@@ -1419,9 +1426,9 @@ int exact_slices(uint64_t count, int64_t n, int r, int64_t& rows) {
 // sizes such enumerations reach (n of a few tens) the row pass is not what
 // costs, the vertex solves and the label combinations are.
 template <int R, int D>
-void launch_level(ExactParams p, bool force_fused, hipStream_t st) {
+void launch_level(ExactParams p, int form, hipStream_t st) {
     const uint64_t blocks = std::min<uint64_t>((p.count + kBlock - 1) / kBlock, 8192);
-    const int slices = force_fused ? 0 : exact_slices(p.count, p.n, R, p.rows_per_slice);
+    const int slices = exact_slices(p.count, p.n, R, p.rows_per_slice, form);
     const int ks = R > kThreadMaxD ? 0 : p.K;
     if (slices == 0) {
         switch (ks) {
@@ -1445,7 +1452,7 @@ void launch_level(ExactParams p, bool force_fused, hipStream_t st) {
 }
 
 template <int R>
-lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, bool force_fused, TopEntry* top,
+lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, int form, TopEntry* top,
                       unsigned long long* ka, unsigned long long* kb, float* floor_buf, RescoreEntry* entries,
                       double* rpart, ExactDevResult* dres, uint8_t* z, hipStream_t st) {
     hipLaunchKernelGGL(k_exact_top_init, dim3(1), dim3(kTopT), 0, st, top);
@@ -1456,14 +1463,14 @@ lrqo_status run_exact(ExactParams p, const LevelTable& lt, uint64_t chunk, bool 
             q.count = std::min<uint64_t>(chunk, lt.count[d] - c0);
             q.rank0 = c0;
             switch (d) {
-                case 1: launch_level<R, 1>(q, force_fused, st); break;
-                case 2: if constexpr (R >= 2) launch_level<R, 2>(q, force_fused, st); break;
-                case 3: if constexpr (R >= 3) launch_level<R, 3>(q, force_fused, st); break;
-                case 4: if constexpr (R >= 4) launch_level<R, 4>(q, force_fused, st); break;
-                case 5: if constexpr (R >= 5) launch_level<R, 5>(q, force_fused, st); break;
-                case 6: if constexpr (R >= 6) launch_level<R, 6>(q, force_fused, st); break;
-                case 7: if constexpr (R >= 7) launch_level<R, 7>(q, force_fused, st); break;
-                case 8: if constexpr (R >= 8) launch_level<R, 8>(q, force_fused, st); break;
+                case 1: launch_level<R, 1>(q, form, st); break;
+                case 2: if constexpr (R >= 2) launch_level<R, 2>(q, form, st); break;
+                case 3: if constexpr (R >= 3) launch_level<R, 3>(q, form, st); break;
+                case 4: if constexpr (R >= 4) launch_level<R, 4>(q, form, st); break;
+                case 5: if constexpr (R >= 5) launch_level<R, 5>(q, form, st); break;
+                case 6: if constexpr (R >= 6) launch_level<R, 6>(q, form, st); break;
+                case 7: if constexpr (R >= 7) launch_level<R, 7>(q, form, st); break;
+                case 8: if constexpr (R >= 8) launch_level<R, 8>(q, form, st); break;
             }
             LRQO_HIP(hipGetLastError());
             const int T = (int)std::min<uint64_t>(kTopT, q.count);
@@ -1508,9 +1515,12 @@ uint64_t exact_chunk() {
     return kChunkSets;
 }
 
-bool exact_force_fused() {
+// LRQO_EXACT_FORM = fused / split forces a form (for tests); unset: auto.
+int exact_form() {
     const char* e = std::getenv("LRQO_EXACT_FORM");
-    return e && std::strcmp(e, "fused") == 0;
+    if (e && std::strcmp(e, "fused") == 0) return kFormFused;
+    if (e && std::strcmp(e, "split") == 0) return kFormSplit;
+    return kFormAuto;
 }
 
 // Shared by the exact enumeration (random = false: every valid index set of
@@ -1560,7 +1570,7 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     if (!is_device_pointer(z)) return fail(LRQO_EINVAL, "z is not device memory");
 
     const uint64_t chunk = random ? (uint64_t)S : exact_chunk();
-    const bool force_fused = exact_force_fused();
+    const int form = exact_form();
     const int rk = r <= kThreadMaxD ? r : kMaxR;     // columns the kernels see
     const bool pad = rk != r;                        // 4 < r < kMaxR: a zero-padded copy of V
     uint64_t cmax = 0;                   // the largest chunk
@@ -1568,12 +1578,12 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
     const int Mmax = 2 * r - 1;
     const size_t binom_entries = (random || Mmax < 2) ? 1 : (size_t)(Mmax + 1) * (size_t)(N + 1);
     uint64_t rec_count = 0, part_floats = 0;     // the largest split chunk's needs
-    if (!force_fused) {
+    if (form != kFormFused) {
         for (int d = r; d >= 1; --d) {
             if (lt.count[d] == 0) continue;
             const uint64_t cnt = std::min<uint64_t>(chunk, lt.count[d]);
             int64_t rows = 0;
-            const int sl = exact_slices(cnt, n, rk, rows);
+            const int sl = exact_slices(cnt, n, rk, rows, form);
             if (sl == 0) continue;
             rec_count = std::max<uint64_t>(rec_count, cnt);
             part_floats = std::max<uint64_t>(part_floats, cnt * (uint64_t)sl * 2 * (2 * rk));
@@ -1697,28 +1707,28 @@ lrqo_status vertex_solve(const double* V, int64_t n, int32_t r, int32_t K, int64
         case 1:
             hipLaunchKernelGGL((k_to_f32<1>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<1>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
+            s = run_exact<1>(p, lt, chunk, form, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         case 2:
             hipLaunchKernelGGL((k_to_f32<2>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<2>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
+            s = run_exact<2>(p, lt, chunk, form, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         case 3:
             hipLaunchKernelGGL((k_to_f32<3>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<3>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
+            s = run_exact<3>(p, lt, chunk, form, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         case 4:
             hipLaunchKernelGGL((k_to_f32<4>), dim3(256), dim3(256), 0, st, V, V32, vcount, nonfinite, complex_v,
                                vmax_bits);
-            s = run_exact<4>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
+            s = run_exact<4>(p, lt, chunk, form, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
         default:
             if (pad) hipLaunchKernelGGL(k_pad_columns, dim3(256), dim3(256), 0, st, V, Vpad, n, r);
             hipLaunchKernelGGL((k_to_f32<kMaxR>), dim3(256), dim3(256), 0, st, p.V64, V32, vcount, nonfinite,
                                complex_v, vmax_bits);
-            s = run_exact<kMaxR>(p, lt, chunk, force_fused, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
+            s = run_exact<kMaxR>(p, lt, chunk, form, top, ka, kb, floor_buf, entries, rpart, dres, z, st);
             break;
     }
     if (s != LRQO_OK) return s;

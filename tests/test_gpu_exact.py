@@ -92,10 +92,11 @@ def test_exact_high_rank_vs_brute(lrqo_mod, n, r, K):
     assert abs(res.obj - opt) <= 1e-12 * opt
 
 
-@pytest.mark.parametrize("n,r,K,chunk,form", [(10, 5, 2, 7, "fused"), (7, 6, 4, 100, ""), (12, 6, 2, 5, "fused"),
-                                              (14, 7, 2, 1000, "fused"), (15, 8, 2, 4096, "")])
+@pytest.mark.parametrize("n,r,K,chunk,form", [(10, 5, 2, 7, "fused"), (7, 6, 4, 100, "split"), (12, 6, 2, 5, "fused"),
+                                              (14, 7, 2, 1000, "fused"), (15, 8, 2, 4096, "split")])
 def test_exact_high_rank_forms(lrqo_mod, n, r, K, chunk, form, monkeypatch):
-    """The fused scorer and ragged chunks at r = 5 .. 8 against the oracle."""
+    """The fused and split scorers and ragged chunks at r = 5 .. 8 against
+    the oracle."""
     monkeypatch.setenv("LRQO_EXACT_CHUNK", str(chunk))
     if form:
         monkeypatch.setenv("LRQO_EXACT_FORM", form)
@@ -259,18 +260,21 @@ def test_exact_general_position_no_warning(lrqo_mod):
     assert res.rank_deficient == 0 and res.warning == 0
 
 
+@pytest.mark.parametrize("form", ["fused", "split"])
 @pytest.mark.parametrize("n,r,K", [(12, 2, 3), (16, 2, 3), (20, 2, 3), (9, 3, 3), (13, 2, 4), (14, 1, 7)])
-def test_exact_fused_form_vs_oracle(lrqo_mod, n, r, K, monkeypatch):
-    """The fused scorer (one pass over all rows per set, the form large
-    enumerations take) forced at small n: optimum, labels and every count
-    equal to the oracle's."""
-    monkeypatch.setenv("LRQO_EXACT_FORM", "fused")
+def test_exact_forms_vs_oracle(lrqo_mod, n, r, K, form, monkeypatch):
+    """Each form forced at small n: the fused scorer (one pass over all rows
+    per set) and the split one (vertex records, the row pass, the
+    combinations; small sizes take the fused form by default): optimum,
+    labels and every count equal to the oracle's."""
+    monkeypatch.setenv("LRQO_EXACT_FORM", form)
     V = inputs.random_V(n, r, 600 + 7 * n + r + K)
     z, res = _solve(lrqo_mod, V, K)
     _check(V, K, z, res)
 
 
-@pytest.mark.parametrize("chunk,form", [(1, ""), (7, "fused"), (1000, ""), (1000, "fused"), (4096, "")])
+@pytest.mark.parametrize("chunk,form", [(1, ""), (7, "fused"), (1000, "split"), (1000, "fused"), (4096, "split"),
+                                        (4096, "")])
 def test_exact_chunked_shortlist(lrqo_mod, chunk, form, monkeypatch):
     """The sets taken in chunks, each chunk's best distinct scores merged into
     the shortlist (chunk = 1: every set merged on its own; 7: ragged
