@@ -13,17 +13,22 @@
 //   k_to_f32        FP32 copy of V for the scorer, and a flag when some
 //                   imaginary part is not zero (the row scorers take real
 //                   arithmetic, half the FMAs, when none is)
-//   k_exact_score   one thread per index set (grid-stride) and row slice:
+//   k_exact_score   fused form: one thread per index set (grid-stride):
 //                   colex unranking (or a random draw), FP64 null vector by
 //                   twice-orthogonalised Gram-Schmidt (in the thread for
 //                   d <= 4, by sixteen lanes per set for larger d), both signs
-//                   scored in
-//                   FP32 over the slice's rows (row tiles in LDS);
-//                   coordinates in the set tried with every label the vertex
-//                   leaves open; best FP32 score per set -> fbuf
-//   k_exact_combine with several row slices: the slice sums in order, then
-//                   the label combinations
-//   topk_select     best 64 sets (select.hip)
+//                   scored in FP32 over every row (row tiles in LDS; runs of
+//                   32 rows that no set of the wave touches with no per-row
+//                   test); coordinates in the set tried with every label the
+//                   vertex leaves open; best FP32 score per set -> fbuf
+//   k_exact_vertex, k_exact_rows, k_exact_combine
+//                   split form, for levels whose rows take several slices:
+//                   each set's vertex kept as a record; the row pass per
+//                   (set, row slice) into slice sums; the slice sums added in
+//                   order, then the label combinations
+//   topk_select     best 64 sets of a chunk (select.hip), scores below a
+//                   floor read on the device dropped
+//   k_exact_merge   the chunk's best into the running shortlist
 //   k_exact_rescore_rows  FP64 row sums of each kept set (both signs),
 //                   grid (kept sets, row slices)
 //   k_exact_rescore FP64 re-evaluation of each kept set from the slice sums
