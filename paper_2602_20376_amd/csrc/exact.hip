@@ -888,8 +888,16 @@ __device__ __forceinline__ void add_stats(const ExactParams& p, bool active, boo
 // every row the set does not touch (row tiles in LDS, the touched rows found
 // with a cursor over their sorted list), then the label combinations.  Used
 // when the sets are too many for the split form's buffers.
+// Waves per SIMD the fused scorer asks the compiler for: five at rank 2,
+// level 2 (96 VGPRs, a few spilled in the per-set work; the rank-2 campaign
+// runs about 4% faster than at four), no bound elsewhere (the larger levels'
+// vertex solves need their registers).
+template <int R, int D>
+constexpr int kScoreMinWaves = (R == 2 && D == 2) ? 5 : 1;
+
 template <int R, int D, int KS>
-__global__ __launch_bounds__(kBlock) void k_exact_score(ExactParams p) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kScoreMinWaves<R, D>)))
+void k_exact_score(ExactParams p) {
     constexpr int M = 2 * D - 1, C2 = 2 * D;
     __shared__ __align__(16) float tile[kTile * 2 * R];
     __shared__ float2 roots_s[KS == 0 ? LRQO_MAX_K : 1];
