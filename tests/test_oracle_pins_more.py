@@ -181,3 +181,20 @@ def test_score_interval_is_tight_without_ambiguity(oracle_lib):
     assert res["nambig"][0] == 0
     assert res["lo"][0] == res["f"][0] == res["hi"][0]
     assert abs(res["f"][0] - f) <= 1e-12 * f
+
+
+# ------------------------------------------------------------ opposite-ray label
+
+@pytest.mark.parametrize("K", [3, 5, 7, 9, 15])
+def test_opposite_ray_label_odd_k(K):
+    """For odd K the ray opposite boundary m, at angle pi (2m + 1)/K + pi,
+    is the direction of root m + (K + 1)/2 (mod K): the decision rule gives
+    that label there and on both sides of the ray up to pi/K away, which the
+    exact path's open labels take without evaluating the rule."""
+    for m in range(K):
+        ang = np.pi * (2 * m + 1) / K + np.pi
+        want = (m + (K + 1) // 2) % K
+        offs = np.array([0.0, 1e-9, -1e-9, 0.4, -0.4, 0.99, -0.99]) * np.pi / K
+        w = 3.7 * np.exp(1j * (ang + offs))
+        assert np.all(exact.decision_labels(w, K) == want), (K, m)
+        assert all(oracle.label(complex(x), K) == want for x in w), (K, m)
